@@ -1,0 +1,186 @@
+/*
+ * dnb.h -- C ABI of the differentiable direct N-body library (libdnb.so).
+ *
+ * The library implements, for one AMD Instinct MI355X (gfx950), the hot path of
+ * the differentiable direct N-body method of arXiv 2511.22468 ("Odisseo"):
+ * the softened pairwise gravity sum (Sec. 1, "N-body codes": direct pairwise
+ * forces with softening, no tree), the analytic NFW-halo and Miyamoto-Nagai-disk
+ * accelerations of the host galaxy (Sec. 2.2.1), the fixed-step Velocity-Verlet
+ * (kick-drift-kick) integrator (Sec. 2.2.1), reverse-mode gradients of the final
+ * state with respect to initial conditions, integration time, particle masses and
+ * potential parameters (Sec. 2), the maximum mean discrepancy loss with its
+ * gradient (Sec. 2.2.1 and Fig. 2, step 4), and the back-integration of the
+ * progenitor's centre of mass and the Plummer-sphere placement that the inference
+ * pipeline chains them with (Fig. 2, steps 2-3).
+ *
+ * Units: every entry point takes internal units, kpc for length, km/s for
+ * velocity, Msun for mass, kpc/(km/s) for time; G is passed in dnb_pot.
+ *
+ * Conventions shared by every entry point:
+ *  - Arrays are DEVICE pointers on the current HIP device unless a comment says
+ *    "host".  Particle arrays are structure-of-arrays: an array of "[3][n]"
+ *    holds n x-values, then n y-values, then n z-values, contiguous; "[n]" is
+ *    one value per particle.  All arrays are FP64 and owned by the caller.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL means the
+ *    null stream).  Outputs are valid once the stream has been synchronised.
+ *    Inputs must stay alive and unmodified until then.
+ *  - Arguments are validated on the host before anything is enqueued; a failed
+ *    check returns DNB_ERR_ARG and enqueues nothing.  A HIP failure returns
+ *    DNB_ERR_HIP.  dnb_last_error() gives a message for the calling thread.
+ *    No C++ exception crosses this interface.
+ *  - A context may be used by one host thread and one stream at a time.
+ *    Contexts on the same device may run concurrently on different streams.
+ *  - eps > 0 is required when two distinct particles may coincide; with
+ *    eps == 0 the self term is masked, and coincident distinct particles give
+ *    inf/NaN accelerations.
+ */
+#ifndef DNB_H
+#define DNB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DNB_OK = 0,
+    DNB_ERR_ARG = -1,    /* invalid argument, nothing enqueued */
+    DNB_ERR_HIP = -2,    /* a HIP runtime call failed */
+    DNB_ERR_NOMEM = -3,  /* device allocation of the context failed */
+    DNB_ERR_STATE = -4   /* call sequence or buffer-size violation */
+} dnb_status;
+
+/* Precision of the pairwise terms.  Positions, velocities, the drift, the
+ * external potential and every reduction are FP64 in both modes.
+ *  DNB_FP64  : pair terms in FP64 (reciprocal square root refined by Newton
+ *              steps).
+ *  DNB_FP32C : pair terms in FP32 on positions staged relative to a per-step
+ *              centre computed in FP64, with compensated (TwoSum) accumulation
+ *              across tiles of 128 sources and an FP64 sum across slices. */
+typedef enum { DNB_FP64 = 0, DNB_FP32C = 1 } dnb_prec;
+
+/* Softening and host potential (Sec. 1 and Sec. 2.2.1).  A zero mass disables
+ * that component.  NFW:  Phi = -G m_nfw ln(1 + r/rs_nfw) / r, m_nfw being the
+ * scale mass 4 pi rho0 rs^3.  Miyamoto-Nagai:  Phi = -G m_mn /
+ * sqrt(R^2 + (a_mn + sqrt(z^2 + b_mn^2))^2).  Pair softening is Plummer:
+ * a_i = G sum_j m_j d_ij (|d_ij|^2 + eps^2)^(-3/2), d_ij = x_j - x_i. */
+typedef struct {
+    double G, eps, m_nfw, rs_nfw, m_mn, a_mn, b_mn;
+} dnb_pot;
+
+typedef struct dnb_ctx dnb_ctx;
+
+/* Create a context for up to max_n particles on the current HIP device.  All
+ * device workspace (staging, slice partials, reduction scratch) is allocated
+ * here, once; no other entry point allocates.  Returns DNB_ERR_ARG for
+ * max_n < 1 or max_n > 2^26, DNB_ERR_NOMEM if allocation fails. */
+dnb_status dnb_create(dnb_ctx** out, int64_t max_n, dnb_prec prec);
+
+/* Free a context (NULL is ignored).  Synchronises the device first. */
+void dnb_destroy(dnb_ctx* ctx);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char* dnb_last_error(void);
+
+/* Library version string. */
+const char* dnb_version(void);
+
+/* Accelerations a = a_int + with_ext * a_ext at positions pos (Sec. 1, Sec.
+ * 2.2.1).  pos [3][n], mass [n], acc [3][n] (output, must not alias pos).
+ * pot is a HOST pointer read during the call. */
+dnb_status dnb_accelerations(dnb_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                             const dnb_pot* pot, int with_ext, double* acc, void* stream);
+
+/* One kick-drift-kick step of size dt (Sec. 2.2.1, Velocity-Verlet), in place on
+ * pos [3][n] and vel [3][n]; the step evaluates a(x_n) and a(x_{n+1}). */
+dnb_status dnb_step(dnb_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
+                    const dnb_pot* pot, double dt, void* stream);
+
+/* Number of doubles of the checkpoint tape that dnb_simulate writes for
+ * (n, n_steps, ckpt_every): ceil(n_steps / ckpt_every) checkpoints of 6n. */
+int64_t dnb_tape_doubles(int64_t n, int64_t n_steps, int64_t ckpt_every);
+
+/* Number of doubles of the segment workspace that dnb_simulate_vjp needs:
+ * 3n (ckpt_every + 1) + 16n. */
+int64_t dnb_vjp_workspace_doubles(int64_t n, int64_t ckpt_every);
+
+/* n_steps kick-drift-kick steps of size dt (Sec. 2.2.1: fixed steps), in place
+ * on pos [3][n] and vel [3][n].  If tape is not NULL it must hold
+ * dnb_tape_doubles(n, n_steps, ckpt_every) doubles and receives the state
+ * (x, v) at steps 0, K, 2K, ... (K = ckpt_every >= 1), each as [6][n]
+ * (x block then v block).  The tape is what dnb_simulate_vjp differentiates. */
+dnb_status dnb_simulate(dnb_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
+                        const dnb_pot* pot, double dt, int64_t n_steps, int64_t ckpt_every,
+                        double* tape, void* stream);
+
+/* Reverse-mode gradient of a scalar loss through dnb_simulate (Sec. 2: the final
+ * state is differentiable with respect to initial conditions, integration time,
+ * particle masses and external-potential parameters).  This is the exact
+ * discrete adjoint of the kick-drift-kick map: positions between checkpoints
+ * are recomputed forward from the tape (bitwise identical to the forward run),
+ * then the sweep runs newest step first with one pair-VJP per step.
+ *
+ * Inputs: the same n, mass, pot, dt, n_steps, ckpt_every and tape as the
+ * forward call; pos_T [3][n], the final positions the forward call produced;
+ * gpos_T, gvel_T [3][n], the loss cotangents of the final state (gvel_T may be
+ * NULL for zero).  workspace holds dnb_vjp_workspace_doubles(n, ckpt_every).
+ * Outputs: gpos_0, gvel_0 [3][n]; gmass [n] (nullable): dL/dm_k; gparams [4]
+ * (device): dL/dm_nfw, dL/dm_mn, dL/ddt, and sum_k m_k dL/dm_k (the derivative
+ * with respect to a common log-scale of all particle masses, which is what a
+ * progenitor-mass parameter needs).  Outputs must not alias inputs. */
+dnb_status dnb_simulate_vjp(dnb_ctx* ctx, int64_t n, const double* mass, const dnb_pot* pot,
+                            double dt, int64_t n_steps, int64_t ckpt_every, const double* tape,
+                            const double* pos_T, const double* gpos_T, const double* gvel_T,
+                            double* workspace, double* gpos_0, double* gvel_0, double* gmass,
+                            double* gparams, void* stream);
+
+/* Squared maximum mean discrepancy between the point clouds pos [3][n] and
+ * tgt [3][m] (Sec. 2.2.1 and Fig. 2, step 4), with the Gaussian kernel
+ * k(x, y) = exp(-|x - y|^2 / (2 h^2)) and the biased (V-statistic) estimate:
+ *   L = mean_ij k(x_i,x_j) + mean_ab k(y_a,y_b) - 2 mean_ia k(x_i,y_a).
+ * loss: device scalar.  gpos [3][n] (nullable): dL/dpos.  FP64 throughout.
+ * Requires n, m <= max_n of the context and h > 0. */
+dnb_status dnb_mmd(dnb_ctx* ctx, int64_t n, const double* pos, int64_t m, const double* tgt,
+                   double h, double* loss, double* gpos, void* stream);
+
+/* Energies of the system (diagnostic): out3 [3] (device) = kinetic energy,
+ * softened pair energy -G sum_{i<j} m_i m_j (r_ij^2 + eps^2)^(-1/2), and
+ * sum_i m_i Phi_ext(x_i).  FP64. */
+dnb_status dnb_energy(dnb_ctx* ctx, int64_t n, const double* pos, const double* vel,
+                      const double* mass, const dnb_pot* pot, double* out3, void* stream);
+
+/* Test-particle orbit in the external potential only (Fig. 2, step 2: the
+ * progenitor's centre of mass integrated backward as a single particle).
+ * w0 [6] = (x, y, z, vx, vy, vz); n_steps kick-drift-kick steps of dt (dt < 0
+ * integrates backward); w_out [6].  traj (nullable) receives the 3 (n_steps+1)
+ * positions x_0..x_{n_steps} as [n_steps+1][3], which dnb_orbit_vjp needs. */
+dnb_status dnb_orbit(dnb_ctx* ctx, const double* w0, const dnb_pot* pot, double dt,
+                     int64_t n_steps, double* w_out, double* traj, void* stream);
+
+/* Adjoint of dnb_orbit.  gw_out [6]: cotangent of w_out.  Outputs gw0 [6] and
+ * gparams [3] = dL/dm_nfw, dL/dm_mn, dL/ddt (device). */
+dnb_status dnb_orbit_vjp(dnb_ctx* ctx, const double* traj, const dnb_pot* pot, double dt,
+                         int64_t n_steps, const double* gw_out, double* gw0, double* gparams,
+                         void* stream);
+
+/* Place a Plummer sphere at the phase-space point w [6] (Fig. 2, step 3):
+ * pos = w_x + a_p * xi, vel = w_v + sqrt(G m_tot / a_p) * zeta, mass = m_tot / n.
+ * xi, zeta [3][n] are unit samples (G = M = a = 1).  m_tot and a_p are host
+ * scalars, w is a device pointer. */
+dnb_status dnb_place_plummer(dnb_ctx* ctx, int64_t n, const double* w, const double* xi,
+                             const double* zeta, double m_tot, double a_p, double G,
+                             double* pos, double* vel, double* mass, void* stream);
+
+/* Adjoint of dnb_place_plummer.  gpos, gvel [3][n], gmass [n] (nullable) are the
+ * cotangents of its outputs.  Outputs: gw [6] = (sum_i gpos_i, sum_i gvel_i) and
+ * gm_tot [1] = dL/dm_tot (device). */
+dnb_status dnb_place_plummer_vjp(dnb_ctx* ctx, int64_t n, const double* zeta, double m_tot,
+                                 double a_p, double G, const double* gpos, const double* gvel,
+                                 const double* gmass, double* gw, double* gm_tot, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DNB_H */

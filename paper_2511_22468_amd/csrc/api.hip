@@ -1,0 +1,433 @@
+// C ABI of libdnb: argument validation, context management and the host-side
+// sequencing of the kernels for each entry point declared in include/dnb.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "dnb_internal.h"
+
+using namespace dnb;
+
+namespace {
+
+thread_local std::string g_err;
+
+dnb_status fail(dnb_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(DNB_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr int64_t MAX_N = int64_t(1) << 26;
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+dnb_status check_ctx(dnb_ctx* c, int64_t n, const char* fn) {
+    if (!c) return fail(DNB_ERR_ARG, "%s: ctx is NULL", fn);
+    if (n < 1 || n > c->max_n)
+        return fail(DNB_ERR_ARG, "%s: n = %lld outside [1, max_n = %lld]", fn, (long long)n,
+                    (long long)c->max_n);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != c->device)
+        return fail(DNB_ERR_ARG, "%s: current device %d is not the context's device %d", fn, dev,
+                    c->device);
+    return DNB_OK;
+}
+
+dnb_status check_pot(const dnb_pot* p, const char* fn) {
+    if (!p) return fail(DNB_ERR_ARG, "%s: pot is NULL", fn);
+    const double v[7] = {p->G, p->eps, p->m_nfw, p->rs_nfw, p->m_mn, p->a_mn, p->b_mn};
+    for (double x : v)
+        if (!is_fin(x)) return fail(DNB_ERR_ARG, "%s: non-finite potential parameter", fn);
+    if (p->eps < 0) return fail(DNB_ERR_ARG, "%s: eps must be >= 0", fn);
+    if (p->m_nfw != 0 && !(p->rs_nfw > 0)) return fail(DNB_ERR_ARG, "%s: rs_nfw must be > 0", fn);
+    if (p->m_mn != 0 && (p->a_mn < 0 || p->b_mn < 0))
+        return fail(DNB_ERR_ARG, "%s: a_mn and b_mn must be >= 0", fn);
+    if (p->m_mn != 0 && p->a_mn == 0 && p->b_mn == 0)
+        return fail(DNB_ERR_ARG, "%s: a_mn = b_mn = 0 makes the disk a point mass; use b_mn > 0", fn);
+    return DNB_OK;
+}
+
+// A pointer must be device memory (or managed) of the current device.
+dnb_status check_dev(const void* p, const char* name, const char* fn, bool nullable = false) {
+    if (!p) {
+        if (nullable) return DNB_OK;
+        return fail(DNB_ERR_ARG, "%s: %s is NULL", fn, name);
+    }
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DNB_ERR_ARG, "%s: %s is not a HIP device pointer", fn, name);
+    }
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+        return fail(DNB_ERR_ARG, "%s: %s is not device memory", fn, name);
+    return DNB_OK;
+}
+
+#define CHECK(x)                          \
+    do {                                  \
+        dnb_status s_ = (x);              \
+        if (s_ != DNB_OK) return s_;      \
+    } while (0)
+
+struct Tape {
+    double* base;
+    int64_t n, n_ckpt;
+    double* state(int64_t c) const { return base + c * 6 * n; }
+    double* centre(int64_t c) const { return base + n_ckpt * 6 * n + 4 * c; }
+};
+
+// Forward integration from (x, v) for n_steps; tape optional.  Positions and
+// velocities are updated in place.
+dnb_status run_forward(dnb_ctx* c, int64_t n, double* pos, double* vel, const double* mass,
+                       const Pot& p, double dt, int64_t T, int64_t K, const Tape* tape,
+                       hipStream_t st) {
+    if (T == 0) return DNB_OK;
+    const int nb = (int)cdiv(n, BS);
+    double* cp[2] = {c->cpart, c->cpart + 4 * c->nbmax};
+    if (c->prec == DNB_FP32C) {
+        HIP_TRY(launch_block_sums(pos, n, cp[0], st));
+        HIP_TRY(launch_stage(pos, mass, n, cp[0], nb, nullptr, c->js,
+                             tape ? tape->centre(0) : nullptr, st));
+    }
+    int q = 0;
+    for (int64_t s = 0; s <= T; ++s) {
+        HIP_TRY(launch_pair_fwd(c, n, pos, mass, p.eps, st));
+        FwdArgs a{};
+        a.n = n; a.mass = mass; a.pot = p; a.dt = dt;
+        a.x = pos; a.x_out = pos; a.v = vel; a.vh = c->vh; a.with_ext = 1;
+        a.cpart_in = cp[q]; a.cpart_out = cp[1 - q]; a.nb_in = nb;
+        if (tape && s < T && s % K == 0) a.tape_state = tape->state(s / K);
+        if (tape && s + 1 < T && (s + 1) % K == 0) a.tape_centre_next = tape->centre((s + 1) / K);
+        KdkMode mode = (s == 0) ? KDK_FIRST : (s == T ? KDK_LAST : KDK_MID);
+        HIP_TRY(launch_kdk(c, mode, a, st));
+        q = 1 - q;
+    }
+    return DNB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dnb_last_error(void) { return g_err.c_str(); }
+
+const char* dnb_version(void) { return "dnb 0.1.0 (gfx950)"; }
+
+dnb_status dnb_create(dnb_ctx** out, int64_t max_n, dnb_prec prec) {
+    if (!out) return fail(DNB_ERR_ARG, "dnb_create: out is NULL");
+    *out = nullptr;
+    if (max_n < 1 || max_n > MAX_N)
+        return fail(DNB_ERR_ARG, "dnb_create: max_n = %lld outside [1, 2^26]", (long long)max_n);
+    if (prec != DNB_FP64 && prec != DNB_FP32C)
+        return fail(DNB_ERR_ARG, "dnb_create: unknown precision %d", (int)prec);
+    dnb_ctx* c = new (std::nothrow) dnb_ctx();
+    if (!c) return fail(DNB_ERR_NOMEM, "dnb_create: host allocation failed");
+    c->max_n = max_n;
+    c->prec = prec;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(DNB_ERR_HIP, "dnb_create: no HIP device");
+    }
+    c->slice_rows = max_slice_rows(max_n);
+    c->nbmax = (int)cdiv(max_n, BS);
+    const int64_t npadmax = (int64_t)c->nbmax * BS;
+    struct A { void** p; size_t bytes; } allocs[] = {
+        {(void**)&c->js, sizeof(float4) * npadmax},
+        {&c->part, 32 * (size_t)c->slice_rows},
+        {(void**)&c->cpart, sizeof(double) * 8 * c->nbmax},
+        {(void**)&c->vh, sizeof(double) * 3 * npadmax},
+        {(void**)&c->jsv, sizeof(float4) * 2 * npadmax},
+        {&c->partv, 64 * (size_t)c->slice_rows},
+        {(void**)&c->cpartv, sizeof(double) * 8 * c->nbmax},
+        {(void**)&c->red, sizeof(double) * 8 * (c->nbmax + 8)},
+    };
+    for (auto& a : allocs) {
+        if (hipMalloc(a.p, a.bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            dnb_destroy(c);
+            return fail(DNB_ERR_NOMEM, "dnb_create: device allocation of %zu bytes failed", a.bytes);
+        }
+    }
+    *out = c;
+    return DNB_OK;
+}
+
+void dnb_destroy(dnb_ctx* c) {
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    void* ps[] = {c->js, c->part, c->cpart, c->vh, c->jsv, c->partv, c->cpartv, c->red};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    delete c;
+}
+
+dnb_status dnb_accelerations(dnb_ctx* c, int64_t n, const double* pos, const double* mass,
+                             const dnb_pot* pot, int with_ext, double* acc, void* stream) {
+    const char* fn = "dnb_accelerations";
+    CHECK(check_ctx(c, n, fn));
+    CHECK(check_pot(pot, fn));
+    CHECK(check_dev(pos, "pos", fn));
+    CHECK(check_dev(mass, "mass", fn));
+    CHECK(check_dev(acc, "acc", fn));
+    if (acc == pos) return fail(DNB_ERR_ARG, "%s: acc must not alias pos", fn);
+    hipStream_t st = (hipStream_t)stream;
+    Pot p = to_pot(*pot);
+    const int nb = (int)cdiv(n, BS);
+    if (c->prec == DNB_FP32C) {
+        HIP_TRY(launch_block_sums(pos, n, c->cpart, st));
+        HIP_TRY(launch_stage(pos, mass, n, c->cpart, nb, nullptr, c->js, nullptr, st));
+    }
+    HIP_TRY(launch_pair_fwd(c, n, pos, mass, p.eps, st));
+    FwdArgs a{};
+    a.n = n; a.mass = mass; a.pot = p; a.x = pos; a.acc_out = acc; a.with_ext = with_ext ? 1 : 0;
+    HIP_TRY(launch_kdk(c, KDK_ACC, a, st));
+    return DNB_OK;
+}
+
+int64_t dnb_tape_doubles(int64_t n, int64_t n_steps, int64_t ckpt_every) {
+    if (n < 1 || n_steps < 0 || ckpt_every < 1) return -1;
+    return cdiv(n_steps, ckpt_every) * (6 * n + 4);
+}
+
+int64_t dnb_vjp_workspace_doubles(int64_t n, int64_t ckpt_every) {
+    if (n < 1 || ckpt_every < 1) return -1;
+    return 3 * n * (ckpt_every + 1) + 16 * n;
+}
+
+static dnb_status check_sim_args(dnb_ctx* c, int64_t n, const void* pos, const void* vel,
+                                 const void* mass, const dnb_pot* pot, double dt, int64_t T,
+                                 int64_t K, const char* fn) {
+    CHECK(check_ctx(c, n, fn));
+    CHECK(check_pot(pot, fn));
+    if (!is_fin(dt)) return fail(DNB_ERR_ARG, "%s: dt is not finite", fn);
+    if (T < 0) return fail(DNB_ERR_ARG, "%s: n_steps < 0", fn);
+    if (K < 1) return fail(DNB_ERR_ARG, "%s: ckpt_every must be >= 1", fn);
+    CHECK(check_dev(pos, "pos", fn));
+    CHECK(check_dev(vel, "vel", fn));
+    CHECK(check_dev(mass, "mass", fn));
+    return DNB_OK;
+}
+
+dnb_status dnb_step(dnb_ctx* c, int64_t n, double* pos, double* vel, const double* mass,
+                    const dnb_pot* pot, double dt, void* stream) {
+    CHECK(check_sim_args(c, n, pos, vel, mass, pot, dt, 1, 1, "dnb_step"));
+    return run_forward(c, n, pos, vel, mass, to_pot(*pot), dt, 1, 1, nullptr, (hipStream_t)stream);
+}
+
+dnb_status dnb_simulate(dnb_ctx* c, int64_t n, double* pos, double* vel, const double* mass,
+                        const dnb_pot* pot, double dt, int64_t n_steps, int64_t ckpt_every,
+                        double* tape, void* stream) {
+    const char* fn = "dnb_simulate";
+    CHECK(check_sim_args(c, n, pos, vel, mass, pot, dt, n_steps, ckpt_every, fn));
+    CHECK(check_dev(tape, "tape", fn, true));
+    Tape tp{tape, n, cdiv(n_steps, ckpt_every)};
+    return run_forward(c, n, pos, vel, mass, to_pot(*pot), dt, n_steps, ckpt_every,
+                       tape ? &tp : nullptr, (hipStream_t)stream);
+}
+
+dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb_pot* pot,
+                            double dt, int64_t n_steps, int64_t ckpt_every, const double* tape,
+                            const double* pos_T, const double* gpos_T, const double* gvel_T,
+                            double* workspace, double* gpos_0, double* gvel_0, double* gmass,
+                            double* gparams, void* stream) {
+    const char* fn = "dnb_simulate_vjp";
+    CHECK(check_sim_args(c, n, pos_T, gpos_0, mass, pot, dt, n_steps, ckpt_every, fn));
+    if (dt == 0.0) return fail(DNB_ERR_ARG, "%s: dt must be non-zero", fn);
+    CHECK(check_dev(gpos_T, "gpos_T", fn));
+    CHECK(check_dev(gvel_T, "gvel_T", fn, true));
+    CHECK(check_dev(workspace, "workspace", fn));
+    CHECK(check_dev(gvel_0, "gvel_0", fn));
+    CHECK(check_dev(gmass, "gmass", fn, true));
+    CHECK(check_dev(gparams, "gparams", fn));
+    if (n_steps > 0) CHECK(check_dev(tape, "tape", fn));
+    if (gpos_0 == gpos_T || gvel_0 == gvel_T || gpos_0 == gvel_0)
+        return fail(DNB_ERR_ARG, "%s: outputs must not alias inputs", fn);
+    hipStream_t st = (hipStream_t)stream;
+    const Pot p = to_pot(*pot);
+    const int64_t T = n_steps, K = ckpt_every;
+    const int nb = (int)cdiv(n, BS);
+    const size_t vec = sizeof(double) * 3 * n;
+    double* lx = gpos_0;
+    double* lv = gvel_0;
+    double* seg = workspace;                         // [(K+1)][3][n]
+    double* vrec = workspace + 3 * n * (K + 1);      // [3][n]
+    double* accum = vrec + 3 * n;                    // [5][n]
+    HIP_TRY(hipMemcpyAsync(lx, gpos_T, vec, hipMemcpyDeviceToDevice, st));
+    if (gvel_T) HIP_TRY(hipMemcpyAsync(lv, gvel_T, vec, hipMemcpyDeviceToDevice, st));
+    else HIP_TRY(hipMemsetAsync(lv, 0, vec, st));
+    HIP_TRY(hipMemsetAsync(accum, 0, sizeof(double) * 5 * n, st));
+    const int with_mass = gmass != nullptr;
+    if (T > 0) {
+        Tape tp{const_cast<double*>(tape), n, cdiv(T, K)};
+        auto get_pos = [&](int64_t m) -> const double* {
+            if (m == T) return pos_T;
+            if (m % K == 0) return tp.state(m / K);
+            return seg + (m % K) * 3 * n;
+        };
+        double* cpf[2] = {c->cpart, c->cpart + 4 * c->nbmax};
+        auto recompute = [&](int64_t cs) -> dnb_status {
+            const int64_t n0 = cs * K, n1 = (n0 + K < T) ? n0 + K : T;
+            if (n1 - n0 < 2) return DNB_OK;
+            double* x0 = tp.state(cs);
+            if (c->prec == DNB_FP32C) {
+                HIP_TRY(launch_block_sums(x0, n, cpf[0], st));
+                HIP_TRY(launch_stage(x0, mass, n, nullptr, 0, tp.centre(cs), c->js, nullptr, st));
+            }
+            int q = 0;
+            for (int64_t s = n0; s <= n1 - 2; ++s) {
+                double* xc = (s == n0) ? x0 : seg + (s - n0) * 3 * n;
+                HIP_TRY(launch_pair_fwd(c, n, xc, mass, p.eps, st));
+                FwdArgs a{};
+                a.n = n; a.mass = mass; a.pot = p; a.dt = dt; a.with_ext = 1;
+                a.x = xc; a.x_out = seg + (s - n0 + 1) * 3 * n;
+                a.v = (s == n0) ? x0 + 3 * n : nullptr;
+                a.vh = vrec;
+                a.cpart_in = cpf[q]; a.cpart_out = cpf[1 - q]; a.nb_in = nb;
+                HIP_TRY(launch_kdk(c, s == n0 ? KDK_FIRST : KDK_MID, a, st));
+                q = 1 - q;
+            }
+            return DNB_OK;
+        };
+        double* cpv[2] = {c->cpartv, c->cpartv + 4 * c->nbmax};
+        int q = 0;
+        if (c->prec == DNB_FP32C) {
+            HIP_TRY(launch_block_sums(pos_T, n, cpv[0], st));
+            HIP_TRY(launch_rev_stage(c, n, pos_T, mass, lv, cpv[0], nb, cpv[1], st));
+            q = 1;
+        }
+        int64_t cur = -1;
+        for (int64_t m = T; m >= 0; --m) {
+            if (m > 0) {
+                const int64_t cs = (m - 1) / K;
+                if ((m - 1) % K != 0 && cur != cs) {
+                    CHECK(recompute(cs));
+                    cur = cs;
+                }
+            }
+            const double* xm = get_pos(m);
+            HIP_TRY(launch_pair_vjp(c, n, xm, mass, lv, with_mass, p.eps, st));
+            RevArgs r{};
+            r.n = n; r.mass = mass; r.pot = p; r.dt = dt;
+            r.coef = (m == T || m == 0) ? 0.5 * dt : dt;
+            r.x_n = xm;
+            r.x_prev = m > 0 ? get_pos(m - 1) : nullptr;
+            r.lx = lx; r.lv = lv; r.accum = accum; r.with_mass = with_mass;
+            r.cpart_in = cpv[q]; r.nb_in = nb; r.cpart_out = cpv[1 - q];
+            HIP_TRY(launch_rev_kick(c, r, st));
+            q = 1 - q;
+        }
+    }
+    HIP_TRY(launch_reduce_accum(accum, n, 4, gparams, c->red, st));
+    if (gmass) HIP_TRY(hipMemcpyAsync(gmass, accum + 4 * n, sizeof(double) * n,
+                                      hipMemcpyDeviceToDevice, st));
+    return DNB_OK;
+}
+
+dnb_status dnb_mmd(dnb_ctx* c, int64_t n, const double* pos, int64_t m, const double* tgt,
+                   double h, double* loss, double* gpos, void* stream) {
+    const char* fn = "dnb_mmd";
+    CHECK(check_ctx(c, n, fn));
+    if (m < 1 || m > c->max_n) return fail(DNB_ERR_ARG, "%s: m outside [1, max_n]", fn);
+    if (!(h > 0) || !is_fin(h)) return fail(DNB_ERR_ARG, "%s: h must be finite and > 0", fn);
+    CHECK(check_dev(pos, "pos", fn));
+    CHECK(check_dev(tgt, "tgt", fn));
+    CHECK(check_dev(loss, "loss", fn));
+    CHECK(check_dev(gpos, "gpos", fn, true));
+    HIP_TRY(launch_mmd(c, n, pos, m, tgt, h, loss, gpos, (hipStream_t)stream));
+    return DNB_OK;
+}
+
+dnb_status dnb_energy(dnb_ctx* c, int64_t n, const double* pos, const double* vel,
+                      const double* mass, const dnb_pot* pot, double* out3, void* stream) {
+    const char* fn = "dnb_energy";
+    CHECK(check_ctx(c, n, fn));
+    CHECK(check_pot(pot, fn));
+    CHECK(check_dev(pos, "pos", fn));
+    CHECK(check_dev(vel, "vel", fn));
+    CHECK(check_dev(mass, "mass", fn));
+    CHECK(check_dev(out3, "out3", fn));
+    HIP_TRY(launch_energy(c, n, pos, vel, mass, to_pot(*pot), out3, (hipStream_t)stream));
+    return DNB_OK;
+}
+
+dnb_status dnb_orbit(dnb_ctx* c, const double* w0, const dnb_pot* pot, double dt, int64_t n_steps,
+                     double* w_out, double* traj, void* stream) {
+    const char* fn = "dnb_orbit";
+    CHECK(check_ctx(c, 1, fn));
+    CHECK(check_pot(pot, fn));
+    if (!is_fin(dt) || n_steps < 0) return fail(DNB_ERR_ARG, "%s: bad dt or n_steps", fn);
+    CHECK(check_dev(w0, "w0", fn));
+    CHECK(check_dev(w_out, "w_out", fn));
+    CHECK(check_dev(traj, "traj", fn, true));
+    HIP_TRY(launch_orbit(w0, to_pot(*pot), dt, n_steps, w_out, traj, (hipStream_t)stream));
+    return DNB_OK;
+}
+
+dnb_status dnb_orbit_vjp(dnb_ctx* c, const double* traj, const dnb_pot* pot, double dt,
+                         int64_t n_steps, const double* gw_out, double* gw0, double* gparams,
+                         void* stream) {
+    const char* fn = "dnb_orbit_vjp";
+    CHECK(check_ctx(c, 1, fn));
+    CHECK(check_pot(pot, fn));
+    if (!is_fin(dt) || dt == 0.0 || n_steps < 0)
+        return fail(DNB_ERR_ARG, "%s: bad dt or n_steps", fn);
+    CHECK(check_dev(traj, "traj", fn));
+    CHECK(check_dev(gw_out, "gw_out", fn));
+    CHECK(check_dev(gw0, "gw0", fn));
+    CHECK(check_dev(gparams, "gparams", fn));
+    HIP_TRY(launch_orbit_vjp(traj, to_pot(*pot), dt, n_steps, gw_out, gw0, gparams,
+                             (hipStream_t)stream));
+    return DNB_OK;
+}
+
+dnb_status dnb_place_plummer(dnb_ctx* c, int64_t n, const double* w, const double* xi,
+                             const double* zeta, double m_tot, double a_p, double G, double* pos,
+                             double* vel, double* mass, void* stream) {
+    const char* fn = "dnb_place_plummer";
+    CHECK(check_ctx(c, n, fn));
+    if (!(m_tot > 0) || !(a_p > 0) || !(G > 0) || !is_fin(m_tot) || !is_fin(a_p) || !is_fin(G))
+        return fail(DNB_ERR_ARG, "%s: m_tot, a_p and G must be finite and > 0", fn);
+    CHECK(check_dev(w, "w", fn));
+    CHECK(check_dev(xi, "xi", fn));
+    CHECK(check_dev(zeta, "zeta", fn));
+    CHECK(check_dev(pos, "pos", fn));
+    CHECK(check_dev(vel, "vel", fn));
+    CHECK(check_dev(mass, "mass", fn));
+    HIP_TRY(launch_place(n, w, xi, zeta, m_tot, a_p, G, pos, vel, mass, (hipStream_t)stream));
+    return DNB_OK;
+}
+
+dnb_status dnb_place_plummer_vjp(dnb_ctx* c, int64_t n, const double* zeta, double m_tot,
+                                 double a_p, double G, const double* gpos, const double* gvel,
+                                 const double* gmass, double* gw, double* gm_tot, void* stream) {
+    const char* fn = "dnb_place_plummer_vjp";
+    CHECK(check_ctx(c, n, fn));
+    if (!(m_tot > 0) || !(a_p > 0) || !(G > 0) || !is_fin(m_tot) || !is_fin(a_p) || !is_fin(G))
+        return fail(DNB_ERR_ARG, "%s: m_tot, a_p and G must be finite and > 0", fn);
+    CHECK(check_dev(zeta, "zeta", fn));
+    CHECK(check_dev(gpos, "gpos", fn));
+    CHECK(check_dev(gvel, "gvel", fn));
+    CHECK(check_dev(gmass, "gmass", fn, true));
+    CHECK(check_dev(gw, "gw", fn));
+    CHECK(check_dev(gm_tot, "gm_tot", fn));
+    HIP_TRY(launch_place_vjp(c, n, zeta, m_tot, a_p, G, gpos, gvel, gmass, gw, gm_tot,
+                             (hipStream_t)stream));
+    return DNB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,360 @@
+// Kernels around the integrator: the MMD loss and its gradient (Sec. 2.2.1 and
+// Fig. 2, step 4), energies, the test-particle orbit of the progenitor's centre of
+// mass and its adjoint (Fig. 2, step 2), and the Plummer-sphere placement with its
+// adjoint (Fig. 2, step 3).  All FP64.
+#include "dnb_internal.h"
+
+namespace dnb {
+
+// ---------------------------------------------------------------------- MMD --
+// For targets p_i and sources q_j of one slice:
+//   part[s][0][i] = sum_j k(p_i, q_j),  part[s][1..3][i] = sum_j k(p_i, q_j) (p_i - q_j)
+// with k(p, q) = exp(-|p - q|^2 / (2 h^2)).
+__global__ __launch_bounds__(BS) void k_mmd_rows(const double* __restrict__ P, int np,
+                                                 const double* __restrict__ Q, int nq,
+                                                 double inv2h2, int jslice, int with_grad,
+                                                 double* __restrict__ part, int64_t npad) {
+    __shared__ double4 tile[TILE];
+    const int i = blockIdx.x * BS + threadIdx.x;
+    const int j0 = blockIdx.y * jslice;
+    const int j1 = min(nq, j0 + jslice);
+    const int ii = min(i, np - 1);
+    const double px = P[ii], py = P[np + ii], pz = P[2 * np + ii];
+    double s0 = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int jt = j0; jt < j1; jt += TILE) {
+        const int j = jt + threadIdx.x;
+        tile[threadIdx.x] = (j < j1) ? make_double4(Q[j], Q[nq + j], Q[2 * nq + j], 1.0)
+                                     : make_double4(0.0, 0.0, 0.0, 0.0);
+        __syncthreads();
+        const int cnt = min(TILE, j1 - jt);
+        for (int k = 0; k < cnt; ++k) {
+            const double4 q = tile[k];
+            const double dx = px - q.x, dy = py - q.y, dz = pz - q.z;
+            const double e = exp(-(dx * dx + dy * dy + dz * dz) * inv2h2);
+            s0 += e;
+            gx = fma(e, dx, gx);
+            gy = fma(e, dy, gy);
+            gz = fma(e, dz, gz);
+        }
+        __syncthreads();
+    }
+    if (i < np) {
+        double* p = part + (int64_t)blockIdx.y * 4 * npad + i;
+        p[0] = s0;
+        if (with_grad) { p[npad] = gx; p[2 * npad] = gy; p[3 * npad] = gz; }
+    }
+}
+
+// Per-target slice sums -> gradient rows and per-block sums of the kernel sums.
+// red[b][0] = sum over the block of sum_j k(x_i, x_j); red[b][1] = of sum_a k(x_i, y_a).
+__global__ __launch_bounds__(BS) void k_mmd_x(const double* __restrict__ pxx, int Sxx,
+                                              const double* __restrict__ pxy, int Sxy,
+                                              int64_t npad, int n, int m, double h,
+                                              double* __restrict__ gpos, double* __restrict__ red) {
+    __shared__ double sh[2 * BS];
+    const int i = blockIdx.x * BS + threadIdx.x;
+    const bool ok = i < n;
+    double v[2] = {0.0, 0.0};
+    if (ok) {
+        double sx = 0.0, sy = 0.0, gx[3] = {0, 0, 0}, gy[3] = {0, 0, 0};
+        for (int s = 0; s < Sxx; ++s) {
+            const double* q = pxx + (int64_t)s * 4 * npad + i;
+            sx += q[0];
+            for (int c = 0; c < 3; ++c) gx[c] += q[(1 + c) * npad];
+        }
+        for (int s = 0; s < Sxy; ++s) {
+            const double* q = pxy + (int64_t)s * 4 * npad + i;
+            sy += q[0];
+            for (int c = 0; c < 3; ++c) gy[c] += q[(1 + c) * npad];
+        }
+        v[0] = sx; v[1] = sy;
+        if (gpos) {
+            const double cxx = -2.0 / ((double)n * n * h * h);
+            const double cxy = 2.0 / ((double)n * m * h * h);
+            for (int c = 0; c < 3; ++c) gpos[(int64_t)c * n + i] = cxx * gx[c] + cxy * gy[c];
+        }
+    }
+    block_sum<2>(v, sh);
+    if (threadIdx.x == 0) { red[8 * blockIdx.x + 0] = v[0]; red[8 * blockIdx.x + 1] = v[1]; }
+}
+
+__global__ __launch_bounds__(BS) void k_mmd_y(const double* __restrict__ pyy, int Syy,
+                                              int64_t npad, int m, double* __restrict__ red) {
+    __shared__ double sh[BS];
+    const int a = blockIdx.x * BS + threadIdx.x;
+    double v[1] = {0.0};
+    if (a < m)
+        for (int s = 0; s < Syy; ++s) v[0] += pyy[(int64_t)s * 4 * npad + a];
+    block_sum<1>(v, sh);
+    if (threadIdx.x == 0) red[8 * blockIdx.x + 2] = v[0];
+}
+
+__global__ __launch_bounds__(BS) void k_mmd_final(const double* __restrict__ red, int nbx, int nby,
+                                                  int n, int m, double* __restrict__ loss) {
+    __shared__ double sh[3 * BS];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nbx; b += BS) { v[0] += red[8 * b]; v[1] += red[8 * b + 1]; }
+    for (int b = threadIdx.x; b < nby; b += BS) v[2] += red[8 * b + 2];
+    block_sum<3>(v, sh);
+    if (threadIdx.x == 0)
+        loss[0] = v[0] / ((double)n * n) + v[2] / ((double)m * m) - 2.0 * v[1] / ((double)n * m);
+}
+
+hipError_t launch_mmd(dnb_ctx* c, int64_t n, const double* pos, int64_t m, const double* tgt,
+                      double h, double* loss, double* gpos, hipStream_t st) {
+    const double inv2h2 = 1.0 / (2.0 * h * h);
+    const int wg = gpos != nullptr;
+    double* pv = (double*)c->partv;   // [S][8][npad] doubles available
+    Slicing sx = slicing_for(n);      // targets x, sources x
+    Slicing sxy = slicing_for(n);     // targets x, sources y: slice length from m
+    {
+        int64_t want = sxy.S;
+        sxy.jslice = (int)(cdiv(cdiv(m, want), TILE) * TILE);
+        sxy.S = (int)cdiv(m, sxy.jslice);
+    }
+    Slicing sy = slicing_for(m);
+    double* pxx = pv;
+    double* pxy = pv + (int64_t)4 * sx.S * sx.npad;
+    double* pyy = (double*)c->part;
+    hipLaunchKernelGGL(k_mmd_rows, dim3(sx.nblk, sx.S), dim3(BS), 0, st, pos, (int)n, pos, (int)n,
+                       inv2h2, sx.jslice, wg, pxx, sx.npad);
+    hipLaunchKernelGGL(k_mmd_rows, dim3(sxy.nblk, sxy.S), dim3(BS), 0, st, pos, (int)n, tgt,
+                       (int)m, inv2h2, sxy.jslice, wg, pxy, sxy.npad);
+    hipLaunchKernelGGL(k_mmd_rows, dim3(sy.nblk, sy.S), dim3(BS), 0, st, tgt, (int)m, tgt, (int)m,
+                       inv2h2, sy.jslice, 0, pyy, sy.npad);
+    hipLaunchKernelGGL(k_mmd_x, dim3(sx.nblk), dim3(BS), 0, st, pxx, sx.S, pxy, sxy.S, sx.npad,
+                       (int)n, (int)m, h, gpos, c->red);
+    hipLaunchKernelGGL(k_mmd_y, dim3(sy.nblk), dim3(BS), 0, st, pyy, sy.S, sy.npad, (int)m,
+                       c->red);
+    hipLaunchKernelGGL(k_mmd_final, dim3(1), dim3(BS), 0, st, c->red, sx.nblk, sy.nblk, (int)n,
+                       (int)m, loss);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ energies --
+__device__ inline double ext_potential(const Pot& p, double x, double y, double z) {
+    double phi = 0.0;
+    if (p.m_nfw != 0.0) {
+        const double r = sqrt(x * x + y * y + z * z);
+        phi += (r == 0.0) ? -p.G * p.m_nfw / p.rs_nfw : -p.G * p.m_nfw * log1p(r / p.rs_nfw) / r;
+    }
+    if (p.m_mn != 0.0) {
+        const double S = sqrt(z * z + p.b_mn * p.b_mn);
+        const double A = p.a_mn + S;
+        phi += -p.G * p.m_mn / sqrt(x * x + y * y + A * A);
+    }
+    return phi;
+}
+
+// part[s][0][i] = sum_{j in slice, j != i} m_j (r_ij^2 + eps^2)^(-1/2)
+__global__ __launch_bounds__(BS) void k_energy_pairs(const double* __restrict__ x,
+                                                     const double* __restrict__ mass, int n,
+                                                     int jslice, double eps2,
+                                                     double* __restrict__ part, int64_t npad) {
+    __shared__ double4 tile[TILE];
+    const int i = blockIdx.x * BS + threadIdx.x;
+    const int j0 = blockIdx.y * jslice;
+    const int j1 = min(n, j0 + jslice);
+    const int ii = min(i, n - 1);
+    const double mx = x[ii], my = x[n + ii], mz = x[2 * n + ii];
+    double acc = 0.0;
+    for (int jt = j0; jt < j1; jt += TILE) {
+        const int j = jt + threadIdx.x;
+        tile[threadIdx.x] = (j < j1) ? make_double4(x[j], x[n + j], x[2 * n + j], mass[j])
+                                     : make_double4(0.0, 0.0, 0.0, 0.0);
+        __syncthreads();
+        const int cnt = min(TILE, j1 - jt);
+        for (int k = 0; k < cnt; ++k) {
+            if (jt + k == i) continue;
+            const double4 q = tile[k];
+            const double dx = q.x - mx, dy = q.y - my, dz = q.z - mz;
+            acc += q.w / sqrt(dx * dx + dy * dy + dz * dz + eps2);
+        }
+        __syncthreads();
+    }
+    if (i < n) part[(int64_t)blockIdx.y * npad + i] = acc;
+}
+
+__global__ __launch_bounds__(BS) void k_energy_rows(const double* __restrict__ x,
+                                                    const double* __restrict__ v,
+                                                    const double* __restrict__ mass, int n,
+                                                    Pot p, const double* __restrict__ part, int S,
+                                                    int64_t npad, double* __restrict__ red) {
+    __shared__ double sh[3 * BS];
+    const int i = blockIdx.x * BS + threadIdx.x;
+    double e[3] = {0.0, 0.0, 0.0};
+    if (i < n) {
+        const double m = mass[i];
+        double w = 0.0;
+        for (int s = 0; s < S; ++s) w += part[(int64_t)s * npad + i];
+        e[0] = 0.5 * m * (v[i] * v[i] + v[n + i] * v[n + i] + v[2 * n + i] * v[2 * n + i]);
+        e[1] = m * w;
+        e[2] = m * ext_potential(p, x[i], x[n + i], x[2 * n + i]);
+    }
+    block_sum<3>(e, sh);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) red[8 * blockIdx.x + c] = e[c];
+}
+
+__global__ __launch_bounds__(BS) void k_energy_final(const double* __restrict__ red, int nb,
+                                                     double G, double* __restrict__ out3) {
+    __shared__ double sh[3 * BS];
+    double e[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += BS)
+        for (int c = 0; c < 3; ++c) e[c] += red[8 * b + c];
+    block_sum<3>(e, sh);
+    if (threadIdx.x == 0) { out3[0] = e[0]; out3[1] = -0.5 * G * e[1]; out3[2] = e[2]; }
+}
+
+hipError_t launch_energy(dnb_ctx* c, int64_t n, const double* pos, const double* vel,
+                         const double* mass, const Pot& p, double* out3, hipStream_t st) {
+    Slicing sl = slicing_for(n);
+    double* part = (double*)c->partv;
+    hipLaunchKernelGGL(k_energy_pairs, dim3(sl.nblk, sl.S), dim3(BS), 0, st, pos, mass, (int)n,
+                       sl.jslice, p.eps * p.eps, part, sl.npad);
+    hipLaunchKernelGGL(k_energy_rows, dim3(sl.nblk), dim3(BS), 0, st, pos, vel, mass, (int)n, p,
+                       (const double*)part, sl.S, sl.npad, c->red);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(BS), 0, st, c->red, sl.nblk, p.G, out3);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------- test-particle orbit --
+// One lane integrates the single particle; the loop is sequential in time.
+__global__ void k_orbit(const double* __restrict__ w0, Pot p, double dt, int64_t n_steps,
+                        double* __restrict__ w_out, double* __restrict__ traj) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double x = w0[0], y = w0[1], z = w0[2], vx = w0[3], vy = w0[4], vz = w0[5];
+    const double hdt = 0.5 * dt;
+    Ext e = ext_accel(p, x, y, z);
+    if (traj) { traj[0] = x; traj[1] = y; traj[2] = z; }
+    for (int64_t s = 0; s < n_steps; ++s) {
+        const double hx = vx + hdt * e.ax, hy = vy + hdt * e.ay, hz = vz + hdt * e.az;
+        x = x + dt * hx; y = y + dt * hy; z = z + dt * hz;
+        e = ext_accel(p, x, y, z);
+        vx = hx + hdt * e.ax; vy = hy + hdt * e.ay; vz = hz + hdt * e.az;
+        if (traj) { traj[3 * (s + 1)] = x; traj[3 * (s + 1) + 1] = y; traj[3 * (s + 1) + 2] = z; }
+    }
+    w_out[0] = x; w_out[1] = y; w_out[2] = z; w_out[3] = vx; w_out[4] = vy; w_out[5] = vz;
+}
+
+// Reverse sweep of k_orbit with merged half kicks (see the N-body sweep).
+// gparams = (dL/dm_nfw, dL/dm_mn, dL/ddt).
+__global__ void k_orbit_vjp(const double* __restrict__ traj, Pot p, double dt, int64_t n_steps,
+                            const double* __restrict__ gw_out, double* __restrict__ gw0,
+                            double* __restrict__ gparams) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double lx = gw_out[0], ly = gw_out[1], lz = gw_out[2];
+    double wx = gw_out[3], wy = gw_out[4], wz = gw_out[5];
+    double g_nfw = 0.0, g_mn = 0.0, g_dt = 0.0;
+    const double inv = 1.0 / dt;
+    for (int64_t s = n_steps; s >= 0 && n_steps > 0; --s) {
+        const double coef = (s == n_steps || s == 0) ? 0.5 * dt : dt;
+        const double kc = (s == n_steps || s == 0) ? 0.5 : 1.0;
+        const double x = traj[3 * s], y = traj[3 * s + 1], z = traj[3 * s + 2];
+        Ext e = ext_accel(p, x, y, z);
+        double hx, hy, hz;
+        ext_hvp(p, x, y, z, wx, wy, wz, hx, hy, hz);
+        lx += coef * hx; ly += coef * hy; lz += coef * hz;
+        g_dt += kc * (e.ax * wx + e.ay * wy + e.az * wz);
+        g_nfw += coef * (e.nx * wx + e.ny * wy + e.nz * wz);
+        g_mn += coef * (e.mx * wx + e.my * wy + e.mz * wz);
+        if (s > 0) {
+            const double vx = (x - traj[3 * (s - 1)]) * inv;
+            const double vy = (y - traj[3 * (s - 1) + 1]) * inv;
+            const double vz = (z - traj[3 * (s - 1) + 2]) * inv;
+            g_dt += vx * lx + vy * ly + vz * lz;
+            wx += dt * lx; wy += dt * ly; wz += dt * lz;
+        }
+    }
+    gw0[0] = lx; gw0[1] = ly; gw0[2] = lz; gw0[3] = wx; gw0[4] = wy; gw0[5] = wz;
+    gparams[0] = g_nfw; gparams[1] = g_mn; gparams[2] = g_dt;
+}
+
+hipError_t launch_orbit(const double* w0, const Pot& p, double dt, int64_t n_steps, double* w_out,
+                        double* traj, hipStream_t st) {
+    hipLaunchKernelGGL(k_orbit, dim3(1), dim3(64), 0, st, w0, p, dt, n_steps, w_out, traj);
+    return hipGetLastError();
+}
+
+hipError_t launch_orbit_vjp(const double* traj, const Pot& p, double dt, int64_t n_steps,
+                            const double* gw_out, double* gw0, double* gparams, hipStream_t st) {
+    hipLaunchKernelGGL(k_orbit_vjp, dim3(1), dim3(64), 0, st, traj, p, dt, n_steps, gw_out, gw0,
+                       gparams);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------- Plummer placement --
+__global__ __launch_bounds__(BS) void k_place(int64_t n, const double* __restrict__ w,
+                                              const double* __restrict__ xi,
+                                              const double* __restrict__ zeta, double a_p,
+                                              double vscale, double mi, double* __restrict__ pos,
+                                              double* __restrict__ vel,
+                                              double* __restrict__ mass) {
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    for (int c = 0; c < 3; ++c) {
+        pos[c * n + i] = w[c] + a_p * xi[c * n + i];
+        vel[c * n + i] = w[3 + c] + vscale * zeta[c * n + i];
+    }
+    mass[i] = mi;
+}
+
+__global__ __launch_bounds__(BS) void k_place_vjp_rows(int64_t n, const double* __restrict__ zeta,
+                                                       const double* __restrict__ gpos,
+                                                       const double* __restrict__ gvel,
+                                                       const double* __restrict__ gmass,
+                                                       double* __restrict__ red) {
+    __shared__ double sh[8 * BS];
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < n) {
+        for (int c = 0; c < 3; ++c) {
+            v[c] = gpos[c * n + i];
+            v[3 + c] = gvel[c * n + i];
+            v[6] += gvel[c * n + i] * zeta[c * n + i];
+        }
+        v[7] = gmass ? gmass[i] : 0.0;
+    }
+    block_sum<8>(v, sh);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 8; ++c) red[8 * blockIdx.x + c] = v[c];
+}
+
+__global__ __launch_bounds__(BS) void k_place_vjp_final(const double* __restrict__ red, int nb,
+                                                        int64_t n, double dvs_dm,
+                                                        double* __restrict__ gw,
+                                                        double* __restrict__ gm_tot) {
+    __shared__ double sh[8 * BS];
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += BS)
+        for (int c = 0; c < 8; ++c) v[c] += red[8 * b + c];
+    block_sum<8>(v, sh);
+    if (threadIdx.x == 0) {
+        for (int c = 0; c < 6; ++c) gw[c] = v[c];
+        gm_tot[0] = v[6] * dvs_dm + v[7] / (double)n;
+    }
+}
+
+hipError_t launch_place(int64_t n, const double* w, const double* xi, const double* zeta,
+                        double m_tot, double a_p, double G, double* pos, double* vel,
+                        double* mass, hipStream_t st) {
+    const double vscale = sqrt(G * m_tot / a_p);
+    hipLaunchKernelGGL(k_place, dim3((unsigned)cdiv(n, BS)), dim3(BS), 0, st, n, w, xi, zeta, a_p,
+                       vscale, m_tot / (double)n, pos, vel, mass);
+    return hipGetLastError();
+}
+
+hipError_t launch_place_vjp(dnb_ctx* c, int64_t n, const double* zeta, double m_tot, double a_p,
+                            double G, const double* gpos, const double* gvel, const double* gmass,
+                            double* gw, double* gm_tot, hipStream_t st) {
+    const int nb = (int)cdiv(n, BS);
+    // d sqrt(G M / a_p) / dM = sqrt(G / (a_p M)) / 2
+    const double dvs_dm = 0.5 * sqrt(G / (a_p * m_tot));
+    hipLaunchKernelGGL(k_place_vjp_rows, dim3(nb), dim3(BS), 0, st, n, zeta, gpos, gvel, gmass,
+                       c->red);
+    hipLaunchKernelGGL(k_place_vjp_final, dim3(1), dim3(BS), 0, st, c->red, nb, n, dvs_dm, gw,
+                       gm_tot);
+    return hipGetLastError();
+}
+
+}  // namespace dnb

@@ -1,0 +1,281 @@
+// Internal declarations of libdnb: context layout, launch geometry and the FP64
+// device functions of the host-galaxy potential.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dnb.h"
+
+namespace dnb {
+
+// ---------------------------------------------------------------- geometry --
+constexpr int BS = 256;              // threads per block of every particle kernel
+constexpr int TILE = 256;            // sources staged in LDS per tile
+constexpr int SUBTILE = 128;         // sources summed in plain FP32 before a TwoSum
+constexpr int TARGET_BLOCKS = 2048;  // pair-kernel blocks wanted per launch (8 per CU)
+constexpr int S_MAX = 64;            // maximum number of source slices
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Source slicing of the O(N^2) kernels: the grid is (target blocks) x S, each
+// block sums one contiguous slice of sources.  Small N gets more slices so the
+// launch still fills the 256 compute units.
+struct Slicing {
+    int S;          // number of slices
+    int jslice;     // sources per slice (a multiple of TILE)
+    int nblk;       // target blocks
+    int64_t npad;   // row stride of the partial buffers (n rounded up to BS)
+};
+
+inline Slicing slicing_for(int64_t n) {
+    Slicing s;
+    s.nblk = (int)cdiv(n, BS);
+    s.npad = (int64_t)s.nblk * BS;
+    int64_t want = TARGET_BLOCKS / s.nblk;
+    int64_t max_by_tiles = cdiv(n, TILE);   // at least one tile per slice
+    if (want > max_by_tiles) want = max_by_tiles;
+    if (want > S_MAX) want = S_MAX;
+    if (want < 1) want = 1;
+    s.jslice = (int)(cdiv(cdiv(n, want), TILE) * TILE);
+    s.S = (int)cdiv(n, s.jslice);
+    return s;
+}
+
+// Upper bound of S * npad over all n <= max_n (sizes the partial buffers).
+// S never exceeds want = clamp(TARGET_BLOCKS / nblk, 1, S_MAX), so
+// S * npad <= want * nblk * BS <= max(S_MAX * BS * (TARGET_BLOCKS / S_MAX), npad).
+inline int64_t max_slice_rows(int64_t max_n) {
+    const int64_t nb = cdiv(max_n, BS);
+    const int64_t small = (int64_t)TARGET_BLOCKS * BS;
+    return nb * BS > small ? nb * BS : small;
+}
+
+// ------------------------------------------------------------- potential ---
+struct Pot {
+    double G, eps, m_nfw, rs_nfw, m_mn, a_mn, b_mn;
+};
+
+inline Pot to_pot(const dnb_pot& p) {
+    return Pot{p.G, p.eps, p.m_nfw, p.rs_nfw, p.m_mn, p.a_mn, p.b_mn};
+}
+
+// mu(x) = ln(1+x) - x/(1+x): NFW enclosed-mass profile in units of the scale mass.
+__device__ inline double nfw_mu(double x) {
+    if (x < 1e-4) return x * x * (0.5 + x * (-2.0 / 3.0 + x * (0.75 - x * 0.8)));
+    return log1p(x) - x / (1.0 + x);
+}
+
+// Acceleration of a unit-mass NFW halo (multiply by m_nfw): -G mu(r/rs) r_vec / r^3.
+__device__ inline void nfw_unit(double G, double rs, double x, double y, double z,
+                                double& ax, double& ay, double& az) {
+    double r2 = x * x + y * y + z * z;
+    if (r2 == 0.0) { ax = ay = az = 0.0; return; }
+    double r = sqrt(r2);
+    double g = G * nfw_mu(r / rs) / (r2 * r);
+    ax = -g * x; ay = -g * y; az = -g * z;
+}
+
+// Acceleration of a unit-mass Miyamoto-Nagai disk.
+__device__ inline void mn_unit(double G, double a, double b, double x, double y, double z,
+                               double& ax, double& ay, double& az) {
+    double S = sqrt(z * z + b * b);
+    double A = a + S;
+    double D2 = x * x + y * y + A * A;
+    double k = G / (D2 * sqrt(D2));
+    ax = -k * x; ay = -k * y;
+    az = (S == 0.0) ? 0.0 : -k * z * A / S;
+}
+
+// Hessian of -Phi_NFW (unit mass) applied to w:  -g w - (g'/r)(r.w) r_vec,
+// g = G mu / r^3, g' = G (1/(r^2 (r+rs)^2) - 3 mu / r^4).
+__device__ inline void nfw_unit_hvp(double G, double rs, double x, double y, double z,
+                                    double wx, double wy, double wz,
+                                    double& hx, double& hy, double& hz) {
+    double r2 = x * x + y * y + z * z;
+    if (r2 == 0.0) { hx = hy = hz = 0.0; return; }
+    double r = sqrt(r2);
+    double mu = nfw_mu(r / rs);
+    double g = G * mu / (r2 * r);
+    double rp = r + rs;
+    double gp = G * (1.0 / (r2 * rp * rp) - 3.0 * mu / (r2 * r2));
+    double c = gp / r * (x * wx + y * wy + z * wz);
+    hx = -g * wx - c * x; hy = -g * wy - c * y; hz = -g * wz - c * z;
+}
+
+// Hessian of -Phi_MN (unit mass) applied to w.  With S = sqrt(z^2+b^2),
+// A = a + S, D^2 = R^2 + A^2 the matrix entries are
+//   xx: -G (1/D^3 - 3x^2/D^5)    xy: 3G xy/D^5    xz: 3G x z A/(S D^5)
+//   yy: -G (1/D^3 - 3y^2/D^5)    yz: 3G y z A/(S D^5)
+//   zz: -G ((1 + a b^2/S^3)/D^3 - 3 z^2 A^2/(S^2 D^5)).
+__device__ inline void mn_unit_hvp(double G, double a, double b, double x, double y, double z,
+                                   double wx, double wy, double wz,
+                                   double& hx, double& hy, double& hz) {
+    double S = sqrt(z * z + b * b);
+    double A = a + S;
+    double D2 = x * x + y * y + A * A;
+    double D = sqrt(D2);
+    double iD3 = 1.0 / (D2 * D);
+    double iD5 = iD3 / D2;
+    double hxx = -G * (iD3 - 3.0 * x * x * iD5);
+    double hyy = -G * (iD3 - 3.0 * y * y * iD5);
+    double hxy = 3.0 * G * x * y * iD5;
+    double hxz = 0.0, hyz = 0.0, hzz = -G * iD3;
+    if (S != 0.0) {
+        double zA_S = z * A / S;
+        hxz = 3.0 * G * x * zA_S * iD5;
+        hyz = 3.0 * G * y * zA_S * iD5;
+        hzz = -G * ((1.0 + a * b * b / (S * S * S)) * iD3 - 3.0 * zA_S * zA_S * iD5);
+    }
+    hx = hxx * wx + hxy * wy + hxz * wz;
+    hy = hxy * wx + hyy * wy + hyz * wz;
+    hz = hxz * wx + hyz * wy + hzz * wz;
+}
+
+// Full external acceleration, and its two unit-mass parts (for the mass cotangents).
+struct Ext {
+    double ax, ay, az;        // total
+    double nx, ny, nz;        // NFW per unit m_nfw
+    double mx, my, mz;        // MN per unit m_mn
+};
+
+__device__ inline Ext ext_accel(const Pot& p, double x, double y, double z) {
+    Ext e{};
+    if (p.m_nfw != 0.0) nfw_unit(p.G, p.rs_nfw, x, y, z, e.nx, e.ny, e.nz);
+    if (p.m_mn != 0.0) mn_unit(p.G, p.a_mn, p.b_mn, x, y, z, e.mx, e.my, e.mz);
+    e.ax = p.m_nfw * e.nx + p.m_mn * e.mx;
+    e.ay = p.m_nfw * e.ny + p.m_mn * e.my;
+    e.az = p.m_nfw * e.nz + p.m_mn * e.mz;
+    return e;
+}
+
+__device__ inline void ext_hvp(const Pot& p, double x, double y, double z, double wx, double wy,
+                               double wz, double& hx, double& hy, double& hz) {
+    hx = hy = hz = 0.0;
+    double tx, ty, tz;
+    if (p.m_nfw != 0.0) {
+        nfw_unit_hvp(p.G, p.rs_nfw, x, y, z, wx, wy, wz, tx, ty, tz);
+        hx += p.m_nfw * tx; hy += p.m_nfw * ty; hz += p.m_nfw * tz;
+    }
+    if (p.m_mn != 0.0) {
+        mn_unit_hvp(p.G, p.a_mn, p.b_mn, x, y, z, wx, wy, wz, tx, ty, tz);
+        hx += p.m_mn * tx; hy += p.m_mn * ty; hz += p.m_mn * tz;
+    }
+}
+
+// Deterministic block sum of NV doubles per thread (fixed tree order).
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double* sh /* [NV][BS] */) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k * BS + t] = v[k];
+    __syncthreads();
+    for (int off = BS / 2; off > 0; off >>= 1) {
+        if (t < off) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) sh[k * BS + t] += sh[k * BS + t + off];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = sh[k * BS];
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ context --
+}  // namespace dnb
+
+struct dnb_ctx {
+    int device;
+    int64_t max_n;
+    dnb_prec prec;
+    int64_t slice_rows;      // capacity of S * npad
+    int nbmax;               // max blocks of the O(N) kernels
+    // forward path
+    float4* js;              // FP32C staged sources (x, y, z relative to a centre; m)
+    void* part;              // slice partials: FP32C float [S][6][npad], FP64 double [S][3][npad]
+    double* cpart;           // [2][nbmax][4] block sums of positions (centre), double buffered
+    double* vh;              // [3][max_n] half-step velocities of the running integration
+    // reverse path
+    float4* jsv;             // FP32C staged [2][max_n]: (x, y, z, m) then (w, 0)
+    void* partv;             // VJP partials: FP32C float [S][14][npad], FP64 double [S][7][npad]
+    double* cpartv;          // [2][nbmax][4]
+    double* red;             // [nbmax][8] reduction scratch
+};
+
+namespace dnb {
+
+// Kernel launchers (defined in the .hip files).  All return hipError_t of the launch.
+enum KdkMode { KDK_FIRST = 0, KDK_MID = 1, KDK_LAST = 2, KDK_ACC = 3 };
+
+struct FwdArgs {
+    int64_t n;
+    const double* mass;
+    Pot pot;
+    double dt;
+    // state
+    const double* x;    // [3][n] positions read (x_n) ...
+    double* x_out;      // ... and written (x_{n+1}); may equal x
+    double* v;          // [3][n] full-step velocity (FIRST reads, MID/LAST write)
+    double* vh;         // [3][n] half-step velocity
+    double* acc_out;    // KDK_ACC: [3][n] output accelerations
+    int with_ext;
+    // centre bookkeeping
+    const double* cpart_in;   // block sums of x (positions being kicked at)
+    double* cpart_out;        // block sums of x_out
+    int nb_in;                // number of blocks that wrote cpart_in
+    // checkpoint: write (x, v) of this step to tape_state, and the centre used
+    // for staging x_out to tape_centre_next (if non-null)
+    double* tape_state;
+    double* tape_centre_next;
+    const double* centre_override;   // if non-null: centre to stage x_out with
+};
+
+hipError_t launch_block_sums(const double* x, int64_t n, double* cpart, hipStream_t st);
+hipError_t launch_stage(const double* x, const double* mass, int64_t n, const double* cpart,
+                        int nb, const double* centre_override, float4* js, double* centre_out,
+                        hipStream_t st);
+hipError_t launch_pair_fwd(dnb_ctx* c, int64_t n, const double* x, const double* mass,
+                           double eps, hipStream_t st);
+hipError_t launch_kdk(dnb_ctx* c, KdkMode mode, const FwdArgs& a, hipStream_t st);
+
+struct RevArgs {
+    int64_t n;
+    const double* mass;
+    Pot pot;
+    double dt;
+    double coef;            // dt or dt/2 for this kick
+    const double* x_n;      // positions of the kick
+    const double* x_prev;   // positions x_{n-1} (null: no drift, last reverse step)
+    double* lx;             // [3][n] position cotangent (in/out)
+    double* lv;             // [3][n] velocity cotangent (in/out)
+    double* accum;          // [5][n] per-particle running sums: m_nfw, m_mn, dt, mass scale, mass
+    int with_mass;
+    const double* cpart_in; int nb_in; double* cpart_out;
+};
+
+hipError_t launch_rev_stage(dnb_ctx* c, int64_t n, const double* x, const double* mass,
+                            const double* w, const double* cpart, int nb, double* cpart_out,
+                            hipStream_t st);
+hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, const double* x, const double* mass,
+                           const double* w, int with_mass, double eps, hipStream_t st);
+hipError_t launch_rev_kick(dnb_ctx* c, const RevArgs& a, hipStream_t st);
+hipError_t launch_reduce_accum(const double* accum, int64_t n, int nterms, double* out,
+                               double* scratch, hipStream_t st);
+
+hipError_t launch_mmd(dnb_ctx* c, int64_t n, const double* pos, int64_t m, const double* tgt,
+                      double h, double* loss, double* gpos, hipStream_t st);
+hipError_t launch_energy(dnb_ctx* c, int64_t n, const double* pos, const double* vel,
+                         const double* mass, const Pot& p, double* out3, hipStream_t st);
+hipError_t launch_orbit(const double* w0, const Pot& p, double dt, int64_t n_steps, double* w_out,
+                        double* traj, hipStream_t st);
+hipError_t launch_orbit_vjp(const double* traj, const Pot& p, double dt, int64_t n_steps,
+                            const double* gw_out, double* gw0, double* gparams, hipStream_t st);
+hipError_t launch_place(int64_t n, const double* w, const double* xi, const double* zeta,
+                        double m_tot, double a_p, double G, double* pos, double* vel,
+                        double* mass, hipStream_t st);
+hipError_t launch_place_vjp(dnb_ctx* c, int64_t n, const double* zeta, double m_tot, double a_p,
+                            double G, const double* gpos, const double* gvel, const double* gmass,
+                            double* gw, double* gm_tot, hipStream_t st);
+
+}  // namespace dnb

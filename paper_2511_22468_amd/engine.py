@@ -1,0 +1,185 @@
+"""Python face of libdnb: one method per C entry point, same names and meaning.
+
+Particle arrays are torch float64 CUDA tensors of shape (3, n) (structure of
+arrays: row 0 holds x, row 1 y, row 2 z) or (n,); see include/dnb.h for the
+definition of every operation.  All calls are asynchronous on the current torch
+stream.
+"""
+from dataclasses import dataclass, replace as _dc_replace
+
+import torch
+
+from . import _lib
+from .units import G as G_DEFAULT
+
+
+@dataclass(frozen=True)
+class Potential:
+    """Softening and host potential (NFW halo + Miyamoto-Nagai disk)."""
+    G: float = G_DEFAULT
+    eps: float = 1.0e-3
+    m_nfw: float = 1.0e12
+    rs_nfw: float = 16.0
+    m_mn: float = 6.5e10
+    a_mn: float = 3.0
+    b_mn: float = 0.28
+
+    def replace(self, **kw):
+        return _dc_replace(self, **kw)
+
+    def c(self):
+        return _lib.dnb_pot(self.G, self.eps, self.m_nfw, self.rs_nfw, self.m_mn, self.a_mn,
+                            self.b_mn)
+
+
+def _vec(t, n, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous() and tuple(t.shape) == (3, n)):
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape (3, {n})")
+    return t
+
+
+def _arr(t, shape, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape {shape}")
+    return t
+
+
+class Context:
+    """Owns a dnb_ctx: device workspace for up to max_n particles."""
+
+    def __init__(self, max_n, prec="fp32c", device=None):
+        if prec not in _lib.PRECISIONS:
+            raise ValueError(f"prec must be one of {list(_lib.PRECISIONS)}")
+        self.prec = prec
+        self.max_n = int(max_n)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self._h = _lib.ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.lib().dnb_create(_lib.ctypes.byref(self._h), self.max_n,
+                                             _lib.PRECISIONS[prec]))
+
+    def close(self):
+        if self._h:
+            _lib.lib().dnb_destroy(self._h)
+            self._h = _lib.ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _new(self, *shape):
+        return torch.empty(*shape, dtype=torch.float64, device=self.device)
+
+    # ------------------------------------------------------------ forward --
+    def accelerations(self, pos, mass, pot, with_ext=True, out=None):
+        n = mass.shape[0]
+        _vec(pos, n, "pos"); _arr(mass, (n,), "mass")
+        acc = self._new(3, n) if out is None else _vec(out, n, "out")
+        _lib.check(_lib.lib().dnb_accelerations(self._h, n, _lib.ptr(pos), _lib.ptr(mass),
+                                                pot.c(), int(bool(with_ext)), _lib.ptr(acc),
+                                                _lib.stream_handle()))
+        return acc
+
+    def step(self, pos, vel, mass, pot, dt):
+        n = mass.shape[0]
+        _vec(pos, n, "pos"); _vec(vel, n, "vel"); _arr(mass, (n,), "mass")
+        _lib.check(_lib.lib().dnb_step(self._h, n, _lib.ptr(pos), _lib.ptr(vel), _lib.ptr(mass),
+                                       pot.c(), float(dt), _lib.stream_handle()))
+
+    def tape_len(self, n, n_steps, ckpt_every):
+        return int(_lib.lib().dnb_tape_doubles(n, n_steps, ckpt_every))
+
+    def simulate(self, pos, vel, mass, pot, dt, n_steps, ckpt_every=0, tape=None):
+        """In-place integration.  With ckpt_every > 0 a tape is written (and returned)."""
+        n = mass.shape[0]
+        _vec(pos, n, "pos"); _vec(vel, n, "vel"); _arr(mass, (n,), "mass")
+        K = int(ckpt_every)
+        if K > 0 and tape is None:
+            tape = self._new(max(1, self.tape_len(n, n_steps, K)))
+        _lib.check(_lib.lib().dnb_simulate(self._h, n, _lib.ptr(pos), _lib.ptr(vel),
+                                           _lib.ptr(mass), pot.c(), float(dt), int(n_steps),
+                                           max(K, 1), _lib.ptr(tape) if K > 0 else None,
+                                           _lib.stream_handle()))
+        return tape
+
+    def simulate_vjp(self, mass, pot, dt, n_steps, ckpt_every, tape, pos_T, gpos_T, gvel_T=None,
+                     with_mass=False, workspace=None):
+        """Returns (gpos_0, gvel_0, gmass or None, gparams[4]) with gparams =
+        (dL/dm_nfw, dL/dm_mn, dL/ddt, sum_k m_k dL/dm_k)."""
+        n = mass.shape[0]
+        _arr(mass, (n,), "mass"); _vec(pos_T, n, "pos_T"); _vec(gpos_T, n, "gpos_T")
+        if gvel_T is not None:
+            _vec(gvel_T, n, "gvel_T")
+        K = int(ckpt_every)
+        if workspace is None:
+            workspace = self._new(int(_lib.lib().dnb_vjp_workspace_doubles(n, K)))
+        gpos0, gvel0 = self._new(3, n), self._new(3, n)
+        gmass = self._new(n) if with_mass else None
+        gpar = self._new(4)
+        _lib.check(_lib.lib().dnb_simulate_vjp(
+            self._h, n, _lib.ptr(mass), pot.c(), float(dt), int(n_steps), K, _lib.ptr(tape),
+            _lib.ptr(pos_T), _lib.ptr(gpos_T), _lib.ptr(gvel_T), _lib.ptr(workspace),
+            _lib.ptr(gpos0), _lib.ptr(gvel0), _lib.ptr(gmass), _lib.ptr(gpar),
+            _lib.stream_handle()))
+        return gpos0, gvel0, gmass, gpar
+
+    # --------------------------------------------------------------- loss --
+    def mmd(self, pos, tgt, h, grad=True):
+        n, m = pos.shape[1], tgt.shape[1]
+        _vec(pos, n, "pos"); _vec(tgt, m, "tgt")
+        loss = self._new(1)
+        g = self._new(3, n) if grad else None
+        _lib.check(_lib.lib().dnb_mmd(self._h, n, _lib.ptr(pos), m, _lib.ptr(tgt), float(h),
+                                      _lib.ptr(loss), _lib.ptr(g), _lib.stream_handle()))
+        return loss, g
+
+    def energy(self, pos, vel, mass, pot):
+        n = mass.shape[0]
+        _vec(pos, n, "pos"); _vec(vel, n, "vel"); _arr(mass, (n,), "mass")
+        out = self._new(3)
+        _lib.check(_lib.lib().dnb_energy(self._h, n, _lib.ptr(pos), _lib.ptr(vel), _lib.ptr(mass),
+                                         pot.c(), _lib.ptr(out), _lib.stream_handle()))
+        return out
+
+    # -------------------------------------------------------- progenitor --
+    def orbit(self, w0, pot, dt, n_steps, keep=True):
+        _arr(w0, (6,), "w0")
+        w_out = self._new(6)
+        traj = self._new(n_steps + 1, 3) if keep else None
+        _lib.check(_lib.lib().dnb_orbit(self._h, _lib.ptr(w0), pot.c(), float(dt), int(n_steps),
+                                        _lib.ptr(w_out), _lib.ptr(traj), _lib.stream_handle()))
+        return w_out, traj
+
+    def orbit_vjp(self, traj, pot, dt, n_steps, gw_out):
+        _arr(traj, (n_steps + 1, 3), "traj"); _arr(gw_out, (6,), "gw_out")
+        gw0, gpar = self._new(6), self._new(3)
+        _lib.check(_lib.lib().dnb_orbit_vjp(self._h, _lib.ptr(traj), pot.c(), float(dt),
+                                            int(n_steps), _lib.ptr(gw_out), _lib.ptr(gw0),
+                                            _lib.ptr(gpar), _lib.stream_handle()))
+        return gw0, gpar
+
+    def place_plummer(self, w, xi, zeta, m_tot, a_p, G=G_DEFAULT):
+        n = xi.shape[1]
+        _arr(w, (6,), "w"); _vec(xi, n, "xi"); _vec(zeta, n, "zeta")
+        pos, vel, mass = self._new(3, n), self._new(3, n), self._new(n)
+        _lib.check(_lib.lib().dnb_place_plummer(self._h, n, _lib.ptr(w), _lib.ptr(xi),
+                                                _lib.ptr(zeta), float(m_tot), float(a_p), float(G),
+                                                _lib.ptr(pos), _lib.ptr(vel), _lib.ptr(mass),
+                                                _lib.stream_handle()))
+        return pos, vel, mass
+
+    def place_plummer_vjp(self, zeta, m_tot, a_p, gpos, gvel, gmass=None, G=G_DEFAULT):
+        n = zeta.shape[1]
+        _vec(zeta, n, "zeta"); _vec(gpos, n, "gpos"); _vec(gvel, n, "gvel")
+        if gmass is not None:
+            _arr(gmass, (n,), "gmass")
+        gw, gm = self._new(6), self._new(1)
+        _lib.check(_lib.lib().dnb_place_plummer_vjp(self._h, n, _lib.ptr(zeta), float(m_tot),
+                                                    float(a_p), float(G), _lib.ptr(gpos),
+                                                    _lib.ptr(gvel), _lib.ptr(gmass), _lib.ptr(gw),
+                                                    _lib.ptr(gm), _lib.stream_handle()))
+        return gw, gm

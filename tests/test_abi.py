@@ -1,0 +1,69 @@
+"""CPU-only checks of the C ABI: the library loads, exports every function that
+include/dnb.h declares, and validates arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dnb.h")
+LIB = os.path.join(ROOT, "paper_2511_22468_amd", "libdnb.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dnb_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libdnb.so is not built (run python -m paper_2511_22468_amd.build)")
+    from paper_2511_22468_amd import _lib
+    return _lib.load_library(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("dnb_create", "dnb_destroy", "dnb_accelerations", "dnb_step", "dnb_simulate",
+                 "dnb_simulate_vjp", "dnb_mmd", "dnb_energy", "dnb_orbit", "dnb_orbit_vjp",
+                 "dnb_place_plummer", "dnb_place_plummer_vjp", "dnb_last_error"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version_and_size_queries(lib):
+    assert b"gfx950" in lib.dnb_version()
+    assert lib.dnb_tape_doubles(10, 7, 3) == 3 * (60 + 4)
+    assert lib.dnb_tape_doubles(10, 0, 3) == 0
+    assert lib.dnb_tape_doubles(10, 7, 0) == -1
+    assert lib.dnb_vjp_workspace_doubles(10, 4) == 3 * 10 * 5 + 160
+    assert lib.dnb_vjp_workspace_doubles(0, 4) == -1
+
+
+def test_arguments_rejected_before_any_device_work(lib):
+    from paper_2511_22468_amd import _lib
+    h = ctypes.c_void_p()
+    assert lib.dnb_create(None, 10, 0) == _lib.DNB_ERR_ARG
+    assert lib.dnb_create(ctypes.byref(h), 0, 0) == _lib.DNB_ERR_ARG
+    assert b"max_n" in lib.dnb_last_error()
+    assert lib.dnb_create(ctypes.byref(h), 1 << 27, 0) == _lib.DNB_ERR_ARG
+    assert lib.dnb_create(ctypes.byref(h), 10, 7) == _lib.DNB_ERR_ARG
+    pot = _lib.dnb_pot(4.3e-6, 1e-3, 1e12, 16.0, 6.5e10, 3.0, 0.28)
+    assert lib.dnb_accelerations(None, 10, None, None, ctypes.byref(pot), 1, None, None) == _lib.DNB_ERR_ARG
+    assert b"ctx is NULL" in lib.dnb_last_error()
+    assert lib.dnb_simulate(None, 10, None, None, None, ctypes.byref(pot), 0.1, 5, 1, None, None) == _lib.DNB_ERR_ARG
+    assert lib.dnb_mmd(None, 1, None, 1, None, 0.2, None, None, None) == _lib.DNB_ERR_ARG
+    lib.dnb_destroy(None)
+
+
+def test_binding_refuses_to_run_without_the_library(tmp_path):
+    from paper_2511_22468_amd import _lib
+    with pytest.raises(ImportError):
+        _lib.load_library(str(tmp_path / "missing.so"))

@@ -1,0 +1,231 @@
+"""GPU-vs-oracle parity of every C-ABI entry point (run on an MI355X).
+
+Tolerances: accelerations <= 1e-5 relative per particle in FP32C (the
+spec bound) and <= 1e-12 in FP64; short-horizon positions and gradients
+as stated per test.  Sizes span several 256-particle tiles, several source
+slices and a ragged tail.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as oadj, forces as of, integrate as oint, mmd as ommd
+from oracle.forces import Potential as OPot
+from synth import plummer_unit, sample_rows
+
+from gpu_util import rel_norm, rel_rows, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+G = 4.3009e-6
+W_X = np.array([12.0, 0.0, 0.0])
+W_V = np.array([0.0, -180.0, 60.0])
+
+
+@pytest.fixture(scope="module")
+def dnb():
+    import paper_2511_22468_amd as pk
+    from paper_2511_22468_amd import engine
+    ctx = {p: engine.Context(20000, p) for p in ("fp64", "fp32c")}
+    yield pk, engine, ctx
+    for c in ctx.values():
+        c.close()
+
+
+def plummer_state(n, seed, m_tot=2e4, a_p=0.01):
+    xi, zeta = plummer_unit(n, seed)
+    x = W_X + a_p * xi
+    v = W_V + np.sqrt(G * m_tot / a_p) * zeta
+    return x, v, np.full(n, m_tot / n)
+
+
+def gpu_pot(engine, op):
+    return engine.Potential(G=op.G, eps=op.eps, m_nfw=op.m_nfw, rs_nfw=op.rs_nfw, m_mn=op.m_mn,
+                            a_mn=op.a_mn, b_mn=op.b_mn)
+
+
+def internal_scale(x, m, eps, rows=None):
+    """G sum_j m_j |d_ij| s^-3/2: the magnitude scale of the pair sum."""
+    idx = np.arange(x.shape[0]) if rows is None else rows
+    d = x[None, :, :] - x[idx, None, :]
+    r2 = (d ** 2).sum(-1)
+    s = np.where(r2 > 0, r2 + eps * eps, 1.0)
+    return G * np.where(r2 > 0, m[None, :] * np.sqrt(r2) * s ** -1.5, 0.0).sum(1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 255, 1000, 1300])
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_accelerations_match_oracle(dnb, n, prec):
+    pk, engine, ctx = dnb
+    say(f"[accel] n={n} prec={prec}")
+    rng = np.random.default_rng(n)
+    x = W_X + rng.normal(scale=0.02, size=(n, 3))
+    m = rng.uniform(1.0, 5.0, n)
+    op = OPot()
+    ref = of.accel(x, m, op)
+    got = to_host(ctx[prec].accelerations(to_dev(x), to_dev(m), gpu_pot(engine, op)))
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert rel_rows(got, ref).max() <= tol
+    # internal part alone, against its own magnitude scale
+    ref_i = of.pair_accel(x, m, G, op.eps)
+    got_i = to_host(ctx[prec].accelerations(to_dev(x), to_dev(m), gpu_pot(engine, op), with_ext=False))
+    err = np.sqrt(((got_i - ref_i) ** 2).sum(1)) / np.maximum(internal_scale(x, m, op.eps), 1e-300)
+    assert err.max() <= (1e-13 if prec == "fp64" else 1e-5), err.max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_zero_softening_masks_self_term(dnb, prec):
+    pk, engine, ctx = dnb
+    rng = np.random.default_rng(3)
+    x = W_X + rng.normal(scale=0.05, size=(300, 3))
+    m = rng.uniform(1.0, 2.0, 300)
+    op = OPot(eps=0.0)
+    ref = of.pair_accel(x, m, G, 0.0)
+    got = to_host(ctx[prec].accelerations(to_dev(x), to_dev(m), gpu_pot(engine, op), with_ext=False))
+    assert np.all(np.isfinite(got))
+    err = np.sqrt(((got - ref) ** 2).sum(1)) / internal_scale(x, m, 0.0)
+    assert err.max() <= (1e-13 if prec == "fp64" else 1e-5)
+
+
+def test_accelerations_plummer_16384_sampled(dnb):
+    pk, engine, ctx = dnb
+    say("[accel] plummer n=16384 fp32c, 256 sampled rows")
+    x, v, m = plummer_state(16384, 2, m_tot=5e4)
+    op = OPot()
+    rows = sample_rows(16384, 256, 20)
+    ref = of.pair_accel(x, m, G, op.eps, rows=rows) + of.ext_accel(x[rows], op)
+    for prec in ("fp32c", "fp64"):
+        got = to_host(ctx[prec].accelerations(to_dev(x), to_dev(m), gpu_pot(engine, op)))[rows]
+        assert rel_rows(got, ref).max() <= (1e-5 if prec == "fp32c" else 1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_simulate_short_horizon(dnb, prec):
+    pk, engine, ctx = dnb
+    say(f"[simulate] n=300 40 steps prec={prec}")
+    x, v, m = plummer_state(300, 5)
+    op = OPot()
+    dt = pk.myr(0.5)
+    xr, vr = oint.simulate(x, v, m, op, dt, 40)
+    px, pv = to_dev(x), to_dev(v)
+    ctx[prec].simulate(px, pv, to_dev(m), gpu_pot(engine, op), dt, 40)
+    gx, gv = to_host(px), to_host(pv)
+    tol = 1e-11 if prec == "fp64" else 1e-7
+    assert rel_rows(gx, xr).max() <= tol
+    assert rel_rows(gv, vr).max() <= tol * 100
+    # dnb_step == one step of simulate
+    px2, pv2 = to_dev(x), to_dev(v)
+    ctx[prec].step(px2, pv2, to_dev(m), gpu_pot(engine, op), dt)
+    x1, v1 = oint.simulate(x, v, m, op, dt, 1)
+    assert rel_rows(to_host(px2), x1).max() <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("K", [1, 4])
+def test_adjoint_matches_oracle(dnb, prec, K):
+    pk, engine, ctx = dnb
+    say(f"[vjp] n=40 T=10 K={K} prec={prec}")
+    x, v, m = plummer_state(40, 7)
+    rng = np.random.default_rng(8)
+    wx, wv = rng.normal(size=x.shape), rng.normal(size=x.shape)
+    op = OPot()
+    dt, T = pk.myr(1.0), 10
+    xT, vT, traj = oint.simulate(x, v, m, op, dt, T, keep=True)
+    ref = oadj.simulate_vjp(traj, m, op, dt, wx, wv)
+    c = ctx[prec]
+    px, pv, pm = to_dev(x), to_dev(v), to_dev(m)
+    pot = gpu_pot(engine, op)
+    tape = c.simulate(px, pv, pm, pot, dt, T, ckpt_every=K)
+    gx0, gv0, gm, gp = c.simulate_vjp(pm, pot, dt, T, K, tape, px, to_dev(wx), to_dev(wv),
+                                      with_mass=True)
+    gp = gp.cpu().numpy()
+    tol = 1e-10 if prec == "fp64" else 1e-3
+    assert rel_norm(to_host(gx0), ref["x0"]) <= tol
+    assert rel_norm(to_host(gv0), ref["v0"]) <= tol
+    assert rel_norm(to_host(gm), ref["mass"]) <= tol
+    assert abs(gp[0] / ref["m_nfw"] - 1) <= tol
+    assert abs(gp[1] / ref["m_mn"] - 1) <= tol
+    assert abs(gp[2] / ref["dt"] - 1) <= tol
+    assert abs(gp[3] / np.sum(m * ref["mass"]) - 1) <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_checkpoint_recompute_is_bitwise(dnb, prec):
+    pk, engine, ctx = dnb
+    say(f"[vjp] recompute bitwise n=600 T=13 prec={prec}")
+    x, v, m = plummer_state(600, 9)
+    rng = np.random.default_rng(10)
+    wx = to_dev(rng.normal(size=x.shape))
+    op = OPot()
+    pot = gpu_pot(engine, op)
+    c = ctx[prec]
+    outs = []
+    for K in (1, 4, 13):
+        px, pv, pm = to_dev(x), to_dev(v), to_dev(m)
+        tape = c.simulate(px, pv, pm, pot, pk.myr(0.5), 13, ckpt_every=K)
+        r = c.simulate_vjp(pm, pot, pk.myr(0.5), 13, K, tape, px, wx)
+        outs.append((px.clone(), r[0], r[1], r[3]))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert torch.equal(a, b)
+
+
+def test_mmd_matches_oracle(dnb):
+    pk, engine, ctx = dnb
+    rng = np.random.default_rng(11)
+    X = W_X + rng.normal(scale=0.3, size=(700, 3))
+    Y = W_X + 0.1 + rng.normal(scale=0.25, size=(300, 3))
+    for prec in ("fp64", "fp32c"):
+        loss, g = ctx[prec].mmd(to_dev(X), to_dev(Y), 0.2)
+        assert abs(loss.item() / ommd.mmd2(X, Y, 0.2) - 1) <= 1e-12
+        assert rel_norm(to_host(g), ommd.mmd2_grad(X, Y, 0.2)) <= 1e-12
+    loss, _ = ctx["fp64"].mmd(to_dev(X), to_dev(X), 0.2, grad=False)
+    assert abs(loss.item()) <= 1e-14
+
+
+def test_energy_matches_oracle(dnb):
+    pk, engine, ctx = dnb
+    x, v, m = plummer_state(777, 12)
+    op = OPot()
+    K, W, X = of.energies(x, v, m, op)
+    e = ctx["fp64"].energy(to_dev(x), to_dev(v), to_dev(m), gpu_pot(engine, op)).cpu().numpy()
+    np.testing.assert_allclose(e, [K, W, X], rtol=1e-12)
+
+
+def test_orbit_and_its_adjoint_match_oracle(dnb):
+    pk, engine, ctx = dnb
+    op = OPot(m_nfw=1.1e12, m_mn=6.0e10)
+    pot = gpu_pot(engine, op)
+    dt, T = -pk.myr(1.0), 300
+    w0 = np.concatenate([W_X, W_V])
+    xr, vr, traj = oint.simulate(W_X[None], W_V[None], np.zeros(1), op, dt, T, self_gravity=False,
+                                 keep=True)
+    wo, tr = ctx["fp64"].orbit(torch.tensor(w0, device="cuda"), pot, dt, T)
+    wo = wo.cpu().numpy()
+    np.testing.assert_allclose(wo[:3], xr[0], rtol=1e-12)
+    np.testing.assert_allclose(wo[3:], vr[0], rtol=1e-12)
+    gw = np.random.default_rng(13).normal(size=6)
+    ref = oadj.simulate_vjp(traj, np.zeros(1), op, dt, gw[None, :3], gw[None, 3:], self_gravity=False)
+    g0, gp = ctx["fp64"].orbit_vjp(tr, pot, dt, T, torch.tensor(gw, device="cuda"))
+    g0, gp = g0.cpu().numpy(), gp.cpu().numpy()
+    np.testing.assert_allclose(g0[:3], ref["x0"][0], rtol=1e-9)
+    np.testing.assert_allclose(g0[3:], ref["v0"][0], rtol=1e-9)
+    np.testing.assert_allclose(gp, [ref["m_nfw"], ref["m_mn"], ref["dt"]], rtol=1e-9)
+
+
+def test_place_plummer_and_adjoint(dnb):
+    pk, engine, ctx = dnb
+    n = 513
+    xi, zeta = plummer_unit(n, 14)
+    w = np.array([1.0, 2.0, 3.0, 4.0, 5.0, 6.0])
+    c = ctx["fp64"]
+    pos, vel, mass = c.place_plummer(torch.tensor(w, device="cuda"), to_dev(xi), to_dev(zeta), 3e4, 0.01)
+    np.testing.assert_allclose(to_host(pos), w[:3] + 0.01 * xi, rtol=1e-15)
+    np.testing.assert_allclose(to_host(vel), w[3:] + np.sqrt(G * 3e4 / 0.01) * zeta, rtol=1e-14)
+    np.testing.assert_allclose(mass.cpu().numpy(), 3e4 / n, rtol=1e-15)
+    rng = np.random.default_rng(15)
+    gp, gv, gm = rng.normal(size=(n, 3)), rng.normal(size=(n, 3)), rng.normal(size=n)
+    gw, gM = c.place_plummer_vjp(to_dev(zeta), 3e4, 0.01, to_dev(gp), to_dev(gv), to_dev(gm))
+    np.testing.assert_allclose(gw.cpu().numpy(), np.concatenate([gp.sum(0), gv.sum(0)]), rtol=1e-12)
+    expect = np.sum(gv * zeta) * 0.5 * np.sqrt(G / (0.01 * 3e4)) + gm.sum() / n
+    np.testing.assert_allclose(gM.item(), expect, rtol=1e-12)
