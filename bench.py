@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark of the differentiable direct N-body hot path on one MI355X.
+
+One step is one full pass of the method at the large-N workload: back-integrate
+the progenitor's centre of mass for t_end in the NFW + Miyamoto-Nagai host,
+place an N = 65536 Plummer sphere (1e5 Msun, scale 0.01 kpc) there, run 1000
+kick-drift-kick steps of 0.5 Myr with softening 5e-4 kpc (FP32 compensated pair
+terms, FP64 drift) while recording the tape, evaluate the MMD against a
+4096-point target stream, and run the full reverse sweep back to the four
+parameters (t_end, M_Plummer, M_NFW, M_MN).
+
+value = (forward pair interactions + adjoint pair interactions) / step time,
+with (T + 1) N^2 pairs each per step.  The roofline object reports the
+dominant kernel (the pair VJP) and its forward sibling, timed with HIP events
+around every launch inside the timed region; cpu_baseline times the FP64 NumPy
+oracle on a bounded subsample of the same pair work on the host's cores.
+
+Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pair interactions/s fwd & adjoint at N=65536; time-to-fit vs plain N-body"
+PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak
+FLOPS_FWD = 20                    # per pair interaction, conventional count
+FLOPS_VJP = 41                    # per pair of the vector-Jacobian product
+
+
+def cpu_baseline(n, t_end_steps, seed, budget_s=15.0):
+    """Time the oracle's pair sum and pair VJP on sampled target rows."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from threadpoolctl import threadpool_limits
+
+    from oracle import adjoint as oadj, forces as of
+    from synth import plummer_unit, random_directions, sample_rows
+
+    G = 4.3009e-6
+    xi, _ = plummer_unit(n, seed)
+    x = np.array([12.0, 0.0, 0.0]) + 0.01 * xi
+    m = np.full(n, 1e5 / n)
+    w = random_directions(n, seed + 1)
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    rows_f = sample_rows(n, 2048, seed + 2)
+    rows_v = sample_rows(n, 512, seed + 3)
+
+    def run(fn, rows):
+        chunks = np.array_split(rows, cores * 2)
+        with threadpool_limits(1), ThreadPoolExecutor(cores) as ex:
+            t0 = time.perf_counter()
+            list(ex.map(fn, chunks))
+            return time.perf_counter() - t0
+
+    tf = run(lambda r: of.pair_accel(x, m, G, 5e-4, rows=r), rows_f)
+    tv = run(lambda r: oadj.pair_vjp(x, m, G, 5e-4, w, rows=r), rows_v)
+    pairs = (rows_f.size + rows_v.size) * n
+    # rate for the same fwd:adjoint mix as the GPU step (one forward and one VJP per pair)
+    rate = 2.0 / (tf / (rows_f.size * n) + tv / (rows_v.size * n))
+    return {
+        "value": rate, "unit": "pair interactions/s", "cores": cores, "kind": "oracle",
+        "sample": (f"FP64 NumPy oracle on the N={n} initial Plummer state: pair sum for "
+                   f"{rows_f.size} sampled targets x {n} sources ({tf:.2f} s) and pair VJP for "
+                   f"{rows_v.size} targets x {n} sources ({tv:.2f} s), {pairs:.3g} pairs in "
+                   f"{cores} threads; rate is the harmonic mix of one forward and one adjoint "
+                   f"pair per interaction pair"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--n-steps", type=int, default=1000)
+    ap.add_argument("--ckpt-every", type=int, default=1)
+    ap.add_argument("--prec", default="fp32c", choices=["fp32c", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2511_22468_amd import engine, myr
+    from paper_2511_22468_amd.pipeline import StreamModel, make_target
+    from synth import plummer_unit
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n, T, K = args.n, args.n_steps, args.ckpt_every
+    dt = myr(0.5)
+    theta = torch.tensor([T * dt, 1.0e5, 1.0e12, 6.5e10], dtype=torch.float64, device=dev)
+    pot = engine.Potential(eps=5e-4)
+
+    def unit(nn, seed):
+        xi, zeta = plummer_unit(nn, seed)
+        return (torch.tensor(np.ascontiguousarray(xi.T), device=dev),
+                torch.tensor(np.ascontiguousarray(zeta.T), device=dev))
+
+    ctx = engine.Context(n, args.prec)
+    # mock observed stream: a 4096-particle run of the same pipeline, own seed,
+    # at slightly different parameters
+    xt, zt = unit(4096, 41)
+    theta_t = theta * torch.tensor([1.0, 0.8, 1.05, 0.95], dtype=torch.float64, device=dev)
+    target = make_target(ctx, xt, zt, theta_t, T, pot=pot)
+    xi, zeta = unit(n, 40)
+    model = StreamModel(ctx, xi, zeta, target, T, pot=pot, h=0.2, ckpt_every=K)
+
+    for _ in range(args.warmup):
+        model.loss_and_grad(theta)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        L, g = model.loss_and_grad(theta)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+
+    sec = (t1 - t0) / args.steps
+    pairs = 2.0 * (T + 1) * float(n) * n
+    fwd_ms = prof["fwd_ms"] / max(prof["fwd_launches"], 1)
+    vjp_ms = prof["vjp_ms"] / max(prof["vjp_launches"], 1)
+    vjp_tf = FLOPS_VJP * float(n) * n / (vjp_ms * 1e-3) / 1e12
+    fwd_tf = FLOPS_FWD * float(n) * n / (fwd_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": pairs / sec,
+        "unit": "pair interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.prec == "fp32c" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"stream pipeline at N={n}: back-integrated centre, Plummer sphere "
+                         f"1e5 Msun / 0.01 kpc, eps 5e-4 kpc, {T} KDK steps of 0.5 Myr, "
+                         f"MMD (h=0.2 kpc) vs 4096-point target, full reverse sweep to "
+                         f"(t_end, M_Plummer, M_NFW, M_MN)"),
+            "n": n, "n_steps": T, "dt_myr": 0.5, "eps_kpc": 5e-4, "ckpt_every": K,
+            "pair_precision": ("FP32 pair terms, TwoSum-compensated, FP64 drift and reductions"
+                               if args.prec == "fp32c" else "FP64"),
+            "pairs_per_step": pairs,
+            "loss": float(L.item()),
+            "grad": [float(v) for v in g.cpu().numpy()],
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_pair_vjp_f32c" if args.prec == "fp32c" else "k_pair_vjp_f64",
+            "achieved": vjp_tf,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": vjp_tf / PEAK_FP32_TFLOPS,
+            "traffic": None,
+            "flops_per_pair": FLOPS_VJP,
+            "avg_launch_ms": vjp_ms,
+            "launches": prof["vjp_launches"],
+        },
+        "roofline_fwd": {
+            "bound": "alu",
+            "kernel": "k_pair_fwd_f32c" if args.prec == "fp32c" else "k_pair_fwd_f64",
+            "achieved": fwd_tf,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": fwd_tf / PEAK_FP32_TFLOPS,
+            "flops_per_pair": FLOPS_FWD,
+            "avg_launch_ms": fwd_ms,
+            "launches": prof["fwd_launches"],
+            "pairs_per_s": float(n) * n / (fwd_ms * 1e-3),
+        },
+        "cpu_baseline": None,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, T, 40)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -179,6 +179,16 @@ dnb_status dnb_place_plummer_vjp(dnb_ctx* ctx, int64_t n, const double* zeta, do
                                  double a_p, double G, const double* gpos, const double* gvel,
                                  const double* gmass, double* gw, double* gm_tot, void* stream);
 
+/* Instrumentation (not part of the method).  With enable != 0, every launch of
+ * the two O(N^2) kernels (forward pair sum, pair VJP) issued through this
+ * context is bracketed by HIP events recorded on the launch's stream.
+ * dnb_profile_read synchronises those events and returns, in the HOST array
+ * out4: total milliseconds and launch count of the forward pair kernel, then the
+ * same for the VJP kernel, since the last read; it then resets the totals.
+ * Event objects are created on demand and kept by the context. */
+dnb_status dnb_profile(dnb_ctx* ctx, int enable);
+dnb_status dnb_profile_read(dnb_ctx* ctx, double* out4);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,15 +24,16 @@ import numpy as np
 from . import forces
 
 
-def pair_vjp(pos, mass, G, eps, w, block=256):
+def pair_vjp(pos, mass, G, eps, w, rows=None, block=256):
+    """(J^T w)_k for all k, or for the index array `rows` only."""
     pos = np.asarray(pos)
     w = np.asarray(w)
     mass = np.asarray(mass)
-    n = pos.shape[0]
-    out = np.zeros(pos.shape, dtype=np.result_type(pos, w, mass, float))
+    idx = np.arange(pos.shape[0]) if rows is None else np.asarray(rows)
+    out = np.zeros((idx.shape[0], 3), dtype=np.result_type(pos, w, mass, float))
     eps2 = eps * eps
-    for b0 in range(0, n, block):
-        kk = np.arange(b0, min(n, b0 + block))
+    for b0 in range(0, idx.shape[0], block):
+        kk = idx[b0:b0 + block]
         d = pos[None, :, :] - pos[kk, None, :]                 # x_j - x_k
         s = d[..., 0] ** 2 + d[..., 1] ** 2 + d[..., 2] ** 2 + eps2
         if eps2 == 0:

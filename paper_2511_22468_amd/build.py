@@ -19,6 +19,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit contraction: every FMA is written out, so template
+    # instantiations round identically and TwoSum stays error-free
+    "-ffp-contract=off",
     "-Wno-unused-result",
 ]
 

@@ -3,9 +3,12 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "dnb_internal.h"
 
@@ -35,6 +38,15 @@ dnb_status fail(dnb_status s, const char* fmt, ...) {
 constexpr int64_t MAX_N = int64_t(1) << 26;
 
 bool is_fin(double v) { return std::isfinite(v); }
+
+int env_int(const char* name, int dflt, std::initializer_list<int> allowed) {
+    const char* s = std::getenv(name);
+    if (!s || !*s) return dflt;
+    const int v = std::atoi(s);
+    for (int a : allowed)
+        if (a == v) return v;
+    return dflt;
+}
 
 dnb_status check_ctx(dnb_ctx* c, int64_t n, const char* fn) {
     if (!c) return fail(DNB_ERR_ARG, "%s: ctx is NULL", fn);
@@ -78,6 +90,39 @@ dnb_status check_dev(const void* p, const char* name, const char* fn, bool nulla
     return DNB_OK;
 }
 
+// Event pool of dnb_profile: one (start, stop) pair per profiled launch.
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> pool;           // reusable events
+    std::vector<hipEvent_t> ev[2];          // recorded pairs: [0] forward, [1] VJP
+    hipEvent_t get() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+
+// Launch one O(N^2) kernel (kind 0: forward pair sum, 1: VJP), bracketed by
+// events when profiling is on.
+template <class F>
+hipError_t profiled(dnb_ctx* c, int kind, hipStream_t st, F launch) {
+    Prof* pf = (Prof*)c->prof;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (pf && pf->on) {
+        e0 = pf->get();
+        e1 = pf->get();
+        if (e0 && e1) (void)hipEventRecord(e0, st);
+    }
+    hipError_t err = launch();
+    if (e0 && e1) {
+        (void)hipEventRecord(e1, st);
+        pf->ev[kind].push_back(e0);
+        pf->ev[kind].push_back(e1);
+    }
+    return err;
+}
+
 #define CHECK(x)                          \
     do {                                  \
         dnb_status s_ = (x);              \
@@ -99,14 +144,11 @@ dnb_status run_forward(dnb_ctx* c, int64_t n, double* pos, double* vel, const do
     if (T == 0) return DNB_OK;
     const int nb = (int)cdiv(n, BS);
     double* cp[2] = {c->cpart, c->cpart + 4 * c->nbmax};
-    if (c->prec == DNB_FP32C) {
-        HIP_TRY(launch_block_sums(pos, n, cp[0], st));
-        HIP_TRY(launch_stage(pos, mass, n, cp[0], nb, nullptr, c->js,
-                             tape ? tape->centre(0) : nullptr, st));
-    }
+    if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(pos, n, cp[0], st));
+    HIP_TRY(launch_stage(c, pos, mass, n, cp[0], nb, nullptr, tape ? tape->centre(0) : nullptr, st));
     int q = 0;
     for (int64_t s = 0; s <= T; ++s) {
-        HIP_TRY(launch_pair_fwd(c, n, pos, mass, p.eps, st));
+        HIP_TRY(profiled(c, 0, st, [&] { return launch_pair_fwd(c, n, p.eps, st); }));
         FwdArgs a{};
         a.n = n; a.mass = mass; a.pot = p; a.dt = dt;
         a.x = pos; a.x_out = pos; a.v = vel; a.vh = c->vh; a.with_ext = 1;
@@ -143,15 +185,18 @@ dnb_status dnb_create(dnb_ctx** out, int64_t max_n, dnb_prec prec) {
         delete c;
         return fail(DNB_ERR_HIP, "dnb_create: no HIP device");
     }
-    c->slice_rows = max_slice_rows(max_n);
+    // Blocks per pair-kernel launch; DNB_TARGET_BLOCKS overrides the tuned
+    // default for experiments.
+    c->target_blocks = env_int("DNB_TARGET_BLOCKS", TARGET_BLOCKS, {1024, 2048, 4096, 8192});
+    c->slice_rows = max_slice_rows(max_n, BS, c->target_blocks);
     c->nbmax = (int)cdiv(max_n, BS);
     const int64_t npadmax = (int64_t)c->nbmax * BS;
     struct A { void** p; size_t bytes; } allocs[] = {
-        {(void**)&c->js, sizeof(float4) * npadmax},
+        {&c->js, sizeof(double4) * npadmax},
         {&c->part, 32 * (size_t)c->slice_rows},
         {(void**)&c->cpart, sizeof(double) * 8 * c->nbmax},
         {(void**)&c->vh, sizeof(double) * 3 * npadmax},
-        {(void**)&c->jsv, sizeof(float4) * 2 * npadmax},
+        {&c->jsv, sizeof(double4) * 2 * npadmax},
         {&c->partv, 64 * (size_t)c->slice_rows},
         {(void**)&c->cpartv, sizeof(double) * 8 * c->nbmax},
         {(void**)&c->red, sizeof(double) * 8 * (c->nbmax + 8)},
@@ -170,6 +215,12 @@ dnb_status dnb_create(dnb_ctx** out, int64_t max_n, dnb_prec prec) {
 void dnb_destroy(dnb_ctx* c) {
     if (!c) return;
     (void)hipDeviceSynchronize();
+    if (c->prof) {
+        Prof* pf = (Prof*)c->prof;
+        for (auto* v : {&pf->pool, &pf->ev[0], &pf->ev[1]})
+            for (hipEvent_t e : *v) (void)hipEventDestroy(e);
+        delete pf;
+    }
     void* ps[] = {c->js, c->part, c->cpart, c->vh, c->jsv, c->partv, c->cpartv, c->red};
     for (void* p : ps)
         if (p) (void)hipFree(p);
@@ -188,11 +239,9 @@ dnb_status dnb_accelerations(dnb_ctx* c, int64_t n, const double* pos, const dou
     hipStream_t st = (hipStream_t)stream;
     Pot p = to_pot(*pot);
     const int nb = (int)cdiv(n, BS);
-    if (c->prec == DNB_FP32C) {
-        HIP_TRY(launch_block_sums(pos, n, c->cpart, st));
-        HIP_TRY(launch_stage(pos, mass, n, c->cpart, nb, nullptr, c->js, nullptr, st));
-    }
-    HIP_TRY(launch_pair_fwd(c, n, pos, mass, p.eps, st));
+    if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(pos, n, c->cpart, st));
+    HIP_TRY(launch_stage(c, pos, mass, n, c->cpart, nb, nullptr, nullptr, st));
+    HIP_TRY(profiled(c, 0, st, [&] { return launch_pair_fwd(c, n, p.eps, st); }));
     FwdArgs a{};
     a.n = n; a.mass = mass; a.pot = p; a.x = pos; a.acc_out = acc; a.with_ext = with_ext ? 1 : 0;
     HIP_TRY(launch_kdk(c, KDK_ACC, a, st));
@@ -284,14 +333,12 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
             const int64_t n0 = cs * K, n1 = (n0 + K < T) ? n0 + K : T;
             if (n1 - n0 < 2) return DNB_OK;
             double* x0 = tp.state(cs);
-            if (c->prec == DNB_FP32C) {
-                HIP_TRY(launch_block_sums(x0, n, cpf[0], st));
-                HIP_TRY(launch_stage(x0, mass, n, nullptr, 0, tp.centre(cs), c->js, nullptr, st));
-            }
+            if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(x0, n, cpf[0], st));
+            HIP_TRY(launch_stage(c, x0, mass, n, nullptr, 0, tp.centre(cs), nullptr, st));
             int q = 0;
             for (int64_t s = n0; s <= n1 - 2; ++s) {
                 double* xc = (s == n0) ? x0 : seg + (s - n0) * 3 * n;
-                HIP_TRY(launch_pair_fwd(c, n, xc, mass, p.eps, st));
+                HIP_TRY(profiled(c, 0, st, [&] { return launch_pair_fwd(c, n, p.eps, st); }));
                 FwdArgs a{};
                 a.n = n; a.mass = mass; a.pot = p; a.dt = dt; a.with_ext = 1;
                 a.x = xc; a.x_out = seg + (s - n0 + 1) * 3 * n;
@@ -305,11 +352,9 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
         };
         double* cpv[2] = {c->cpartv, c->cpartv + 4 * c->nbmax};
         int q = 0;
-        if (c->prec == DNB_FP32C) {
-            HIP_TRY(launch_block_sums(pos_T, n, cpv[0], st));
-            HIP_TRY(launch_rev_stage(c, n, pos_T, mass, lv, cpv[0], nb, cpv[1], st));
-            q = 1;
-        }
+        if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(pos_T, n, cpv[0], st));
+        HIP_TRY(launch_rev_stage(c, n, pos_T, mass, lv, cpv[0], nb, cpv[1], st));
+        q = 1;
         int64_t cur = -1;
         for (int64_t m = T; m >= 0; --m) {
             if (m > 0) {
@@ -320,7 +365,7 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
                 }
             }
             const double* xm = get_pos(m);
-            HIP_TRY(launch_pair_vjp(c, n, xm, mass, lv, with_mass, p.eps, st));
+            HIP_TRY(profiled(c, 1, st, [&] { return launch_pair_vjp(c, n, with_mass, p.eps, st); }));
             RevArgs r{};
             r.n = n; r.mass = mass; r.pot = p; r.dt = dt;
             r.coef = (m == T || m == 0) ? 0.5 * dt : dt;
@@ -427,6 +472,38 @@ dnb_status dnb_place_plummer_vjp(dnb_ctx* c, int64_t n, const double* zeta, doub
     CHECK(check_dev(gm_tot, "gm_tot", fn));
     HIP_TRY(launch_place_vjp(c, n, zeta, m_tot, a_p, G, gpos, gvel, gmass, gw, gm_tot,
                              (hipStream_t)stream));
+    return DNB_OK;
+}
+
+dnb_status dnb_profile(dnb_ctx* c, int enable) {
+    if (!c) return fail(DNB_ERR_ARG, "dnb_profile: ctx is NULL");
+    if (!c->prof) {
+        c->prof = new (std::nothrow) Prof();
+        if (!c->prof) return fail(DNB_ERR_NOMEM, "dnb_profile: host allocation failed");
+    }
+    ((Prof*)c->prof)->on = enable != 0;
+    return DNB_OK;
+}
+
+dnb_status dnb_profile_read(dnb_ctx* c, double* out4) {
+    if (!c || !out4) return fail(DNB_ERR_ARG, "dnb_profile_read: NULL argument");
+    for (int k = 0; k < 4; ++k) out4[k] = 0.0;
+    Prof* pf = (Prof*)c->prof;
+    if (!pf) return DNB_OK;
+    for (int kind = 0; kind < 2; ++kind) {
+        auto& v = pf->ev[kind];
+        double tot = 0.0;
+        for (size_t k = 0; k + 1 < v.size(); k += 2) {
+            HIP_TRY(hipEventSynchronize(v[k + 1]));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, v[k], v[k + 1]));
+            tot += ms;
+        }
+        out4[2 * kind] = tot;
+        out4[2 * kind + 1] = (double)(v.size() / 2);
+        for (hipEvent_t e : v) pf->pool.push_back(e);
+        v.clear();
+    }
     return DNB_OK;
 }
 

@@ -105,14 +105,14 @@ hipError_t launch_mmd(dnb_ctx* c, int64_t n, const double* pos, int64_t m, const
     const double inv2h2 = 1.0 / (2.0 * h * h);
     const int wg = gpos != nullptr;
     double* pv = (double*)c->partv;   // [S][8][npad] doubles available
-    Slicing sx = slicing_for(n);      // targets x, sources x
-    Slicing sxy = slicing_for(n);     // targets x, sources y: slice length from m
+    Slicing sx = plain_slicing(c, n);    // targets x, sources x
+    Slicing sxy = plain_slicing(c, n);    // targets x, sources y: slice length from m
     {
         int64_t want = sxy.S;
         sxy.jslice = (int)(cdiv(cdiv(m, want), TILE) * TILE);
         sxy.S = (int)cdiv(m, sxy.jslice);
     }
-    Slicing sy = slicing_for(m);
+    Slicing sy = plain_slicing(c, m);
     double* pxx = pv;
     double* pxy = pv + (int64_t)4 * sx.S * sx.npad;
     double* pyy = (double*)c->part;
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(BS) void k_energy_final(const double* __restrict__ 
 
 hipError_t launch_energy(dnb_ctx* c, int64_t n, const double* pos, const double* vel,
                          const double* mass, const Pot& p, double* out3, hipStream_t st) {
-    Slicing sl = slicing_for(n);
+    Slicing sl = plain_slicing(c, n);
     double* part = (double*)c->partv;
     hipLaunchKernelGGL(k_energy_pairs, dim3(sl.nblk, sl.S), dim3(BS), 0, st, pos, mass, (int)n,
                        sl.jslice, p.eps * p.eps, part, sl.npad);
@@ -228,10 +228,10 @@ __global__ void k_orbit(const double* __restrict__ w0, Pot p, double dt, int64_t
     Ext e = ext_accel(p, x, y, z);
     if (traj) { traj[0] = x; traj[1] = y; traj[2] = z; }
     for (int64_t s = 0; s < n_steps; ++s) {
-        const double hx = vx + hdt * e.ax, hy = vy + hdt * e.ay, hz = vz + hdt * e.az;
-        x = x + dt * hx; y = y + dt * hy; z = z + dt * hz;
+        const double hx = fma(hdt, e.ax, vx), hy = fma(hdt, e.ay, vy), hz = fma(hdt, e.az, vz);
+        x = fma(dt, hx, x); y = fma(dt, hy, y); z = fma(dt, hz, z);
         e = ext_accel(p, x, y, z);
-        vx = hx + hdt * e.ax; vy = hy + hdt * e.ay; vz = hz + hdt * e.az;
+        vx = fma(hdt, e.ax, hx); vy = fma(hdt, e.ay, hy); vz = fma(hdt, e.az, hz);
         if (traj) { traj[3 * (s + 1)] = x; traj[3 * (s + 1) + 1] = y; traj[3 * (s + 1) + 2] = z; }
     }
     w_out[0] = x; w_out[1] = y; w_out[2] = z; w_out[3] = vx; w_out[4] = vy; w_out[5] = vz;

@@ -13,26 +13,31 @@ namespace dnb {
 constexpr int BS = 256;              // threads per block of every particle kernel
 constexpr int TILE = 256;            // sources staged in LDS per tile
 constexpr int SUBTILE = 128;         // sources summed in plain FP32 before a TwoSum
-constexpr int TARGET_BLOCKS = 2048;  // pair-kernel blocks wanted per launch (8 per CU)
+constexpr int TARGET_BLOCKS = 8192;  // pair-kernel blocks wanted per launch (32 per CU)
 constexpr int S_MAX = 64;            // maximum number of source slices
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Length of the staged source arrays: n rounded up to whole sub-tiles; the
+// entries past n are far-away zero-mass particles.
+inline int64_t pad_sources(int64_t n) { return cdiv(n, SUBTILE) * SUBTILE; }
+
 // Source slicing of the O(N^2) kernels: the grid is (target blocks) x S, each
-// block sums one contiguous slice of sources.  Small N gets more slices so the
-// launch still fills the 256 compute units.
+// block owns tpb = BS * RI targets (RI per lane) and sums one contiguous slice of
+// sources.  Small N gets more slices so that the launch still fills the 256
+// compute units with about `target` blocks.
 struct Slicing {
     int S;          // number of slices
     int jslice;     // sources per slice (a multiple of TILE)
     int nblk;       // target blocks
-    int64_t npad;   // row stride of the partial buffers (n rounded up to BS)
+    int64_t npad;   // row stride of the partial buffers (n rounded up to tpb)
 };
 
-inline Slicing slicing_for(int64_t n) {
+inline Slicing slicing_for(int64_t n, int tpb, int target) {
     Slicing s;
-    s.nblk = (int)cdiv(n, BS);
-    s.npad = (int64_t)s.nblk * BS;
-    int64_t want = TARGET_BLOCKS / s.nblk;
+    s.nblk = (int)cdiv(n, tpb);
+    s.npad = (int64_t)s.nblk * tpb;
+    int64_t want = target / s.nblk;
     int64_t max_by_tiles = cdiv(n, TILE);   // at least one tile per slice
     if (want > max_by_tiles) want = max_by_tiles;
     if (want > S_MAX) want = S_MAX;
@@ -42,13 +47,13 @@ inline Slicing slicing_for(int64_t n) {
     return s;
 }
 
-// Upper bound of S * npad over all n <= max_n (sizes the partial buffers).
-// S never exceeds want = clamp(TARGET_BLOCKS / nblk, 1, S_MAX), so
-// S * npad <= want * nblk * BS <= max(S_MAX * BS * (TARGET_BLOCKS / S_MAX), npad).
-inline int64_t max_slice_rows(int64_t max_n) {
-    const int64_t nb = cdiv(max_n, BS);
-    const int64_t small = (int64_t)TARGET_BLOCKS * BS;
-    return nb * BS > small ? nb * BS : small;
+// Upper bound of S * npad over all n <= max_n for blocks of at most tpb targets:
+// S <= want = clamp(target / nblk, 1, S_MAX), so S * npad <= want * nblk * tpb
+// <= max(target * tpb, npad(max_n)).
+inline int64_t max_slice_rows(int64_t max_n, int tpb, int target) {
+    const int64_t np = cdiv(max_n, tpb) * tpb;
+    const int64_t small = (int64_t)target * tpb;
+    return np > small ? np : small;
 }
 
 // ------------------------------------------------------------- potential ---
@@ -191,19 +196,35 @@ struct dnb_ctx {
     dnb_prec prec;
     int64_t slice_rows;      // capacity of S * npad
     int nbmax;               // max blocks of the O(N) kernels
+    int target_blocks;       // pair-kernel blocks wanted per launch
     // forward path
-    float4* js;              // FP32C staged sources (x, y, z relative to a centre; m)
+    void* js;                // staged sources: FP32C float4 (x, y, z relative to a centre; m),
+                             // FP64 double4 (x, y, z, m); padded to pad_sources(n)
     void* part;              // slice partials: FP32C float [S][6][npad], FP64 double [S][3][npad]
     double* cpart;           // [2][nbmax][4] block sums of positions (centre), double buffered
     double* vh;              // [3][max_n] half-step velocities of the running integration
     // reverse path
-    float4* jsv;             // FP32C staged [2][max_n]: (x, y, z, m) then (w, 0)
+    void* jsv;               // staged VJP sources, interleaved per particle:
+                             // [2 j] = (x, y, z, m), [2 j + 1] = (w, 0); float4 or double4
     void* partv;             // VJP partials: FP32C float [S][14][npad], FP64 double [S][7][npad]
     double* cpartv;          // [2][nbmax][4]
     double* red;             // [nbmax][8] reduction scratch
+    void* prof;              // host-side event pool of dnb_profile (null when off)
 };
 
 namespace dnb {
+
+// Geometry of the forward and VJP pair kernels for this context (FP64 uses one
+// target per lane).
+inline Slicing fwd_slicing(const dnb_ctx* c, int64_t n) {
+    return slicing_for(n, BS, c->target_blocks);
+}
+inline Slicing vjp_slicing(const dnb_ctx* c, int64_t n) {
+    return slicing_for(n, BS, c->target_blocks);
+}
+inline Slicing plain_slicing(const dnb_ctx* c, int64_t n) {
+    return slicing_for(n, BS, c->target_blocks);
+}
 
 // Kernel launchers (defined in the .hip files).  All return hipError_t of the launch.
 enum KdkMode { KDK_FIRST = 0, KDK_MID = 1, KDK_LAST = 2, KDK_ACC = 3 };
@@ -232,11 +253,13 @@ struct FwdArgs {
 };
 
 hipError_t launch_block_sums(const double* x, int64_t n, double* cpart, hipStream_t st);
-hipError_t launch_stage(const double* x, const double* mass, int64_t n, const double* cpart,
-                        int nb, const double* centre_override, float4* js, double* centre_out,
-                        hipStream_t st);
-hipError_t launch_pair_fwd(dnb_ctx* c, int64_t n, const double* x, const double* mass,
-                           double eps, hipStream_t st);
+// Stage x (and mass) into ctx->js: FP32C relative to the centre (from the block
+// sums cpart over nb blocks, or centre_override), FP64 as absolute positions.
+// Pads the tail to pad_sources(n).  centre_out (nullable) receives the centre.
+hipError_t launch_stage(dnb_ctx* c, const double* x, const double* mass, int64_t n,
+                        const double* cpart, int nb, const double* centre_override,
+                        double* centre_out, hipStream_t st);
+hipError_t launch_pair_fwd(dnb_ctx* c, int64_t n, double eps, hipStream_t st);
 hipError_t launch_kdk(dnb_ctx* c, KdkMode mode, const FwdArgs& a, hipStream_t st);
 
 struct RevArgs {
@@ -257,8 +280,7 @@ struct RevArgs {
 hipError_t launch_rev_stage(dnb_ctx* c, int64_t n, const double* x, const double* mass,
                             const double* w, const double* cpart, int nb, double* cpart_out,
                             hipStream_t st);
-hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, const double* x, const double* mass,
-                           const double* w, int with_mass, double eps, hipStream_t st);
+hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, int with_mass, double eps, hipStream_t st);
 hipError_t launch_rev_kick(dnb_ctx* c, const RevArgs& a, hipStream_t st);
 hipError_t launch_reduce_accum(const double* accum, int64_t n, int nterms, double* out,
                                double* scratch, hipStream_t st);

@@ -7,12 +7,13 @@
 //     v_n      = v_half + dt/2 a(x_n)          (closing kick of step n-1)
 //     v_half'  = v_n + dt/2 a(x_n)             (opening kick of step n)
 //     x_{n+1}  = x_n + dt v_half'              (drift, FP64)
-// It then stages x_{n+1} for the next pair kernel (FP32C mode) and writes the
-// block sums of x_{n+1}, from which the next launch takes its staging centre.
+// It then stages x_{n+1} as the sources of the next pair kernel and, in FP32C
+// mode, writes the block sums of x_{n+1}, from which the next launch takes its
+// staging centre.
 //
-// Staging centre.  Positions x_{n+1} are staged relative to the mean of x_n (the
-// centre lags one step; it only has to lie near the particles).  Because the
-// centre is a deterministic function of x_n, a recomputation started from a
+// Staging centre (FP32C).  Positions x_{n+1} are staged relative to the mean of
+// x_n (the centre lags one step; it only has to lie near the particles).  The
+// centre is a deterministic function of x_n, so a recomputation started from a
 // checkpoint reproduces the forward run bit for bit once the checkpoint also
 // stores the centre its positions were staged with.
 //
@@ -25,6 +26,9 @@
 #include "dnb_internal.h"
 
 namespace dnb {
+
+constexpr float FAR32 = 1.0e18f;
+constexpr double FAR64 = 1.0e150;
 
 __device__ inline void centre_from(const double* __restrict__ cpart, int nb, int64_t n, double* sh,
                                    double& cx, double& cy, double& cz) {
@@ -51,6 +55,35 @@ __device__ inline void write_block_sums(double x, double y, double z, bool valid
     }
 }
 
+// Source record of particle i (i < n) or padding (n <= i < pad_sources(n)).
+template <bool F32>
+__device__ inline void put_source(void* js, int64_t i, bool real, double x, double y, double z,
+                                  double m, double cx, double cy, double cz) {
+    if (F32)
+        ((float4*)js)[i] = real ? make_float4((float)(x - cx), (float)(y - cy), (float)(z - cz),
+                                              (float)m)
+                                : make_float4(FAR32, FAR32, FAR32, 0.f);
+    else
+        ((double4*)js)[i] = real ? make_double4(x, y, z, m) : make_double4(FAR64, FAR64, FAR64, 0.0);
+}
+
+template <bool F32>
+__device__ inline void put_source_w(void* jsv, int64_t i, bool real, double x, double y, double z,
+                                    double m, double cx, double cy, double cz, double wx, double wy,
+                                    double wz) {
+    if (F32) {
+        float4* p = (float4*)jsv + 2 * i;
+        p[0] = real ? make_float4((float)(x - cx), (float)(y - cy), (float)(z - cz), (float)m)
+                    : make_float4(FAR32, FAR32, FAR32, 0.f);
+        p[1] = real ? make_float4((float)wx, (float)wy, (float)wz, 0.f)
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+        double4* p = (double4*)jsv + 2 * i;
+        p[0] = real ? make_double4(x, y, z, m) : make_double4(FAR64, FAR64, FAR64, 0.0);
+        p[1] = real ? make_double4(wx, wy, wz, 0.0) : make_double4(0.0, 0.0, 0.0, 0.0);
+    }
+}
+
 __global__ __launch_bounds__(BS) void k_block_sums(const double* __restrict__ x, int64_t n,
                                                    double* __restrict__ cpart) {
     __shared__ double sh[3 * BS];
@@ -60,24 +93,29 @@ __global__ __launch_bounds__(BS) void k_block_sums(const double* __restrict__ x,
     write_block_sums(x[k], x[n + k], x[2 * n + k], ok, sh, cpart);
 }
 
+template <bool F32>
 __global__ __launch_bounds__(BS) void k_stage(const double* __restrict__ x,
                                               const double* __restrict__ mass, int64_t n,
-                                              const double* __restrict__ cpart, int nb,
-                                              const double* __restrict__ centre_override,
-                                              float4* __restrict__ js,
+                                              int64_t nj, const double* __restrict__ cpart,
+                                              int nb, const double* __restrict__ centre_override,
+                                              void* __restrict__ js,
                                               double* __restrict__ centre_out) {
     __shared__ double sh[3 * BS];
-    double cx, cy, cz;
-    if (centre_override) {
-        cx = centre_override[0]; cy = centre_override[1]; cz = centre_override[2];
-    } else {
-        centre_from(cpart, nb, n, sh, cx, cy, cz);
+    double cx = 0.0, cy = 0.0, cz = 0.0;
+    if (F32) {
+        if (centre_override) {
+            cx = centre_override[0]; cy = centre_override[1]; cz = centre_override[2];
+        } else {
+            centre_from(cpart, nb, n, sh, cx, cy, cz);
+        }
     }
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-    if (i < n)
-        js[i] = make_float4((float)(x[i] - cx), (float)(x[n + i] - cy), (float)(x[2 * n + i] - cz),
-                            (float)mass[i]);
-    if (centre_out && blockIdx.x == 0 && threadIdx.x == 0) {
+    if (i < nj) {
+        const bool real = i < n;
+        const int64_t k = real ? i : 0;
+        put_source<F32>(js, i, real, x[k], x[n + k], x[2 * n + k], mass[k], cx, cy, cz);
+    }
+    if (F32 && centre_out && blockIdx.x == 0 && threadIdx.x == 0) {
         centre_out[0] = cx; centre_out[1] = cy; centre_out[2] = cz; centre_out[3] = 0.0;
     }
 }
@@ -107,7 +145,7 @@ __device__ inline void pair_sum(const void* part, int S, int64_t npad, int64_t i
 
 template <int MODE, bool F32>
 __global__ __launch_bounds__(BS) void k_kdk(FwdArgs a, const void* __restrict__ part, int S,
-                                            int64_t npad, float4* __restrict__ js) {
+                                            int64_t npad, int64_t nj, void* __restrict__ js) {
     __shared__ double sh[3 * BS];
     const int64_t n = a.n;
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
@@ -131,65 +169,76 @@ __global__ __launch_bounds__(BS) void k_kdk(FwdArgs a, const void* __restrict__ 
         if (MODE == KDK_ACC) {
             a.acc_out[i] = ax; a.acc_out[n + i] = ay; a.acc_out[2 * n + i] = az;
         } else if (MODE == KDK_LAST) {
-            a.v[i] = a.vh[i] + hdt * ax;
-            a.v[n + i] = a.vh[n + i] + hdt * ay;
-            a.v[2 * n + i] = a.vh[2 * n + i] + hdt * az;
+            a.v[i] = fma(hdt, ax, a.vh[i]);
+            a.v[n + i] = fma(hdt, ay, a.vh[n + i]);
+            a.v[2 * n + i] = fma(hdt, az, a.vh[2 * n + i]);
         } else {
             double vx, vy, vz;
             if (MODE == KDK_FIRST) {
                 vx = a.v[i]; vy = a.v[n + i]; vz = a.v[2 * n + i];
             } else {
-                vx = a.vh[i] + hdt * ax; vy = a.vh[n + i] + hdt * ay; vz = a.vh[2 * n + i] + hdt * az;
+                vx = fma(hdt, ax, a.vh[i]);
+                vy = fma(hdt, ay, a.vh[n + i]);
+                vz = fma(hdt, az, a.vh[2 * n + i]);
             }
             if (a.tape_state) {
                 double* t = a.tape_state;
                 t[i] = x; t[n + i] = y; t[2 * n + i] = z;
                 t[3 * n + i] = vx; t[4 * n + i] = vy; t[5 * n + i] = vz;
             }
-            const double hx = vx + hdt * ax, hy = vy + hdt * ay, hz = vz + hdt * az;
-            xn = x + a.dt * hx; yn = y + a.dt * hy; zn = z + a.dt * hz;
+            const double hx = fma(hdt, ax, vx), hy = fma(hdt, ay, vy), hz = fma(hdt, az, vz);
+            xn = fma(a.dt, hx, x); yn = fma(a.dt, hy, y); zn = fma(a.dt, hz, z);
             a.vh[i] = hx; a.vh[n + i] = hy; a.vh[2 * n + i] = hz;
             a.x_out[i] = xn; a.x_out[n + i] = yn; a.x_out[2 * n + i] = zn;
-            if (F32)
-                js[i] = make_float4((float)(xn - cx), (float)(yn - cy), (float)(zn - cz),
-                                    (float)a.mass[i]);
         }
     }
-    if (F32 && drift) {
-        write_block_sums(xn, yn, zn, ok, sh, a.cpart_out);
-        if (a.tape_centre_next && blockIdx.x == 0 && threadIdx.x == 0) {
-            a.tape_centre_next[0] = cx; a.tape_centre_next[1] = cy;
-            a.tape_centre_next[2] = cz; a.tape_centre_next[3] = 0.0;
+    if (drift) {
+        if (i < nj) put_source<F32>(js, i, ok, xn, yn, zn, a.mass[k], cx, cy, cz);
+        if (F32) {
+            write_block_sums(xn, yn, zn, ok, sh, a.cpart_out);
+            if (a.tape_centre_next && blockIdx.x == 0 && threadIdx.x == 0) {
+                a.tape_centre_next[0] = cx; a.tape_centre_next[1] = cy;
+                a.tape_centre_next[2] = cz; a.tape_centre_next[3] = 0.0;
+            }
         }
     }
 }
+
+// Blocks of an O(N) kernel that also writes the padded source array.
+static inline unsigned onblocks(int64_t n) { return (unsigned)cdiv(pad_sources(n), BS); }
 
 hipError_t launch_block_sums(const double* x, int64_t n, double* cpart, hipStream_t st) {
     hipLaunchKernelGGL(k_block_sums, dim3((unsigned)cdiv(n, BS)), dim3(BS), 0, st, x, n, cpart);
     return hipGetLastError();
 }
 
-hipError_t launch_stage(const double* x, const double* mass, int64_t n, const double* cpart,
-                        int nb, const double* centre_override, float4* js, double* centre_out,
-                        hipStream_t st) {
-    hipLaunchKernelGGL(k_stage, dim3((unsigned)cdiv(n, BS)), dim3(BS), 0, st, x, mass, n, cpart,
-                       nb, centre_override, js, centre_out);
+hipError_t launch_stage(dnb_ctx* c, const double* x, const double* mass, int64_t n,
+                        const double* cpart, int nb, const double* centre_override,
+                        double* centre_out, hipStream_t st) {
+    const int64_t nj = pad_sources(n);
+    if (c->prec == DNB_FP32C)
+        hipLaunchKernelGGL(k_stage<true>, dim3(onblocks(n)), dim3(BS), 0, st, x, mass, n, nj,
+                           cpart, nb, centre_override, c->js, centre_out);
+    else
+        hipLaunchKernelGGL(k_stage<false>, dim3(onblocks(n)), dim3(BS), 0, st, x, mass, n, nj,
+                           cpart, nb, centre_override, c->js, centre_out);
     return hipGetLastError();
 }
 
 template <int MODE>
 static void kdk_dispatch(dnb_ctx* c, const FwdArgs& a, const Slicing& sl, hipStream_t st) {
-    dim3 grid((unsigned)cdiv(a.n, BS));
+    dim3 grid(onblocks(a.n));
+    const int64_t nj = pad_sources(a.n);
     if (c->prec == DNB_FP32C)
         hipLaunchKernelGGL((k_kdk<MODE, true>), grid, dim3(BS), 0, st, a, (const void*)c->part,
-                           sl.S, sl.npad, c->js);
+                           sl.S, sl.npad, nj, c->js);
     else
         hipLaunchKernelGGL((k_kdk<MODE, false>), grid, dim3(BS), 0, st, a, (const void*)c->part,
-                           sl.S, sl.npad, c->js);
+                           sl.S, sl.npad, nj, c->js);
 }
 
 hipError_t launch_kdk(dnb_ctx* c, KdkMode mode, const FwdArgs& a, hipStream_t st) {
-    Slicing sl = slicing_for(a.n);
+    Slicing sl = fwd_slicing(c, a.n);
     switch (mode) {
         case KDK_FIRST: kdk_dispatch<KDK_FIRST>(c, a, sl, st); break;
         case KDK_MID: kdk_dispatch<KDK_MID>(c, a, sl, st); break;
@@ -201,24 +250,23 @@ hipError_t launch_kdk(dnb_ctx* c, KdkMode mode, const FwdArgs& a, hipStream_t st
 
 // ------------------------------------------------------------------ reverse --
 
+template <bool F32>
 __global__ __launch_bounds__(BS) void k_rev_stage(const double* __restrict__ x,
                                                   const double* __restrict__ mass,
                                                   const double* __restrict__ w, int64_t n,
-                                                  const double* __restrict__ cpart, int nb,
-                                                  float4* __restrict__ jsv,
+                                                  int64_t nj, const double* __restrict__ cpart,
+                                                  int nb, void* __restrict__ jsv,
                                                   double* __restrict__ cpart_out) {
     __shared__ double sh[3 * BS];
-    double cx, cy, cz;
-    centre_from(cpart, nb, n, sh, cx, cy, cz);
+    double cx = 0.0, cy = 0.0, cz = 0.0;
+    if (F32) centre_from(cpart, nb, n, sh, cx, cy, cz);
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
     const bool ok = i < n;
     const int64_t k = ok ? i : 0;
     const double x0 = x[k], y0 = x[n + k], z0 = x[2 * n + k];
-    if (ok) {
-        jsv[i] = make_float4((float)(x0 - cx), (float)(y0 - cy), (float)(z0 - cz), (float)mass[i]);
-        jsv[n + i] = make_float4((float)w[i], (float)w[n + i], (float)w[2 * n + i], 0.f);
-    }
-    write_block_sums(x0, y0, z0, ok, sh, cpart_out);
+    if (i < nj)
+        put_source_w<F32>(jsv, i, ok, x0, y0, z0, mass[k], cx, cy, cz, w[k], w[n + k], w[2 * n + k]);
+    if (F32) write_block_sums(x0, y0, z0, ok, sh, cpart_out);
 }
 
 // Slice sums of the VJP kernel for particle i: J^T w, a_int (both times G) and the
@@ -255,7 +303,8 @@ __device__ inline void vjp_sum(const void* part, int S, int64_t npad, int64_t i,
 
 template <bool F32>
 __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restrict__ part, int S,
-                                                 int64_t npad, float4* __restrict__ jsv) {
+                                                 int64_t npad, int64_t nj,
+                                                 void* __restrict__ jsv) {
     __shared__ double sh[3 * BS];
     const int64_t n = a.n;
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
@@ -274,9 +323,9 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
     double hx, hy, hz;
     ext_hvp(a.pot, x, y, z, wx, wy, wz, hx, hy, hz);
 
-    double lx = a.lx[k] + a.coef * (g[0] + hx);
-    double ly = a.lx[n + k] + a.coef * (g[1] + hy);
-    double lz = a.lx[2 * n + k] + a.coef * (g[2] + hz);
+    const double lx = fma(a.coef, g[0] + hx, a.lx[k]);
+    const double ly = fma(a.coef, g[1] + hy, a.lx[n + k]);
+    const double lz = fma(a.coef, g[2] + hz, a.lx[2 * n + k]);
     const double kc = a.coef / a.dt;
     const double aw_int = ai[0] * wx + ai[1] * wy + ai[2] * wz;
     const double aw_ext = e.ax * wx + e.ay * wy + e.az * wz;
@@ -292,7 +341,7 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
         const double inv = 1.0 / a.dt;
         const double vx = (x - px) * inv, vy = (y - py) * inv, vz = (z - pz) * inv;
         d_dt += vx * lx + vy * ly + vz * lz;
-        nwx = wx + a.dt * lx; nwy = wy + a.dt * ly; nwz = wz + a.dt * lz;
+        nwx = fma(a.dt, lx, wx); nwy = fma(a.dt, ly, wy); nwz = fma(a.dt, lz, wz);
     }
     if (ok) {
         a.lx[i] = lx; a.lx[n + i] = ly; a.lx[2 * n + i] = lz;
@@ -301,35 +350,38 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
         a.accum[2 * n + i] += d_dt;
         a.accum[3 * n + i] += d_ms;
         if (a.with_mass) a.accum[4 * n + i] -= a.coef * gm;
-        if (drift) {
-            a.lv[i] = nwx; a.lv[n + i] = nwy; a.lv[2 * n + i] = nwz;
-            if (F32) {
-                jsv[i] = make_float4((float)(px - cx), (float)(py - cy), (float)(pz - cz),
-                                     (float)a.mass[i]);
-                jsv[n + i] = make_float4((float)nwx, (float)nwy, (float)nwz, 0.f);
-            }
-        }
+        if (drift) { a.lv[i] = nwx; a.lv[n + i] = nwy; a.lv[2 * n + i] = nwz; }
     }
-    if (F32 && drift) write_block_sums(px, py, pz, ok, sh, a.cpart_out);
+    if (drift) {
+        if (i < nj)
+            put_source_w<F32>(jsv, i, ok, px, py, pz, a.mass[k], cx, cy, cz, nwx, nwy, nwz);
+        if (F32) write_block_sums(px, py, pz, ok, sh, a.cpart_out);
+    }
 }
 
 hipError_t launch_rev_stage(dnb_ctx* c, int64_t n, const double* x, const double* mass,
                             const double* w, const double* cpart, int nb, double* cpart_out,
                             hipStream_t st) {
-    hipLaunchKernelGGL(k_rev_stage, dim3((unsigned)cdiv(n, BS)), dim3(BS), 0, st, x, mass, w, n,
-                       cpart, nb, c->jsv, cpart_out);
+    const int64_t nj = pad_sources(n);
+    if (c->prec == DNB_FP32C)
+        hipLaunchKernelGGL(k_rev_stage<true>, dim3(onblocks(n)), dim3(BS), 0, st, x, mass, w, n,
+                           nj, cpart, nb, c->jsv, cpart_out);
+    else
+        hipLaunchKernelGGL(k_rev_stage<false>, dim3(onblocks(n)), dim3(BS), 0, st, x, mass, w, n,
+                           nj, cpart, nb, c->jsv, cpart_out);
     return hipGetLastError();
 }
 
 hipError_t launch_rev_kick(dnb_ctx* c, const RevArgs& a, hipStream_t st) {
-    Slicing sl = slicing_for(a.n);
-    dim3 grid((unsigned)cdiv(a.n, BS));
+    Slicing sl = vjp_slicing(c, a.n);
+    dim3 grid(onblocks(a.n));
+    const int64_t nj = pad_sources(a.n);
     if (c->prec == DNB_FP32C)
         hipLaunchKernelGGL((k_rev_kick<true>), grid, dim3(BS), 0, st, a, (const void*)c->partv,
-                           sl.S, sl.npad, c->jsv);
+                           sl.S, sl.npad, nj, c->jsv);
     else
         hipLaunchKernelGGL((k_rev_kick<false>), grid, dim3(BS), 0, st, a, (const void*)c->partv,
-                           sl.S, sl.npad, c->jsv);
+                           sl.S, sl.npad, nj, c->jsv);
     return hipGetLastError();
 }
 

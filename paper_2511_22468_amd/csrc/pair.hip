@@ -3,13 +3,20 @@
 // gradients through the simulation).
 //
 // Layout.  A launch is a grid of (target blocks) x (source slices).  Each
-// 256-thread block owns 256 target particles (one per lane) and one contiguous
-// slice of sources, which it streams through LDS in tiles of 256.  Every lane
-// reads the same source from LDS at the same time (a broadcast read), so LDS
-// bandwidth is not a limit; the kernel is bound by VALU issue.  Each block writes
-// its per-target partial sums for its slice; the O(N) kernel that consumes the
-// sum adds the slices in FP64 in slice order, so results are deterministic and
-// independent of scheduling.  No floating-point atomics are used.
+// 256-thread block owns 256 targets (one per lane) and one contiguous slice of
+// sources.  Every lane of a wave needs the same source at the same time, so the
+// sources are read with wave-uniform addresses: the compiler turns these into
+// scalar loads (s_load_dwordx8/x16 through the scalar cache) and the VALU
+// instructions take the source coordinates straight from SGPRs.  No LDS, no
+// barriers, and the source data costs no VGPRs.  Sources are read in batches,
+// one batch ahead of use, so the scalar-load latency overlaps the arithmetic of
+// the current batch.  The staged source arrays are padded with far-away
+// zero-mass particles to a multiple of 128, so every batch is whole and in
+// bounds.
+//
+// Each block writes per-target partial sums for its slice; the O(N) kernel that
+// consumes them adds the slices in FP64 in slice order, so results are
+// deterministic and independent of scheduling.  No floating-point atomics.
 //
 // FP32C: pair terms in FP32 on positions staged relative to a common centre.
 // Within a sub-tile of 128 sources a lane sums in plain FP32; each sub-tile sum
@@ -23,10 +30,6 @@
 #include "dnb_internal.h"
 
 namespace dnb {
-
-// Padding source far away with zero mass: contributes exactly zero.
-constexpr float FAR32 = 1.0e18f;
-constexpr double FAR64 = 1.0e150;
 
 __device__ __forceinline__ void two_sum_acc(float& hi, float& lo, float x) {
     float s = hi + x;
@@ -44,43 +47,54 @@ __device__ __forceinline__ double rsqrt_f64(double s) {
     return y;
 }
 
+// Start index of the batch loaded ahead of batch k of a sub-tile starting at jt;
+// on the last batch of the slice it re-reads the slice's last batch (in bounds).
+__device__ __forceinline__ int next_batch(int jt, int k, int PB, int j1) {
+    return (k + PB < SUBTILE) ? jt + k + PB : min(jt + SUBTILE, j1 - PB);
+}
+
 // ------------------------------------------------------------ forward FP32C --
-// js: staged sources (x, y, z, m).  part: [S][6][npad] = (hi_x, hi_y, hi_z,
-// lo_x, lo_y, lo_z) of sum_j m_j d_ij s_ij^-3/2 over the block's slice.
+// js: staged sources (x, y, z, m), padded to nj = roundup(n, 128).
+// part: [S][6][npad] = (hi_x, hi_y, hi_z, lo_x, lo_y, lo_z) of
+// sum_j m_j d_ij s_ij^-3/2 over the block's slice.
 template <bool EPS0>
 __global__ __launch_bounds__(BS) void k_pair_fwd_f32c(const float4* __restrict__ js, int n,
-                                                      int jslice, float eps2,
+                                                      int nj, int jslice, float eps2,
                                                       float* __restrict__ part, int64_t npad) {
-    __shared__ float4 tile[TILE];
+    constexpr int PB = 8;
     const int i = blockIdx.x * BS + threadIdx.x;
     const int j0 = blockIdx.y * jslice;
-    const int j1 = min(n, j0 + jslice);
+    const int j1 = min(nj, j0 + jslice);
     const float4 me = js[min(i, n - 1)];
     float hx = 0.f, hy = 0.f, hz = 0.f, lx = 0.f, ly = 0.f, lz = 0.f;
-    for (int jt = j0; jt < j1; jt += TILE) {
-        const int j = jt + threadIdx.x;
-        tile[threadIdx.x] = (j < j1) ? js[j] : make_float4(FAR32, FAR32, FAR32, 0.f);
-        __syncthreads();
+    float4 qa[PB];
 #pragma unroll
-        for (int h = 0; h < TILE / SUBTILE; ++h) {
-            float ax = 0.f, ay = 0.f, az = 0.f;
-#pragma unroll 16
-            for (int k = 0; k < SUBTILE; ++k) {
-                const float4 q = tile[h * SUBTILE + k];
+    for (int u = 0; u < PB; ++u) qa[u] = js[j0 + u];
+    for (int jt = j0; jt < j1; jt += SUBTILE) {
+        float ax = 0.f, ay = 0.f, az = 0.f;
+        for (int k = 0; k < SUBTILE; k += PB) {
+            const int nx = next_batch(jt, k, PB, j1);
+            float4 qb[PB];
+#pragma unroll
+            for (int u = 0; u < PB; ++u) qb[u] = js[nx + u];
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                const float4 q = qa[u];
                 const float dx = q.x - me.x, dy = q.y - me.y, dz = q.z - me.z;
                 const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
                 const float r = __builtin_amdgcn_rsqf(s);
                 float w = (q.w * r) * (r * r);
-                if (EPS0) w = (jt + h * SUBTILE + k == i) ? 0.f : w;
+                if (EPS0) w = (jt + k + u == i) ? 0.f : w;
                 ax = fmaf(w, dx, ax);
                 ay = fmaf(w, dy, ay);
                 az = fmaf(w, dz, az);
             }
-            two_sum_acc(hx, lx, ax);
-            two_sum_acc(hy, ly, ay);
-            two_sum_acc(hz, lz, az);
+#pragma unroll
+            for (int u = 0; u < PB; ++u) qa[u] = qb[u];
         }
-        __syncthreads();
+        two_sum_acc(hx, lx, ax);
+        two_sum_acc(hy, ly, ay);
+        two_sum_acc(hz, lz, az);
     }
     if (i < n) {
         float* p = part + (int64_t)blockIdx.y * 6 * npad + i;
@@ -90,37 +104,42 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f32c(const float4* __restrict__
 }
 
 // ------------------------------------------------------------- forward FP64 --
+// js: staged sources (x, y, z, m) in FP64, padded like the FP32C array.
 // part: [S][3][npad] doubles.
 template <bool EPS0>
-__global__ __launch_bounds__(BS) void k_pair_fwd_f64(const double* __restrict__ x,
-                                                     const double* __restrict__ mass, int n,
-                                                     int jslice, double eps2,
+__global__ __launch_bounds__(BS) void k_pair_fwd_f64(const double4* __restrict__ js, int n,
+                                                     int nj, int jslice, double eps2,
                                                      double* __restrict__ part, int64_t npad) {
-    __shared__ double4 tile[TILE];
+    constexpr int PB = 4;
     const int i = blockIdx.x * BS + threadIdx.x;
     const int j0 = blockIdx.y * jslice;
-    const int j1 = min(n, j0 + jslice);
-    const int ii = min(i, n - 1);
-    const double mx = x[ii], my = x[n + ii], mz = x[2 * n + ii];
+    const int j1 = min(nj, j0 + jslice);
+    const double4 me = js[min(i, n - 1)];
     double ax = 0.0, ay = 0.0, az = 0.0;
-    for (int jt = j0; jt < j1; jt += TILE) {
-        const int j = jt + threadIdx.x;
-        tile[threadIdx.x] = (j < j1) ? make_double4(x[j], x[n + j], x[2 * n + j], mass[j])
-                                     : make_double4(FAR64, FAR64, FAR64, 0.0);
-        __syncthreads();
-#pragma unroll 8
-        for (int k = 0; k < TILE; ++k) {
-            const double4 q = tile[k];
-            const double dx = q.x - mx, dy = q.y - my, dz = q.z - mz;
-            const double s = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-            const double r = rsqrt_f64(s);
-            double w = (q.w * r) * (r * r);
-            if (EPS0) w = (jt + k == i) ? 0.0 : w;
-            ax = fma(w, dx, ax);
-            ay = fma(w, dy, ay);
-            az = fma(w, dz, az);
+    double4 qa[PB];
+#pragma unroll
+    for (int u = 0; u < PB; ++u) qa[u] = js[j0 + u];
+    for (int jt = j0; jt < j1; jt += SUBTILE) {
+        for (int k = 0; k < SUBTILE; k += PB) {
+            const int nx = next_batch(jt, k, PB, j1);
+            double4 qb[PB];
+#pragma unroll
+            for (int u = 0; u < PB; ++u) qb[u] = js[nx + u];
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                const double4 q = qa[u];
+                const double dx = q.x - me.x, dy = q.y - me.y, dz = q.z - me.z;
+                const double s = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+                const double r = rsqrt_f64(s);
+                double w = (q.w * r) * (r * r);
+                if (EPS0) w = (jt + k + u == i) ? 0.0 : w;
+                ax = fma(w, dx, ax);
+                ay = fma(w, dy, ay);
+                az = fma(w, dz, az);
+            }
+#pragma unroll
+            for (int u = 0; u < PB; ++u) qa[u] = qb[u];
         }
-        __syncthreads();
     }
     if (i < n) {
         double* p = part + (int64_t)blockIdx.y * 3 * npad + i;
@@ -133,43 +152,39 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f64(const double* __restrict__ 
 //   (J^T w)_k / G = sum_j [s^-3/2 u - 3 s^-5/2 (d.u) d],  u = m_k w_j - m_j w_k
 //   a_int,k / G   = sum_j m_j s^-3/2 d            (needed for the dt and mass terms)
 //   gm_k / G      = sum_j (d.w_j) s^-3/2          (mass cotangent, negated later)
-// jsv: [0..n) staged (x, y, z, m), [n..2n) staged (wx, wy, wz, 0).
+// jsv: interleaved [2 j] = (x, y, z, m), [2 j + 1] = (wx, wy, wz, 0), padded.
 // part: [S][14][npad] floats: JTw hi(3) lo(3), a hi(3) lo(3), gm hi, lo.
 template <bool EPS0, bool MASS>
 __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__ jsv, int n,
-                                                      int jslice, float eps2,
+                                                      int nj, int jslice, float eps2,
                                                       float* __restrict__ part, int64_t npad) {
-    __shared__ float4 tp[TILE];
-    __shared__ float4 tw[TILE];
+    constexpr int PB = 4;
     const int i = blockIdx.x * BS + threadIdx.x;
     const int j0 = blockIdx.y * jslice;
-    const int j1 = min(n, j0 + jslice);
+    const int j1 = min(nj, j0 + jslice);
     const int ii = min(i, n - 1);
-    const float4 me = jsv[ii];
-    const float4 mw = jsv[n + ii];
+    const float4 me = jsv[2 * ii];
+    const float4 mw = jsv[2 * ii + 1];
     float h[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float l[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int jt = j0; jt < j1; jt += TILE) {
-        const int j = jt + threadIdx.x;
-        if (j < j1) {
-            tp[threadIdx.x] = jsv[j];
-            tw[threadIdx.x] = jsv[n + j];
-        } else {
-            tp[threadIdx.x] = make_float4(FAR32, FAR32, FAR32, 0.f);
-            tw[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        __syncthreads();
+    float4 pa[PB], wa[PB];
 #pragma unroll
-        for (int hh = 0; hh < TILE / SUBTILE; ++hh) {
-            float gx = 0.f, gy = 0.f, gz = 0.f, ax = 0.f, ay = 0.f, az = 0.f, gm = 0.f;
-#pragma unroll 8
-            for (int k = 0; k < SUBTILE; ++k) {
-                const float4 q = tp[hh * SUBTILE + k];
-                const float4 qw = tw[hh * SUBTILE + k];
+    for (int u = 0; u < PB; ++u) { pa[u] = jsv[2 * (j0 + u)]; wa[u] = jsv[2 * (j0 + u) + 1]; }
+    for (int jt = j0; jt < j1; jt += SUBTILE) {
+        float acc[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int k = 0; k < SUBTILE; k += PB) {
+            const int nx = next_batch(jt, k, PB, j1);
+            float4 pb[PB], wb[PB];
+#pragma unroll
+            for (int u = 0; u < PB; ++u) { pb[u] = jsv[2 * (nx + u)]; wb[u] = jsv[2 * (nx + u) + 1]; }
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                const float4 q = pa[u];
+                const float4 qw = wa[u];
                 const float dx = q.x - me.x, dy = q.y - me.y, dz = q.z - me.z;
                 const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
                 float r = __builtin_amdgcn_rsqf(s);
-                if (EPS0) r = (jt + hh * SUBTILE + k == i) ? 0.f : r;
+                if (EPS0) r = (jt + k + u == i) ? 0.f : r;
                 const float r2 = r * r;
                 const float r3 = r2 * r;
                 const float r5 = r3 * r2;
@@ -177,28 +192,24 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__
                 const float uy = fmaf(me.w, qw.y, -(q.w * mw.y));
                 const float uz = fmaf(me.w, qw.z, -(q.w * mw.z));
                 const float du = fmaf(dx, ux, fmaf(dy, uy, dz * uz));
-                const float c = -3.f * (r5 * du);
-                gx = fmaf(c, dx, fmaf(r3, ux, gx));
-                gy = fmaf(c, dy, fmaf(r3, uy, gy));
-                gz = fmaf(c, dz, fmaf(r3, uz, gz));
+                const float c3 = -3.f * (r5 * du);
+                acc[0] = fmaf(c3, dx, fmaf(r3, ux, acc[0]));
+                acc[1] = fmaf(c3, dy, fmaf(r3, uy, acc[1]));
+                acc[2] = fmaf(c3, dz, fmaf(r3, uz, acc[2]));
                 const float mr3 = q.w * r3;
-                ax = fmaf(mr3, dx, ax);
-                ay = fmaf(mr3, dy, ay);
-                az = fmaf(mr3, dz, az);
+                acc[3] = fmaf(mr3, dx, acc[3]);
+                acc[4] = fmaf(mr3, dy, acc[4]);
+                acc[5] = fmaf(mr3, dz, acc[5]);
                 if (MASS) {
                     const float dw = fmaf(dx, qw.x, fmaf(dy, qw.y, dz * qw.z));
-                    gm = fmaf(dw, r3, gm);
+                    acc[6] = fmaf(dw, r3, acc[6]);
                 }
             }
-            two_sum_acc(h[0], l[0], gx);
-            two_sum_acc(h[1], l[1], gy);
-            two_sum_acc(h[2], l[2], gz);
-            two_sum_acc(h[3], l[3], ax);
-            two_sum_acc(h[4], l[4], ay);
-            two_sum_acc(h[5], l[5], az);
-            if (MASS) two_sum_acc(h[6], l[6], gm);
+#pragma unroll
+            for (int u = 0; u < PB; ++u) { pa[u] = pb[u]; wa[u] = wb[u]; }
         }
-        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < (MASS ? 7 : 6); ++c) two_sum_acc(h[c], l[c], acc[c]);
     }
     if (i < n) {
         float* p = part + (int64_t)blockIdx.y * 14 * npad + i;
@@ -217,135 +228,120 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__
 }
 
 // ---------------------------------------------------------------- VJP FP64 --
+// jsv: interleaved double4 [2 j] = (x, y, z, m), [2 j + 1] = (w, 0), padded.
 // part: [S][7][npad] doubles: JTw(3), a(3), gm.
 template <bool EPS0, bool MASS>
-__global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double* __restrict__ x,
-                                                     const double* __restrict__ mass,
-                                                     const double* __restrict__ w, int n,
-                                                     int jslice, double eps2,
+__global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__ jsv, int n,
+                                                     int nj, int jslice, double eps2,
                                                      double* __restrict__ part, int64_t npad) {
-    __shared__ double4 tp[TILE];
-    __shared__ double4 tw[TILE];
+    constexpr int PB = 2;
     const int i = blockIdx.x * BS + threadIdx.x;
     const int j0 = blockIdx.y * jslice;
-    const int j1 = min(n, j0 + jslice);
+    const int j1 = min(nj, j0 + jslice);
     const int ii = min(i, n - 1);
-    const double mx = x[ii], my = x[n + ii], mz = x[2 * n + ii], mm = mass[ii];
-    const double wx0 = w[ii], wy0 = w[n + ii], wz0 = w[2 * n + ii];
-    double gx = 0, gy = 0, gz = 0, ax = 0, ay = 0, az = 0, gm = 0;
-    for (int jt = j0; jt < j1; jt += TILE) {
-        const int j = jt + threadIdx.x;
-        if (j < j1) {
-            tp[threadIdx.x] = make_double4(x[j], x[n + j], x[2 * n + j], mass[j]);
-            tw[threadIdx.x] = make_double4(w[j], w[n + j], w[2 * n + j], 0.0);
-        } else {
-            tp[threadIdx.x] = make_double4(FAR64, FAR64, FAR64, 0.0);
-            tw[threadIdx.x] = make_double4(0.0, 0.0, 0.0, 0.0);
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int k = 0; k < TILE; ++k) {
-            const double4 q = tp[k];
-            const double4 qw = tw[k];
-            const double dx = q.x - mx, dy = q.y - my, dz = q.z - mz;
-            const double s = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-            double r = rsqrt_f64(s);
-            if (EPS0) r = (jt + k == i) ? 0.0 : r;
-            const double r2 = r * r;
-            const double r3 = r2 * r;
-            const double r5 = r3 * r2;
-            const double ux = fma(mm, qw.x, -(q.w * wx0));
-            const double uy = fma(mm, qw.y, -(q.w * wy0));
-            const double uz = fma(mm, qw.z, -(q.w * wz0));
-            const double du = fma(dx, ux, fma(dy, uy, dz * uz));
-            const double c = -3.0 * (r5 * du);
-            gx = fma(c, dx, fma(r3, ux, gx));
-            gy = fma(c, dy, fma(r3, uy, gy));
-            gz = fma(c, dz, fma(r3, uz, gz));
-            const double mr3 = q.w * r3;
-            ax = fma(mr3, dx, ax);
-            ay = fma(mr3, dy, ay);
-            az = fma(mr3, dz, az);
-            if (MASS) {
-                const double dw = fma(dx, qw.x, fma(dy, qw.y, dz * qw.z));
-                gm = fma(dw, r3, gm);
+    const double4 me = jsv[2 * ii];
+    const double4 mw = jsv[2 * ii + 1];
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    double4 pa[PB], wa[PB];
+#pragma unroll
+    for (int u = 0; u < PB; ++u) { pa[u] = jsv[2 * (j0 + u)]; wa[u] = jsv[2 * (j0 + u) + 1]; }
+    for (int jt = j0; jt < j1; jt += SUBTILE) {
+        for (int k = 0; k < SUBTILE; k += PB) {
+            const int nx = next_batch(jt, k, PB, j1);
+            double4 pb[PB], wb[PB];
+#pragma unroll
+            for (int u = 0; u < PB; ++u) { pb[u] = jsv[2 * (nx + u)]; wb[u] = jsv[2 * (nx + u) + 1]; }
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                const double4 q = pa[u];
+                const double4 qw = wa[u];
+                const double dx = q.x - me.x, dy = q.y - me.y, dz = q.z - me.z;
+                const double s = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+                double r = rsqrt_f64(s);
+                if (EPS0) r = (jt + k + u == i) ? 0.0 : r;
+                const double r2 = r * r;
+                const double r3 = r2 * r;
+                const double r5 = r3 * r2;
+                const double ux = fma(me.w, qw.x, -(q.w * mw.x));
+                const double uy = fma(me.w, qw.y, -(q.w * mw.y));
+                const double uz = fma(me.w, qw.z, -(q.w * mw.z));
+                const double du = fma(dx, ux, fma(dy, uy, dz * uz));
+                const double c3 = -3.0 * (r5 * du);
+                acc[0] = fma(c3, dx, fma(r3, ux, acc[0]));
+                acc[1] = fma(c3, dy, fma(r3, uy, acc[1]));
+                acc[2] = fma(c3, dz, fma(r3, uz, acc[2]));
+                const double mr3 = q.w * r3;
+                acc[3] = fma(mr3, dx, acc[3]);
+                acc[4] = fma(mr3, dy, acc[4]);
+                acc[5] = fma(mr3, dz, acc[5]);
+                if (MASS) {
+                    const double dw = fma(dx, qw.x, fma(dy, qw.y, dz * qw.z));
+                    acc[6] = fma(dw, r3, acc[6]);
+                }
             }
+#pragma unroll
+            for (int u = 0; u < PB; ++u) { pa[u] = pb[u]; wa[u] = wb[u]; }
         }
-        __syncthreads();
     }
     if (i < n) {
         double* p = part + (int64_t)blockIdx.y * 7 * npad + i;
-        p[0] = gx; p[npad] = gy; p[2 * npad] = gz;
-        p[3 * npad] = ax; p[4 * npad] = ay; p[5 * npad] = az;
-        if (MASS) p[6 * npad] = gm;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) p[c * npad] = acc[c];
+        if (MASS) p[6 * npad] = acc[6];
     }
 }
 
 // ---------------------------------------------------------------- launchers --
-hipError_t launch_pair_fwd(dnb_ctx* c, int64_t n, const double* x, const double* mass,
-                               double eps, hipStream_t st) {
-    Slicing sl = slicing_for(n);
+hipError_t launch_pair_fwd(dnb_ctx* c, int64_t n, double eps, hipStream_t st) {
+    const Slicing sl = fwd_slicing(c, n);
+    const int nj = (int)pad_sources(n);
     dim3 grid(sl.nblk, sl.S);
     if (c->prec == DNB_FP32C) {
         const float eps2 = (float)(eps * eps);
+        const float4* js = (const float4*)c->js;
         if (eps == 0.0)
-            hipLaunchKernelGGL(k_pair_fwd_f32c<true>, grid, dim3(BS), 0, st, c->js, (int)n,
+            hipLaunchKernelGGL(k_pair_fwd_f32c<true>, grid, dim3(BS), 0, st, js, (int)n, nj,
                                sl.jslice, eps2, (float*)c->part, sl.npad);
         else
-            hipLaunchKernelGGL(k_pair_fwd_f32c<false>, grid, dim3(BS), 0, st, c->js, (int)n,
+            hipLaunchKernelGGL(k_pair_fwd_f32c<false>, grid, dim3(BS), 0, st, js, (int)n, nj,
                                sl.jslice, eps2, (float*)c->part, sl.npad);
     } else {
         const double eps2 = eps * eps;
+        const double4* js = (const double4*)c->js;
         if (eps == 0.0)
-            hipLaunchKernelGGL(k_pair_fwd_f64<true>, grid, dim3(BS), 0, st, x, mass, (int)n,
+            hipLaunchKernelGGL(k_pair_fwd_f64<true>, grid, dim3(BS), 0, st, js, (int)n, nj,
                                sl.jslice, eps2, (double*)c->part, sl.npad);
         else
-            hipLaunchKernelGGL(k_pair_fwd_f64<false>, grid, dim3(BS), 0, st, x, mass, (int)n,
+            hipLaunchKernelGGL(k_pair_fwd_f64<false>, grid, dim3(BS), 0, st, js, (int)n, nj,
                                sl.jslice, eps2, (double*)c->part, sl.npad);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, const double* x, const double* mass,
-                               const double* w, int with_mass, double eps, hipStream_t st) {
-    Slicing sl = slicing_for(n);
+template <bool EPS0, bool MASS>
+static void vjp_dispatch(dnb_ctx* c, const Slicing& sl, int64_t n, int nj, double eps2,
+                         hipStream_t st) {
     dim3 grid(sl.nblk, sl.S);
-    if (c->prec == DNB_FP32C) {
-        const float eps2 = (float)(eps * eps);
-        float* p = (float*)c->partv;
-        if (eps == 0.0) {
-            if (with_mass)
-                hipLaunchKernelGGL((k_pair_vjp_f32c<true, true>), grid, dim3(BS), 0, st, c->jsv,
-                                   (int)n, sl.jslice, eps2, p, sl.npad);
-            else
-                hipLaunchKernelGGL((k_pair_vjp_f32c<true, false>), grid, dim3(BS), 0, st, c->jsv,
-                                   (int)n, sl.jslice, eps2, p, sl.npad);
-        } else {
-            if (with_mass)
-                hipLaunchKernelGGL((k_pair_vjp_f32c<false, true>), grid, dim3(BS), 0, st, c->jsv,
-                                   (int)n, sl.jslice, eps2, p, sl.npad);
-            else
-                hipLaunchKernelGGL((k_pair_vjp_f32c<false, false>), grid, dim3(BS), 0, st,
-                                   c->jsv, (int)n, sl.jslice, eps2, p, sl.npad);
-        }
+    if (c->prec == DNB_FP32C)
+        hipLaunchKernelGGL((k_pair_vjp_f32c<EPS0, MASS>), grid, dim3(BS), 0, st,
+                           (const float4*)c->jsv, (int)n, nj, sl.jslice, (float)eps2,
+                           (float*)c->partv, sl.npad);
+    else
+        hipLaunchKernelGGL((k_pair_vjp_f64<EPS0, MASS>), grid, dim3(BS), 0, st,
+                           (const double4*)c->jsv, (int)n, nj, sl.jslice, eps2,
+                           (double*)c->partv, sl.npad);
+}
+
+hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, int with_mass, double eps, hipStream_t st) {
+    const Slicing sl = vjp_slicing(c, n);
+    const int nj = (int)pad_sources(n);
+    const double eps2 = eps * eps;
+    if (eps == 0.0) {
+        if (with_mass) vjp_dispatch<true, true>(c, sl, n, nj, eps2, st);
+        else vjp_dispatch<true, false>(c, sl, n, nj, eps2, st);
     } else {
-        const double eps2 = eps * eps;
-        double* p = (double*)c->partv;
-        if (eps == 0.0) {
-            if (with_mass)
-                hipLaunchKernelGGL((k_pair_vjp_f64<true, true>), grid, dim3(BS), 0, st, x, mass,
-                                   w, (int)n, sl.jslice, eps2, p, sl.npad);
-            else
-                hipLaunchKernelGGL((k_pair_vjp_f64<true, false>), grid, dim3(BS), 0, st, x, mass,
-                                   w, (int)n, sl.jslice, eps2, p, sl.npad);
-        } else {
-            if (with_mass)
-                hipLaunchKernelGGL((k_pair_vjp_f64<false, true>), grid, dim3(BS), 0, st, x, mass,
-                                   w, (int)n, sl.jslice, eps2, p, sl.npad);
-            else
-                hipLaunchKernelGGL((k_pair_vjp_f64<false, false>), grid, dim3(BS), 0, st, x,
-                                   mass, w, (int)n, sl.jslice, eps2, p, sl.npad);
-        }
+        if (with_mass) vjp_dispatch<false, true>(c, sl, n, nj, eps2, st);
+        else vjp_dispatch<false, false>(c, sl, n, nj, eps2, st);
     }
     return hipGetLastError();
 }

@@ -74,6 +74,18 @@ class Context:
     def _new(self, *shape):
         return torch.empty(*shape, dtype=torch.float64, device=self.device)
 
+    # --------------------------------------------------- instrumentation --
+    def profile(self, enable=True):
+        """Bracket every O(N^2) kernel launch with HIP events (see dnb_profile)."""
+        _lib.check(_lib.lib().dnb_profile(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        """{'fwd_ms', 'fwd_launches', 'vjp_ms', 'vjp_launches'} since the last read."""
+        out = (_lib.ctypes.c_double * 4)()
+        _lib.check(_lib.lib().dnb_profile_read(self._h, out))
+        return dict(fwd_ms=out[0], fwd_launches=int(out[1]), vjp_ms=out[2],
+                    vjp_launches=int(out[3]))
+
     # ------------------------------------------------------------ forward --
     def accelerations(self, pos, mass, pot, with_ext=True, out=None):
         n = mass.shape[0]

@@ -165,9 +165,13 @@ def test_checkpoint_recompute_is_bitwise(dnb, prec):
         tape = c.simulate(px, pv, pm, pot, pk.myr(0.5), 13, ckpt_every=K)
         r = c.simulate_vjp(pm, pot, pk.myr(0.5), 13, K, tape, px, wx)
         outs.append((px.clone(), r[0], r[1], r[3]))
-    for o in outs[1:]:
-        for a, b in zip(outs[0], o):
-            assert torch.equal(a, b)
+    names = ("pos_T", "gpos_0", "gvel_0", "gparams")
+    bad = []
+    for k, o in enumerate(outs[1:]):
+        for name, a, b in zip(names, outs[0], o):
+            if not torch.equal(a, b):
+                bad.append((k, name, (a - b).abs().max().item(), a.abs().max().item()))
+    assert not bad, bad
 
 
 def test_mmd_matches_oracle(dnb):
@@ -229,3 +233,49 @@ def test_place_plummer_and_adjoint(dnb):
     np.testing.assert_allclose(gw.cpu().numpy(), np.concatenate([gp.sum(0), gv.sum(0)]), rtol=1e-12)
     expect = np.sum(gv * zeta) * 0.5 * np.sqrt(G / (0.01 * 3e4)) + gm.sum() / n
     np.testing.assert_allclose(gM.item(), expect, rtol=1e-12)
+
+
+@pytest.mark.parametrize("prec,K", [("fp64", 1), ("fp64", 7), ("fp32c", 1)])
+def test_pipeline_gradient_matches_oracle(dnb, prec, K):
+    """Fig. 2 steps 2-4 end to end: loss and dL/dtheta against the oracle pipeline."""
+    from oracle import pipeline as opipe
+    from paper_2511_22468_amd.pipeline import StreamModel
+    pk, engine, ctx = dnb
+    say(f"[pipeline] n=300 T=30 K={K} prec={prec}")
+    n, T = 300, 30
+    xi, zeta = plummer_unit(n, 31)
+    target = W_X + 0.05 * np.random.default_rng(32).normal(size=(128, 3))
+    theta = np.array([pk.myr(30.0), 3e4, 1.1e12, 6.0e10])
+    L_ref, g = opipe.loss_and_grad(theta, xi, zeta, OPot(), T, target, 0.2)
+    g_ref = np.array([g["t_end"], g["m_prog"], g["m_nfw"], g["m_mn"]])
+    model = StreamModel(ctx[prec], to_dev(xi), to_dev(zeta), to_dev(target), T,
+                        pot=engine.Potential(), ckpt_every=K)
+    L, gg = model.loss_and_grad(torch.tensor(theta, device="cuda"))
+    tol = 1e-8 if prec == "fp64" else 1e-3
+    assert abs(L.item() / L_ref - 1) <= tol
+    np.testing.assert_allclose(gg.cpu().numpy(), g_ref, rtol=tol)
+
+
+def test_autograd_mass_and_initial_condition_gradients(dnb):
+    """Per-particle mass and IC gradients through torch.autograd vs the oracle adjoint."""
+    from paper_2511_22468_amd import autograd as AG
+    pk, engine, ctx = dnb
+    x, v, m = plummer_state(64, 33)
+    op = OPot()
+    dt, T = pk.myr(1.0), 12
+    wx = np.random.default_rng(34).normal(size=x.shape)
+    xT, vT, traj = oint.simulate(x, v, m, op, dt, T, keep=True)
+    ref = oadj.simulate_vjp(traj, m, op, dt, wx, np.zeros_like(wx))
+    px = to_dev(x).requires_grad_(True)
+    pv = to_dev(v).requires_grad_(True)
+    pm = to_dev(m).requires_grad_(True)
+    mn = torch.tensor(op.m_nfw, dtype=torch.float64, device="cuda", requires_grad=True)
+    md = torch.tensor(op.m_mn, dtype=torch.float64, device="cuda", requires_grad=True)
+    tdt = torch.tensor(dt, dtype=torch.float64, device="cuda", requires_grad=True)
+    pT, _ = AG.simulate(ctx["fp64"], px, pv, pm, mn, md, tdt, gpu_pot(engine, op), T, ckpt_every=3)
+    (pT * to_dev(wx)).sum().backward()
+    assert rel_norm(to_host(px.grad), ref["x0"]) <= 1e-10
+    assert rel_norm(to_host(pv.grad), ref["v0"]) <= 1e-10
+    assert rel_norm(pm.grad.cpu().numpy(), ref["mass"]) <= 1e-10
+    for t, k in ((mn, "m_nfw"), (md, "m_mn"), (tdt, "dt")):
+        assert abs(t.grad.item() / ref[k] - 1) <= 1e-10
