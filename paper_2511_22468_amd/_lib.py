@@ -53,6 +53,16 @@ def load_library(path=LIB_PATH):
         "dnb_place_plummer_vjp": ([P, I64, P, D, D, D, P, P, P, P, P, P], I),
         "dnb_profile": ([P, I], I),
         "dnb_profile_read": ([P, ctypes.POINTER(ctypes.c_double)], I),
+        # learned surrogate (include/dnb_surrogate.h)
+        "dnb_mlp_param_count": ([], I64),
+        "dnb_mlp_workspace_bytes": ([I64], I64),
+        "dnb_mlp_to_bf16": ([I64, P, P, P], I),
+        "dnb_mlp_forward": ([P, P, I64, P, P, P, P], I),
+        "dnb_mlp_backward": ([P, I64, P, P, P, P, P], I),
+        "dnb_mlp_mse": ([I64, P, P, P, P, P], I),
+        "dnb_mlp_adam": ([I64, P, P, P, P, P, D, D, D, D, I64, P], I),
+        "dnb_grid_workspace_bytes": ([], I64),
+        "dnb_density_grid": ([I64, P, ctypes.POINTER(ctypes.c_double), P, P, P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

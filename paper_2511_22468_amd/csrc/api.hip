@@ -164,6 +164,8 @@ dnb_status run_forward(dnb_ctx* c, int64_t n, double* pos, double* vel, const do
 
 }  // namespace
 
+void dnb::set_error(const char* msg) { g_err = msg; }
+
 extern "C" {
 
 const char* dnb_last_error(void) { return g_err.c_str(); }

@@ -214,6 +214,9 @@ struct dnb_ctx {
 
 namespace dnb {
 
+// Message returned by dnb_last_error() on this host thread.
+void set_error(const char* msg);
+
 // Geometry of the forward and VJP pair kernels for this context (FP64 uses one
 // target per lane).
 inline Slicing fwd_slicing(const dnb_ctx* c, int64_t n) {

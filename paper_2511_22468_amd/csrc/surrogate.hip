@@ -1,0 +1,409 @@
+// Learned-surrogate kernels: BF16 matrix-core MLP (forward, backward, MSE,
+// Adam) and the orbit-frame density image of a stream.
+//
+// The MLP products use v_mfma_f32_16x16x16_bf16 (BF16 inputs, FP32
+// accumulation).  A 256-thread block computes a 64 x 64 output tile; each of its
+// four waves owns a 32 x 32 quadrant as 2 x 2 MFMA tiles; K advances in steps of
+// 16 through LDS.  Operand strides are arguments, so transposed operands (W^T in
+// the data gradient, X^T in the weight gradient) need no copies.  Tile loads are
+// bounds-checked and zero-filled, so any M, N, K work (the first layer has K = 4).
+// Epilogues fuse the bias, the GELU, and the GELU derivative of the backward
+// pass.  The networks here are small (batch <= 65536, widths <= 2048); these
+// kernels are latency-bound, not MFMA-bound.
+#include <stdint.h>
+#include <cstdio>
+
+#include "dnb_internal.h"
+#include "../../include/dnb_surrogate.h"
+
+namespace dnb {
+
+typedef short mfma_s4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t b = __float_as_uint(f);
+    b += 0x7FFFu + ((b >> 16) & 1u);   // round to nearest, ties to even
+    return (uint16_t)(b >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float gelu_f(float z) {
+    return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad_f(float z) {
+    const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+    const float pdf = expf(-0.5f * z * z) * 0.39894228040143268f;
+    return fmaf(z, pdf, cdf);
+}
+
+enum Epi { EPI_PLAIN = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_BWD = 3 };
+
+// C[M x N] = A[M x K] . B[K x N];  A(m, k) = A[m * sam + k * sak], B(k, n) = B[k * sbk + n * sbn].
+// EPI_PLAIN:     outf = C
+// EPI_BIAS:      outf = C + bias
+// EPI_BIAS_GELU: outf = z = C + bias, outb = bf16(gelu(z))
+// EPI_GELU_BWD:  g = C * gelu'(zin), outf = g, outb = bf16(g)
+// Outputs are row-major with leading dimension ldo.
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K,
+                                                   const uint16_t* __restrict__ A, int64_t sam,
+                                                   int64_t sak, const uint16_t* __restrict__ B,
+                                                   int64_t sbk, int64_t sbn,
+                                                   const float* __restrict__ bias,
+                                                   const float* __restrict__ zin,
+                                                   float* __restrict__ outf,
+                                                   uint16_t* __restrict__ outb, int64_t ldo) {
+    __shared__ uint16_t As[64][16];
+    __shared__ uint16_t Bs[16][64];
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    mfma_f4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+        for (int e = t; e < 1024; e += 256) {
+            const int r = e >> 4, kk = e & 15;
+            const int gm = m0 + r, gk = k0 + kk;
+            As[r][kk] = (gm < M && gk < K) ? A[gm * sam + gk * sak] : (uint16_t)0;
+            const int kb = e >> 6, c = e & 63;
+            const int gk2 = k0 + kb, gn = n0 + c;
+            Bs[kb][c] = (gk2 < K && gn < N) ? B[gk2 * sbk + gn * sbn] : (uint16_t)0;
+        }
+        __syncthreads();
+        const int kq = 4 * (lane >> 4);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int row = wr + i * 16 + (lane & 15);
+            const mfma_s4 a = {(short)As[row][kq], (short)As[row][kq + 1], (short)As[row][kq + 2],
+                               (short)As[row][kq + 3]};
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = wc + j * 16 + (lane & 15);
+                const mfma_s4 b = {(short)Bs[kq][col], (short)Bs[kq + 1][col],
+                                   (short)Bs[kq + 2][col], (short)Bs[kq + 3][col]};
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = m0 + wr + i * 16 + 4 * (lane >> 4) + q;
+                const int col = n0 + wc + j * 16 + (lane & 15);
+                if (row >= M || col >= N) continue;
+                const float c = acc[i][j][q];
+                const int64_t o = (int64_t)row * ldo + col;
+                if (EPI == EPI_PLAIN) {
+                    outf[o] = c;
+                } else if (EPI == EPI_BIAS) {
+                    outf[o] = c + bias[col];
+                } else if (EPI == EPI_BIAS_GELU) {
+                    const float z = c + bias[col];
+                    outf[o] = z;
+                    outb[o] = f2bf(gelu_f(z));
+                } else {
+                    const float g = c * gelu_grad_f(zin[o]);
+                    outf[o] = g;
+                    outb[o] = f2bf(g);
+                }
+            }
+}
+
+template <int EPI>
+static void gemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak,
+                 const uint16_t* B, int64_t sbk, int64_t sbn, const float* bias, const float* zin,
+                 float* outf, uint16_t* outb, int64_t ldo, hipStream_t st) {
+    dim3 grid((unsigned)cdiv(N, 64), (unsigned)cdiv(M, 64));
+    hipLaunchKernelGGL(k_gemm_bf16<EPI>, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk,
+                       sbn, bias, zin, outf, outb, ldo);
+}
+
+__global__ void k_to_bf16(int64_t n, const float* __restrict__ x, uint16_t* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+// Column sums of g [rows][cols] (bias gradient), one thread per column, fixed order.
+__global__ void k_colsum(int rows, int cols, const float* __restrict__ g, float* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    float s = 0.f;
+    for (int r = 0; r < rows; ++r) s += g[(int64_t)r * cols + c];
+    out[c] = s;
+}
+
+__global__ __launch_bounds__(BS) void k_mse(int64_t n, const float* __restrict__ y,
+                                            const float* __restrict__ t, double* __restrict__ loss,
+                                            float* __restrict__ dy) {
+    __shared__ double sh[BS];
+    double s[1] = {0.0};
+    const float sc = (float)(2.0 / (double)n);
+    for (int64_t i = threadIdx.x; i < n; i += BS) {
+        const float d = y[i] - t[i];
+        s[0] += (double)d * (double)d;
+        dy[i] = sc * d;
+    }
+    block_sum<1>(s, sh);
+    if (threadIdx.x == 0) loss[0] = s[0] / (double)n;
+}
+
+__global__ void k_adam(int64_t n, float* __restrict__ p, uint16_t* __restrict__ pb,
+                       float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
+    const float vi = fmaf(b2, v[i], (1.f - b2) * gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    pb[i] = f2bf(pi);
+}
+
+// Network geometry and workspace layout.
+constexpr int NL = 4;
+constexpr int LIN[NL] = {4, 256, 256, 256};
+constexpr int LOUT[NL] = {256, 256, 256, 2048};
+
+inline int64_t w_off(int l) {
+    int64_t o = 0;
+    for (int k = 0; k < l; ++k) o += (int64_t)LIN[k] * LOUT[k] + LOUT[k];
+    return o;
+}
+inline int64_t b_off(int l) { return w_off(l) + (int64_t)LIN[l] * LOUT[l]; }
+inline int64_t param_count() { return w_off(NL); }
+
+struct MlpWs {
+    uint16_t* a[NL];     // layer inputs, BF16 [B][in_l]
+    float* z[NL - 1];    // hidden pre-activations, FP32 [B][out_l]
+    float* g;            // gradient, FP32 [B][2048]
+    uint16_t* gb;        // gradient, BF16 [B][2048]
+    float* h;            // gradient, FP32 [B][256]
+    uint16_t* hb;        // gradient, BF16 [B][256]
+};
+
+inline int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+inline int64_t mlp_ws_layout(int64_t B, char* base, MlpWs* w) {
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) { char* p = base ? base + off : nullptr; off += align256(bytes); return p; };
+    for (int l = 0; l < NL; ++l) { char* p = take(2 * B * LIN[l]); if (w) w->a[l] = (uint16_t*)p; }
+    for (int l = 0; l < NL - 1; ++l) { char* p = take(4 * B * LOUT[l]); if (w) w->z[l] = (float*)p; }
+    char* p;
+    p = take(4 * B * 2048); if (w) w->g = (float*)p;
+    p = take(2 * B * 2048); if (w) w->gb = (uint16_t*)p;
+    p = take(4 * B * 256); if (w) w->h = (float*)p;
+    p = take(2 * B * 256); if (w) w->hb = (uint16_t*)p;
+    return off;
+}
+
+// --------------------------------------------------------------- density grid --
+struct Frame { double e1[3], e2[3], n[3]; };
+
+__global__ void k_grid_count(int64_t n, const double* __restrict__ pos, Frame f,
+                             unsigned int* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = pos[i], y = pos[n + i], z = pos[2 * n + i];
+    const double r = sqrt(x * x + y * y + z * z);
+    const double u = x * f.e1[0] + y * f.e1[1] + z * f.e1[2];
+    const double w = x * f.e2[0] + y * f.e2[1] + z * f.e2[2];
+    const double h = x * f.n[0] + y * f.n[1] + z * f.n[2];
+    const double phi1 = atan2(w, u);
+    const double phi2 = asin(fmin(1.0, fmax(-1.0, h / r)));
+    const double pi = 3.141592653589793;
+    const int i1 = (int)floor((phi1 + pi) / (2.0 * pi) * 64.0);
+    const int i2 = (int)floor((phi2 + 0.1) / 0.2 * 32.0);
+    if (i1 >= 0 && i1 < 64 && i2 >= 0 && i2 < 32) atomicAdd(&cnt[i2 * 64 + i1], 1u);
+}
+
+// One block: blur along phi1 (periodic), then phi2 (zero padded), normalise.
+__global__ __launch_bounds__(BS) void k_grid_blur(const unsigned int* __restrict__ cnt,
+                                                  float* __restrict__ out) {
+    __shared__ double c[2048];
+    __shared__ double t[2048];
+    __shared__ double sh[BS];
+    double k[7], ks = 0.0;
+    for (int d = -3; d <= 3; ++d) { k[d + 3] = exp(-0.5 * d * d); ks += k[d + 3]; }
+    for (int d = 0; d < 7; ++d) k[d] /= ks;
+    for (int e = threadIdx.x; e < 2048; e += BS) c[e] = (double)cnt[e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2048; e += BS) {
+        const int r = e >> 6, col = e & 63;
+        double s = 0.0;
+        for (int d = -3; d <= 3; ++d) s += k[d + 3] * c[r * 64 + ((col - d + 64) & 63)];
+        t[e] = s;
+    }
+    __syncthreads();
+    double v[8];
+    double tot[1] = {0.0};
+    for (int q = 0; q < 8; ++q) {
+        const int e = threadIdx.x + q * BS;
+        const int r = e >> 6, col = e & 63;
+        double s = 0.0;
+        for (int d = -3; d <= 3; ++d) {
+            const int rr = r - d;
+            if (rr >= 0 && rr < 32) s += k[d + 3] * t[rr * 64 + col];
+        }
+        v[q] = s;
+        tot[0] += s;
+    }
+    block_sum<1>(tot, sh);
+    const double inv = tot[0] > 0.0 ? 1.0 / tot[0] : 0.0;
+    for (int q = 0; q < 8; ++q) out[threadIdx.x + q * BS] = (float)(v[q] * inv);
+}
+
+}  // namespace dnb
+
+using namespace dnb;
+
+namespace {
+dnb_status sfail(const char* m) {
+    set_error(m);
+    return DNB_ERR_ARG;
+}
+bool is_dev(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) { (void)hipGetLastError(); return false; }
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+dnb_status hip_status(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return DNB_OK;
+    char msg[256];
+    snprintf(msg, sizeof msg, "%s: %s", what, hipGetErrorString(e));
+    set_error(msg);
+    return DNB_ERR_HIP;
+}
+}  // namespace
+
+extern "C" {
+
+int64_t dnb_mlp_param_count(void) { return param_count(); }
+
+int64_t dnb_mlp_workspace_bytes(int64_t batch) {
+    if (batch < 1) return -1;
+    return mlp_ws_layout(batch, nullptr, nullptr);
+}
+
+dnb_status dnb_mlp_to_bf16(int64_t count, const float* params, uint16_t* params_bf16,
+                           void* stream) {
+    if (count < 1 || !is_dev(params) || !is_dev(params_bf16)) return sfail("dnb_mlp_to_bf16: bad argument");
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)cdiv(count, 256)), dim3(256), 0,
+                       (hipStream_t)stream, count, params, params_bf16);
+    return hip_status("dnb_mlp_to_bf16");
+}
+
+dnb_status dnb_mlp_forward(const float* params, const uint16_t* pb, int64_t B, const float* x,
+                           float* y, void* workspace, void* stream) {
+    if (B < 16 || B > 65536 || B % 16 != 0) return sfail("dnb_mlp_forward: batch must be a multiple of 16 in [16, 65536]");
+    if (!is_dev(params) || !is_dev(pb) || !is_dev(x) || !is_dev(y) || !is_dev(workspace))
+        return sfail("dnb_mlp_forward: every pointer must be device memory");
+    hipStream_t st = (hipStream_t)stream;
+    MlpWs w;
+    mlp_ws_layout(B, (char*)workspace, &w);
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)cdiv(B * 4, 256)), dim3(256), 0, st, B * 4, x,
+                       w.a[0]);
+    for (int l = 0; l < NL; ++l) {
+        const uint16_t* W = pb + w_off(l);
+        const float* bias = params + b_off(l);
+        const int K = LIN[l], N = LOUT[l];
+        if (l < NL - 1)
+            gemm<EPI_BIAS_GELU>((int)B, N, K, w.a[l], K, 1, W, N, 1, bias, nullptr, w.z[l],
+                                w.a[l + 1], N, st);
+        else
+            gemm<EPI_BIAS>((int)B, N, K, w.a[l], K, 1, W, N, 1, bias, nullptr, y, nullptr, N, st);
+    }
+    return hip_status("dnb_mlp_forward");
+}
+
+dnb_status dnb_mlp_backward(const uint16_t* pb, int64_t B, const float* dy, void* workspace,
+                            float* grads, float* dx, void* stream) {
+    if (B < 16 || B > 65536 || B % 16 != 0) return sfail("dnb_mlp_backward: bad batch");
+    if (!is_dev(pb) || !is_dev(dy) || !is_dev(workspace) || !is_dev(grads) || (dx && !is_dev(dx)))
+        return sfail("dnb_mlp_backward: every pointer must be device memory");
+    hipStream_t st = (hipStream_t)stream;
+    MlpWs w;
+    mlp_ws_layout(B, (char*)workspace, &w);
+    // output layer: the incoming cotangent is the gradient of its pre-activation
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)cdiv(B * 2048, 256)), dim3(256), 0, st,
+                       B * 2048, dy, w.gb);
+    const float* gf = dy;            // FP32 gradient of the current layer's pre-activation
+    const uint16_t* gbf = w.gb;      // its BF16 copy
+    for (int l = NL - 1; l >= 0; --l) {
+        const int K = LIN[l], N = LOUT[l];
+        // dW_l = a_l^T . g  (M = K, N = N, inner dimension = batch)
+        gemm<EPI_PLAIN>(K, N, (int)B, w.a[l], 1, K, gbf, N, 1, nullptr, nullptr,
+                        grads + w_off(l), nullptr, N, st);
+        hipLaunchKernelGGL(k_colsum, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, st, (int)B, N,
+                           gf, grads + b_off(l));
+        const uint16_t* W = pb + w_off(l);
+        if (l > 0) {
+            // g_{l-1} = (g . W_l^T) * gelu'(z_{l-1})
+            float* hf = (l % 2 == 1) ? w.h : w.g;
+            uint16_t* hb = (l % 2 == 1) ? w.hb : w.gb;
+            if (l == NL - 1) { hf = w.h; hb = w.hb; }
+            gemm<EPI_GELU_BWD>((int)B, K, N, gbf, N, 1, W, 1, N, nullptr, w.z[l - 1], hf, hb, K,
+                               st);
+            gf = hf;
+            gbf = hb;
+        } else if (dx) {
+            gemm<EPI_PLAIN>((int)B, K, N, gbf, N, 1, W, 1, N, nullptr, nullptr, dx, nullptr, K, st);
+        }
+    }
+    return hip_status("dnb_mlp_backward");
+}
+
+dnb_status dnb_mlp_mse(int64_t count, const float* y, const float* t, double* loss, float* dy,
+                       void* stream) {
+    if (count < 1 || !is_dev(y) || !is_dev(t) || !is_dev(loss) || !is_dev(dy))
+        return sfail("dnb_mlp_mse: bad argument");
+    hipLaunchKernelGGL(k_mse, dim3(1), dim3(BS), 0, (hipStream_t)stream, count, y, t, loss, dy);
+    return hip_status("dnb_mlp_mse");
+}
+
+dnb_status dnb_mlp_adam(int64_t count, float* params, uint16_t* pb, float* m, float* v,
+                        const float* grads, double lr, double beta1, double beta2, double eps,
+                        int64_t t, void* stream) {
+    if (count < 1 || t < 1 || !is_dev(params) || !is_dev(pb) || !is_dev(m) || !is_dev(v) ||
+        !is_dev(grads))
+        return sfail("dnb_mlp_adam: bad argument");
+    const double c1 = 1.0 - pow(beta1, (double)t), c2 = 1.0 - pow(beta2, (double)t);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)cdiv(count, 256)), dim3(256), 0, (hipStream_t)stream,
+                       count, params, pb, m, v, grads, (float)lr, (float)beta1, (float)beta2,
+                       (float)eps, (float)c1, (float)c2);
+    return hip_status("dnb_mlp_adam");
+}
+
+int64_t dnb_grid_workspace_bytes(void) { return 2048 * sizeof(unsigned int); }
+
+dnb_status dnb_density_grid(int64_t n, const double* pos, const double* frame9, float* grid,
+                            void* workspace, void* stream) {
+    if (n < 1 || !frame9 || !is_dev(pos) || !is_dev(grid) || !is_dev(workspace))
+        return sfail("dnb_density_grid: bad argument");
+    Frame f;
+    for (int c = 0; c < 3; ++c) { f.e1[c] = frame9[c]; f.e2[c] = frame9[3 + c]; f.n[c] = frame9[6 + c]; }
+    hipStream_t st = (hipStream_t)stream;
+    unsigned int* cnt = (unsigned int*)workspace;
+    if (hipMemsetAsync(cnt, 0, 2048 * sizeof(unsigned int), st) != hipSuccess)
+        return hip_status("dnb_density_grid: memset");
+    hipLaunchKernelGGL(k_grid_count, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, n, pos, f,
+                       cnt);
+    hipLaunchKernelGGL(k_grid_blur, dim3(1), dim3(BS), 0, st, cnt, grid);
+    return hip_status("dnb_density_grid");
+}
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+"""Time-to-fit: surrogate-warm-started N-body gradient descent against plain descent.
+
+The paper fits Theta = (t_end, M_Plummer, M_NFW, M_MN) by vanilla gradient
+descent on the MMD between simulated and observed streams, with gradients from
+the differentiable N-body run (Sec. 2.2.1, Fig. 2).  Both arms here use that
+same descent, in the normalised coordinates u in [-1, 1]^4 of the surrogate
+(t_end linear, masses logarithmic over the prior box), with a fixed step that
+is halved whenever a step would raise the loss.
+
+plain arm:  from the prior centre u = 0, B iterations; L* = best loss reached.
+warm arm:   invert the surrogate on the target's density image (Adam on u through
+            the network, many starts), then descend from there until L <= L*.
+
+Usage: python -m paper_2511_22468_amd.fit [--quick]   (prints one JSON line)
+"""
+import argparse
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import engine
+from .pipeline import StreamModel, make_target
+from .surrogate import (MLP, PRIOR, denormalise, density_grid, generate_dataset, normalise,
+                        orbit_frame)
+from .units import gyr
+
+W_X, W_V = (12.0, 0.0, 0.0), (0.0, -180.0, 60.0)
+
+
+def theta_internal(u):
+    th = denormalise(u)[0]
+    return np.array([gyr(th[0]), th[1], th[2], th[3]])
+
+
+def dtheta_du(u):
+    """Diagonal Jacobian of theta_internal with respect to u."""
+    th = denormalise(u)[0]
+    d = np.empty(4)
+    d[0] = gyr(1.5)
+    for k in range(1, 4):
+        lo, hi = np.log10(PRIOR[k][0]), np.log10(PRIOR[k][1])
+        d[k] = th[k] * np.log(10.0) * 0.5 * (hi - lo)
+    return d
+
+
+def descend(model, u0, lr, max_iter, stop_loss=None, clock0=None):
+    """Vanilla gradient descent on u with step halving on a rise of the loss."""
+    dev = model.ctx.device
+    clock0 = time.perf_counter() if clock0 is None else clock0
+    u = np.array(u0, float)
+    hist = []
+    L, g = model.loss_and_grad(torch.tensor(theta_internal(u), device=dev))
+    L = L.item()
+    gu = g.cpu().numpy() * dtheta_du(u)
+    hist.append((time.perf_counter() - clock0, L, u.tolist()))
+    it = 0
+    while it < max_iter and not (stop_loss is not None and L <= stop_loss):
+        it += 1
+        cand = np.clip(u - lr * gu, -1.0, 1.0)
+        Lc, gc = model.loss_and_grad(torch.tensor(theta_internal(cand), device=dev))
+        Lc = Lc.item()
+        if Lc <= L:
+            u, L, gu = cand, Lc, gc.cpu().numpy() * dtheta_du(cand)
+        else:
+            lr *= 0.5
+        hist.append((time.perf_counter() - clock0, L, u.tolist()))
+    return u, L, hist
+
+
+def run(quick=False, seed=50):
+    dev = torch.device("cuda", 0)
+    from synth import draw_theta, mlp_init, flatten, plummer_unit
+
+    n_fit, n_train, T = (2048, 1024, 1000) if quick else (8192, 4096, 4000)
+    n_draws = 64 if quick else 512
+    iters = 8 if quick else 20
+    pot = engine.Potential(eps=1e-3)
+    t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device=dev)
+    ctx = engine.Context(max(n_fit, n_train), "fp32c")
+    f9 = orbit_frame(W_X, W_V)
+
+    # held-out target: parameters from the priors (own seed), own IC seed
+    th_star = draw_theta(1, seed + 1)[0]
+    xt, zt = plummer_unit(n_fit, seed + 2)
+    u_star = normalise(th_star)[0]
+    target = make_target(ctx, t3(xt), t3(zt), torch.tensor(theta_internal(u_star), device=dev), T,
+                         pot=pot)
+    target_img = density_grid(target, f9).reshape(-1)
+    xi, zeta = plummer_unit(n_fit, seed + 3)
+    model = StreamModel(ctx, t3(xi), t3(zeta), target, T, pot=pot, h=0.2, ckpt_every=1)
+    model.loss_and_grad(torch.tensor(theta_internal(np.zeros(4)), device=dev))   # warm-up
+    torch.cuda.synchronize()
+
+    # plain arm
+    t0 = time.perf_counter()
+    u_plain, L_star, hist_plain = descend(model, np.zeros(4), 0.5, iters, clock0=t0)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+
+    # surrogate: data from the engine's own runs, then training
+    t0 = time.perf_counter()
+    thetas = draw_theta(n_draws, seed)
+    xs, zs = plummer_unit(n_train, seed + 4)
+    X, Y = generate_dataset(ctx, thetas, t3(xs), t3(zs), T, pot, f9)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net = MLP(flatten(mlp_init(seed + 5)), dev)
+    Ym = Y.mean(dim=0, keepdim=True)
+    losses = net.train(X, (Y - Ym).contiguous() * 100.0, epochs=60 if quick else 300,
+                       batch=64, lr=2e-3, lr_final=2e-4, seed=seed + 6)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    # warm arm: surrogate inversion, then the same descent until L <= L*
+    t0 = time.perf_counter()
+    u_warm, err_w = net.invert(((target_img - Ym.reshape(-1)) * 100.0).contiguous(),
+                               n_starts=64, iters=300, lr=0.05, seed=seed + 7)
+    t_inv = time.perf_counter() - t0
+    u_fit, L_warm, hist_warm = descend(model, u_warm, 0.5, iters, stop_loss=L_star,
+                                       clock0=t0)
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    reached = L_warm <= L_star
+    out = {
+        "metric": "time-to-fit: surrogate warm start vs plain N-body gradient descent",
+        "n_fit": n_fit, "n_steps": T, "n_train_runs": n_draws, "n_train_particles": n_train,
+        "theta_star": th_star.tolist(),
+        "plain": {"seconds": t_plain, "iterations": len(hist_plain) - 1, "L_star": L_star,
+                  "u": u_plain.tolist(), "loss_curve": [h[1] for h in hist_plain]},
+        "warm": {"seconds": t_warm, "inversion_seconds": t_inv,
+                 "iterations": len(hist_warm) - 1, "loss": L_warm, "reached_L_star": reached,
+                 "u_surrogate": u_warm.tolist(), "u": u_fit.tolist(),
+                 "loss_curve": [h[1] for h in hist_warm]},
+        "surrogate": {"data_seconds": t_data, "train_seconds": t_train,
+                      "train_loss_first_last": [losses[0], losses[-1]],
+                      "inversion_image_mse": err_w},
+        "u_star": u_star.tolist(),
+        "speedup_excl_training": t_plain / t_warm if reached else None,
+        "speedup_incl_training": (t_plain / (t_warm + t_data + t_train)) if reached else None,
+    }
+    ctx.close()
+    return out
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true")
+    a = ap.parse_args()
+    print(json.dumps(run(a.quick)), flush=True)

@@ -8,3 +8,4 @@ of the computation they are compared on.
 """
 from .plummer import plummer_unit, random_directions, sample_rows  # noqa: F401
 from .priors import draw_theta, PRIOR_BOUNDS  # noqa: F401
+from .weights import mlp_init, flatten, unflatten  # noqa: F401

@@ -1,0 +1,96 @@
+"""GPU parity of the surrogate kernels (BF16 MFMA MLP, MSE, Adam, density grid)
+against the FP64 oracle with BF16 rounding emulated at the same points."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import surrogate as S
+from synth import flatten, mlp_init, unflatten
+
+from gpu_util import rel_norm, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _mlp(seed=0):
+    from paper_2511_22468_amd.surrogate import MLP
+    params = mlp_init(seed)
+    # non-zero biases so that the bias paths are exercised
+    rng = np.random.default_rng(seed + 100)
+    params = [(W, rng.normal(scale=0.1, size=b.shape).astype(np.float32)) for W, b in params]
+    return params, MLP(flatten(params), torch.device("cuda"))
+
+
+@pytest.mark.parametrize("B", [16, 80])
+def test_mlp_forward_backward_match_oracle(B):
+    say(f"[mlp] forward/backward B={B}")
+    params, net = _mlp(1)
+    rng = np.random.default_rng(2)
+    X = rng.uniform(-1, 1, size=(B, 4)).astype(np.float32)
+    T = rng.normal(scale=0.01, size=(B, 2048)).astype(np.float32)
+    P64 = [(W.astype(np.float64), b.astype(np.float64)) for W, b in params]
+    Y_ref, cache = S.forward(P64, X.astype(np.float64))
+    L_ref, dY_ref = S.mse(Y_ref, T)
+    grads_ref, dX_ref = S.backward(P64, cache, dY_ref)
+
+    x = torch.tensor(X, device="cuda")
+    y = net.forward(x)
+    loss, dy = net.mse(y, torch.tensor(T, device="cuda"))
+    dx = net.backward(dy, want_dx=True)
+    Y = y.cpu().numpy()
+    assert rel_norm(Y, Y_ref) <= 2e-3, rel_norm(Y, Y_ref)
+    assert abs(loss.item() / L_ref - 1) <= 5e-3
+    g = unflatten(net.grads.cpu().numpy())
+    for li, ((gW, gb), (rW, rb)) in enumerate(zip(g, grads_ref)):
+        eW, eb = rel_norm(gW, rW), rel_norm(gb, rb)
+        say(f"  layer {li}: dW rel {eW:.2e}  db rel {eb:.2e}")
+        assert eW <= 1e-2 and eb <= 1e-2
+    assert rel_norm(dx.cpu().numpy(), dX_ref) <= 1e-2
+
+
+def test_adam_step_matches_oracle():
+    params, net = _mlp(3)
+    rng = np.random.default_rng(4)
+    P64 = [(W.astype(np.float64), b.astype(np.float64)) for W, b in params]
+    state = [tuple(np.zeros_like(a) for a in (W, W, b, b)) for W, b in P64]
+    for t in range(1, 4):
+        grads = [(rng.normal(size=W.shape), rng.normal(size=b.shape)) for W, b in P64]
+        P64 = S.adam(P64, grads, state, 1e-3, t)
+        net.grads.copy_(torch.tensor(flatten([(a.astype(np.float32), c.astype(np.float32))
+                                              for a, c in grads])))
+        net.adam(1e-3)
+    got = net.p.cpu().numpy().astype(np.float64)
+    ref = flatten([(W.astype(np.float32), b.astype(np.float32)) for W, b in P64]).astype(np.float64)
+    assert np.abs(got - ref).max() <= 1e-6
+    # the BF16 copy is the rounded master
+    pb = net.pb.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    np.testing.assert_array_equal(pb.view(np.float32).astype(np.float64), S.bf16(got))
+
+
+def test_density_grid_matches_oracle():
+    from paper_2511_22468_amd.surrogate import density_grid, orbit_frame
+    rng = np.random.default_rng(5)
+    e1, e2, n = S.frame((12.0, 0, 0), (0, -180.0, 60.0))
+    phi1 = rng.uniform(-np.pi, np.pi, 6000)
+    phi2 = rng.normal(scale=0.05, size=6000)
+    r = rng.uniform(5, 30, 6000)
+    pos = (r[:, None] * (np.cos(phi2)[:, None] * (np.cos(phi1)[:, None] * e1 + np.sin(phi1)[:, None] * e2)
+                         + np.sin(phi2)[:, None] * n))
+    ref = S.density_grid(pos, (12.0, 0, 0), (0, -180.0, 60.0))
+    f9 = orbit_frame((12.0, 0, 0), (0, -180.0, 60.0))
+    got = density_grid(torch.tensor(np.ascontiguousarray(pos.T), device="cuda"), f9).cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-7 * max(1.0, ref.max()) + 1e-9
+    # nothing inside: all zeros
+    far = torch.tensor(np.ascontiguousarray(np.array([[0.0, 0.0, 10.0]]).T), device="cuda")
+    assert float(density_grid(far, f9).abs().sum().item()) == 0.0
+
+
+def test_training_reduces_loss():
+    _, net = _mlp(6)
+    rng = np.random.default_rng(7)
+    X = torch.tensor(rng.uniform(-1, 1, size=(256, 4)), dtype=torch.float32, device="cuda")
+    # smooth synthetic target images
+    Y = torch.sin(X[:, :1] * 3 + torch.linspace(0, 6, 2048, device="cuda")[None]) * 0.01
+    losses = net.train(X, Y.contiguous(), epochs=30, batch=64, lr=1e-3)
+    say(f"[mlp] training loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    assert losses[-1] < 0.2 * losses[0]
