@@ -50,8 +50,8 @@ def cpu_baseline(n, t_end_steps, seed, budget_s=15.0):
     m = np.full(n, 1e5 / n)
     w = random_directions(n, seed + 1)
     cores = min(len(os.sched_getaffinity(0)), 16)
-    rows_f = sample_rows(n, 2048, seed + 2)
-    rows_v = sample_rows(n, 512, seed + 3)
+    rows_f = sample_rows(n, min(n, 32768), seed + 2)
+    rows_v = sample_rows(n, min(n, 8192), seed + 3)
 
     def run(fn, rows):
         chunks = np.array_split(rows, cores * 2)
