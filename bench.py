@@ -85,7 +85,13 @@ def main():
     ap.add_argument("--ckpt-every", type=int, default=1)
     ap.add_argument("--prec", default="fp32c", choices=["fp32c", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="short run for hardware counters: one step of 20 KDK steps at the "
+                         "same N, plus a 256 MiB device copy that calibrates FETCH_SIZE and "
+                         "WRITE_SIZE")
     args = ap.parse_args()
+    if args.profile_run:
+        args.n_steps, args.steps, args.warmup, args.no_cpu_baseline = 20, 1, 0, True
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -190,6 +196,13 @@ def main():
         "cpu_baseline": None,
     }
     ctx.close()
+    if args.profile_run:
+        # calibration for the traffic counters: a plain copy of 256 MiB
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, T, 40)
     print(json.dumps(out), flush=True)
