@@ -201,6 +201,7 @@ dnb_status dnb_create(dnb_ctx** out, int64_t max_n, dnb_prec prec) {
         {&c->jsv, sizeof(double4) * 2 * npadmax},
         {&c->partv, 64 * (size_t)c->slice_rows},
         {(void**)&c->cpartv, sizeof(double) * 8 * c->nbmax},
+        {(void**)&c->wscale, sizeof(double) * 2},
         {(void**)&c->red, sizeof(double) * 8 * (c->nbmax + 8)},
     };
     for (auto& a : allocs) {
@@ -223,7 +224,7 @@ void dnb_destroy(dnb_ctx* c) {
             for (hipEvent_t e : *v) (void)hipEventDestroy(e);
         delete pf;
     }
-    void* ps[] = {c->js, c->part, c->cpart, c->vh, c->jsv, c->partv, c->cpartv, c->red};
+    void* ps[] = {c->js, c->part, c->cpart, c->vh, c->jsv, c->partv, c->cpartv, c->wscale, c->red};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     delete c;
@@ -354,9 +355,10 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
         };
         double* cpv[2] = {c->cpartv, c->cpartv + 4 * c->nbmax};
         int q = 0;
-        if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(pos_T, n, cpv[0], st));
-        HIP_TRY(launch_rev_stage(c, n, pos_T, mass, lv, cpv[0], nb, cpv[1], st));
+        if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(pos_T, n, cpv[0], st, lv));
+        HIP_TRY(launch_rev_stage(c, n, pos_T, mass, lv, cpv[0], nb, cpv[1], c->wscale, st));
         q = 1;
+        int wq = 0;   // c->wscale[wq]: scale of the currently staged cotangent
         int64_t cur = -1;
         for (int64_t m = T; m >= 0; --m) {
             if (m > 0) {
@@ -375,8 +377,10 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
             r.x_prev = m > 0 ? get_pos(m - 1) : nullptr;
             r.lx = lx; r.lv = lv; r.accum = accum; r.with_mass = with_mass;
             r.cpart_in = cpv[q]; r.nb_in = nb; r.cpart_out = cpv[1 - q];
+            r.wscale_in = c->wscale + wq; r.wscale_out = c->wscale + (1 - wq);
             HIP_TRY(launch_rev_kick(c, r, st));
             q = 1 - q;
+            wq = 1 - wq;
         }
     }
     HIP_TRY(launch_reduce_accum(accum, n, 4, gparams, c->red, st));

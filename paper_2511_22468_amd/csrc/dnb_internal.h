@@ -208,6 +208,7 @@ struct dnb_ctx {
                              // [2 j] = (x, y, z, m), [2 j + 1] = (w, 0); float4 or double4
     void* partv;             // VJP partials: FP32C float [S][14][npad], FP64 double [S][7][npad]
     double* cpartv;          // [2][nbmax][4]
+    double* wscale;          // [2] cotangent staging scales of the reverse sweep
     double* red;             // [nbmax][8] reduction scratch
     void* prof;              // host-side event pool of dnb_profile (null when off)
 };
@@ -255,7 +256,10 @@ struct FwdArgs {
     const double* centre_override;   // if non-null: centre to stage x_out with
 };
 
-hipError_t launch_block_sums(const double* x, int64_t n, double* cpart, hipStream_t st);
+// Block sums of x into cpart[b][0..2]; with w non-null also the block maximum of
+// |w| components into cpart[b][3] (the cotangent scale of the reverse sweep).
+hipError_t launch_block_sums(const double* x, int64_t n, double* cpart, hipStream_t st,
+                             const double* w = nullptr);
 // Stage x (and mass) into ctx->js: FP32C relative to the centre (from the block
 // sums cpart over nb blocks, or centre_override), FP64 as absolute positions.
 // Pads the tail to pad_sources(n).  centre_out (nullable) receives the centre.
@@ -278,11 +282,13 @@ struct RevArgs {
     double* accum;          // [5][n] per-particle running sums: m_nfw, m_mn, dt, mass scale, mass
     int with_mass;
     const double* cpart_in; int nb_in; double* cpart_out;
+    const double* wscale_in;   // scale the consumed cotangent was staged with (FP32C)
+    double* wscale_out;        // scale of the cotangent staged by this kernel (FP32C)
 };
 
 hipError_t launch_rev_stage(dnb_ctx* c, int64_t n, const double* x, const double* mass,
                             const double* w, const double* cpart, int nb, double* cpart_out,
-                            hipStream_t st);
+                            double* wscale_out, hipStream_t st);
 hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, int with_mass, double eps, hipStream_t st);
 hipError_t launch_rev_kick(dnb_ctx* c, const RevArgs& a, hipStream_t st);
 hipError_t launch_reduce_accum(const double* accum, int64_t n, int nterms, double* out,

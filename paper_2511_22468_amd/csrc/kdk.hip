@@ -55,6 +55,46 @@ __device__ inline void write_block_sums(double x, double y, double z, bool valid
     }
 }
 
+// Cotangent scaling (FP32C reverse sweep).  Over long horizons the velocity
+// cotangent of a chaotic system grows without bound (1e45 after 2000 steps is
+// typical) and would overflow FP32.  The cotangent is therefore staged as w * S
+// with S a power of two (exact) chosen so that max |w S| is about 1; the pair VJP
+// is linear in w, so the consumer divides the slice sums by S in FP64.  S is
+// taken from the block maxima of the previous cotangent (slot 3 of the
+// block-sum records), which differs from the staged one by one drift update.
+__device__ inline double absmax3(double a, double b, double c) {
+    return fmax(fabs(a), fmax(fabs(b), fabs(c)));
+}
+
+__device__ inline void write_block_max(double v, double* sh, double* __restrict__ cpart_out) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = BS / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cpart_out[4 * blockIdx.x + 3] = sh[0];
+    __syncthreads();
+}
+
+// Power-of-two scale from the block maxima in slot 3 of cpart (1 if all zero).
+__device__ inline double scale_from(const double* __restrict__ cpart, int nb, double* sh) {
+    double m = 0.0;
+    for (int b = threadIdx.x; b < nb; b += BS) m = fmax(m, cpart[4 * b + 3]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = BS / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    m = sh[0];
+    __syncthreads();
+    if (!(m > 0.0) || !isfinite(m)) return 1.0;
+    int e;
+    (void)frexp(m, &e);
+    return ldexp(1.0, -e);
+}
+
 // Source record of particle i (i < n) or padding (n <= i < pad_sources(n)).
 template <bool F32>
 __device__ inline void put_source(void* js, int64_t i, bool real, double x, double y, double z,
@@ -85,12 +125,14 @@ __device__ inline void put_source_w(void* jsv, int64_t i, bool real, double x, d
 }
 
 __global__ __launch_bounds__(BS) void k_block_sums(const double* __restrict__ x, int64_t n,
-                                                   double* __restrict__ cpart) {
+                                                   double* __restrict__ cpart,
+                                                   const double* __restrict__ w) {
     __shared__ double sh[3 * BS];
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
     const bool ok = i < n;
     const int64_t k = ok ? i : 0;
     write_block_sums(x[k], x[n + k], x[2 * n + k], ok, sh, cpart);
+    if (w) write_block_max(ok ? absmax3(w[k], w[n + k], w[2 * n + k]) : 0.0, sh, cpart);
 }
 
 template <bool F32>
@@ -207,8 +249,9 @@ __global__ __launch_bounds__(BS) void k_kdk(FwdArgs a, const void* __restrict__ 
 // Blocks of an O(N) kernel that also writes the padded source array.
 static inline unsigned onblocks(int64_t n) { return (unsigned)cdiv(pad_sources(n), BS); }
 
-hipError_t launch_block_sums(const double* x, int64_t n, double* cpart, hipStream_t st) {
-    hipLaunchKernelGGL(k_block_sums, dim3((unsigned)cdiv(n, BS)), dim3(BS), 0, st, x, n, cpart);
+hipError_t launch_block_sums(const double* x, int64_t n, double* cpart, hipStream_t st,
+                             const double* w) {
+    hipLaunchKernelGGL(k_block_sums, dim3((unsigned)cdiv(n, BS)), dim3(BS), 0, st, x, n, cpart, w);
     return hipGetLastError();
 }
 
@@ -256,17 +299,27 @@ __global__ __launch_bounds__(BS) void k_rev_stage(const double* __restrict__ x,
                                                   const double* __restrict__ w, int64_t n,
                                                   int64_t nj, const double* __restrict__ cpart,
                                                   int nb, void* __restrict__ jsv,
-                                                  double* __restrict__ cpart_out) {
+                                                  double* __restrict__ cpart_out,
+                                                  double* __restrict__ wscale_out) {
     __shared__ double sh[3 * BS];
     double cx = 0.0, cy = 0.0, cz = 0.0;
-    if (F32) centre_from(cpart, nb, n, sh, cx, cy, cz);
+    double S = 1.0;
+    if (F32) {
+        centre_from(cpart, nb, n, sh, cx, cy, cz);
+        S = scale_from(cpart, nb, sh);
+    }
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
     const bool ok = i < n;
     const int64_t k = ok ? i : 0;
     const double x0 = x[k], y0 = x[n + k], z0 = x[2 * n + k];
+    const double wx = w[k], wy = w[n + k], wz = w[2 * n + k];
     if (i < nj)
-        put_source_w<F32>(jsv, i, ok, x0, y0, z0, mass[k], cx, cy, cz, w[k], w[n + k], w[2 * n + k]);
-    if (F32) write_block_sums(x0, y0, z0, ok, sh, cpart_out);
+        put_source_w<F32>(jsv, i, ok, x0, y0, z0, mass[k], cx, cy, cz, wx * S, wy * S, wz * S);
+    if (F32) {
+        write_block_sums(x0, y0, z0, ok, sh, cpart_out);
+        write_block_max(ok ? absmax3(wx, wy, wz) : 0.0, sh, cpart_out);
+        if (blockIdx.x == 0 && threadIdx.x == 0) wscale_out[0] = S;
+    }
 }
 
 // Slice sums of the VJP kernel for particle i: J^T w, a_int (both times G) and the
@@ -317,6 +370,12 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
 
     double g[3], ai[3], gm;
     vjp_sum<F32>(part, S, npad, k, a.pot.G, a.with_mass != 0, g, ai, gm);
+    if (F32) {
+        // undo the power-of-two scale the consumed cotangent was staged with
+        const double inv_s = 1.0 / a.wscale_in[0];
+        g[0] *= inv_s; g[1] *= inv_s; g[2] *= inv_s;
+        gm *= inv_s;
+    }
     const double x = a.x_n[k], y = a.x_n[n + k], z = a.x_n[2 * n + k];
     const double wx = a.lv[k], wy = a.lv[n + k], wz = a.lv[2 * n + k];
     Ext e = ext_accel(a.pot, x, y, z);
@@ -353,22 +412,28 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
         if (drift) { a.lv[i] = nwx; a.lv[n + i] = nwy; a.lv[2 * n + i] = nwz; }
     }
     if (drift) {
+        const double Sn = F32 ? scale_from(a.cpart_in, a.nb_in, sh) : 1.0;
         if (i < nj)
-            put_source_w<F32>(jsv, i, ok, px, py, pz, a.mass[k], cx, cy, cz, nwx, nwy, nwz);
-        if (F32) write_block_sums(px, py, pz, ok, sh, a.cpart_out);
+            put_source_w<F32>(jsv, i, ok, px, py, pz, a.mass[k], cx, cy, cz, nwx * Sn, nwy * Sn,
+                              nwz * Sn);
+        if (F32) {
+            write_block_sums(px, py, pz, ok, sh, a.cpart_out);
+            write_block_max(ok ? absmax3(nwx, nwy, nwz) : 0.0, sh, a.cpart_out);
+            if (blockIdx.x == 0 && threadIdx.x == 0) a.wscale_out[0] = Sn;
+        }
     }
 }
 
 hipError_t launch_rev_stage(dnb_ctx* c, int64_t n, const double* x, const double* mass,
                             const double* w, const double* cpart, int nb, double* cpart_out,
-                            hipStream_t st) {
+                            double* wscale_out, hipStream_t st) {
     const int64_t nj = pad_sources(n);
     if (c->prec == DNB_FP32C)
         hipLaunchKernelGGL(k_rev_stage<true>, dim3(onblocks(n)), dim3(BS), 0, st, x, mass, w, n,
-                           nj, cpart, nb, c->jsv, cpart_out);
+                           nj, cpart, nb, c->jsv, cpart_out, wscale_out);
     else
         hipLaunchKernelGGL(k_rev_stage<false>, dim3(onblocks(n)), dim3(BS), 0, st, x, mass, w, n,
-                           nj, cpart, nb, c->jsv, cpart_out);
+                           nj, cpart, nb, c->jsv, cpart_out, wscale_out);
     return hipGetLastError();
 }
 
