@@ -34,6 +34,26 @@ PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak
 FLOPS_FWD = 20                    # per pair interaction, conventional count
 FLOPS_VJP = 41                    # per pair of the vector-Jacobian product
 
+# HBM bytes per launch from the two rocprofv3 counter passes recorded in
+# profiles/pair_kernels_n65536_traffic.md (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the
+# factors measured on a 256 MiB copy), valid only for the kernel source they were
+# measured on (sha256 prefix of pair.hip) and for N = 65536.
+TRAFFIC_SRC_SHA = "115cc9bbaaff8482"
+TRAFFIC_N = 65536
+TRAFFIC_KIB = {"k_pair_fwd_f32c": (7698.1, 49152.0), "k_pair_vjp_f32c": (15397.2, 98304.0)}
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
+
+
+def measured_traffic(kernel, n):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2511_22468_amd", "csrc", "pair.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    if sha != TRAFFIC_SRC_SHA or n != TRAFFIC_N or kernel not in TRAFFIC_KIB:
+        return None
+    fetch, write = TRAFFIC_KIB[kernel]
+    return (fetch * FETCH_FACTOR + write * WRITE_FACTOR) * 1024.0
+
 
 def cpu_baseline(n, t_end_steps, seed, budget_s=15.0):
     """Time the oracle's pair sum and pair VJP on sampled target rows."""
@@ -176,7 +196,9 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": vjp_tf / PEAK_FP32_TFLOPS,
-            "traffic": None,
+            "traffic": (measured_traffic("k_pair_vjp_f32c", n) if args.prec == "fp32c"
+                        else None),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE)",
             "flops_per_pair": FLOPS_VJP,
             "avg_launch_ms": vjp_ms,
             "launches": prof["vjp_launches"],
@@ -192,6 +214,8 @@ def main():
             "avg_launch_ms": fwd_ms,
             "launches": prof["fwd_launches"],
             "pairs_per_s": float(n) * n / (fwd_ms * 1e-3),
+            "traffic": (measured_traffic("k_pair_fwd_f32c", n) if args.prec == "fp32c"
+                        else None),
         },
         "cpu_baseline": None,
     }
