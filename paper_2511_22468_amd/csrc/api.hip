@@ -144,6 +144,7 @@ dnb_status run_forward(dnb_ctx* c, int64_t n, double* pos, double* vel, const do
     if (T == 0) return DNB_OK;
     const int nb = (int)cdiv(n, BS);
     double* cp[2] = {c->cpart, c->cpart + 4 * c->nbmax};
+    HIP_TRY(launch_mass_info(c, mass, n, st));
     if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(pos, n, cp[0], st));
     HIP_TRY(launch_stage(c, pos, mass, n, cp[0], nb, nullptr, tape ? tape->centre(0) : nullptr, st));
     int q = 0;
@@ -202,6 +203,7 @@ dnb_status dnb_create(dnb_ctx** out, int64_t max_n, dnb_prec prec) {
         {&c->partv, 64 * (size_t)c->slice_rows},
         {(void**)&c->cpartv, sizeof(double) * 8 * c->nbmax},
         {(void**)&c->wscale, sizeof(double) * 2},
+        {(void**)&c->muni, sizeof(float) * 4},
         {(void**)&c->red, sizeof(double) * 8 * (c->nbmax + 8)},
     };
     for (auto& a : allocs) {
@@ -224,7 +226,8 @@ void dnb_destroy(dnb_ctx* c) {
             for (hipEvent_t e : *v) (void)hipEventDestroy(e);
         delete pf;
     }
-    void* ps[] = {c->js, c->part, c->cpart, c->vh, c->jsv, c->partv, c->cpartv, c->wscale, c->red};
+    void* ps[] = {c->js, c->part, c->cpart, c->vh, c->jsv, c->partv, c->cpartv, c->wscale, c->muni,
+                  c->red};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     delete c;
@@ -242,6 +245,7 @@ dnb_status dnb_accelerations(dnb_ctx* c, int64_t n, const double* pos, const dou
     hipStream_t st = (hipStream_t)stream;
     Pot p = to_pot(*pot);
     const int nb = (int)cdiv(n, BS);
+    HIP_TRY(launch_mass_info(c, mass, n, st));
     if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(pos, n, c->cpart, st));
     HIP_TRY(launch_stage(c, pos, mass, n, c->cpart, nb, nullptr, nullptr, st));
     HIP_TRY(profiled(c, 0, st, [&] { return launch_pair_fwd(c, n, p.eps, st); }));
@@ -323,6 +327,7 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
     if (gvel_T) HIP_TRY(hipMemcpyAsync(lv, gvel_T, vec, hipMemcpyDeviceToDevice, st));
     else HIP_TRY(hipMemsetAsync(lv, 0, vec, st));
     HIP_TRY(hipMemsetAsync(accum, 0, sizeof(double) * 5 * n, st));
+    HIP_TRY(launch_mass_info(c, mass, n, st));
     const int with_mass = gmass != nullptr;
     if (T > 0) {
         Tape tp{const_cast<double*>(tape), n, cdiv(T, K)};

@@ -209,6 +209,7 @@ struct dnb_ctx {
     void* partv;             // VJP partials: FP32C float [S][14][npad], FP64 double [S][7][npad]
     double* cpartv;          // [2][nbmax][4]
     double* wscale;          // [2] cotangent staging scales of the reverse sweep
+    float* muni;             // [2] (flag, m): all particle masses equal m (FP32C fast path)
     double* red;             // [nbmax][8] reduction scratch
     void* prof;              // host-side event pool of dnb_profile (null when off)
 };
@@ -267,6 +268,8 @@ hipError_t launch_stage(dnb_ctx* c, const double* x, const double* mass, int64_t
                         const double* cpart, int nb, const double* centre_override,
                         double* centre_out, hipStream_t st);
 hipError_t launch_pair_fwd(dnb_ctx* c, int64_t n, double eps, hipStream_t st);
+// Sets c->muni = (1, m) if all n masses equal m, else (0, 0); one block.
+hipError_t launch_mass_info(dnb_ctx* c, const double* mass, int64_t n, hipStream_t st);
 hipError_t launch_kdk(dnb_ctx* c, KdkMode mode, const FwdArgs& a, hipStream_t st);
 
 struct RevArgs {

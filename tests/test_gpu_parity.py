@@ -122,10 +122,13 @@ def test_simulate_short_horizon(dnb, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
 @pytest.mark.parametrize("K", [1, 4])
-def test_adjoint_matches_oracle(dnb, prec, K):
+@pytest.mark.parametrize("masses", ["equal", "unequal"])
+def test_adjoint_matches_oracle(dnb, prec, K, masses):
     pk, engine, ctx = dnb
-    say(f"[vjp] n=40 T=10 K={K} prec={prec}")
+    say(f"[vjp] n=40 T=10 K={K} prec={prec} masses={masses}")
     x, v, m = plummer_state(40, 7)
+    if masses == "unequal":   # the general pair path; equal masses take the fast path
+        m = m * np.random.default_rng(9).uniform(0.5, 1.5, m.shape)
     rng = np.random.default_rng(8)
     wx, wv = rng.normal(size=x.shape), rng.normal(size=x.shape)
     op = OPot()
