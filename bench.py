@@ -95,6 +95,48 @@ def cpu_baseline(n, t_end_steps, seed, budget_s=15.0):
     }
 
 
+def sweep(prec, sizes=(1024, 4096, 8192, 16384, 65536), reps=20):
+    """Average launch time of the two O(N^2) kernels at each size (HIP events around
+    every launch), on a Plummer sphere placed at the present-day point."""
+    import torch
+
+    from paper_2511_22468_amd import engine, myr
+    from synth import plummer_unit, random_directions
+
+    dev = torch.device("cuda", 0)
+    G = 4.3009e-6
+    rows = []
+    for n in sizes:
+        xi, zeta = plummer_unit(n, 7)
+        x = torch.tensor(np.ascontiguousarray((np.array([12.0, 0, 0]) + 0.01 * xi).T), device=dev)
+        v = torch.tensor(np.ascontiguousarray((np.array([0, -180.0, 60.0])
+                                               + np.sqrt(G * 1e5 / 0.01) * zeta).T), device=dev)
+        m = torch.full((n,), 1e5 / n, dtype=torch.float64, device=dev)
+        w = torch.tensor(np.ascontiguousarray(random_directions(n, 8).T), device=dev)
+        pot = engine.Potential(eps=5e-4 if n >= 65536 else 1e-3)
+        ctx = engine.Context(n, prec)
+        T = max(4, reps // 2)
+        for _ in range(2):     # warm-up, then a profiled pass
+            ctx.profile(True)
+            ctx.profile_read()
+            for _ in range(reps):
+                ctx.accelerations(x, m, pot)
+            xx, vv = x.clone(), v.clone()
+            tape = ctx.simulate(xx, vv, m, pot, myr(0.5), T, ckpt_every=1)
+            ctx.simulate_vjp(m, pot, myr(0.5), T, 1, tape, xx, w)
+            torch.cuda.synchronize()
+            p = ctx.profile_read()
+        ctx.close()
+        f_ms = p["fwd_ms"] / p["fwd_launches"]
+        v_ms = p["vjp_ms"] / p["vjp_launches"]
+        rows.append({"n": n, "fwd_us": f_ms * 1e3, "vjp_us": v_ms * 1e3,
+                     "fwd_pairs_per_s": n * n / (f_ms * 1e-3),
+                     "vjp_pairs_per_s": n * n / (v_ms * 1e-3),
+                     "fwd_frac_of_157.3TF": FLOPS_FWD * n * n / (f_ms * 1e-3) / 157.3e12,
+                     "vjp_frac_of_157.3TF": FLOPS_VJP * n * n / (v_ms * 1e-3) / 157.3e12})
+    return {"sweep": rows, "prec": prec}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,7 +151,15 @@ def main():
                     help="short run for hardware counters: one step of 20 KDK steps at the "
                          "same N, plus a 256 MiB device copy that calibrates FETCH_SIZE and "
                          "WRITE_SIZE")
+    ap.add_argument("--sweep", action="store_true",
+                    help="kernel rates of the forward and VJP pair kernels at every workload "
+                         "size (N = 1024 ... 65536), one JSON line")
     args = ap.parse_args()
+    if args.sweep:
+        if args.gpus != 1:
+            sys.exit(2)
+        print(json.dumps(sweep(args.prec)), flush=True)
+        return
     if args.profile_run:
         args.n_steps, args.steps, args.warmup, args.no_cpu_baseline = 20, 1, 0, True
     if args.gpus != 1:
