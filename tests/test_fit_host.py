@@ -1,0 +1,31 @@
+"""CPU checks of the host-side parameter maps used by the surrogate and the fit."""
+import numpy as np
+
+from oracle import surrogate as S
+from synth import draw_theta
+
+
+def test_normalisation_matches_oracle_and_inverts():
+    from paper_2511_22468_amd import surrogate as P
+    th = draw_theta(50, 3)
+    np.testing.assert_allclose(P.normalise(th), S.normalise_theta(th), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(P.denormalise(P.normalise(th)), th, rtol=1e-12)
+
+
+def test_theta_jacobian_matches_finite_differences():
+    from paper_2511_22468_amd import fit
+    u = np.array([0.3, -0.4, 0.1, 0.7])
+    J = fit.dtheta_du(u[None])
+    for k in range(4):
+        e = np.zeros(4)
+        e[k] = 1e-6
+        fd = (fit.theta_internal((u + e)[None]) - fit.theta_internal((u - e)[None])) / 2e-6
+        np.testing.assert_allclose(fd[k], J[k], rtol=1e-7)
+        assert np.all(np.delete(fd, k) == 0)
+
+
+def test_orbit_frame_matches_oracle():
+    from paper_2511_22468_amd.surrogate import orbit_frame
+    e1, e2, n = S.frame((12.0, 0, 0), (0, -180.0, 60.0))
+    np.testing.assert_allclose(orbit_frame((12.0, 0, 0), (0, -180.0, 60.0)),
+                               np.concatenate([e1, e2, n]), atol=1e-15)
