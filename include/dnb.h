@@ -179,6 +179,31 @@ dnb_status dnb_place_plummer_vjp(dnb_ctx* ctx, int64_t n, const double* zeta, do
                                  double a_p, double G, const double* gpos, const double* gvel,
                                  const double* gmass, double* gw, double* gm_tot, void* stream);
 
+/* ------------------------------------------------------ batched ensembles ---
+ * Many independent systems of the same size advanced together (Sec. 2: running
+ * many simulations at once by vectorising over them, which is how training sets
+ * for the surrogate and parameter grids are produced).  Member b owns
+ * pos[b] and vel[b] ([batch][3][n], device), mass[b] ([batch][n], device) and
+ * the row params[b] of a HOST table [batch][8] = (G, eps, m_nfw, rs_nfw, m_mn,
+ * a_mn, b_mn, dt).  Every member takes n_steps kick-drift-kick steps of its own
+ * dt in place; there is no tape and no VJP.  Pair terms use the DNB_FP32C
+ * arithmetic whatever the context's precision, so every eps must be > 0.
+ * The table is copied to the context before the call returns; the copy waits
+ * for work already queued on the stream.  The ensemble must fit the context:
+ * batch <= DNB_BATCH_MAX and roughly batch * n <= max_n (DNB_ERR_ARG names the
+ * limit that is exceeded). */
+#define DNB_BATCH_MAX 4096
+
+dnb_status dnb_simulate_batch(dnb_ctx* ctx, int64_t batch, int64_t n, double* pos, double* vel,
+                              const double* mass, const double* params, int64_t n_steps,
+                              void* stream);
+
+/* Test-particle orbits of a batch (the batched form of dnb_orbit): w0, w_out
+ * [batch][6] (device), params the same HOST table as dnb_simulate_batch (eps
+ * is unused).  batch <= DNB_BATCH_MAX. */
+dnb_status dnb_orbit_batch(dnb_ctx* ctx, int64_t batch, const double* w0, const double* params,
+                           int64_t n_steps, double* w_out, void* stream);
+
 /* Instrumentation (not part of the method).  With enable != 0, every launch of
  * the two O(N^2) kernels (forward pair sum, pair VJP) issued through this
  * context is bracketed by HIP events recorded on the launch's stream.

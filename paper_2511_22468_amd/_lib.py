@@ -51,6 +51,8 @@ def load_library(path=LIB_PATH):
         "dnb_orbit_vjp": ([P, P, POT, D, I64, P, P, P, P], I),
         "dnb_place_plummer": ([P, I64, P, P, P, D, D, D, P, P, P, P], I),
         "dnb_place_plummer_vjp": ([P, I64, P, D, D, D, P, P, P, P, P, P], I),
+        "dnb_simulate_batch": ([P, I64, I64, P, P, P, ctypes.POINTER(ctypes.c_double), I64, P], I),
+        "dnb_orbit_batch": ([P, I64, P, ctypes.POINTER(ctypes.c_double), I64, P, P], I),
         "dnb_profile": ([P, I], I),
         "dnb_profile_read": ([P, ctypes.POINTER(ctypes.c_double)], I),
         # learned surrogate (include/dnb_surrogate.h)

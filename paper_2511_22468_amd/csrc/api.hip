@@ -203,7 +203,8 @@ dnb_status dnb_create(dnb_ctx** out, int64_t max_n, dnb_prec prec) {
         {&c->partv, 64 * (size_t)c->slice_rows},
         {(void**)&c->cpartv, sizeof(double) * 8 * c->nbmax},
         {(void**)&c->wscale, sizeof(double) * 2},
-        {(void**)&c->muni, sizeof(float) * 4},
+        {(void**)&c->muni, sizeof(float) * 2 * DNB_BATCH_MAX},
+        {(void**)&c->bparams, sizeof(double) * 8 * DNB_BATCH_MAX},
         {(void**)&c->red, sizeof(double) * 8 * (c->nbmax + 8)},
     };
     for (auto& a : allocs) {
@@ -227,7 +228,7 @@ void dnb_destroy(dnb_ctx* c) {
         delete pf;
     }
     void* ps[] = {c->js, c->part, c->cpart, c->vh, c->jsv, c->partv, c->cpartv, c->wscale, c->muni,
-                  c->red};
+                  c->bparams, c->red};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     delete c;
@@ -448,6 +449,63 @@ dnb_status dnb_orbit_vjp(dnb_ctx* c, const double* traj, const dnb_pot* pot, dou
     CHECK(check_dev(gparams, "gparams", fn));
     HIP_TRY(launch_orbit_vjp(traj, to_pot(*pot), dt, n_steps, gw_out, gw0, gparams,
                              (hipStream_t)stream));
+    return DNB_OK;
+}
+
+// Validates the host parameter table of a batch and copies it to c->bparams.
+static dnb_status put_batch_params(dnb_ctx* c, int64_t batch, const double* params,
+                                   bool need_eps, hipStream_t st, const char* fn) {
+    if (batch < 1 || batch > DNB_BATCH_MAX)
+        return fail(DNB_ERR_ARG, "%s: batch = %lld outside [1, %d]", fn, (long long)batch,
+                    DNB_BATCH_MAX);
+    if (!params) return fail(DNB_ERR_ARG, "%s: params is NULL", fn);
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, params) == hipSuccess && at.type == hipMemoryTypeDevice)
+        return fail(DNB_ERR_ARG, "%s: params must be a host array", fn);
+    (void)hipGetLastError();
+    for (int64_t b = 0; b < batch; ++b) {
+        const double* r = params + 8 * b;
+        const dnb_pot p{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
+        const dnb_status s = check_pot(&p, fn);
+        if (s != DNB_OK) return s;
+        if (!is_fin(r[7])) return fail(DNB_ERR_ARG, "%s: member %lld: dt is not finite", fn, (long long)b);
+        if (need_eps && !(r[1] > 0))
+            return fail(DNB_ERR_ARG, "%s: member %lld: eps must be > 0", fn, (long long)b);
+    }
+    HIP_TRY(hipMemcpyAsync(c->bparams, params, sizeof(double) * 8 * batch, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return DNB_OK;
+}
+
+dnb_status dnb_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* pos, double* vel,
+                              const double* mass, const double* params, int64_t n_steps,
+                              void* stream) {
+    const char* fn = "dnb_simulate_batch";
+    CHECK(check_ctx(c, 1, fn));
+    if (n < 1) return fail(DNB_ERR_ARG, "%s: n must be >= 1", fn);
+    if (n_steps < 0) return fail(DNB_ERR_ARG, "%s: n_steps < 0", fn);
+    if (batch >= 1 && batch <= DNB_BATCH_MAX && !batch_fits(c, batch, n))
+        return fail(DNB_ERR_ARG, "%s: batch %lld x n %lld does not fit a context of max_n = %lld",
+                    fn, (long long)batch, (long long)n, (long long)c->max_n);
+    CHECK(check_dev(pos, "pos", fn));
+    CHECK(check_dev(vel, "vel", fn));
+    CHECK(check_dev(mass, "mass", fn));
+    hipStream_t st = (hipStream_t)stream;
+    CHECK(put_batch_params(c, batch, params, true, st, fn));
+    HIP_TRY(launch_simulate_batch(c, batch, n, pos, vel, mass, c->bparams, n_steps, st));
+    return DNB_OK;
+}
+
+dnb_status dnb_orbit_batch(dnb_ctx* c, int64_t batch, const double* w0, const double* params,
+                           int64_t n_steps, double* w_out, void* stream) {
+    const char* fn = "dnb_orbit_batch";
+    CHECK(check_ctx(c, 1, fn));
+    if (n_steps < 0) return fail(DNB_ERR_ARG, "%s: n_steps < 0", fn);
+    CHECK(check_dev(w0, "w0", fn));
+    CHECK(check_dev(w_out, "w_out", fn));
+    hipStream_t st = (hipStream_t)stream;
+    CHECK(put_batch_params(c, batch, params, false, st, fn));
+    HIP_TRY(launch_orbit_batch(batch, w0, c->bparams, n_steps, w_out, st));
     return DNB_OK;
 }
 

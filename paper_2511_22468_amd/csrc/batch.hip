@@ -1,0 +1,286 @@
+// Batched ensembles: many independent small systems advanced together.
+//
+// The paper relies on automatic vectorisation to run many simulations of one
+// small system at once (Sec. 2), which is what a training set for the surrogate
+// or a parameter grid needs.  A single system of a few thousand particles is far
+// too small to fill 256 compute units; here every O(N^2) and O(N) launch carries
+// a third grid dimension over the members of the ensemble, so one launch per step
+// advances all of them.  Each member has its own potential parameters and step
+// size (a row of the parameter table).  Pair terms are FP32 with compensated
+// accumulation (the FP32C path), drift FP64, exactly as for a single system; the
+// per-target slice sums reuse the single-system device code.
+#include "dnb_internal.h"
+#include "pair_common.h"
+
+namespace dnb {
+
+struct BatchGeom {
+    int n;            // particles per member
+    int nj;           // padded sources per member
+    int S, jslice;    // source slicing per member
+    int nblk;         // target blocks per member (BS targets each)
+    int64_t npad;     // partial row stride per member
+    int nb;           // O(N) blocks per member
+};
+
+constexpr float BFAR32 = 1.0e18f;
+
+// Parameter row: (G, eps, m_nfw, rs_nfw, m_mn, a_mn, b_mn, dt).
+__device__ inline Pot pot_row(const double* __restrict__ P) {
+    return Pot{P[0], P[1], P[2], P[3], P[4], P[5], P[6]};
+}
+
+__device__ inline void bsum3(double (&v)[3], double* sh) { block_sum<3>(v, sh); }
+
+__global__ __launch_bounds__(BS) void k_batch_mass_info(const double* __restrict__ mass, int n,
+                                                        float* __restrict__ muni) {
+    __shared__ double sh[BS];
+    const double* m = mass + (int64_t)blockIdx.x * n;
+    const double m0 = m[0];
+    double diff = 0.0;
+    for (int i = threadIdx.x; i < n; i += BS) diff = fmax(diff, fabs(m[i] - m0));
+    sh[threadIdx.x] = diff;
+    __syncthreads();
+    for (int off = BS / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const bool uni = sh[0] == 0.0 && isfinite(m0);
+        muni[2 * blockIdx.x] = uni ? 1.f : 0.f;
+        muni[2 * blockIdx.x + 1] = uni ? (float)m0 : 0.f;
+    }
+}
+
+// Block sums of member positions (for the staging centre).  grid (nb, batch).
+__global__ __launch_bounds__(BS) void k_batch_block_sums(const double* __restrict__ pos, int n,
+                                                         int nb, double* __restrict__ cpart) {
+    __shared__ double sh[3 * BS];
+    const int b = blockIdx.y;
+    const double* x = pos + (int64_t)b * 3 * n;
+    const int i = blockIdx.x * BS + threadIdx.x;
+    const bool ok = i < n;
+    const int k = ok ? i : 0;
+    double v[3] = {ok ? x[k] : 0.0, ok ? x[n + k] : 0.0, ok ? x[2 * n + k] : 0.0};
+    bsum3(v, sh);
+    if (threadIdx.x == 0) {
+        double* c = cpart + ((int64_t)b * nb + blockIdx.x) * 4;
+        c[0] = v[0]; c[1] = v[1]; c[2] = v[2]; c[3] = 0.0;
+    }
+}
+
+__device__ inline void member_centre(const double* __restrict__ cp, int nb, int n, double* sh,
+                                     double& cx, double& cy, double& cz) {
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int q = threadIdx.x; q < nb; q += BS) {
+        v[0] += cp[4 * q]; v[1] += cp[4 * q + 1]; v[2] += cp[4 * q + 2];
+    }
+    bsum3(v, sh);
+    const double inv = 1.0 / (double)n;   // as the single-system centre, so that members match it bitwise
+    cx = v[0] * inv; cy = v[1] * inv; cz = v[2] * inv;
+}
+
+// Stage member positions relative to their centre.  grid (cdiv(nj, BS), batch).
+__global__ __launch_bounds__(BS) void k_batch_stage(const double* __restrict__ pos,
+                                                    const double* __restrict__ mass, BatchGeom g,
+                                                    const double* __restrict__ cpart,
+                                                    float4* __restrict__ js) {
+    __shared__ double sh[3 * BS];
+    const int b = blockIdx.y;
+    double cx, cy, cz;
+    member_centre(cpart + (int64_t)b * g.nb * 4, g.nb, g.n, sh, cx, cy, cz);
+    const double* x = pos + (int64_t)b * 3 * g.n;
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i < g.nj) {
+        float4* o = js + (int64_t)b * g.nj + i;
+        if (i < g.n)
+            *o = make_float4((float)(x[i] - cx), (float)(x[g.n + i] - cy),
+                             (float)(x[2 * g.n + i] - cz), (float)mass[(int64_t)b * g.n + i]);
+        else
+            *o = make_float4(BFAR32, BFAR32, BFAR32, 0.f);
+    }
+}
+
+// Pair sums of every member.  grid (nblk, S, batch).
+__global__ __launch_bounds__(BS) void k_batch_pair_fwd(const float4* __restrict__ js, BatchGeom g,
+                                                       const double* __restrict__ params,
+                                                       const float* __restrict__ muni,
+                                                       float* __restrict__ part) {
+    const int b = blockIdx.z;
+    const float4* jb = js + (int64_t)b * g.nj;
+    const int i = blockIdx.x * BS + threadIdx.x;
+    const int j0 = blockIdx.y * g.jslice;
+    const int j1 = min(g.nj, j0 + g.jslice);
+    const double eps = params[8 * b + 1];
+    const float eps2 = (float)(eps * eps);
+    const float4 me = jb[min(i, g.n - 1)];
+    float h[3] = {0.f, 0.f, 0.f}, l[3] = {0.f, 0.f, 0.f};
+    if (muni[2 * b] != 0.f) {
+        fwd_f32c_slice<false, true>(jb, i, j0, j1, eps2, me, h, l);
+        const float m = muni[2 * b + 1];
+        for (int c = 0; c < 3; ++c) { h[c] *= m; l[c] *= m; }
+    } else {
+        fwd_f32c_slice<false, false>(jb, i, j0, j1, eps2, me, h, l);
+    }
+    if (i < g.n) {
+        float* p = part + ((int64_t)b * g.S + blockIdx.y) * 6 * g.npad + i;
+        p[0] = h[0]; p[g.npad] = h[1]; p[2 * g.npad] = h[2];
+        p[3 * g.npad] = l[0]; p[4 * g.npad] = l[1]; p[5 * g.npad] = l[2];
+    }
+}
+
+// Kick-drift-kick of every member (same arithmetic as k_kdk), staging the new
+// positions.  grid (cdiv(nj, BS), batch).  mode 0: first (v is full-step), 1: mid,
+// 2: last (closing kick only).
+template <int MODE>
+__global__ __launch_bounds__(BS) void k_batch_kdk(double* __restrict__ pos,
+                                                  double* __restrict__ vel,
+                                                  double* __restrict__ vh,
+                                                  const double* __restrict__ mass, BatchGeom g,
+                                                  const double* __restrict__ params,
+                                                  const float* __restrict__ part,
+                                                  const double* __restrict__ cp_in,
+                                                  double* __restrict__ cp_out,
+                                                  float4* __restrict__ js) {
+    __shared__ double sh[3 * BS];
+    const int b = blockIdx.y;
+    const int n = g.n;
+    const double* P = params + 8 * b;
+    const Pot pot = pot_row(P);
+    const double dt = P[7], hdt = 0.5 * dt;
+    double* x = pos + (int64_t)b * 3 * n;
+    double* v = vel + (int64_t)b * 3 * n;
+    double* w = vh + (int64_t)b * 3 * n;
+    const int i = blockIdx.x * BS + threadIdx.x;
+    const bool ok = i < n;
+    const int k = ok ? i : 0;
+    double cx = 0.0, cy = 0.0, cz = 0.0;
+    if (MODE != 2) member_centre(cp_in + (int64_t)b * g.nb * 4, g.nb, n, sh, cx, cy, cz);
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int s = 0; s < g.S; ++s) {
+        const float* q = part + ((int64_t)b * g.S + s) * 6 * g.npad + k;
+        ax += (double)q[0]; ax += (double)q[3 * g.npad];
+        ay += (double)q[g.npad]; ay += (double)q[4 * g.npad];
+        az += (double)q[2 * g.npad]; az += (double)q[5 * g.npad];
+    }
+    ax *= pot.G; ay *= pot.G; az *= pot.G;
+    const double x0 = x[k], y0 = x[n + k], z0 = x[2 * n + k];
+    const Ext e = ext_accel(pot, x0, y0, z0);
+    ax += e.ax; ay += e.ay; az += e.az;
+    double xn = x0, yn = y0, zn = z0;
+    if (ok) {
+        if (MODE == 2) {
+            v[i] = fma(hdt, ax, w[i]);
+            v[n + i] = fma(hdt, ay, w[n + i]);
+            v[2 * n + i] = fma(hdt, az, w[2 * n + i]);
+        } else {
+            double vx, vy, vz;
+            if (MODE == 0) { vx = v[i]; vy = v[n + i]; vz = v[2 * n + i]; }
+            else { vx = fma(hdt, ax, w[i]); vy = fma(hdt, ay, w[n + i]); vz = fma(hdt, az, w[2 * n + i]); }
+            const double hx = fma(hdt, ax, vx), hy = fma(hdt, ay, vy), hz = fma(hdt, az, vz);
+            xn = fma(dt, hx, x0); yn = fma(dt, hy, y0); zn = fma(dt, hz, z0);
+            w[i] = hx; w[n + i] = hy; w[2 * n + i] = hz;
+            x[i] = xn; x[n + i] = yn; x[2 * n + i] = zn;
+        }
+    }
+    if (MODE != 2) {
+        if (i < g.nj) {
+            float4* o = js + (int64_t)b * g.nj + i;
+            *o = ok ? make_float4((float)(xn - cx), (float)(yn - cy), (float)(zn - cz),
+                                  (float)mass[(int64_t)b * n + i])
+                    : make_float4(BFAR32, BFAR32, BFAR32, 0.f);
+        }
+        double sv[3] = {ok ? xn : 0.0, ok ? yn : 0.0, ok ? zn : 0.0};
+        bsum3(sv, sh);
+        if (threadIdx.x == 0 && blockIdx.x < g.nb) {
+            double* c = cp_out + ((int64_t)b * g.nb + blockIdx.x) * 4;
+            c[0] = sv[0]; c[1] = sv[1]; c[2] = sv[2]; c[3] = 0.0;
+        }
+    }
+}
+
+// Test-particle orbits of every member, one lane each (the batched form of k_orbit).
+__global__ void k_batch_orbit(const double* __restrict__ w0, const double* __restrict__ params,
+                              int batch, int64_t n_steps, double* __restrict__ w_out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const double* P = params + 8 * b;
+    const Pot p = pot_row(P);
+    const double dt = P[7], hdt = 0.5 * dt;
+    const double* w = w0 + 6 * b;
+    double x = w[0], y = w[1], z = w[2], vx = w[3], vy = w[4], vz = w[5];
+    Ext e = ext_accel(p, x, y, z);
+    for (int64_t s = 0; s < n_steps; ++s) {
+        const double hx = fma(hdt, e.ax, vx), hy = fma(hdt, e.ay, vy), hz = fma(hdt, e.az, vz);
+        x = fma(dt, hx, x); y = fma(dt, hy, y); z = fma(dt, hz, z);
+        e = ext_accel(p, x, y, z);
+        vx = fma(hdt, e.ax, hx); vy = fma(hdt, e.ay, hy); vz = fma(hdt, e.az, hz);
+    }
+    double* o = w_out + 6 * b;
+    o[0] = x; o[1] = y; o[2] = z; o[3] = vx; o[4] = vy; o[5] = vz;
+}
+
+BatchGeom batch_geom(const dnb_ctx* c, int64_t batch, int64_t n) {
+    BatchGeom g;
+    g.n = (int)n;
+    g.nj = (int)pad_sources(n);
+    g.nblk = (int)cdiv(n, BS);
+    g.npad = (int64_t)g.nblk * BS;
+    g.nb = (int)cdiv(g.nj, BS);
+    int64_t want = c->target_blocks / ((int64_t)g.nblk * batch);
+    const int64_t max_by_tiles = cdiv(n, TILE);
+    if (want > max_by_tiles) want = max_by_tiles;
+    if (want > S_MAX) want = S_MAX;
+    if (want < 1) want = 1;
+    g.jslice = (int)(cdiv(cdiv(n, want), TILE) * TILE);
+    g.S = (int)cdiv(n, g.jslice);
+    return g;
+}
+
+// Capacity of the context for a batch (checked before anything is enqueued).
+bool batch_fits(const dnb_ctx* c, int64_t batch, int64_t n) {
+    const BatchGeom g = batch_geom(c, batch, n);
+    const int64_t npadmax = (int64_t)c->nbmax * BS;
+    return batch <= DNB_BATCH_MAX && batch * g.nj <= 2 * npadmax && batch * n <= npadmax &&
+           batch * g.S * g.npad * 6 <= 8 * c->slice_rows && batch * g.nb <= c->nbmax;
+}
+
+hipError_t launch_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* pos, double* vel,
+                                 const double* mass, const double* params_dev, int64_t n_steps,
+                                 hipStream_t st) {
+    if (n_steps == 0) return hipSuccess;
+    const BatchGeom g = batch_geom(c, batch, n);
+    float4* js = (float4*)c->js;
+    float* part = (float*)c->part;
+    double* cp[2] = {c->cpart, c->cpart + 4 * c->nbmax};
+    const dim3 on(g.nb, (unsigned)batch);
+    hipLaunchKernelGGL(k_batch_mass_info, dim3((unsigned)batch), dim3(BS), 0, st, mass, g.n,
+                       c->muni);
+    hipLaunchKernelGGL(k_batch_block_sums, on, dim3(BS), 0, st, pos, g.n, g.nb, cp[0]);
+    hipLaunchKernelGGL(k_batch_stage, on, dim3(BS), 0, st, pos, mass, g, cp[0], js);
+    int q = 0;
+    for (int64_t s = 0; s <= n_steps; ++s) {
+        hipLaunchKernelGGL(k_batch_pair_fwd, dim3(g.nblk, g.S, (unsigned)batch), dim3(BS), 0, st,
+                           js, g, params_dev, c->muni, part);
+        if (s == 0)
+            hipLaunchKernelGGL(k_batch_kdk<0>, on, dim3(BS), 0, st, pos, vel, c->vh, mass, g,
+                               params_dev, part, cp[q], cp[1 - q], js);
+        else if (s == n_steps)
+            hipLaunchKernelGGL(k_batch_kdk<2>, on, dim3(BS), 0, st, pos, vel, c->vh, mass, g,
+                               params_dev, part, cp[q], cp[1 - q], js);
+        else
+            hipLaunchKernelGGL(k_batch_kdk<1>, on, dim3(BS), 0, st, pos, vel, c->vh, mass, g,
+                               params_dev, part, cp[q], cp[1 - q], js);
+        q = 1 - q;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_orbit_batch(int64_t batch, const double* w0, const double* params_dev,
+                              int64_t n_steps, double* w_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_orbit, dim3((unsigned)cdiv(batch, 64)), dim3(64), 0, st, w0,
+                       params_dev, (int)batch, n_steps, w_out);
+    return hipGetLastError();
+}
+
+}  // namespace dnb

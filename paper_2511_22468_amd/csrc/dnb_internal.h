@@ -209,7 +209,9 @@ struct dnb_ctx {
     void* partv;             // VJP partials: FP32C float [S][14][npad], FP64 double [S][7][npad]
     double* cpartv;          // [2][nbmax][4]
     double* wscale;          // [2] cotangent staging scales of the reverse sweep
-    float* muni;             // [2] (flag, m): all particle masses equal m (FP32C fast path)
+    float* muni;             // [DNB_BATCH_MAX][2] (flag, m): all masses of the system (or of
+                             // ensemble member b) equal m (FP32C fast path)
+    double* bparams;         // [DNB_BATCH_MAX][8] parameter table of a batched ensemble
     double* red;             // [nbmax][8] reduction scratch
     void* prof;              // host-side event pool of dnb_profile (null when off)
 };
@@ -311,5 +313,13 @@ hipError_t launch_place(int64_t n, const double* w, const double* xi, const doub
 hipError_t launch_place_vjp(dnb_ctx* c, int64_t n, const double* zeta, double m_tot, double a_p,
                             double G, const double* gpos, const double* gvel, const double* gmass,
                             double* gw, double* gm_tot, hipStream_t st);
+
+// Batched ensembles (batch.hip).  params_dev is the [batch][8] table on the device.
+bool batch_fits(const dnb_ctx* c, int64_t batch, int64_t n);
+hipError_t launch_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* pos, double* vel,
+                                 const double* mass, const double* params_dev, int64_t n_steps,
+                                 hipStream_t st);
+hipError_t launch_orbit_batch(int64_t batch, const double* w0, const double* params_dev,
+                              int64_t n_steps, double* w_out, hipStream_t st);
 
 }  // namespace dnb

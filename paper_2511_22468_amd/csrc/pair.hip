@@ -28,16 +28,10 @@
 // about 23 correct bits and two Newton steps y <- y (3/2 - s y^2 / 2) bring it
 // to full precision.
 #include "dnb_internal.h"
+#include "pair_common.h"
 
 namespace dnb {
 
-__device__ __forceinline__ void two_sum_acc(float& hi, float& lo, float x) {
-    float s = hi + x;
-    float bp = s - hi;
-    float e = (hi - (s - bp)) + (x - bp);
-    hi = s;
-    lo += e;
-}
 
 __device__ __forceinline__ double rsqrt_f64(double s) {
     double y = __builtin_amdgcn_rsq(s);
@@ -47,55 +41,11 @@ __device__ __forceinline__ double rsqrt_f64(double s) {
     return y;
 }
 
-// Start index of the batch loaded ahead of batch k of a sub-tile starting at jt;
-// on the last batch of the slice it re-reads the slice's last batch (in bounds).
-__device__ __forceinline__ int next_batch(int jt, int k, int PB, int j1) {
-    return (k + PB < SUBTILE) ? jt + k + PB : min(jt + SUBTILE, j1 - PB);
-}
 
 // ------------------------------------------------------------ forward FP32C --
 // js: staged sources (x, y, z, m), padded to nj = roundup(n, 128).
 // part: [S][6][npad] = (hi_x, hi_y, hi_z, lo_x, lo_y, lo_z) of
 // sum_j m_j d_ij s_ij^-3/2 over the block's slice.
-// Sum over the slice [j0, j1) for target i into the (hi, lo) pairs.  With UNI
-// (all masses equal) the mass is left out of the pair term and applied once by
-// the caller: 11 VALU operations and one v_rsq_f32 per pair instead of 12.
-template <bool EPS0, bool UNI>
-__device__ __forceinline__ void fwd_f32c_slice(const float4* __restrict__ js, int i, int j0,
-                                               int j1, float eps2, float4 me, float (&h)[3],
-                                               float (&l)[3]) {
-    constexpr int PB = 8;
-    float4 qa[PB];
-#pragma unroll
-    for (int u = 0; u < PB; ++u) qa[u] = js[j0 + u];
-    for (int jt = j0; jt < j1; jt += SUBTILE) {
-        float ax = 0.f, ay = 0.f, az = 0.f;
-        for (int k = 0; k < SUBTILE; k += PB) {
-            const int nx = next_batch(jt, k, PB, j1);
-            float4 qb[PB];
-#pragma unroll
-            for (int u = 0; u < PB; ++u) qb[u] = js[nx + u];
-#pragma unroll
-            for (int u = 0; u < PB; ++u) {
-                const float4 q = qa[u];
-                const float dx = q.x - me.x, dy = q.y - me.y, dz = q.z - me.z;
-                const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
-                const float r = __builtin_amdgcn_rsqf(s);
-                float w = UNI ? (r * r) * r : (q.w * r) * (r * r);
-                if (EPS0) w = (jt + k + u == i) ? 0.f : w;
-                ax = fmaf(w, dx, ax);
-                ay = fmaf(w, dy, ay);
-                az = fmaf(w, dz, az);
-            }
-#pragma unroll
-            for (int u = 0; u < PB; ++u) qa[u] = qb[u];
-        }
-        two_sum_acc(h[0], l[0], ax);
-        two_sum_acc(h[1], l[1], ay);
-        two_sum_acc(h[2], l[2], az);
-    }
-}
-
 // muni: [flag, m] -- flag != 0 when every particle has mass m (set per call by
 // k_mass_info); the branch on it is uniform over the grid.
 template <bool EPS0>

@@ -5,8 +5,10 @@ arrays: row 0 holds x, row 1 y, row 2 z) or (n,); see include/dnb.h for the
 definition of every operation.  All calls are asynchronous on the current torch
 stream.
 """
+import ctypes
 from dataclasses import dataclass, replace as _dc_replace
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -30,6 +32,16 @@ class Potential:
     def c(self):
         return _lib.dnb_pot(self.G, self.eps, self.m_nfw, self.rs_nfw, self.m_mn, self.a_mn,
                             self.b_mn)
+
+
+def batch_table(pots, dts, B):
+    """Host parameter table [B][8] = (G, eps, m_nfw, rs_nfw, m_mn, a_mn, b_mn, dt)."""
+    pots, dts = list(pots), list(dts)
+    if len(pots) != B or len(dts) != B:
+        raise ValueError(f"need {B} potentials and {B} step sizes")
+    return np.ascontiguousarray(
+        [[p.G, p.eps, p.m_nfw, p.rs_nfw, p.m_mn, p.a_mn, p.b_mn, float(dt)]
+         for p, dt in zip(pots, dts)], dtype=np.float64)
 
 
 def _vec(t, n, name):
@@ -173,6 +185,28 @@ class Context:
                                             int(n_steps), _lib.ptr(gw_out), _lib.ptr(gw0),
                                             _lib.ptr(gpar), _lib.stream_handle()))
         return gw0, gpar
+
+    def simulate_batch(self, pos, vel, mass, pots, dts, n_steps):
+        """In-place integration of an ensemble: pos, vel (B, 3, n), mass (B, n),
+        pots a sequence of B Potential, dts a sequence of B step sizes."""
+        B, n = mass.shape
+        _arr(pos, (B, 3, n), "pos"); _arr(vel, (B, 3, n), "vel"); _arr(mass, (B, n), "mass")
+        table = batch_table(pots, dts, B)
+        _lib.check(_lib.lib().dnb_simulate_batch(
+            self._h, B, n, _lib.ptr(pos), _lib.ptr(vel), _lib.ptr(mass),
+            table.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(n_steps),
+            _lib.stream_handle()))
+
+    def orbit_batch(self, w0, pots, dts, n_steps):
+        """Test-particle orbits w0 (B, 6) -> w_out (B, 6), member b in pots[b] with dts[b]."""
+        B = w0.shape[0]
+        _arr(w0, (B, 6), "w0")
+        table = batch_table(pots, dts, B)
+        w_out = self._new(B, 6)
+        _lib.check(_lib.lib().dnb_orbit_batch(
+            self._h, B, _lib.ptr(w0), table.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            int(n_steps), _lib.ptr(w_out), _lib.stream_handle()))
+        return w_out
 
     def place_plummer(self, w, xi, zeta, m_tot, a_p, G=G_DEFAULT):
         n = xi.shape[1]
