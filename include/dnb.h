@@ -198,6 +198,10 @@ dnb_status dnb_simulate_batch(dnb_ctx* ctx, int64_t batch, int64_t n, double* po
                               const double* mass, const double* params, int64_t n_steps,
                               void* stream);
 
+/* Largest batch of systems of n particles that dnb_simulate_batch accepts on
+ * this context (0 if ctx is NULL or n < 1).  Host arithmetic only. */
+int64_t dnb_batch_capacity(const dnb_ctx* ctx, int64_t n);
+
 /* Test-particle orbits of a batch (the batched form of dnb_orbit): w0, w_out
  * [batch][6] (device), params the same HOST table as dnb_simulate_batch (eps
  * is unused).  batch <= DNB_BATCH_MAX. */

@@ -496,6 +496,14 @@ dnb_status dnb_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* pos,
     return DNB_OK;
 }
 
+int64_t dnb_batch_capacity(const dnb_ctx* c, int64_t n) {
+    if (!c || n < 1) return 0;
+    int64_t b = c->max_n / n + 1;
+    if (b > DNB_BATCH_MAX) b = DNB_BATCH_MAX;
+    while (b > 0 && !batch_fits(c, b, n)) --b;
+    return b;
+}
+
 dnb_status dnb_orbit_batch(dnb_ctx* c, int64_t batch, const double* w0, const double* params,
                            int64_t n_steps, double* w_out, void* stream) {
     const char* fn = "dnb_orbit_batch";

@@ -197,6 +197,10 @@ class Context:
             table.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(n_steps),
             _lib.stream_handle()))
 
+    def batch_capacity(self, n):
+        """Largest ensemble of n-particle systems that simulate_batch accepts."""
+        return int(_lib.lib().dnb_batch_capacity(self._h, int(n)))
+
     def orbit_batch(self, w0, pots, dts, n_steps):
         """Test-particle orbits w0 (B, 6) -> w_out (B, 6), member b in pots[b] with dts[b]."""
         B = w0.shape[0]

@@ -169,18 +169,30 @@ class MLP:
 def generate_dataset(engine_ctx, thetas_gyr, xi, zeta, n_steps, pot, frame9,
                      w_now=(12.0, 0.0, 0.0, 0.0, -180.0, 60.0), a_p=0.01):
     """Density images of pipeline runs (back-integration, Plummer placement,
-    n_steps forward steps) at each parameter row; returns (X, Y) FP32 device tensors."""
+    n_steps forward steps) at each parameter row; returns (X, Y) FP32 device tensors.
+    The runs are advanced as batched ensembles, as many members per launch as
+    the context holds (pair terms in FP32C)."""
     dev = xi.device
-    M = thetas_gyr.shape[0]
+    th = np.asarray(thetas_gyr, float)
+    M, n = th.shape[0], xi.shape[1]
     Y = torch.empty(M, NPIX, dtype=torch.float32, device=dev)
-    w0 = torch.tensor(w_now, dtype=torch.float64, device=dev)
     ws = torch.empty(int(_lib.lib().dnb_grid_workspace_bytes()), dtype=torch.uint8, device=dev)
-    for k, (t_gyr, m_prog, m_nfw, m_mn) in enumerate(np.asarray(thetas_gyr, float)):
-        p = pot.replace(m_nfw=m_nfw, m_mn=m_mn)
-        dt = gyr(t_gyr) / n_steps
-        w_init, _ = engine_ctx.orbit(w0, p, -dt, n_steps, keep=False)
-        pos, vel, mass = engine_ctx.place_plummer(w_init, xi, zeta, m_prog, a_p, p.G)
-        engine_ctx.simulate(pos, vel, mass, p, dt, n_steps)
-        Y[k] = density_grid(pos, frame9, ws).reshape(NPIX)
-    X = torch.tensor(normalise(thetas_gyr), dtype=torch.float32, device=dev)
+    pots = [pot.replace(m_nfw=r[2], m_mn=r[3]) for r in th]
+    dts = [gyr(r[0]) / n_steps for r in th]
+    cap = engine_ctx.batch_capacity(n)
+    if cap < 1:
+        raise ValueError(f"the context cannot hold one system of {n} particles")
+    for s in range(0, M, cap):
+        e = min(M, s + cap)
+        w0 = torch.tensor(w_now, dtype=torch.float64, device=dev).repeat(e - s, 1)
+        w_init = engine_ctx.orbit_batch(w0, pots[s:e], [-d for d in dts[s:e]], n_steps)
+        pos = torch.empty(e - s, 3, n, dtype=torch.float64, device=dev)
+        vel, mass = torch.empty_like(pos), torch.empty(e - s, n, dtype=torch.float64, device=dev)
+        for b in range(e - s):
+            p, v, m = engine_ctx.place_plummer(w_init[b], xi, zeta, th[s + b, 1], a_p, pots[s + b].G)
+            pos[b].copy_(p); vel[b].copy_(v); mass[b].copy_(m)
+        engine_ctx.simulate_batch(pos, vel, mass, pots[s:e], dts[s:e], n_steps)
+        for b in range(e - s):
+            Y[s + b] = density_grid(pos[b], frame9, ws).reshape(NPIX)
+    X = torch.tensor(normalise(th), dtype=torch.float32, device=dev)
     return X, Y

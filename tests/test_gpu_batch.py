@@ -110,11 +110,14 @@ def test_zero_steps_and_limits(eng):
     assert torch.equal(px, x0)
     with pytest.raises(DnbError, match="eps must be > 0"):
         ctx.simulate_batch(px, pv, pm, [engine.Potential(eps=0.0)] * 3, [0.01] * 3, 1)
-    big = torch.zeros(200, 3, 1000, dtype=torch.float64, device="cuda")
+    # 65536-particle context, n = 1000: 4 blocks of 256 per member, 256 blocks in all
+    cap = ctx.batch_capacity(1000)
+    assert cap == 64
+    big = torch.zeros(cap + 1, 3, 1000, dtype=torch.float64, device="cuda")
     with pytest.raises(DnbError, match="does not fit"):
-        ctx.simulate_batch(big, big.clone(), torch.ones(200, 1000, dtype=torch.float64,
+        ctx.simulate_batch(big, big.clone(), torch.ones(cap + 1, 1000, dtype=torch.float64,
                                                         device="cuda"),
-                           [engine.Potential()] * 200, [0.01] * 200, 1)
+                           [engine.Potential()] * (cap + 1), [0.01] * (cap + 1), 1)
     assert torch.equal(px, x0)
 
 
