@@ -137,6 +137,62 @@ def sweep(prec, sizes=(1024, 4096, 8192, 16384, 65536), reps=20):
     return {"sweep": rows, "prec": prec}
 
 
+def ensemble(B=512, n=4096, T=200, n_single=8):
+    """Training-set generation of the surrogate: B independent runs of n particles
+    (priors as for the surrogate), T kick-drift-kick steps, advanced as one batched
+    ensemble, against the same runs one system at a time (n_single of them, the
+    rate extrapolated).  Pair interactions per second of each."""
+    import torch
+
+    from paper_2511_22468_amd import engine, gyr
+    from synth import draw_theta, plummer_unit
+
+    dev = torch.device("cuda", 0)
+    G = 4.3009e-6
+    th = draw_theta(B, 11)
+    pots = [engine.Potential(eps=1e-3, m_nfw=r[2], m_mn=r[3]) for r in th]
+    dts = [gyr(r[0]) / 4000 for r in th]
+    xi, zeta = plummer_unit(n, 12)
+    x0 = np.array([12.0, 0, 0]) + 0.01 * xi
+    pos = torch.empty(B, 3, n, dtype=torch.float64, device=dev)
+    vel, mass = torch.empty_like(pos), torch.empty(B, n, dtype=torch.float64, device=dev)
+    for b in range(B):
+        pos[b] = torch.tensor(np.ascontiguousarray(x0.T), device=dev)
+        v = np.array([0, -180.0, 60.0]) + np.sqrt(G * th[b, 1] / 0.01) * zeta
+        vel[b] = torch.tensor(np.ascontiguousarray(v.T), device=dev)
+        mass[b] = th[b, 1] / n
+    bctx = engine.Context(B * n, "fp32c")
+    p0, v0 = pos.clone(), vel.clone()
+    bctx.simulate_batch(pos, vel, mass, pots, dts, 2)      # warm-up
+    torch.cuda.synchronize()
+    pos.copy_(p0); vel.copy_(v0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    bctx.simulate_batch(pos, vel, mass, pots, dts, T)
+    e1.record()
+    torch.cuda.synchronize()
+    t_batch = e0.elapsed_time(e1) * 1e-3
+    bctx.close()
+    sctx = engine.Context(n, "fp32c")
+    px, pv = p0[0].clone(), v0[0].clone()
+    sctx.simulate(px, pv, mass[0], pots[0], dts[0], 2)
+    torch.cuda.synchronize()
+    e0.record()
+    for b in range(n_single):
+        px.copy_(p0[b]); pv.copy_(v0[b])
+        sctx.simulate(px, pv, mass[b], pots[b], dts[b], T)
+    e1.record()
+    torch.cuda.synchronize()
+    t_single = e0.elapsed_time(e1) * 1e-3 * B / n_single
+    sctx.close()
+    pairs = B * (T + 1) * float(n) * n
+    return {"ensemble": {"members": B, "n": n, "steps": T,
+                         "batched_s": t_batch, "batched_pairs_per_s": pairs / t_batch,
+                         "one_at_a_time_s_extrapolated": t_single,
+                         "one_at_a_time_pairs_per_s": pairs / t_single,
+                         "speedup": t_single / t_batch}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,11 +210,18 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="kernel rates of the forward and VJP pair kernels at every workload "
                          "size (N = 1024 ... 65536), one JSON line")
+    ap.add_argument("--ensemble", action="store_true",
+                    help="surrogate training-set generation (512 runs of N = 4096) as one "
+                         "batched ensemble vs one run at a time, one JSON line")
     args = ap.parse_args()
+    if (args.sweep or args.ensemble) and args.gpus != 1:
+        print("bench.py measures one GPU only (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
     if args.sweep:
-        if args.gpus != 1:
-            sys.exit(2)
         print(json.dumps(sweep(args.prec)), flush=True)
+        return
+    if args.ensemble:
+        print(json.dumps(ensemble()), flush=True)
         return
     if args.profile_run:
         args.n_steps, args.steps, args.warmup, args.no_cpu_baseline = 20, 1, 0, True

@@ -198,6 +198,15 @@ dnb_status dnb_simulate_batch(dnb_ctx* ctx, int64_t batch, int64_t n, double* po
                               const double* mass, const double* params, int64_t n_steps,
                               void* stream);
 
+/* Loss of every member of an ensemble against one target (the grid-search stage
+ * of the inference pipeline, Sec. 2.2.1: the MMD between simulated and observed
+ * streams at many parameter combinations).  pos [batch][3][n] (device), tgt
+ * [3][m], loss [batch] (device): loss[b] = the squared MMD of dnb_mmd between
+ * pos[b] and tgt.  No gradient.  Requires n, m <= max_n, h > 0, batch <=
+ * DNB_BATCH_MAX and the partial sums to fit the context (DNB_ERR_ARG otherwise). */
+dnb_status dnb_mmd_batch(dnb_ctx* ctx, int64_t batch, int64_t n, const double* pos, int64_t m,
+                         const double* tgt, double h, double* loss, void* stream);
+
 /* Largest batch of systems of n particles that dnb_simulate_batch accepts on
  * this context (0 if ctx is NULL or n < 1).  Host arithmetic only. */
 int64_t dnb_batch_capacity(const dnb_ctx* ctx, int64_t n);

@@ -496,6 +496,21 @@ dnb_status dnb_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* pos,
     return DNB_OK;
 }
 
+dnb_status dnb_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* pos, int64_t m,
+                         const double* tgt, double h, double* loss, void* stream) {
+    const char* fn = "dnb_mmd_batch";
+    CHECK(check_ctx(c, 1, fn));
+    if (!(h > 0) || !is_fin(h)) return fail(DNB_ERR_ARG, "%s: h must be finite and > 0", fn);
+    if (!mmd_batch_fits(c, batch, n, m))
+        return fail(DNB_ERR_ARG, "%s: batch %lld, n %lld, m %lld do not fit a context of max_n = %lld",
+                    fn, (long long)batch, (long long)n, (long long)m, (long long)c->max_n);
+    CHECK(check_dev(pos, "pos", fn));
+    CHECK(check_dev(tgt, "tgt", fn));
+    CHECK(check_dev(loss, "loss", fn));
+    HIP_TRY(launch_mmd_batch(c, batch, n, pos, m, tgt, h, loss, (hipStream_t)stream));
+    return DNB_OK;
+}
+
 int64_t dnb_batch_capacity(const dnb_ctx* c, int64_t n) {
     if (!c || n < 1) return 0;
     int64_t b = c->max_n / n + 1;

@@ -9,12 +9,19 @@ namespace dnb {
 // ---------------------------------------------------------------------- MMD --
 // For targets p_i and sources q_j of one slice:
 //   part[s][0][i] = sum_j k(p_i, q_j),  part[s][1..3][i] = sum_j k(p_i, q_j) (p_i - q_j)
-// with k(p, q) = exp(-|p - q|^2 / (2 h^2)).
+// with k(p, q) = exp(-|p - q|^2 / (2 h^2)); slice s starts at part + s * sstride
+// (4 npad with the gradient terms, npad without).  blockIdx.z selects a member of
+// an ensemble: P, Q and part advance by the given member strides (0 for one system).
 __global__ __launch_bounds__(BS) void k_mmd_rows(const double* __restrict__ P, int np,
                                                  const double* __restrict__ Q, int nq,
                                                  double inv2h2, int jslice, int with_grad,
-                                                 double* __restrict__ part, int64_t npad) {
+                                                 double* __restrict__ part, int64_t npad,
+                                                 int64_t sstride, int64_t p_bstride,
+                                                 int64_t q_bstride, int64_t part_bstride) {
     __shared__ double4 tile[TILE];
+    P += blockIdx.z * p_bstride;
+    Q += blockIdx.z * q_bstride;
+    part += blockIdx.z * part_bstride;
     const int i = blockIdx.x * BS + threadIdx.x;
     const int j0 = blockIdx.y * jslice;
     const int j1 = min(nq, j0 + jslice);
@@ -39,7 +46,7 @@ __global__ __launch_bounds__(BS) void k_mmd_rows(const double* __restrict__ P, i
         __syncthreads();
     }
     if (i < np) {
-        double* p = part + (int64_t)blockIdx.y * 4 * npad + i;
+        double* p = part + (int64_t)blockIdx.y * sstride + i;
         p[0] = s0;
         if (with_grad) { p[npad] = gx; p[2 * npad] = gy; p[3 * npad] = gz; }
     }
@@ -117,17 +124,90 @@ hipError_t launch_mmd(dnb_ctx* c, int64_t n, const double* pos, int64_t m, const
     double* pxy = pv + (int64_t)4 * sx.S * sx.npad;
     double* pyy = (double*)c->part;
     hipLaunchKernelGGL(k_mmd_rows, dim3(sx.nblk, sx.S), dim3(BS), 0, st, pos, (int)n, pos, (int)n,
-                       inv2h2, sx.jslice, wg, pxx, sx.npad);
+                       inv2h2, sx.jslice, wg, pxx, sx.npad, 4 * sx.npad, 0, 0, 0);
     hipLaunchKernelGGL(k_mmd_rows, dim3(sxy.nblk, sxy.S), dim3(BS), 0, st, pos, (int)n, tgt,
-                       (int)m, inv2h2, sxy.jslice, wg, pxy, sxy.npad);
+                       (int)m, inv2h2, sxy.jslice, wg, pxy, sxy.npad, 4 * sxy.npad, 0, 0, 0);
     hipLaunchKernelGGL(k_mmd_rows, dim3(sy.nblk, sy.S), dim3(BS), 0, st, tgt, (int)m, tgt, (int)m,
-                       inv2h2, sy.jslice, 0, pyy, sy.npad);
+                       inv2h2, sy.jslice, 0, pyy, sy.npad, 4 * sy.npad, 0, 0, 0);
     hipLaunchKernelGGL(k_mmd_x, dim3(sx.nblk), dim3(BS), 0, st, pxx, sx.S, pxy, sxy.S, sx.npad,
                        (int)n, (int)m, h, gpos, c->red);
     hipLaunchKernelGGL(k_mmd_y, dim3(sy.nblk), dim3(BS), 0, st, pyy, sy.S, sy.npad, (int)m,
                        c->red);
     hipLaunchKernelGGL(k_mmd_final, dim3(1), dim3(BS), 0, st, c->red, sx.nblk, sy.nblk, (int)n,
                        (int)m, loss);
+    return hipGetLastError();
+}
+
+// Loss of every member of an ensemble against one target (no gradient).
+// pxx, pxy: [batch][S][npad] kernel sums per target; red[8 q + 2] holds the block
+// sums of sum_ab k(y_a, y_b) from k_mmd_y.  One block per member.
+__global__ __launch_bounds__(BS) void k_mmd_batch_final(const double* __restrict__ pxx, int S,
+                                                        const double* __restrict__ pxy, int Sxy,
+                                                        int64_t npad, int n, int m,
+                                                        const double* __restrict__ red, int nby,
+                                                        double* __restrict__ loss) {
+    __shared__ double sh[3 * BS];
+    const int b = blockIdx.x;
+    const double* qx = pxx + (int64_t)b * S * npad;
+    const double* qy = pxy + (int64_t)b * Sxy * npad;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < S; ++s)
+        for (int i = threadIdx.x; i < n; i += BS) v[0] += qx[(int64_t)s * npad + i];
+    for (int s = 0; s < Sxy; ++s)
+        for (int i = threadIdx.x; i < n; i += BS) v[1] += qy[(int64_t)s * npad + i];
+    for (int q = threadIdx.x; q < nby; q += BS) v[2] += red[8 * q + 2];
+    block_sum<3>(v, sh);
+    if (threadIdx.x == 0)
+        loss[b] = v[0] / ((double)n * n) + v[2] / ((double)m * m) - 2.0 * v[1] / ((double)n * m);
+}
+
+// Source slicing of the batched loss: slices of whole tiles, about target_blocks
+// blocks per launch over all members.
+static void mmd_batch_slices(const dnb_ctx* c, int64_t batch, int64_t n, int64_t m, int& S,
+                             int& jslice, int& Sxy, int& jslice_xy) {
+    const int64_t nblk = cdiv(n, BS);
+    int64_t want = c->target_blocks / (nblk * batch);
+    if (want > S_MAX) want = S_MAX;
+    if (want < 1) want = 1;
+    const int64_t wx = want < cdiv(n, TILE) ? want : cdiv(n, TILE);
+    const int64_t wy = want < cdiv(m, TILE) ? want : cdiv(m, TILE);
+    jslice = (int)(cdiv(cdiv(n, wx), TILE) * TILE);
+    S = (int)cdiv(n, jslice);
+    jslice_xy = (int)(cdiv(cdiv(m, wy), TILE) * TILE);
+    Sxy = (int)cdiv(m, jslice_xy);
+}
+
+bool mmd_batch_fits(const dnb_ctx* c, int64_t batch, int64_t n, int64_t m) {
+    if (batch < 1 || batch > DNB_BATCH_MAX || n < 1 || m < 1 || n > c->max_n || m > c->max_n)
+        return false;
+    int S, js, Sxy, jsxy;
+    mmd_batch_slices(c, batch, n, m, S, js, Sxy, jsxy);
+    const int64_t npad = cdiv(n, BS) * BS;
+    return batch * (S + Sxy) * npad <= 8 * c->slice_rows;
+}
+
+hipError_t launch_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* pos, int64_t m,
+                            const double* tgt, double h, double* loss, hipStream_t st) {
+    const double inv2h2 = 1.0 / (2.0 * h * h);
+    int S, jslice, Sxy, jslice_xy;
+    mmd_batch_slices(c, batch, n, m, S, jslice, Sxy, jslice_xy);
+    const int nblk = (int)cdiv(n, BS);
+    const int64_t npad = (int64_t)nblk * BS;
+    double* pxx = (double*)c->partv;
+    double* pxy = pxx + batch * S * npad;
+    double* pyy = (double*)c->part;
+    const Slicing sy = plain_slicing(c, m);
+    hipLaunchKernelGGL(k_mmd_rows, dim3(nblk, S, (unsigned)batch), dim3(BS), 0, st, pos, (int)n,
+                       pos, (int)n, inv2h2, jslice, 0, pxx, npad, npad, 3 * n, 3 * n, S * npad);
+    hipLaunchKernelGGL(k_mmd_rows, dim3(nblk, Sxy, (unsigned)batch), dim3(BS), 0, st, pos, (int)n,
+                       tgt, (int)m, inv2h2, jslice_xy, 0, pxy, npad, npad, 3 * n, (int64_t)0,
+                       Sxy * npad);
+    hipLaunchKernelGGL(k_mmd_rows, dim3(sy.nblk, sy.S), dim3(BS), 0, st, tgt, (int)m, tgt, (int)m,
+                       inv2h2, sy.jslice, 0, pyy, sy.npad, 4 * sy.npad, 0, 0, 0);
+    hipLaunchKernelGGL(k_mmd_y, dim3(sy.nblk), dim3(BS), 0, st, pyy, sy.S, sy.npad, (int)m,
+                       c->red);
+    hipLaunchKernelGGL(k_mmd_batch_final, dim3((unsigned)batch), dim3(BS), 0, st, pxx, S, pxy, Sxy,
+                       npad, (int)n, (int)m, c->red, sy.nblk, loss);
     return hipGetLastError();
 }
 

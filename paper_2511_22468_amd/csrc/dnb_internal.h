@@ -321,5 +321,8 @@ hipError_t launch_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* p
                                  hipStream_t st);
 hipError_t launch_orbit_batch(int64_t batch, const double* w0, const double* params_dev,
                               int64_t n_steps, double* w_out, hipStream_t st);
+bool mmd_batch_fits(const dnb_ctx* c, int64_t batch, int64_t n, int64_t m);
+hipError_t launch_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* pos, int64_t m,
+                            const double* tgt, double h, double* loss, hipStream_t st);
 
 }  // namespace dnb

@@ -197,6 +197,15 @@ class Context:
             table.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(n_steps),
             _lib.stream_handle()))
 
+    def mmd_batch(self, pos, tgt, h):
+        """Loss of each member pos[b] (B, 3, n) against tgt (3, m): a (B,) tensor."""
+        B, n, m = pos.shape[0], pos.shape[2], tgt.shape[1]
+        _arr(pos, (B, 3, n), "pos"); _vec(tgt, m, "tgt")
+        loss = self._new(B)
+        _lib.check(_lib.lib().dnb_mmd_batch(self._h, B, n, _lib.ptr(pos), m, _lib.ptr(tgt),
+                                            float(h), _lib.ptr(loss), _lib.stream_handle()))
+        return loss
+
     def batch_capacity(self, n):
         """Largest ensemble of n-particle systems that simulate_batch accepts."""
         return int(_lib.lib().dnb_batch_capacity(self._h, int(n)))

@@ -10,6 +10,7 @@ theta = (t_end, M_Plummer, M_NFW, M_MN), t_end in internal time units.
 Every stage is a call into libdnb (autograd.py); torch only forms dt = t_end/n
 and chains the scalar cotangents.
 """
+import numpy as np
 import torch
 
 from . import autograd as AG
@@ -53,3 +54,45 @@ def make_target(engine_ctx, xi, zeta, theta, n_steps, pot=None, a_p=0.01):
     m = StreamModel(engine_ctx, xi, zeta, None, n_steps, pot=pot, a_p=a_p)
     with torch.no_grad():
         return m.final_positions(theta).detach()
+
+
+def run_ensemble(engine_ctx, thetas, xi, zeta, n_steps, pot=None, a_p=0.01, w_now=W_NOW):
+    """Final positions of pipeline runs at many parameter rows, advanced as
+    batched ensembles (FP32C pair terms).  thetas: (M, 4) host array of
+    (t_end [internal], M_Plummer, M_NFW, M_MN).  Yields (first row, positions
+    (B, 3, n)) per chunk of as many members as the context holds; the positions
+    tensor is reused by the next chunk."""
+    pot = pot if pot is not None else Potential()
+    dev = xi.device
+    th = np.asarray(thetas, float).reshape(-1, 4)
+    M, n = th.shape[0], xi.shape[1]
+    pots = [pot.replace(m_nfw=r[2], m_mn=r[3]) for r in th]
+    dts = [r[0] / n_steps for r in th]
+    cap = engine_ctx.batch_capacity(n)
+    if cap < 1:
+        raise ValueError(f"the context cannot hold one system of {n} particles")
+    cap = min(cap, M)
+    pos = torch.empty(cap, 3, n, dtype=torch.float64, device=dev)
+    vel, mass = torch.empty_like(pos), torch.empty(cap, n, dtype=torch.float64, device=dev)
+    w_now_t = torch.tensor(w_now, dtype=torch.float64, device=dev)
+    for s in range(0, M, cap):
+        e = min(M, s + cap)
+        B = e - s
+        w0 = w_now_t.repeat(B, 1)
+        w_init = engine_ctx.orbit_batch(w0, pots[s:e], [-d for d in dts[s:e]], n_steps)
+        for b in range(B):
+            p, v, m = engine_ctx.place_plummer(w_init[b], xi, zeta, th[s + b, 1], a_p, pots[s + b].G)
+            pos[b].copy_(p); vel[b].copy_(v); mass[b].copy_(m)
+        engine_ctx.simulate_batch(pos[:B], vel[:B], mass[:B], pots[s:e], dts[s:e], n_steps)
+        yield s, pos[:B]
+
+
+def grid_search(engine_ctx, thetas, xi, zeta, target, n_steps, pot=None, h=0.2, a_p=0.01,
+                w_now=W_NOW):
+    """MMD loss of the pipeline at every parameter row (the grid-search stage of
+    the inference, Sec. 2.2.1): a host array of M losses."""
+    th = np.asarray(thetas, float).reshape(-1, 4)
+    out = torch.empty(th.shape[0], dtype=torch.float64, device=xi.device)
+    for s, pos in run_ensemble(engine_ctx, th, xi, zeta, n_steps, pot, a_p, w_now):
+        out[s:s + pos.shape[0]] = engine_ctx.mmd_batch(pos, target, h)
+    return out.cpu().numpy()

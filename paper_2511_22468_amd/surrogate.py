@@ -14,6 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
+from .pipeline import run_ensemble
 from .units import gyr
 
 PRIOR = ((1.0, 4.0), (1.0e4, 1.0e5), (5.0e11, 2.0e12), (3.0e10, 1.0e11))
@@ -173,26 +174,13 @@ def generate_dataset(engine_ctx, thetas_gyr, xi, zeta, n_steps, pot, frame9,
     The runs are advanced as batched ensembles, as many members per launch as
     the context holds (pair terms in FP32C)."""
     dev = xi.device
-    th = np.asarray(thetas_gyr, float)
-    M, n = th.shape[0], xi.shape[1]
-    Y = torch.empty(M, NPIX, dtype=torch.float32, device=dev)
+    th = np.array(thetas_gyr, float).reshape(-1, 4)
+    th_int = th.copy()
+    th_int[:, 0] = [gyr(t) for t in th[:, 0]]
+    Y = torch.empty(th.shape[0], NPIX, dtype=torch.float32, device=dev)
     ws = torch.empty(int(_lib.lib().dnb_grid_workspace_bytes()), dtype=torch.uint8, device=dev)
-    pots = [pot.replace(m_nfw=r[2], m_mn=r[3]) for r in th]
-    dts = [gyr(r[0]) / n_steps for r in th]
-    cap = engine_ctx.batch_capacity(n)
-    if cap < 1:
-        raise ValueError(f"the context cannot hold one system of {n} particles")
-    for s in range(0, M, cap):
-        e = min(M, s + cap)
-        w0 = torch.tensor(w_now, dtype=torch.float64, device=dev).repeat(e - s, 1)
-        w_init = engine_ctx.orbit_batch(w0, pots[s:e], [-d for d in dts[s:e]], n_steps)
-        pos = torch.empty(e - s, 3, n, dtype=torch.float64, device=dev)
-        vel, mass = torch.empty_like(pos), torch.empty(e - s, n, dtype=torch.float64, device=dev)
-        for b in range(e - s):
-            p, v, m = engine_ctx.place_plummer(w_init[b], xi, zeta, th[s + b, 1], a_p, pots[s + b].G)
-            pos[b].copy_(p); vel[b].copy_(v); mass[b].copy_(m)
-        engine_ctx.simulate_batch(pos, vel, mass, pots[s:e], dts[s:e], n_steps)
-        for b in range(e - s):
+    for s, pos in run_ensemble(engine_ctx, th_int, xi, zeta, n_steps, pot, a_p, w_now):
+        for b in range(pos.shape[0]):
             Y[s + b] = density_grid(pos[b], frame9, ws).reshape(NPIX)
     X = torch.tensor(normalise(th), dtype=torch.float32, device=dev)
     return X, Y

@@ -1,5 +1,6 @@
-"""Batched ensembles (dnb_simulate_batch, dnb_orbit_batch) against the oracle and
-against single-system runs (run on an MI355X).
+"""Batched ensembles (dnb_simulate_batch, dnb_orbit_batch, dnb_mmd_batch and the
+grid search built on them) against the oracle and against single-system runs
+(run on an MI355X).
 
 Every member of an ensemble is an independent system with its own potential,
 softening and step size.  Members are checked against the FP64 oracle at the
@@ -137,3 +138,47 @@ def test_orbit_batch_matches_single_orbits_and_oracle(eng):
                                self_gravity=False)
         np.testing.assert_allclose(wo[b, :3].cpu().numpy(), xr[0], rtol=1e-12)
         np.testing.assert_allclose(wo[b, 3:].cpu().numpy(), vr[0], rtol=1e-12)
+
+
+def test_mmd_batch_matches_oracle(eng):
+    pk, engine, ctx = eng
+    from oracle import mmd as ommd
+    rng = np.random.default_rng(21)
+    B, n, m = 5, 700, 300
+    X = W_X + rng.normal(scale=0.3, size=(B, n, 3)) * rng.uniform(0.8, 1.2, (B, 1, 1))
+    Y = W_X + 0.1 + rng.normal(scale=0.25, size=(m, 3))
+    pos = torch.tensor(np.ascontiguousarray(X.transpose(0, 2, 1)), device="cuda")
+    tgt = torch.tensor(np.ascontiguousarray(Y.T), device="cuda")
+    loss = ctx.mmd_batch(pos, tgt, 0.2).cpu().numpy()
+    for b in range(B):
+        ref = ommd.mmd2(X[b], Y, 0.2)
+        assert abs(loss[b] / ref - 1) <= 1e-12, b
+        single, _ = ctx.mmd(pos[b], tgt, 0.2, grad=False)
+        assert abs(loss[b] / single.item() - 1) <= 1e-13, b
+    # a member identical to the target gives zero
+    same = torch.tensor(np.ascontiguousarray(Y.T)[None], device="cuda")
+    assert abs(ctx.mmd_batch(same, tgt, 0.2).item()) <= 1e-14
+
+
+def test_grid_search_matches_oracle_pipeline(eng):
+    pk, engine, ctx = eng
+    from oracle import pipeline as opipe
+    from paper_2511_22468_amd.pipeline import grid_search, StreamModel
+    n, T, B = 300, 60, 6
+    say(f"[grid] B={B} n={n} T={T}")
+    xi, zeta = plummer_unit(n, 8)
+    rng = np.random.default_rng(9)
+    Y = W_X + rng.normal(scale=0.05, size=(400, 3))
+    op = OPot()
+    thetas = np.array([[pk.gyr(0.05 + 0.01 * b), 2e4 * (1 + 0.1 * b), 1e12 * (1 + 0.05 * b),
+                        6.5e10 * (1 - 0.03 * b)] for b in range(B)])
+    t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device="cuda")
+    losses = grid_search(ctx, thetas, t3(xi), t3(zeta), t3(Y), T, gpu_pot(engine, op), h=0.2)
+    model = StreamModel(ctx, t3(xi), t3(zeta), t3(Y), T, pot=gpu_pot(engine, op), h=0.2)
+    for b in range(B):
+        ref = opipe.loss(tuple(thetas[b]), xi, zeta, op, T, Y, 0.2)
+        # FP32C positions carry ~1e-7 relative error; the loss moves by at most
+        # |grad L| * |dx| ~ (1/h) * 1e-6 kpc, a few 1e-6 of an O(0.1) loss
+        assert abs(losses[b] / ref - 1) <= 1e-5, (b, losses[b], ref)
+        single = model.loss(torch.tensor(thetas[b], device="cuda")).item()
+        assert abs(losses[b] / single - 1) <= 1e-12, (b, losses[b], single)
