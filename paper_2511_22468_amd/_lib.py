@@ -28,12 +28,19 @@ class dnb_pot(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in ("G", "eps", "m_nfw", "rs_nfw", "m_mn", "a_mn", "b_mn")]
 
 
+class dnb_track_model(ctypes.Structure):
+    _fields_ = [("w_now", ctypes.c_double * 6), ("G", ctypes.c_double),
+                ("dt_total", ctypes.c_double), ("n_steps", ctypes.c_int64),
+                ("sigma", ctypes.c_double * 3)]
+
+
 def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_2511_22468_amd.build`")
     lib = ctypes.CDLL(path)
     P, I64, I, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
     POT = ctypes.POINTER(dnb_pot)
+    TM = ctypes.POINTER(dnb_track_model)
     sig = {
         "dnb_create": ([ctypes.POINTER(P), I64, I], I),
         "dnb_destroy": ([P], None),
@@ -66,6 +73,11 @@ def load_library(path=LIB_PATH):
         "dnb_mlp_mse": ([I64, P, P, P, P, P], I),
         "dnb_mlp_adam": ([I64, P, P, P, P, P, D, D, D, D, I64, P], I),
         "dnb_grid_workspace_bytes": ([], I64),
+        # orbit fit (include/dnb_orbitfit.h)
+        "dnb_track_observe": ([P, TM, I64, P, P, P, P], I),
+        "dnb_track_chi2": ([P, TM, I64, P, I64, P, P, P, P, P], I),
+        "dnb_track_hessian": ([P, TM, I64, P, I64, P, P, P, P], I),
+        "dnb_track_lm": ([P, TM, I64, P, I64, P, I64, D, P, P], I),
         "dnb_density_grid": ([I64, P, ctypes.POINTER(ctypes.c_double), P, P, P], I),
     }
     for name, (args, res) in sig.items():

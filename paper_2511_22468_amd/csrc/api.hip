@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "dnb_internal.h"
+#include "../../include/dnb_orbitfit.h"
 
 using namespace dnb;
 
@@ -564,6 +565,95 @@ dnb_status dnb_place_plummer_vjp(dnb_ctx* c, int64_t n, const double* zeta, doub
     CHECK(check_dev(gm_tot, "gm_tot", fn));
     HIP_TRY(launch_place_vjp(c, n, zeta, m_tot, a_p, G, gpos, gvel, gmass, gw, gm_tot,
                              (hipStream_t)stream));
+    return DNB_OK;
+}
+
+// ------------------------------------------------------------- orbit fit --
+static dnb_status check_track(dnb_ctx* c, const dnb_track_model* md, int64_t K,
+                              const double* pts, const char* what, const char* fn) {
+    CHECK(check_ctx(c, 1, fn));
+    if (!md) return fail(DNB_ERR_ARG, "%s: model is NULL", fn);
+    for (double w : md->w_now)
+        if (!is_fin(w)) return fail(DNB_ERR_ARG, "%s: w_now is not finite", fn);
+    const double* x = md->w_now;
+    const double* v = md->w_now + 3;
+    const double n[3] = {x[1] * v[2] - x[2] * v[1], x[2] * v[0] - x[0] * v[2],
+                         x[0] * v[1] - x[1] * v[0]};
+    if (!(n[0] * n[0] + n[1] * n[1] + n[2] * n[2] > 0))
+        return fail(DNB_ERR_ARG, "%s: w_now has no angular momentum (no orbital frame)", fn);
+    if (!(md->G > 0) || !is_fin(md->G)) return fail(DNB_ERR_ARG, "%s: G must be > 0", fn);
+    if (!(md->dt_total > 0) || !is_fin(md->dt_total))
+        return fail(DNB_ERR_ARG, "%s: dt_total must be finite and > 0", fn);
+    if (md->n_steps < 1) return fail(DNB_ERR_ARG, "%s: n_steps must be >= 1", fn);
+    for (double s : md->sigma)
+        if (!(s > 0) || !is_fin(s)) return fail(DNB_ERR_ARG, "%s: sigma must be finite and > 0", fn);
+    if (K < 1 || K > DNB_TRACK_MAX)
+        return fail(DNB_ERR_ARG, "%s: K = %lld outside [1, %d]", fn, (long long)K, DNB_TRACK_MAX);
+    return check_dev(pts, what, fn);
+}
+
+static dnb_status check_batch(int64_t batch, const char* fn) {
+    if (batch < 1 || batch > DNB_BATCH_MAX)
+        return fail(DNB_ERR_ARG, "%s: batch = %lld outside [1, %d]", fn, (long long)batch,
+                    DNB_BATCH_MAX);
+    return DNB_OK;
+}
+
+dnb_status dnb_track_observe(dnb_ctx* c, const dnb_track_model* md, int64_t K, const double* phi1,
+                             const double* p, double* y, void* stream) {
+    const char* fn = "dnb_track_observe";
+    CHECK(check_track(c, md, K, phi1, "phi1", fn));
+    CHECK(check_dev(p, "p", fn));
+    CHECK(check_dev(y, "y", fn));
+    HIP_TRY(launch_track_observe(*md, (int)K, phi1, p, y, (hipStream_t)stream));
+    return DNB_OK;
+}
+
+dnb_status dnb_track_chi2(dnb_ctx* c, const dnb_track_model* md, int64_t K, const double* track,
+                          int64_t batch, const double* p, double* chi2, double* jtr, double* jtj,
+                          void* stream) {
+    const char* fn = "dnb_track_chi2";
+    CHECK(check_track(c, md, K, track, "track", fn));
+    CHECK(check_batch(batch, fn));
+    CHECK(check_dev(p, "p", fn));
+    CHECK(check_dev(chi2, "chi2", fn));
+    CHECK(check_dev(jtr, "jtr", fn, true));
+    CHECK(check_dev(jtj, "jtj", fn, true));
+    HIP_TRY(launch_track_eval(*md, track, (int)K, (int)batch, p, chi2, jtr, jtj,
+                              (hipStream_t)stream));
+    return DNB_OK;
+}
+
+dnb_status dnb_track_hessian(dnb_ctx* c, const dnb_track_model* md, int64_t K,
+                             const double* track, int64_t batch, const double* p, double* hess,
+                             double* cov, void* stream) {
+    const char* fn = "dnb_track_hessian";
+    CHECK(check_track(c, md, K, track, "track", fn));
+    CHECK(check_batch(batch, fn));
+    CHECK(check_dev(p, "p", fn));
+    CHECK(check_dev(hess, "hess", fn));
+    CHECK(check_dev(cov, "cov", fn, true));
+    if (cov == hess) return fail(DNB_ERR_ARG, "%s: cov must not alias hess", fn);
+    HIP_TRY(launch_track_hessian(*md, track, (int)K, (int)batch, p, hess, cov,
+                                 (hipStream_t)stream));
+    return DNB_OK;
+}
+
+dnb_status dnb_track_lm(dnb_ctx* c, const dnb_track_model* md, int64_t K, const double* track,
+                        int64_t batch, double* p, int64_t n_iter, double lambda0, double* chi2,
+                        void* stream) {
+    const char* fn = "dnb_track_lm";
+    CHECK(check_track(c, md, K, track, "track", fn));
+    CHECK(check_batch(batch, fn));
+    if (n_iter < 0) return fail(DNB_ERR_ARG, "%s: n_iter < 0", fn);
+    if (!(lambda0 > 0) || !is_fin(lambda0)) return fail(DNB_ERR_ARG, "%s: lambda0 must be > 0", fn);
+    CHECK(check_dev(p, "p", fn));
+    CHECK(check_dev(chi2, "chi2", fn));
+    // workspace: the VJP partial buffer, 64 * slice_rows >= 64 * 2^21 bytes
+    if (lm_workspace_bytes(batch) > 64 * (size_t)c->slice_rows)
+        return fail(DNB_ERR_ARG, "%s: batch too large for the context workspace", fn);
+    HIP_TRY(launch_track_lm(*md, track, (int)K, (int)batch, p, n_iter, lambda0, chi2, c->partv,
+                            (hipStream_t)stream));
     return DNB_OK;
 }
 

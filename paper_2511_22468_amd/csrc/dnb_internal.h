@@ -322,6 +322,22 @@ hipError_t launch_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* p
 hipError_t launch_orbit_batch(int64_t batch, const double* w0, const double* params_dev,
                               int64_t n_steps, double* w_out, hipStream_t st);
 bool mmd_batch_fits(const dnb_ctx* c, int64_t batch, int64_t n, int64_t m);
+
+// Orbit fit (orbitfit.hip).  The model struct is declared in dnb_orbitfit.h.
+}  // namespace dnb
+struct dnb_track_model;
+namespace dnb {
+hipError_t launch_track_observe(const dnb_track_model& md, int K, const double* phi1,
+                                const double* p, double* y, hipStream_t st);
+hipError_t launch_track_eval(const dnb_track_model& md, const double* trk, int K, int batch,
+                             const double* p, double* chi2, double* jtr, double* jtj,
+                             hipStream_t st);
+hipError_t launch_track_hessian(const dnb_track_model& md, const double* trk, int K, int batch,
+                                const double* p, double* hess, double* cov, hipStream_t st);
+size_t lm_workspace_bytes(int64_t batch);
+hipError_t launch_track_lm(const dnb_track_model& md, const double* trk, int K, int batch,
+                           double* p, int64_t n_iter, double lam0, double* chi2, void* work,
+                           hipStream_t st);
 hipError_t launch_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* pos, int64_t m,
                             const double* tgt, double h, double* loss, hipStream_t st);
 
