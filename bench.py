@@ -37,18 +37,25 @@ FLOPS_VJP = 41                    # per pair of the vector-Jacobian product
 # HBM bytes per launch from the two rocprofv3 counter passes recorded in
 # profiles/pair_kernels_n65536_traffic.md (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the
 # factors measured on a 256 MiB copy), valid only for the kernel source they were
-# measured on (sha256 prefix of pair.hip) and for N = 65536.
+# measured on (sha256 prefix of pair.hip followed by pair_common.h) and for N = 65536.
 TRAFFIC_SRC_SHA = "115cc9bbaaff8482"
 TRAFFIC_N = 65536
 TRAFFIC_KIB = {"k_pair_fwd_f32c": (7698.1, 49152.0), "k_pair_vjp_f32c": (15397.2, 98304.0)}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
-def measured_traffic(kernel, n):
+def kernel_source_sha():
+    """sha256 prefix of the pair-kernel sources (pair.hip, then pair_common.h)."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2511_22468_amd", "csrc", "pair.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("pair.hip", "pair_common.h"):
+        with open(os.path.join(ROOT, "paper_2511_22468_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, n):
+    sha = kernel_source_sha()
     if sha != TRAFFIC_SRC_SHA or n != TRAFFIC_N or kernel not in TRAFFIC_KIB:
         return None
     fetch, write = TRAFFIC_KIB[kernel]

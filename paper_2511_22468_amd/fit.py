@@ -4,8 +4,9 @@ The paper fits Theta = (t_end, M_Plummer, M_NFW, M_MN) by vanilla gradient
 descent on the MMD between simulated and observed streams, with gradients from
 the differentiable N-body run (Sec. 2.2.1, Fig. 2).  Both arms here use that
 same descent, in the normalised coordinates u in [-1, 1]^4 of the surrogate
-(t_end linear, masses logarithmic over the prior box), with a fixed step that
-is halved whenever a step would raise the loss.
+(t_end linear, masses logarithmic over the prior box), with steps of fixed
+length along the negative gradient, halved whenever a step would raise the
+loss.
 
 plain arm:  from the prior centre u = 0, B iterations; L* = best loss reached.
 warm arm:   invert the surrogate on the target's density image (Adam on u through
@@ -46,7 +47,12 @@ def dtheta_du(u):
 
 
 def descend(model, u0, lr, max_iter, stop_loss=None, clock0=None):
-    """Vanilla gradient descent on u with step halving on a rise of the loss."""
+    """Gradient descent on u with steps of length lr along the negative gradient
+    direction, the length halved whenever a step would raise the loss.  The step
+    is normalised because the exact gradient of the discrete map grows
+    exponentially with the horizon (the bound core of the progenitor is
+    chaotic): at thousands of steps its magnitude says nothing about a useful
+    step length, while its direction still points downhill for small steps."""
     dev = model.ctx.device
     clock0 = time.perf_counter() if clock0 is None else clock0
     u = np.array(u0, float)
@@ -58,7 +64,10 @@ def descend(model, u0, lr, max_iter, stop_loss=None, clock0=None):
     it = 0
     while it < max_iter and not (stop_loss is not None and L <= stop_loss):
         it += 1
-        cand = np.clip(u - lr * gu, -1.0, 1.0)
+        gn = float(np.sqrt(np.sum(gu * gu)))
+        if not np.isfinite(gn) or gn == 0.0:
+            break
+        cand = np.clip(u - lr * gu / gn, -1.0, 1.0)
         Lc, gc = model.loss_and_grad(torch.tensor(theta_internal(cand), device=dev))
         Lc = Lc.item()
         if Lc <= L:

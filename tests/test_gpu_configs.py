@@ -17,7 +17,7 @@ import torch
 
 from oracle import forces as of, integrate as oint
 from oracle.forces import Potential as OPot
-from synth import plummer_unit, sample_rows
+from synth import plummer_unit, random_directions, sample_rows
 
 from gpu_util import rel_rows, say, to_dev, to_host
 
@@ -170,27 +170,35 @@ def test_three_way_precision_n65536():
     say(f"[cfg] N=65536 accel vs oracle (1024 sampled): FP32C max {e32.max():.2e} "
         f"median {np.median(e32):.2e}; FP64 max {e64.max():.2e}")
     assert e32.max() <= 1e-5 and e64.max() <= 1e-12
+    # FP64 floors: initial positions moved by one ulp, and by the FP32 rounding
+    # of a position staged relative to the centre (6e-8 of |x - c|, seeded
+    # directions), which is the size of error the FP32C path makes at every step
+    rel = x - x.mean(0)
+    x32 = x + 6e-8 * np.sqrt((rel ** 2).sum(1))[:, None] * random_directions(n, 41)
     final = {}
-    runs = (("fp32c", x), ("fp64", x), ("fp64+1ulp", np.nextafter(x, np.inf)))
+    runs = (("fp32c", x), ("fp64", x), ("fp64+1ulp", np.nextafter(x, np.inf)),
+            ("fp64+fp32", x32))
     for name, x0 in runs:
         c = ctx[name.split("+")[0]]
         px, pv, pm = to_dev(x0), to_dev(v), to_dev(m)
         c.simulate(px, pv, pm, pot, pk.myr(0.5), 1000)
         final[name] = to_host(px)
     d = rel_rows(final["fp32c"], final["fp64"])
-    floor = rel_rows(final["fp64+1ulp"], final["fp64"])
-    say(f"[cfg] N=65536 final positions after 1000 steps, FP32C vs FP64-GPU: "
-        f"max {d.max():.2e} p99 {np.quantile(d, 0.99):.2e} median {np.median(d):.2e}; "
-        f"FP64 1-ulp floor: max {floor.max():.2e} p99 {np.quantile(floor, 0.99):.2e} "
-        f"median {np.median(floor):.2e}")
-    # chaos saturates both differences at the size of the bound core; per particle,
-    # FP32C must be no further from FP64 than a one-ulp change of the initial
-    # conditions is, and as a cloud (MMD, h = 0.2 kpc) the same holds
-    assert np.median(d) <= 2 * np.median(floor) + 1e-6
+    stats = lambda e: f"max {e.max():.2e} p99 {np.quantile(e, 0.99):.2e} median {np.median(e):.2e}"
+    fl1 = rel_rows(final["fp64+1ulp"], final["fp64"])
+    fl32 = rel_rows(final["fp64+fp32"], final["fp64"])
+    say(f"[cfg] N=65536 final positions after 1000 steps vs FP64-GPU: FP32C {stats(d)}; "
+        f"FP64 one-ulp floor {stats(fl1)}; FP64 FP32-rounding floor {stats(fl32)}")
     c64 = ctx["fp64"]
-    mmd32 = c64.mmd(to_dev(final["fp32c"]), to_dev(final["fp64"]), 0.2, grad=False)[0].item()
-    mmdfl = c64.mmd(to_dev(final["fp64+1ulp"]), to_dev(final["fp64"]), 0.2, grad=False)[0].item()
-    say(f"[cfg] N=65536 cloud MMD^2 vs FP64: FP32C {mmd32:.3e}, FP64 one-ulp floor {mmdfl:.3e}")
-    assert mmd32 <= 3 * mmdfl + 1e-9
+    mmd = {k: c64.mmd(to_dev(final[k]), to_dev(final["fp64"]), 0.2, grad=False)[0].item()
+           for k in ("fp32c", "fp64+1ulp", "fp64+fp32")}
+    say(f"[cfg] N=65536 cloud MMD^2 vs FP64: FP32C {mmd['fp32c']:.3e}, one-ulp floor "
+        f"{mmd['fp64+1ulp']:.3e}, FP32-rounding floor {mmd['fp64+fp32']:.3e}")
+    # chaos saturates per-particle differences at the size of the bound core: per
+    # particle (median and p99) and as a cloud (MMD, h = 0.2 kpc) FP32C must be no
+    # further from FP64 than an FP64 run started with FP32-sized rounding errors
+    assert np.median(d) <= 2 * np.median(fl32) + 1e-6
+    assert np.quantile(d, 0.99) <= 3 * np.quantile(fl32, 0.99) + 1e-6
+    assert mmd["fp32c"] <= 3 * mmd["fp64+fp32"] + 1e-9
     for c in ctx.values():
         c.close()
