@@ -98,18 +98,22 @@ dnb_status dnb_step(dnb_ctx* ctx, int64_t n, double* pos, double* vel, const dou
                     const dnb_pot* pot, double dt, void* stream);
 
 /* Number of doubles of the checkpoint tape that dnb_simulate writes for
- * (n, n_steps, ckpt_every): ceil(n_steps / ckpt_every) checkpoints of 6n. */
+ * (n, n_steps, ckpt_every): for each of the ceil(n_steps / ckpt_every)
+ * checkpoints the state (6n), the staging centre (4) and the internal (pair)
+ * acceleration (3n), plus the internal acceleration at the final positions
+ * (3n); 0 for n_steps = 0. */
 int64_t dnb_tape_doubles(int64_t n, int64_t n_steps, int64_t ckpt_every);
 
 /* Number of doubles of the segment workspace that dnb_simulate_vjp needs:
- * 3n (ckpt_every + 1) + 16n. */
+ * 3n (ckpt_every + 1) + 16n + 3n ckpt_every. */
 int64_t dnb_vjp_workspace_doubles(int64_t n, int64_t ckpt_every);
 
 /* n_steps kick-drift-kick steps of size dt (Sec. 2.2.1: fixed steps), in place
  * on pos [3][n] and vel [3][n].  If tape is not NULL it must hold
  * dnb_tape_doubles(n, n_steps, ckpt_every) doubles and receives the state
  * (x, v) at steps 0, K, 2K, ... (K = ckpt_every >= 1), each as [6][n]
- * (x block then v block).  The tape is what dnb_simulate_vjp differentiates. */
+ * (x block then v block), and the quantities the reverse sweep reuses (see
+ * dnb_tape_doubles).  The tape is what dnb_simulate_vjp differentiates. */
 dnb_status dnb_simulate(dnb_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,
                         const dnb_pot* pot, double dt, int64_t n_steps, int64_t ckpt_every,
                         double* tape, void* stream);

@@ -130,11 +130,18 @@ hipError_t profiled(dnb_ctx* c, int kind, hipStream_t st, F launch) {
         if (s_ != DNB_OK) return s_;      \
     } while (0)
 
+// Tape of one integration, in order: the states (x, v) at the checkpoints
+// [n_ckpt][6][n], the staging centres [n_ckpt][4], the internal accelerations
+// at the checkpoints [n_ckpt][3][n], and the internal acceleration at the final
+// positions [3][n].  The reverse sweep reads the accelerations instead of
+// summing them again in the pair VJP.
 struct Tape {
     double* base;
     int64_t n, n_ckpt;
     double* state(int64_t c) const { return base + c * 6 * n; }
     double* centre(int64_t c) const { return base + n_ckpt * 6 * n + 4 * c; }
+    double* aint(int64_t c) const { return base + n_ckpt * (6 * n + 4) + c * 3 * n; }
+    double* aint_final() const { return aint(n_ckpt); }
 };
 
 // Forward integration from (x, v) for n_steps; tape optional.  Positions and
@@ -155,7 +162,11 @@ dnb_status run_forward(dnb_ctx* c, int64_t n, double* pos, double* vel, const do
         a.n = n; a.mass = mass; a.pot = p; a.dt = dt;
         a.x = pos; a.x_out = pos; a.v = vel; a.vh = c->vh; a.with_ext = 1;
         a.cpart_in = cp[q]; a.cpart_out = cp[1 - q]; a.nb_in = nb;
-        if (tape && s < T && s % K == 0) a.tape_state = tape->state(s / K);
+        if (tape && s < T && s % K == 0) {
+            a.tape_state = tape->state(s / K);
+            a.aint_out = tape->aint(s / K);
+        }
+        if (tape && s == T) a.aint_out = tape->aint_final();
         if (tape && s + 1 < T && (s + 1) % K == 0) a.tape_centre_next = tape->centre((s + 1) / K);
         KdkMode mode = (s == 0) ? KDK_FIRST : (s == T ? KDK_LAST : KDK_MID);
         HIP_TRY(launch_kdk(c, mode, a, st));
@@ -259,12 +270,13 @@ dnb_status dnb_accelerations(dnb_ctx* c, int64_t n, const double* pos, const dou
 
 int64_t dnb_tape_doubles(int64_t n, int64_t n_steps, int64_t ckpt_every) {
     if (n < 1 || n_steps < 0 || ckpt_every < 1) return -1;
-    return cdiv(n_steps, ckpt_every) * (6 * n + 4);
+    if (n_steps == 0) return 0;
+    return cdiv(n_steps, ckpt_every) * (9 * n + 4) + 3 * n;
 }
 
 int64_t dnb_vjp_workspace_doubles(int64_t n, int64_t ckpt_every) {
     if (n < 1 || ckpt_every < 1) return -1;
-    return 3 * n * (ckpt_every + 1) + 16 * n;
+    return 3 * n * (ckpt_every + 1) + 16 * n + 3 * n * ckpt_every;
 }
 
 static dnb_status check_sim_args(dnb_ctx* c, int64_t n, const void* pos, const void* vel,
@@ -325,6 +337,7 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
     double* seg = workspace;                         // [(K+1)][3][n]
     double* vrec = workspace + 3 * n * (K + 1);      // [3][n]
     double* accum = vrec + 3 * n;                    // [5][n]
+    double* seg_a = workspace + 3 * n * (K + 1) + 16 * n;   // [K][3][n]
     HIP_TRY(hipMemcpyAsync(lx, gpos_T, vec, hipMemcpyDeviceToDevice, st));
     if (gvel_T) HIP_TRY(hipMemcpyAsync(lv, gvel_T, vec, hipMemcpyDeviceToDevice, st));
     else HIP_TRY(hipMemsetAsync(lv, 0, vec, st));
@@ -338,7 +351,14 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
             if (m % K == 0) return tp.state(m / K);
             return seg + (m % K) * 3 * n;
         };
+        auto get_aint = [&](int64_t m) -> const double* {
+            if (m == T) return tp.aint_final();
+            if (m % K == 0) return tp.aint(m / K);
+            return seg_a + (m % K) * 3 * n;
+        };
         double* cpf[2] = {c->cpart, c->cpart + 4 * c->nbmax};
+        // Positions x_{n0+1} .. x_{n1-1} of segment cs and their internal
+        // accelerations, from its checkpoint, bitwise as in the forward run.
         auto recompute = [&](int64_t cs) -> dnb_status {
             const int64_t n0 = cs * K, n1 = (n0 + K < T) ? n0 + K : T;
             if (n1 - n0 < 2) return DNB_OK;
@@ -346,12 +366,18 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
             if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(x0, n, cpf[0], st));
             HIP_TRY(launch_stage(c, x0, mass, n, nullptr, 0, tp.centre(cs), nullptr, st));
             int q = 0;
-            for (int64_t s = n0; s <= n1 - 2; ++s) {
+            for (int64_t s = n0; s <= n1 - 1; ++s) {
                 double* xc = (s == n0) ? x0 : seg + (s - n0) * 3 * n;
                 HIP_TRY(profiled(c, 0, st, [&] { return launch_pair_fwd(c, n, p.eps, st); }));
                 FwdArgs a{};
                 a.n = n; a.mass = mass; a.pot = p; a.dt = dt; a.with_ext = 1;
-                a.x = xc; a.x_out = seg + (s - n0 + 1) * 3 * n;
+                a.x = xc;
+                a.aint_out = (s == n0) ? nullptr : seg_a + (s - n0) * 3 * n;
+                if (s == n1 - 1) {   // last position of the segment: acceleration only
+                    HIP_TRY(launch_kdk(c, KDK_ACC, a, st));
+                    break;
+                }
+                a.x_out = seg + (s - n0 + 1) * 3 * n;
                 a.v = (s == n0) ? x0 + 3 * n : nullptr;
                 a.vh = vrec;
                 a.cpart_in = cpf[q]; a.cpart_out = cpf[1 - q]; a.nb_in = nb;
@@ -382,6 +408,7 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
             r.coef = (m == T || m == 0) ? 0.5 * dt : dt;
             r.x_n = xm;
             r.x_prev = m > 0 ? get_pos(m - 1) : nullptr;
+            r.aint = get_aint(m);
             r.lx = lx; r.lv = lv; r.accum = accum; r.with_mass = with_mass;
             r.cpart_in = cpv[q]; r.nb_in = nb; r.cpart_out = cpv[1 - q];
             r.wscale_in = c->wscale + wq; r.wscale_out = c->wscale + (1 - wq);

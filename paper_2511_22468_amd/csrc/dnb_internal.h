@@ -206,7 +206,7 @@ struct dnb_ctx {
     // reverse path
     void* jsv;               // staged VJP sources, interleaved per particle:
                              // [2 j] = (x, y, z, m), [2 j + 1] = (w, 0); float4 or double4
-    void* partv;             // VJP partials: FP32C float [S][14][npad], FP64 double [S][7][npad]
+    void* partv;             // VJP partials: FP32C float [S][8][npad], FP64 double [S][4][npad]
     double* cpartv;          // [2][nbmax][4]
     double* wscale;          // [2] cotangent staging scales of the reverse sweep
     float* muni;             // [DNB_BATCH_MAX][2] (flag, m): all masses of the system (or of
@@ -246,7 +246,8 @@ struct FwdArgs {
     double* x_out;      // ... and written (x_{n+1}); may equal x
     double* v;          // [3][n] full-step velocity (FIRST reads, MID/LAST write)
     double* vh;         // [3][n] half-step velocity
-    double* acc_out;    // KDK_ACC: [3][n] output accelerations
+    double* acc_out;    // KDK_ACC: [3][n] output accelerations (nullable)
+    double* aint_out;   // [3][n] internal (pair) acceleration at x, any mode (nullable)
     int with_ext;
     // centre bookkeeping
     const double* cpart_in;   // block sums of x (positions being kicked at)
@@ -282,6 +283,7 @@ struct RevArgs {
     double coef;            // dt or dt/2 for this kick
     const double* x_n;      // positions of the kick
     const double* x_prev;   // positions x_{n-1} (null: no drift, last reverse step)
+    const double* aint;     // [3][n] internal acceleration at x_n (from the forward pass)
     double* lx;             // [3][n] position cotangent (in/out)
     double* lv;             // [3][n] velocity cotangent (in/out)
     double* accum;          // [5][n] per-particle running sums: m_nfw, m_mn, dt, mass scale, mass

@@ -200,6 +200,9 @@ __global__ __launch_bounds__(BS) void k_kdk(FwdArgs a, const void* __restrict__ 
 
     double ax, ay, az;
     pair_sum<F32>(part, S, npad, k, a.pot.G, ax, ay, az);
+    if (a.aint_out && ok) {
+        a.aint_out[i] = ax; a.aint_out[n + i] = ay; a.aint_out[2 * n + i] = az;
+    }
     const double x = a.x[k], y = a.x[n + k], z = a.x[2 * n + k];
     if (a.with_ext) {
         Ext e = ext_accel(a.pot, x, y, z);
@@ -209,7 +212,7 @@ __global__ __launch_bounds__(BS) void k_kdk(FwdArgs a, const void* __restrict__ 
     double xn = x, yn = y, zn = z;
     if (ok) {
         if (MODE == KDK_ACC) {
-            a.acc_out[i] = ax; a.acc_out[n + i] = ay; a.acc_out[2 * n + i] = az;
+            if (a.acc_out) { a.acc_out[i] = ax; a.acc_out[n + i] = ay; a.acc_out[2 * n + i] = az; }
         } else if (MODE == KDK_LAST) {
             a.v[i] = fma(hdt, ax, a.vh[i]);
             a.v[n + i] = fma(hdt, ay, a.vh[n + i]);
@@ -352,31 +355,25 @@ __global__ __launch_bounds__(BS) void k_rev_stage(const double* __restrict__ x,
 // raw mass term sum_j (d.w_j) s^-3/2 (times G).
 template <bool F32>
 __device__ inline void vjp_sum(const void* part, int S, int64_t npad, int64_t i, double G,
-                               bool with_mass, double (&g)[3], double (&a)[3], double& gm) {
-    for (int c = 0; c < 3; ++c) g[c] = a[c] = 0.0;
+                               bool with_mass, double (&g)[3], double& gm) {
+    for (int c = 0; c < 3; ++c) g[c] = 0.0;
     gm = 0.0;
     if (F32) {
         const float* p = (const float*)part;
         for (int s = 0; s < S; ++s) {
-            const float* q = p + (int64_t)s * 14 * npad + i;
-            for (int c = 0; c < 3; ++c) {
-                g[c] += (double)q[c * npad]; g[c] += (double)q[(3 + c) * npad];
-                a[c] += (double)q[(6 + c) * npad]; a[c] += (double)q[(9 + c) * npad];
-            }
-            if (with_mass) { gm += (double)q[12 * npad]; gm += (double)q[13 * npad]; }
+            const float* q = p + (int64_t)s * 8 * npad + i;
+            for (int c = 0; c < 3; ++c) { g[c] += (double)q[c * npad]; g[c] += (double)q[(3 + c) * npad]; }
+            if (with_mass) { gm += (double)q[6 * npad]; gm += (double)q[7 * npad]; }
         }
     } else {
         const double* p = (const double*)part;
         for (int s = 0; s < S; ++s) {
-            const double* q = p + (int64_t)s * 7 * npad + i;
-            for (int c = 0; c < 3; ++c) {
-                g[c] += q[c * npad];
-                a[c] += q[(3 + c) * npad];
-            }
-            if (with_mass) gm += q[6 * npad];
+            const double* q = p + (int64_t)s * 4 * npad + i;
+            for (int c = 0; c < 3; ++c) g[c] += q[c * npad];
+            if (with_mass) gm += q[3 * npad];
         }
     }
-    for (int c = 0; c < 3; ++c) { g[c] *= G; a[c] *= G; }
+    for (int c = 0; c < 3; ++c) g[c] *= G;
     gm *= G;
 }
 
@@ -394,8 +391,9 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
     double cx = 0.0, cy = 0.0, cz = 0.0;
     if (F32 && drift) centre_from(a.cpart_in, a.nb_in, n, sh, cx, cy, cz);
 
-    double g[3], ai[3], gm;
-    vjp_sum<F32>(part, S, npad, k, a.pot.G, a.with_mass != 0, g, ai, gm);
+    double g[3], gm;
+    vjp_sum<F32>(part, S, npad, k, a.pot.G, a.with_mass != 0, g, gm);
+    const double ai[3] = {a.aint[k], a.aint[n + k], a.aint[2 * n + k]};
     if (F32) {
         // undo the power-of-two scale the consumed cotangent was staged with
         const double inv_s = 1.0 / a.wscale_in[0];

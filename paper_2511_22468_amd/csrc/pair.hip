@@ -121,22 +121,26 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f64(const double4* __restrict__
 // --------------------------------------------------------------- VJP FP32C --
 // For target k and cotangent w, with d = x_j - x_k, s = |d|^2 + eps^2:
 //   (J^T w)_k / G = sum_j [s^-3/2 u - 3 s^-5/2 (d.u) d],  u = m_k w_j - m_j w_k
-//   a_int,k / G   = sum_j m_j s^-3/2 d            (needed for the dt and mass terms)
 //   gm_k / G      = sum_j (d.w_j) s^-3/2          (mass cotangent, negated later)
+// The internal acceleration the dt and mass-scale terms need is not summed here:
+// the forward pass stores it with the tape.
 // jsv: interleaved [2 j] = (x, y, z, m), [2 j + 1] = (wx, wy, wz, 0), padded.
-// part: [S][14][npad] floats: JTw hi(3) lo(3), a hi(3) lo(3), gm hi, lo.
-// With UNI (all masses equal to m) u = m (w_j - w_k): the mass leaves the pair
-// term and is applied once per target, 26 VALU operations per pair instead of 33.
+// part: [S][8][npad] floats: JTw hi(3) lo(3), gm hi, lo.
+// The two terms of J^T w are accumulated apart (A = sum s^-3/2 u,
+// B = sum s^-5/2 (d.u) d) and combined as A - 3 B once per sub-tile, which takes
+// the factor -3 out of the pair loop.  With UNI (all masses equal to m)
+// u = m (w_j - w_k): the mass leaves the pair term and is applied once per
+// target, 22 VALU operations and one v_rsq_f32 per pair.
 template <bool EPS0, bool MASS, bool UNI>
 __device__ __forceinline__ void vjp_f32c_slice(const float4* __restrict__ jsv, int i, int j0,
                                                int j1, float eps2, float4 me, float4 mw,
-                                               float (&h)[7], float (&l)[7]) {
+                                               float (&h)[4], float (&l)[4]) {
     constexpr int PB = 4;
     float4 pa[PB], wa[PB];
 #pragma unroll
     for (int u = 0; u < PB; ++u) { pa[u] = jsv[2 * (j0 + u)]; wa[u] = jsv[2 * (j0 + u) + 1]; }
     for (int jt = j0; jt < j1; jt += SUBTILE) {
-        float acc[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float A[3] = {0.f, 0.f, 0.f}, B[3] = {0.f, 0.f, 0.f}, gm = 0.f;
         for (int k = 0; k < SUBTILE; k += PB) {
             const int nx = next_batch(jt, k, PB, j1);
             float4 pb[PB], wb[PB];
@@ -156,25 +160,21 @@ __device__ __forceinline__ void vjp_f32c_slice(const float4* __restrict__ jsv, i
                 const float ux = UNI ? qw.x - mw.x : fmaf(me.w, qw.x, -(q.w * mw.x));
                 const float uy = UNI ? qw.y - mw.y : fmaf(me.w, qw.y, -(q.w * mw.y));
                 const float uz = UNI ? qw.z - mw.z : fmaf(me.w, qw.z, -(q.w * mw.z));
-                const float du = fmaf(dx, ux, fmaf(dy, uy, dz * uz));
-                const float c3 = -3.f * (r5 * du);
-                acc[0] = fmaf(c3, dx, fmaf(r3, ux, acc[0]));
-                acc[1] = fmaf(c3, dy, fmaf(r3, uy, acc[1]));
-                acc[2] = fmaf(c3, dz, fmaf(r3, uz, acc[2]));
-                const float mr3 = UNI ? r3 : q.w * r3;
-                acc[3] = fmaf(mr3, dx, acc[3]);
-                acc[4] = fmaf(mr3, dy, acc[4]);
-                acc[5] = fmaf(mr3, dz, acc[5]);
-                if (MASS) {
-                    const float dw = fmaf(dx, qw.x, fmaf(dy, qw.y, dz * qw.z));
-                    acc[6] = fmaf(dw, r3, acc[6]);
-                }
+                const float t = r5 * fmaf(dx, ux, fmaf(dy, uy, dz * uz));
+                A[0] = fmaf(r3, ux, A[0]);
+                A[1] = fmaf(r3, uy, A[1]);
+                A[2] = fmaf(r3, uz, A[2]);
+                B[0] = fmaf(t, dx, B[0]);
+                B[1] = fmaf(t, dy, B[1]);
+                B[2] = fmaf(t, dz, B[2]);
+                if (MASS) gm = fmaf(fmaf(dx, qw.x, fmaf(dy, qw.y, dz * qw.z)), r3, gm);
             }
 #pragma unroll
             for (int u = 0; u < PB; ++u) { pa[u] = pb[u]; wa[u] = wb[u]; }
         }
 #pragma unroll
-        for (int c = 0; c < (MASS ? 7 : 6); ++c) two_sum_acc(h[c], l[c], acc[c]);
+        for (int c = 0; c < 3; ++c) two_sum_acc(h[c], l[c], fmaf(-3.f, B[c], A[c]));
+        if (MASS) two_sum_acc(h[3], l[3], gm);
     }
 }
 
@@ -189,35 +189,33 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__
     const int ii = min(i, n - 1);
     const float4 me = jsv[2 * ii];
     const float4 mw = jsv[2 * ii + 1];
-    float h[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float l[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float h[4] = {0.f, 0.f, 0.f, 0.f};
+    float l[4] = {0.f, 0.f, 0.f, 0.f};
     if (muni[0] != 0.f) {
         vjp_f32c_slice<EPS0, MASS, true>(jsv, i, j0, j1, eps2, me, mw, h, l);
         const float m = muni[1];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) { h[c] *= m; l[c] *= m; }
+        for (int c = 0; c < 3; ++c) { h[c] *= m; l[c] *= m; }
     } else {
         vjp_f32c_slice<EPS0, MASS, false>(jsv, i, j0, j1, eps2, me, mw, h, l);
     }
     if (i < n) {
-        float* p = part + (int64_t)blockIdx.y * 14 * npad + i;
+        float* p = part + (int64_t)blockIdx.y * 8 * npad + i;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             p[c * npad] = h[c];
             p[(3 + c) * npad] = l[c];
-            p[(6 + c) * npad] = h[3 + c];
-            p[(9 + c) * npad] = l[3 + c];
         }
         if (MASS) {
-            p[12 * npad] = h[6];
-            p[13 * npad] = l[6];
+            p[6 * npad] = h[3];
+            p[7 * npad] = l[3];
         }
     }
 }
 
 // ---------------------------------------------------------------- VJP FP64 --
 // jsv: interleaved double4 [2 j] = (x, y, z, m), [2 j + 1] = (w, 0), padded.
-// part: [S][7][npad] doubles: JTw(3), a(3), gm.
+// part: [S][4][npad] doubles: JTw(3), gm.
 template <bool EPS0, bool MASS>
 __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__ jsv, int n,
                                                      int nj, int jslice, double eps2,
@@ -229,7 +227,7 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__
     const int ii = min(i, n - 1);
     const double4 me = jsv[2 * ii];
     const double4 mw = jsv[2 * ii + 1];
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    double acc[4] = {0, 0, 0, 0};
     double4 pa[PB], wa[PB];
 #pragma unroll
     for (int u = 0; u < PB; ++u) { pa[u] = jsv[2 * (j0 + u)]; wa[u] = jsv[2 * (j0 + u) + 1]; }
@@ -258,13 +256,9 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__
                 acc[0] = fma(c3, dx, fma(r3, ux, acc[0]));
                 acc[1] = fma(c3, dy, fma(r3, uy, acc[1]));
                 acc[2] = fma(c3, dz, fma(r3, uz, acc[2]));
-                const double mr3 = q.w * r3;
-                acc[3] = fma(mr3, dx, acc[3]);
-                acc[4] = fma(mr3, dy, acc[4]);
-                acc[5] = fma(mr3, dz, acc[5]);
                 if (MASS) {
                     const double dw = fma(dx, qw.x, fma(dy, qw.y, dz * qw.z));
-                    acc[6] = fma(dw, r3, acc[6]);
+                    acc[3] = fma(dw, r3, acc[3]);
                 }
             }
 #pragma unroll
@@ -272,10 +266,10 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__
         }
     }
     if (i < n) {
-        double* p = part + (int64_t)blockIdx.y * 7 * npad + i;
+        double* p = part + (int64_t)blockIdx.y * 4 * npad + i;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) p[c * npad] = acc[c];
-        if (MASS) p[6 * npad] = acc[6];
+        for (int c = 0; c < 3; ++c) p[c * npad] = acc[c];
+        if (MASS) p[3 * npad] = acc[3];
     }
 }
 
