@@ -200,6 +200,49 @@ def ensemble(B=512, n=4096, T=200, n_single=8):
                          "speedup": t_single / t_batch}}
 
 
+def orbit_fit(n_starts=1000, n_iter=60, K=32):
+    """The orbit fit of the progenitor: Levenberg-Marquardt from n_starts starts
+    drawn in [theta/2, 2 theta] on a noise-free K-point mock track (2 Gyr forward and
+    backward, 2000 steps each way), then the exact Hessian and the Fisher covariance
+    at the best fit.  Wall time of each part (HIP events) and the recovery error."""
+    import torch
+
+    from paper_2511_22468_amd import engine, orbitfit
+
+    dev = torch.device("cuda", 0)
+    ctx = engine.Context(1024, "fp64")
+    model = orbitfit.TrackModel()
+    p_true = np.log10([1.0e12, 16.0, 6.5e10, 3.0, 0.28])
+    pt = torch.tensor(p_true, device=dev)
+    phi1 = torch.linspace(-1.2, 0.8, K, dtype=torch.float64, device=dev)
+    y = orbitfit.observe(ctx, model, phi1, pt)
+    track = torch.cat([phi1[:, None], y], 1).contiguous()
+    orbitfit.fit(ctx, model, track, p_true, n_starts=64, n_iter=2)     # warm-up
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    rng = np.random.Generator(np.random.PCG64(0))
+    half = np.log10(2.0)
+    p0 = torch.tensor(p_true[None, :] + rng.uniform(-half, half, (n_starts, 5)), device=dev)
+    e[0].record()
+    fits, c = orbitfit.lm(ctx, model, track, p0, n_iter)
+    e[1].record()
+    k = int(torch.argmin(torch.nan_to_num(c, nan=float("inf"))).item())
+    H, C = orbitfit.hessian(ctx, model, track, fits[k:k + 1].contiguous())
+    e[2].record()
+    torch.cuda.synchronize()
+    best = fits[k].cpu().numpy()
+    ok = (c < 1e-10).sum().item()
+    ctx.close()
+    return {"orbit_fit": {"starts": n_starts, "iterations": n_iter, "track_points": K,
+                          "steps_per_branch": model.n_steps,
+                          "lm_seconds": e[0].elapsed_time(e[1]) * 1e-3,
+                          "hessian_and_covariance_seconds": e[1].elapsed_time(e[2]) * 1e-3,
+                          "starts_reaching_chi2_below_1e-10": ok,
+                          "best_chi2": c[k].item(),
+                          "best_minus_true_dex": (best - p_true).tolist(),
+                          "fisher_sigma_dex": np.sqrt(np.diag(C[0].cpu().numpy())).tolist()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,8 +263,11 @@ def main():
     ap.add_argument("--ensemble", action="store_true",
                     help="surrogate training-set generation (512 runs of N = 4096) as one "
                          "batched ensemble vs one run at a time, one JSON line")
+    ap.add_argument("--orbit-fit", action="store_true",
+                    help="orbit fit of the progenitor: Levenberg-Marquardt from 1000 starts, "
+                         "exact Hessian and Fisher covariance, one JSON line")
     args = ap.parse_args()
-    if (args.sweep or args.ensemble) and args.gpus != 1:
+    if (args.sweep or args.ensemble or args.orbit_fit) and args.gpus != 1:
         print("bench.py measures one GPU only (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.sweep:
@@ -229,6 +275,9 @@ def main():
         return
     if args.ensemble:
         print(json.dumps(ensemble()), flush=True)
+        return
+    if args.orbit_fit:
+        print(json.dumps(orbit_fit()), flush=True)
         return
     if args.profile_run:
         args.n_steps, args.steps, args.warmup, args.no_cpu_baseline = 20, 1, 0, True
