@@ -200,6 +200,36 @@ def ensemble(B=512, n=4096, T=200, n_single=8):
                          "speedup": t_single / t_batch}}
 
 
+def cpu_sweep(sizes=(1024, 8192, 16384, 65536), budget_pairs=2.0e8):
+    """The oracle's pair sum at each workload size on one host thread and on all of
+    them (at most 16), on sampled target rows bounded by budget_pairs pairs."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from threadpoolctl import threadpool_limits
+
+    from oracle import forces as of
+    from synth import plummer_unit, sample_rows
+
+    G = 4.3009e-6
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    rows_out = []
+    for n in sizes:
+        xi, _ = plummer_unit(n, 7)
+        x = np.array([12.0, 0.0, 0.0]) + 0.01 * xi
+        m = np.full(n, 1e5 / n)
+        rows = sample_rows(n, int(min(n, max(cores * 64, budget_pairs // n))), 8)
+        out = {"n": n, "rows": int(rows.size)}
+        for threads in (1, cores):
+            chunks = np.array_split(rows, threads * 2)
+            with threadpool_limits(1), ThreadPoolExecutor(threads) as ex:
+                t0 = time.perf_counter()
+                list(ex.map(lambda r: of.pair_accel(x, m, G, 1e-3, rows=r), chunks))
+                dt = time.perf_counter() - t0
+            out[f"pairs_per_s_{threads}_threads"] = rows.size * n / dt
+        rows_out.append(out)
+    return {"cpu_sweep": rows_out, "kind": "oracle", "cores": cores}
+
+
 def orbit_fit(n_starts=1000, n_iter=60, K=32):
     """The orbit fit of the progenitor: Levenberg-Marquardt from n_starts starts
     drawn in [theta/2, 2 theta] on a noise-free K-point mock track (2 Gyr forward and
@@ -266,7 +296,13 @@ def main():
     ap.add_argument("--orbit-fit", action="store_true",
                     help="orbit fit of the progenitor: Levenberg-Marquardt from 1000 starts, "
                          "exact Hessian and Fisher covariance, one JSON line")
+    ap.add_argument("--cpu-sweep", action="store_true",
+                    help="the FP64 oracle's pair sum at every workload size on one and on all "
+                         "host threads, one JSON line (no GPU)")
     args = ap.parse_args()
+    if args.cpu_sweep:
+        print(json.dumps(cpu_sweep()), flush=True)
+        return
     if (args.sweep or args.ensemble or args.orbit_fit) and args.gpus != 1:
         print("bench.py measures one GPU only (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
