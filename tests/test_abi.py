@@ -1,20 +1,43 @@
 """CPU-only checks of the C ABI: the library loads, exports every function that
-include/dnb.h declares, and validates arguments before touching a device."""
+a header under include/ declares, and validates arguments before touching a
+device; the build flags keep packed FP32 off and FMA contraction explicit."""
 import ctypes
+import glob
 import os
 import re
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "dnb.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 LIB = os.path.join(ROOT, "paper_2511_22468_amd", "libdnb.so")
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(dnb_[a-z0-9_]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"\b(dnb_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_all_headers_are_scanned():
+    names = {os.path.basename(h) for h in HEADERS}
+    assert {"dnb.h", "dnb_surrogate.h", "dnb_orbitfit.h"} <= names
+    fns = declared_functions()
+    for must in ("dnb_mlp_forward", "dnb_track_lm", "dnb_simulate_batch", "dnb_mmd_batch"):
+        assert must in fns
+
+
+def test_build_flags():
+    from paper_2511_22468_amd import build
+    flags = " ".join(build.FLAGS)
+    assert "--offload-arch=gfx950" in flags
+    assert "-Xclang -target-feature -Xclang -packed-fp32-ops" in flags
+    assert "-ffp-contract=off" in flags
+    assert set(build.SOURCES) == {os.path.basename(p) for p in
+                                  glob.glob(os.path.join(ROOT, "paper_2511_22468_amd", "csrc",
+                                                         "*.hip"))}
 
 
 @pytest.fixture(scope="module")
@@ -60,6 +83,17 @@ def test_arguments_rejected_before_any_device_work(lib):
     assert b"ctx is NULL" in lib.dnb_last_error()
     assert lib.dnb_simulate(None, 10, None, None, None, ctypes.byref(pot), 0.1, 5, 1, None, None) == _lib.DNB_ERR_ARG
     assert lib.dnb_mmd(None, 1, None, 1, None, 0.2, None, None, None) == _lib.DNB_ERR_ARG
+    table = (ctypes.c_double * 8)(4.3e-6, 1e-3, 1e12, 16.0, 6.5e10, 3.0, 0.28, 0.01)
+    assert lib.dnb_simulate_batch(None, 1, 10, None, None, None, table, 5, None) == _lib.DNB_ERR_ARG
+    assert lib.dnb_orbit_batch(None, 1, None, table, 5, None, None) == _lib.DNB_ERR_ARG
+    assert lib.dnb_mmd_batch(None, 1, 10, None, 10, None, 0.2, None, None) == _lib.DNB_ERR_ARG
+    assert lib.dnb_batch_capacity(None, 10) == 0
+    model = _lib.dnb_track_model()
+    assert lib.dnb_track_chi2(None, ctypes.byref(model), 4, None, 1, None, None, None, None,
+                              None) == _lib.DNB_ERR_ARG
+    assert lib.dnb_track_lm(None, ctypes.byref(model), 4, None, 1, None, 10, 1e-3, None,
+                            None) == _lib.DNB_ERR_ARG
+    assert b"ctx is NULL" in lib.dnb_last_error()
     lib.dnb_destroy(None)
 
 

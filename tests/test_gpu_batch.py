@@ -191,3 +191,33 @@ def test_grid_search_matches_oracle_pipeline(eng):
         xi_p = xi + 6e-8 * np.sqrt((xi ** 2).sum(1))[:, None] * random_directions(n, 50 + b)
         floor = abs(opipe.loss(tuple(thetas[b]), xi_p, zeta, op, T, Y, 0.2) - ref)
         assert abs(losses[b] - ref) <= max(5 * floor, 2e-6), (b, losses[b], ref, floor)
+
+
+def test_single_particle_members_follow_the_host_potential(eng):
+    """n = 1: no pair force (the self term vanishes for eps > 0), so every member is a
+    test particle in its own potential."""
+    pk, engine, ctx = eng
+    B, T = 4, 100
+    rng = np.random.default_rng(12)
+    x = W_X + rng.normal(0, 1, (B, 1, 3))
+    v = W_V + rng.normal(0, 10, (B, 1, 3))
+    ops = [member_pot(b) for b in range(B)]
+    dts = [pk.myr(1.0) * (1 + 0.3 * b) for b in range(B)]
+    px, pv, pm = stack([(x[b], v[b], np.array([5e3])) for b in range(B)])
+    ctx.simulate_batch(px, pv, pm, [gpu_pot(engine, o) for o in ops], dts, T)
+    for b in range(B):
+        xr, vr = oint.simulate(x[b], v[b], np.array([5e3]), ops[b], dts[b], T, self_gravity=False)
+        np.testing.assert_allclose(px[b].cpu().numpy().T, xr, rtol=1e-12)
+        np.testing.assert_allclose(pv[b].cpu().numpy().T, vr, rtol=1e-12)
+    assert ctx.batch_capacity(0) == 0
+
+
+def test_mmd_batch_single_points_closed_form(eng):
+    """n = m = 1: MMD^2 = 2 - 2 exp(-|x - y|^2 / (2 h^2))."""
+    pk, engine, ctx = eng
+    pos = torch.tensor([[[0.0], [0.0], [0.0]], [[0.3], [0.0], [0.0]], [[0.1], [0.2], [-0.2]]],
+                       dtype=torch.float64, device="cuda")
+    tgt = torch.zeros(3, 1, dtype=torch.float64, device="cuda")
+    got = ctx.mmd_batch(pos, tgt, 0.2).cpu().numpy()
+    d2 = (pos.cpu().numpy() ** 2).sum(axis=(1, 2))
+    np.testing.assert_allclose(got, 2 - 2 * np.exp(-d2 / (2 * 0.2 ** 2)), rtol=1e-14, atol=1e-16)

@@ -125,3 +125,25 @@ def test_argument_checks(fx):
     radial = gof.TrackModel(w_now=(12.0, 0, 0, 5.0, 0, 0))
     with pytest.raises(DnbError, match="angular momentum"):
         gof.chi2(ctx, radial, trk, p)
+
+
+def test_single_point_and_unreachable_tracks(fx):
+    gof, ctx, model, track, trk = fx
+    # one track point: chi2 and the exact Hessian still match the oracle
+    one = track[5:6]
+    p = P_TRUE + np.array([0.02, -0.01, 0.01, 0.0, 0.01])
+    c, g, h = gof.chi2(ctx, model, dev(one), dev(p[None]))
+    r, J = oof.jacobian(p, *OARGS(one))
+    np.testing.assert_allclose(c.item(), r @ r, rtol=1e-10)
+    np.testing.assert_allclose(g[0].cpu().numpy(), J.T @ r, rtol=1e-8,
+                               atol=1e-9 * np.abs(J.T @ r).max())
+    # a point the orbit never reaches: chi2 is infinite, the start stays put, the
+    # Hessian is NaN
+    far = np.vstack([track[:3], [[50.0, 0.0, 12.0, 0.0]]])
+    P0 = dev(np.stack([P_TRUE, p]))
+    c, _, _ = gof.chi2(ctx, model, dev(far), P0)
+    assert torch.isinf(c).all()
+    fits, cf = gof.lm(ctx, model, dev(far), P0, n_iter=5)
+    assert torch.equal(fits, P0) and torch.isinf(cf).all()
+    H, C = gof.hessian(ctx, model, dev(far), P0)
+    assert torch.isnan(H).all() and torch.isnan(C).all()
