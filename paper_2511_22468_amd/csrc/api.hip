@@ -202,7 +202,7 @@ dnb_status dnb_create(dnb_ctx** out, int64_t max_n, dnb_prec prec) {
     }
     // Blocks per pair-kernel launch; DNB_TARGET_BLOCKS overrides the tuned
     // default for experiments.
-    c->target_blocks = env_int("DNB_TARGET_BLOCKS", TARGET_BLOCKS, {1024, 2048, 4096, 8192});
+    c->target_blocks = env_int("DNB_TARGET_BLOCKS", TARGET_BLOCKS, {1024, 2048, 4096, 8192, 16384});
     c->slice_rows = max_slice_rows(max_n, BS, c->target_blocks);
     c->nbmax = (int)cdiv(max_n, BS);
     const int64_t npadmax = (int64_t)c->nbmax * BS;
