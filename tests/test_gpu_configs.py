@@ -202,3 +202,49 @@ def test_three_way_precision_n65536():
     assert mmd["fp32c"] <= 3 * mmd["fp64+fp32"] + 1e-9
     for c in ctx.values():
         c.close()
+
+
+def _vjp_scale(x, m, eps, w, rows, block=128):
+    """G sum_j m-weighted magnitudes of the two J^T w terms: the size the pair VJP
+    of each sampled row is summed from."""
+    out = np.zeros(rows.size)
+    for b0 in range(0, rows.size, block):
+        kk = rows[b0:b0 + block]
+        d = x[None, :, :] - x[kk, None, :]
+        s = (d ** 2).sum(-1) + eps * eps
+        u = m[kk, None, None] * w[None, :, :] - m[None, :, None] * w[kk, None, :]
+        un = np.sqrt((u ** 2).sum(-1))
+        dn = np.sqrt((d ** 2).sum(-1))
+        out[b0:b0 + block] = G * (s ** -1.5 * un + 3 * s ** -2.5 * dn * dn * un).sum(1)
+    return out
+
+
+def test_pair_vjp_n65536_sampled_rows():
+    """The adjoint of the N = 65536 workload at full size, through the C ABI: one
+    kick-drift-kick step with a zero velocity cotangent gives exactly
+    gpos_0 = w + (dt^2 / 2) (J_int(x_0)^T w + H_ext(x_0) w), so (gpos_0 - w) / (dt^2 / 2)
+    on 1024 sampled rows is the pair VJP of the launch the benchmark times, compared
+    with the oracle's J^T w of those rows."""
+    import paper_2511_22468_amd as pk
+    from oracle import adjoint as oadj
+    from paper_2511_22468_amd import engine
+    n = 65536
+    x, v, m = plummer_state(n, 4, 1e5)
+    op = OPot(eps=5e-4)
+    pot = gpot(engine, op)
+    w = random_directions(n, 43)
+    rows = sample_rows(n, 1024, 44)
+    ref = oadj.pair_vjp(x, m, G, op.eps, w, rows=rows) + of.ext_hvp(x[rows], w[rows], op)
+    scale = _vjp_scale(x, m, op.eps, w, rows)
+    dt = pk.myr(0.5)
+    for prec, tol in (("fp32c", 1e-5), ("fp64", 1e-11)):
+        c = engine.Context(n, prec)
+        px, pv, pm = to_dev(x), to_dev(v), to_dev(m)
+        tape = c.simulate(px, pv, pm, pot, dt, 1, ckpt_every=1)
+        g0, _, _, _ = c.simulate_vjp(pm, pot, dt, 1, 1, tape, px, to_dev(w))
+        got = (to_host(g0)[rows] - w[rows]) / (0.5 * dt * dt)
+        err = np.sqrt(((got - ref) ** 2).sum(1)) / scale
+        say(f"[cfg] N=65536 pair VJP, 1024 sampled rows, {prec}: max {err.max():.2e} "
+            f"median {np.median(err):.2e} (relative to the summed term magnitudes)")
+        assert err.max() <= tol
+        c.close()
