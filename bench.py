@@ -200,6 +200,72 @@ def ensemble(B=512, n=4096, T=200, n_single=8):
                          "speedup": t_single / t_batch}}
 
 
+def configs():
+    """End-to-end wall time of the three smaller workloads (HIP events, after one
+    warm-up): N = 1024 FP64, 400 steps of 0.5 Myr; N = 16384 FP32C, 4000 steps;
+    N = 8192 stream pipeline, 2000 steps of t_acc / 2000, loss and gradient with
+    checkpoints every 100 steps (FP32C).  One JSON line per workload."""
+    import torch
+
+    from paper_2511_22468_amd import engine, gyr, myr
+    from paper_2511_22468_amd.pipeline import StreamModel, make_target
+    from synth import plummer_unit
+
+    dev = torch.device("cuda", 0)
+    G = 4.3009e-6
+    t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device=dev)
+    out = []
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3, r
+
+    for n, prec, m_tot, T, seed in ((1024, "fp64", 2e4, 400, 1), (16384, "fp32c", 5e4, 4000, 2)):
+        xi, zeta = plummer_unit(n, seed)
+        x = t3(np.array([12.0, 0, 0]) + 0.01 * xi)
+        v = t3(np.array([0, -180.0, 60.0]) + np.sqrt(G * m_tot / 0.01) * zeta)
+        m = torch.full((n,), m_tot / n, dtype=torch.float64, device=dev)
+        ctx = engine.Context(n, prec)
+        pot = engine.Potential(eps=1e-3)
+        state = {}
+
+        def run():
+            state["x"], state["v"] = x.clone(), v.clone()
+            ctx.simulate(state["x"], state["v"], m, pot, myr(0.5), T)
+
+        secs, _ = timed(run)
+        e = ctx.energy(state["x"], state["v"], m, pot).sum().item()
+        e0 = ctx.energy(x, v, m, pot).sum().item()
+        out.append({"workload": f"N={n} {prec} Plummer {m_tot:g} Msun, {T} KDK steps of 0.5 Myr",
+                    "seconds": secs, "pair_interactions_per_s": (T + 1) * n * n / secs,
+                    "energy_drift": (e - e0) / abs(e0)})
+        ctx.close()
+    n, T, K = 8192, 2000, 100
+    ctx = engine.Context(n, "fp32c")
+    xt, zt = plummer_unit(4096, 30)
+    theta_true = torch.tensor([gyr(2.0), 3e4, 1.0e12, 6.5e10], dtype=torch.float64, device=dev)
+    target = make_target(ctx, t3(xt), t3(zt), theta_true, T)
+    xi, zeta = plummer_unit(n, 3)
+    model = StreamModel(ctx, t3(xi), t3(zeta), target, T, ckpt_every=K)
+    theta = theta_true * torch.tensor([1.1, 1.2, 0.9, 1.1], dtype=torch.float64, device=dev)
+    secs, _ = timed(lambda: model.loss_and_grad(theta))
+    # forward: T + 1 pair sums; recompute: K pair sums per segment (K - 1 steps
+    # and the acceleration of the segment's last position), T in all; reverse:
+    # T + 1 pair VJPs
+    pairs = (2 * (T + 1) + T) * n * n
+    out.append({"workload": f"N={n} stream pipeline, {T} steps of t_acc/2000, MMD vs 4096, "
+                            f"loss and gradient, checkpoints every {K} (FP32C)",
+                "seconds": secs, "pair_interactions_per_s": pairs / secs})
+    ctx.close()
+    return out
+
+
 def cpu_sweep(sizes=(1024, 8192, 16384, 65536), budget_pairs=2.0e8):
     """The oracle's pair sum at each workload size on one host thread and on all of
     them (at most 16), on sampled target rows bounded by budget_pairs pairs."""
@@ -296,6 +362,9 @@ def main():
     ap.add_argument("--orbit-fit", action="store_true",
                     help="orbit fit of the progenitor: Levenberg-Marquardt from 1000 starts, "
                          "exact Hessian and Fisher covariance, one JSON line")
+    ap.add_argument("--configs", action="store_true",
+                    help="end-to-end time of the N = 1024, 16384 and 8192 (gradient) workloads, "
+                         "one JSON line each")
     ap.add_argument("--cpu-sweep", action="store_true",
                     help="the FP64 oracle's pair sum at every workload size on one and on all "
                          "host threads, one JSON line (no GPU)")
@@ -303,7 +372,7 @@ def main():
     if args.cpu_sweep:
         print(json.dumps(cpu_sweep()), flush=True)
         return
-    if (args.sweep or args.ensemble or args.orbit_fit) and args.gpus != 1:
+    if (args.sweep or args.ensemble or args.orbit_fit or args.configs) and args.gpus != 1:
         print("bench.py measures one GPU only (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.sweep:
@@ -314,6 +383,10 @@ def main():
         return
     if args.orbit_fit:
         print(json.dumps(orbit_fit()), flush=True)
+        return
+    if args.configs:
+        for row in configs():
+            print(json.dumps(row), flush=True)
         return
     if args.profile_run:
         args.n_steps, args.steps, args.warmup, args.no_cpu_baseline = 20, 1, 0, True

@@ -23,14 +23,14 @@ __device__ __forceinline__ int next_batch(int jt, int k, int PB, int j1) {
 // Sum over the slice [j0, j1) of the staged sources js for target i (position
 // me) into the (hi, lo) pairs: plain FP32 within sub-tiles of 128 sources, TwoSum
 // across them.  Sources are read with wave-uniform addresses (scalar loads), one
-// batch of 8 ahead of use.  With UNI (all masses equal) the mass is left out of
+// batch of 4 ahead of use.  With UNI (all masses equal) the mass is left out of
 // the pair term and applied once by the caller: 11 VALU operations and one
 // v_rsq_f32 per pair instead of 12.
 template <bool EPS0, bool UNI>
 __device__ __forceinline__ void fwd_f32c_slice(const float4* __restrict__ js, int i, int j0,
                                                int j1, float eps2, float4 me, float (&h)[3],
                                                float (&l)[3]) {
-    constexpr int PB = 8;
+    constexpr int PB = 4;
     float4 qa[PB];
 #pragma unroll
     for (int u = 0; u < PB; ++u) qa[u] = js[j0 + u];
