@@ -200,6 +200,48 @@ def ensemble(B=512, n=4096, T=200, n_single=8):
                          "speedup": t_single / t_batch}}
 
 
+def grid(n=1000, T=1000, per_axis=10):
+    """The grid-search stage of the stream inference: the MMD loss of the full
+    pipeline (back-integration, Plummer placement, T kick-drift-kick steps) at
+    per_axis^4 = 10^4 parameter combinations spanning the prior box, with n = 1000
+    particles and 1000 steps as in the paper's inference, against a mock stream
+    generated at known parameters from its own initial-condition seed."""
+    import torch
+
+    from paper_2511_22468_amd import engine, gyr
+    from paper_2511_22468_amd.pipeline import grid_search, make_target
+    from synth import plummer_unit
+
+    dev = torch.device("cuda", 0)
+    t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device=dev)
+    lo = np.array([1.0, 4.0, np.log10(5e11), np.log10(3e10)])
+    hi = np.array([4.0, 5.0, np.log10(2e12), np.log10(1e11)])
+    axes = [np.linspace(lo[k], hi[k], per_axis) for k in range(4)]
+    g = np.stack(np.meshgrid(*axes, indexing="ij"), -1).reshape(-1, 4)
+    thetas = np.column_stack([[gyr(t) for t in g[:, 0]], 10 ** g[:, 1], 10 ** g[:, 2],
+                              10 ** g[:, 3]])
+    k_true = np.ravel_multi_index((6, 5, 4, 5), (per_axis,) * 4)
+    pot = engine.Potential(eps=1e-3)
+    ctx = engine.Context(4096 * 1024, "fp32c")
+    xt, zt = plummer_unit(n, 71)
+    xi, zeta = plummer_unit(n, 72)
+    target = make_target(ctx, t3(xt), t3(zt), torch.tensor(thetas[k_true], device=dev), T,
+                         pot=pot)
+    grid_search(ctx, thetas[:64], t3(xi), t3(zeta), target, T, pot)      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = grid_search(ctx, thetas, t3(xi), t3(zeta), target, T, pot)
+    secs = time.perf_counter() - t0
+    ctx.close()
+    best = int(np.argmin(losses))
+    return {"grid_search": {"points": len(thetas), "n": n, "steps": T, "seconds": secs,
+                            "pair_interactions_per_s": len(thetas) * (T + 1) * n * n / secs,
+                            "true_point": int(k_true), "best_point": best,
+                            "best_loss": float(losses[best]),
+                            "loss_at_true_point": float(losses[k_true]),
+                            "rank_of_true_point": int((losses < losses[k_true]).sum())}}
+
+
 def configs():
     """End-to-end wall time of the three smaller workloads (HIP events, after one
     warm-up): N = 1024 FP64, 400 steps of 0.5 Myr; N = 16384 FP32C, 4000 steps;
@@ -362,6 +404,9 @@ def main():
     ap.add_argument("--orbit-fit", action="store_true",
                     help="orbit fit of the progenitor: Levenberg-Marquardt from 1000 starts, "
                          "exact Hessian and Fisher covariance, one JSON line")
+    ap.add_argument("--grid", action="store_true",
+                    help="grid-search stage of the stream inference: the pipeline loss at "
+                         "10^4 parameter combinations (N = 1000, 1000 steps), one JSON line")
     ap.add_argument("--configs", action="store_true",
                     help="end-to-end time of the N = 1024, 16384 and 8192 (gradient) workloads, "
                          "one JSON line each")
@@ -372,7 +417,8 @@ def main():
     if args.cpu_sweep:
         print(json.dumps(cpu_sweep()), flush=True)
         return
-    if (args.sweep or args.ensemble or args.orbit_fit or args.configs) and args.gpus != 1:
+    if (args.sweep or args.ensemble or args.orbit_fit or args.configs or args.grid) \
+            and args.gpus != 1:
         print("bench.py measures one GPU only (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.sweep:
@@ -383,6 +429,9 @@ def main():
         return
     if args.orbit_fit:
         print(json.dumps(orbit_fit()), flush=True)
+        return
+    if args.grid:
+        print(json.dumps(grid()), flush=True)
         return
     if args.configs:
         for row in configs():

@@ -211,6 +211,16 @@ dnb_status dnb_simulate_batch(dnb_ctx* ctx, int64_t batch, int64_t n, double* po
 dnb_status dnb_mmd_batch(dnb_ctx* ctx, int64_t batch, int64_t n, const double* pos, int64_t m,
                          const double* tgt, double h, double* loss, void* stream);
 
+/* Plummer spheres for every member of an ensemble (the batched form of
+ * dnb_place_plummer, Fig. 2 step 3): member b is centred on w[b] ([batch][6],
+ * device) with total mass m_tot[b] ([batch], device, > 0); the unit samples xi,
+ * zeta [3][n] are shared.  Outputs pos, vel [batch][3][n] and mass [batch][n]:
+ * pos = w_x + a_p xi, vel = w_v + sqrt(G m_tot / a_p) zeta, mass = m_tot / n. */
+dnb_status dnb_place_plummer_batch(dnb_ctx* ctx, int64_t batch, int64_t n, const double* w,
+                                   const double* xi, const double* zeta, const double* m_tot,
+                                   double a_p, double G, double* pos, double* vel, double* mass,
+                                   void* stream);
+
 /* Largest batch of systems of n particles that dnb_simulate_batch accepts on
  * this context (0 if ctx is NULL or n < 1).  Host arithmetic only. */
 int64_t dnb_batch_capacity(const dnb_ctx* ctx, int64_t n);

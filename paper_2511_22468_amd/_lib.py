@@ -60,6 +60,7 @@ def load_library(path=LIB_PATH):
         "dnb_place_plummer_vjp": ([P, I64, P, D, D, D, P, P, P, P, P, P], I),
         "dnb_simulate_batch": ([P, I64, I64, P, P, P, ctypes.POINTER(ctypes.c_double), I64, P], I),
         "dnb_batch_capacity": ([P, I64], I64),
+        "dnb_place_plummer_batch": ([P, I64, I64, P, P, P, P, D, D, P, P, P, P], I),
         "dnb_mmd_batch": ([P, I64, I64, P, I64, P, D, P, P], I),
         "dnb_orbit_batch": ([P, I64, P, ctypes.POINTER(ctypes.c_double), I64, P, P], I),
         "dnb_profile": ([P, I], I),

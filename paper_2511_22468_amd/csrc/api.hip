@@ -539,6 +539,30 @@ dnb_status dnb_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* pos
     return DNB_OK;
 }
 
+dnb_status dnb_place_plummer_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* w,
+                                   const double* xi, const double* zeta, const double* m_tot,
+                                   double a_p, double G, double* pos, double* vel, double* mass,
+                                   void* stream) {
+    const char* fn = "dnb_place_plummer_batch";
+    CHECK(check_ctx(c, 1, fn));
+    if (batch < 1 || batch > DNB_BATCH_MAX)
+        return fail(DNB_ERR_ARG, "%s: batch = %lld outside [1, %d]", fn, (long long)batch,
+                    DNB_BATCH_MAX);
+    if (n < 1) return fail(DNB_ERR_ARG, "%s: n must be >= 1", fn);
+    if (!(a_p > 0) || !(G > 0) || !is_fin(a_p) || !is_fin(G))
+        return fail(DNB_ERR_ARG, "%s: a_p and G must be finite and > 0", fn);
+    CHECK(check_dev(w, "w", fn));
+    CHECK(check_dev(xi, "xi", fn));
+    CHECK(check_dev(zeta, "zeta", fn));
+    CHECK(check_dev(m_tot, "m_tot", fn));
+    CHECK(check_dev(pos, "pos", fn));
+    CHECK(check_dev(vel, "vel", fn));
+    CHECK(check_dev(mass, "mass", fn));
+    HIP_TRY(launch_place_batch(batch, n, w, xi, zeta, m_tot, a_p, G, pos, vel, mass,
+                               (hipStream_t)stream));
+    return DNB_OK;
+}
+
 int64_t dnb_batch_capacity(const dnb_ctx* c, int64_t n) {
     if (!c || n < 1) return 0;
     int64_t b = c->max_n / n + 1;

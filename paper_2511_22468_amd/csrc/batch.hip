@@ -220,6 +220,39 @@ __global__ void k_batch_orbit(const double* __restrict__ w0, const double* __res
     o[0] = x; o[1] = y; o[2] = z; o[3] = vx; o[4] = vy; o[5] = vz;
 }
 
+// Plummer spheres of every member placed at their own phase-space points (the
+// batched form of k_place): the unit samples xi, zeta [3][n] are shared, member b
+// has centre w[b] [6] and total mass m_tot[b].  grid (cdiv(n, BS), batch).
+__global__ __launch_bounds__(BS) void k_batch_place(int64_t n, const double* __restrict__ w,
+                                                    const double* __restrict__ xi,
+                                                    const double* __restrict__ zeta,
+                                                    const double* __restrict__ m_tot, double a_p,
+                                                    double G, double* __restrict__ pos,
+                                                    double* __restrict__ vel,
+                                                    double* __restrict__ mass) {
+    const int64_t b = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    const double M = m_tot[b];
+    const double vscale = sqrt(G * M / a_p);
+    const double* wb = w + 6 * b;
+    double* x = pos + b * 3 * n;
+    double* v = vel + b * 3 * n;
+    for (int c = 0; c < 3; ++c) {
+        x[c * n + i] = wb[c] + a_p * xi[c * n + i];
+        v[c * n + i] = wb[3 + c] + vscale * zeta[c * n + i];
+    }
+    mass[b * n + i] = M / (double)n;
+}
+
+hipError_t launch_place_batch(int64_t batch, int64_t n, const double* w, const double* xi,
+                              const double* zeta, const double* m_tot, double a_p, double G,
+                              double* pos, double* vel, double* mass, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_place, dim3((unsigned)cdiv(n, BS), (unsigned)batch), dim3(BS), 0,
+                       st, n, w, xi, zeta, m_tot, a_p, G, pos, vel, mass);
+    return hipGetLastError();
+}
+
 BatchGeom batch_geom(const dnb_ctx* c, int64_t batch, int64_t n) {
     BatchGeom g;
     g.n = (int)n;

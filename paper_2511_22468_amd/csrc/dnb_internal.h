@@ -323,6 +323,9 @@ hipError_t launch_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* p
                                  hipStream_t st);
 hipError_t launch_orbit_batch(int64_t batch, const double* w0, const double* params_dev,
                               int64_t n_steps, double* w_out, hipStream_t st);
+hipError_t launch_place_batch(int64_t batch, int64_t n, const double* w, const double* xi,
+                              const double* zeta, const double* m_tot, double a_p, double G,
+                              double* pos, double* vel, double* mass, hipStream_t st);
 bool mmd_batch_fits(const dnb_ctx* c, int64_t batch, int64_t n, int64_t m);
 
 // Orbit fit (orbitfit.hip).  The model struct is declared in dnb_orbitfit.h.

@@ -206,6 +206,18 @@ class Context:
                                             float(h), _lib.ptr(loss), _lib.stream_handle()))
         return loss
 
+    def place_plummer_batch(self, w, xi, zeta, m_tot, a_p, G=G_DEFAULT):
+        """Plummer spheres at w (B, 6) with masses m_tot (B,), shared unit samples
+        xi, zeta (3, n): (pos (B, 3, n), vel (B, 3, n), mass (B, n))."""
+        B, n = w.shape[0], xi.shape[1]
+        _arr(w, (B, 6), "w"); _vec(xi, n, "xi"); _vec(zeta, n, "zeta"); _arr(m_tot, (B,), "m_tot")
+        pos, vel, mass = self._new(B, 3, n), self._new(B, 3, n), self._new(B, n)
+        _lib.check(_lib.lib().dnb_place_plummer_batch(
+            self._h, B, n, _lib.ptr(w), _lib.ptr(xi), _lib.ptr(zeta), _lib.ptr(m_tot),
+            float(a_p), float(G), _lib.ptr(pos), _lib.ptr(vel), _lib.ptr(mass),
+            _lib.stream_handle()))
+        return pos, vel, mass
+
     def batch_capacity(self, n):
         """Largest ensemble of n-particle systems that simulate_batch accepts."""
         return int(_lib.lib().dnb_batch_capacity(self._h, int(n)))

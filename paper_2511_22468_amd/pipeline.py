@@ -60,8 +60,7 @@ def run_ensemble(engine_ctx, thetas, xi, zeta, n_steps, pot=None, a_p=0.01, w_no
     """Final positions of pipeline runs at many parameter rows, advanced as
     batched ensembles (FP32C pair terms).  thetas: (M, 4) host array of
     (t_end [internal], M_Plummer, M_NFW, M_MN).  Yields (first row, positions
-    (B, 3, n)) per chunk of as many members as the context holds; the positions
-    tensor is reused by the next chunk."""
+    (B, 3, n)) per chunk of as many members as the context holds."""
     pot = pot if pot is not None else Potential()
     dev = xi.device
     th = np.asarray(thetas, float).reshape(-1, 4)
@@ -72,19 +71,16 @@ def run_ensemble(engine_ctx, thetas, xi, zeta, n_steps, pot=None, a_p=0.01, w_no
     if cap < 1:
         raise ValueError(f"the context cannot hold one system of {n} particles")
     cap = min(cap, M)
-    pos = torch.empty(cap, 3, n, dtype=torch.float64, device=dev)
-    vel, mass = torch.empty_like(pos), torch.empty(cap, n, dtype=torch.float64, device=dev)
     w_now_t = torch.tensor(w_now, dtype=torch.float64, device=dev)
+    m_prog = torch.tensor(th[:, 1], dtype=torch.float64, device=dev)
     for s in range(0, M, cap):
         e = min(M, s + cap)
-        B = e - s
-        w0 = w_now_t.repeat(B, 1)
+        w0 = w_now_t.repeat(e - s, 1)
         w_init = engine_ctx.orbit_batch(w0, pots[s:e], [-d for d in dts[s:e]], n_steps)
-        for b in range(B):
-            p, v, m = engine_ctx.place_plummer(w_init[b], xi, zeta, th[s + b, 1], a_p, pots[s + b].G)
-            pos[b].copy_(p); vel[b].copy_(v); mass[b].copy_(m)
-        engine_ctx.simulate_batch(pos[:B], vel[:B], mass[:B], pots[s:e], dts[s:e], n_steps)
-        yield s, pos[:B]
+        pos, vel, mass = engine_ctx.place_plummer_batch(w_init, xi, zeta, m_prog[s:e].contiguous(),
+                                                        a_p, pot.G)
+        engine_ctx.simulate_batch(pos, vel, mass, pots[s:e], dts[s:e], n_steps)
+        yield s, pos
 
 
 def grid_search(engine_ctx, thetas, xi, zeta, target, n_steps, pot=None, h=0.2, a_p=0.01,

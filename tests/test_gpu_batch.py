@@ -221,3 +221,18 @@ def test_mmd_batch_single_points_closed_form(eng):
     got = ctx.mmd_batch(pos, tgt, 0.2).cpu().numpy()
     d2 = (pos.cpu().numpy() ** 2).sum(axis=(1, 2))
     np.testing.assert_allclose(got, 2 - 2 * np.exp(-d2 / (2 * 0.2 ** 2)), rtol=1e-14, atol=1e-16)
+
+
+def test_place_plummer_batch_equals_single_placements(eng):
+    pk, engine, ctx = eng
+    n, B = 700, 5
+    xi, zeta = plummer_unit(n, 61)
+    t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device="cuda")
+    rng = np.random.default_rng(62)
+    w = torch.tensor(np.concatenate([W_X + rng.normal(0, 1, (B, 3)),
+                                     W_V + rng.normal(0, 10, (B, 3))], 1), device="cuda")
+    m = torch.tensor(rng.uniform(1e4, 1e5, B), device="cuda")
+    pos, vel, mass = ctx.place_plummer_batch(w, t3(xi), t3(zeta), m, 0.01, G)
+    for b in range(B):
+        p, v, mm = ctx.place_plummer(w[b], t3(xi), t3(zeta), m[b].item(), 0.01, G)
+        assert torch.equal(p, pos[b]) and torch.equal(v, vel[b]) and torch.equal(mm, mass[b])
