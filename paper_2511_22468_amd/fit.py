@@ -164,5 +164,7 @@ def run(quick=False, seed=50):
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--seed", type=int, default=50,
+                    help="seed of the priors draw; the held-out target uses seed + 1")
     a = ap.parse_args()
-    print(json.dumps(run(a.quick)), flush=True)
+    print(json.dumps(run(a.quick, a.seed)), flush=True)
