@@ -190,7 +190,8 @@ dnb_status dnb_place_plummer_vjp(dnb_ctx* ctx, int64_t n, const double* zeta, do
  * pos[b] and vel[b] ([batch][3][n], device), mass[b] ([batch][n], device) and
  * the row params[b] of a HOST table [batch][8] = (G, eps, m_nfw, rs_nfw, m_mn,
  * a_mn, b_mn, dt).  Every member takes n_steps kick-drift-kick steps of its own
- * dt in place; there is no tape and no VJP.  Pair terms use the DNB_FP32C
+ * dt in place; with tape not NULL (dnb_batch_tape_doubles) every step is
+ * recorded for dnb_simulate_batch_vjp.  Pair terms use the DNB_FP32C
  * arithmetic whatever the context's precision, so every eps must be > 0.
  * The table is copied to the context before the call returns; the copy waits
  * for work already queued on the stream.  The ensemble must fit the context:
@@ -200,7 +201,28 @@ dnb_status dnb_place_plummer_vjp(dnb_ctx* ctx, int64_t n, const double* zeta, do
 
 dnb_status dnb_simulate_batch(dnb_ctx* ctx, int64_t batch, int64_t n, double* pos, double* vel,
                               const double* mass, const double* params, int64_t n_steps,
-                              void* stream);
+                              double* tape, void* stream);
+
+/* Number of doubles of the tape dnb_simulate_batch writes when tape is not NULL:
+ * every step is kept, the states (x, v) of steps 0 .. T-1 ([T][batch][6][n]) and
+ * the internal accelerations of steps 0 .. T ([T+1][batch][3][n]); 0 for T = 0,
+ * -1 for invalid sizes. */
+int64_t dnb_batch_tape_doubles(int64_t batch, int64_t n, int64_t n_steps);
+
+/* Reverse-mode gradient through dnb_simulate_batch for every member (the
+ * batched form of dnb_simulate_vjp: the same discrete adjoint, member by member,
+ * FP32C pair terms).  Inputs: the same batch, n, mass, params (HOST table) and
+ * n_steps >= 1 as the forward call, its tape, the final positions pos_T
+ * [batch][3][n] and the loss cotangents gpos_T, gvel_T [batch][3][n] (gvel_T may
+ * be NULL).  workspace: 4 batch n doubles.  Outputs gpos_0, gvel_0 [batch][3][n]
+ * and gparams [batch][4] (device) = per member (dL/dm_nfw, dL/dm_mn, dL/ddt,
+ * sum_k m_k dL/dm_k).  No per-particle mass gradient.  Outputs must not alias
+ * inputs. */
+dnb_status dnb_simulate_batch_vjp(dnb_ctx* ctx, int64_t batch, int64_t n, const double* mass,
+                                  const double* params, int64_t n_steps, const double* tape,
+                                  const double* pos_T, const double* gpos_T, const double* gvel_T,
+                                  double* workspace, double* gpos_0, double* gvel_0,
+                                  double* gparams, void* stream);
 
 /* Loss of every member of an ensemble against one target (the grid-search stage
  * of the inference pipeline, Sec. 2.2.1: the MMD between simulated and observed

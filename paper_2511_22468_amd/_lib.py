@@ -58,7 +58,11 @@ def load_library(path=LIB_PATH):
         "dnb_orbit_vjp": ([P, P, POT, D, I64, P, P, P, P], I),
         "dnb_place_plummer": ([P, I64, P, P, P, D, D, D, P, P, P, P], I),
         "dnb_place_plummer_vjp": ([P, I64, P, D, D, D, P, P, P, P, P, P], I),
-        "dnb_simulate_batch": ([P, I64, I64, P, P, P, ctypes.POINTER(ctypes.c_double), I64, P], I),
+        "dnb_simulate_batch": ([P, I64, I64, P, P, P, ctypes.POINTER(ctypes.c_double), I64, P, P],
+                               I),
+        "dnb_batch_tape_doubles": ([I64, I64, I64], I64),
+        "dnb_simulate_batch_vjp": ([P, I64, I64, P, ctypes.POINTER(ctypes.c_double), I64, P, P, P,
+                                    P, P, P, P, P, P], I),
         "dnb_batch_capacity": ([P, I64], I64),
         "dnb_place_plummer_batch": ([P, I64, I64, P, P, P, P, D, D, P, P, P, P], I),
         "dnb_mmd_batch": ([P, I64, I64, P, I64, P, D, P, P], I),

@@ -217,6 +217,7 @@ dnb_status dnb_create(dnb_ctx** out, int64_t max_n, dnb_prec prec) {
         {(void**)&c->wscale, sizeof(double) * 2},
         {(void**)&c->muni, sizeof(float) * 2 * DNB_BATCH_MAX},
         {(void**)&c->bparams, sizeof(double) * 8 * DNB_BATCH_MAX},
+        {(void**)&c->bwscale, sizeof(double) * 2 * DNB_BATCH_MAX},
         {(void**)&c->red, sizeof(double) * 8 * (c->nbmax + 8)},
     };
     for (auto& a : allocs) {
@@ -240,7 +241,7 @@ void dnb_destroy(dnb_ctx* c) {
         delete pf;
     }
     void* ps[] = {c->js, c->part, c->cpart, c->vh, c->jsv, c->partv, c->cpartv, c->wscale, c->muni,
-                  c->bparams, c->red};
+                  c->bparams, c->bwscale, c->red};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     delete c;
@@ -482,7 +483,8 @@ dnb_status dnb_orbit_vjp(dnb_ctx* c, const double* traj, const dnb_pot* pot, dou
 
 // Validates the host parameter table of a batch and copies it to c->bparams.
 static dnb_status put_batch_params(dnb_ctx* c, int64_t batch, const double* params,
-                                   bool need_eps, hipStream_t st, const char* fn) {
+                                   bool need_eps, hipStream_t st, const char* fn,
+                                   bool need_dt = false) {
     if (batch < 1 || batch > DNB_BATCH_MAX)
         return fail(DNB_ERR_ARG, "%s: batch = %lld outside [1, %d]", fn, (long long)batch,
                     DNB_BATCH_MAX);
@@ -499,15 +501,23 @@ static dnb_status put_batch_params(dnb_ctx* c, int64_t batch, const double* para
         if (!is_fin(r[7])) return fail(DNB_ERR_ARG, "%s: member %lld: dt is not finite", fn, (long long)b);
         if (need_eps && !(r[1] > 0))
             return fail(DNB_ERR_ARG, "%s: member %lld: eps must be > 0", fn, (long long)b);
+        if (need_dt && r[7] == 0.0)
+            return fail(DNB_ERR_ARG, "%s: member %lld: dt must be non-zero", fn, (long long)b);
     }
     HIP_TRY(hipMemcpyAsync(c->bparams, params, sizeof(double) * 8 * batch, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     return DNB_OK;
 }
 
+int64_t dnb_batch_tape_doubles(int64_t batch, int64_t n, int64_t n_steps) {
+    if (batch < 1 || n < 1 || n_steps < 0) return -1;
+    if (n_steps == 0) return 0;
+    return (6 * n_steps + 3 * (n_steps + 1)) * batch * n;
+}
+
 dnb_status dnb_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* pos, double* vel,
                               const double* mass, const double* params, int64_t n_steps,
-                              void* stream) {
+                              double* tape, void* stream) {
     const char* fn = "dnb_simulate_batch";
     CHECK(check_ctx(c, 1, fn));
     if (n < 1) return fail(DNB_ERR_ARG, "%s: n must be >= 1", fn);
@@ -518,9 +528,45 @@ dnb_status dnb_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* pos,
     CHECK(check_dev(pos, "pos", fn));
     CHECK(check_dev(vel, "vel", fn));
     CHECK(check_dev(mass, "mass", fn));
+    CHECK(check_dev(tape, "tape", fn, true));
     hipStream_t st = (hipStream_t)stream;
     CHECK(put_batch_params(c, batch, params, true, st, fn));
-    HIP_TRY(launch_simulate_batch(c, batch, n, pos, vel, mass, c->bparams, n_steps, st));
+    HIP_TRY(launch_simulate_batch(c, batch, n, pos, vel, mass, c->bparams, n_steps, tape, st));
+    return DNB_OK;
+}
+
+dnb_status dnb_simulate_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const double* mass,
+                                  const double* params, int64_t n_steps, const double* tape,
+                                  const double* pos_T, const double* gpos_T, const double* gvel_T,
+                                  double* workspace, double* gpos_0, double* gvel_0,
+                                  double* gparams, void* stream) {
+    const char* fn = "dnb_simulate_batch_vjp";
+    CHECK(check_ctx(c, 1, fn));
+    if (n < 1) return fail(DNB_ERR_ARG, "%s: n must be >= 1", fn);
+    if (n_steps < 1) return fail(DNB_ERR_ARG, "%s: n_steps must be >= 1", fn);
+    if (batch >= 1 && batch <= DNB_BATCH_MAX && !batch_fits(c, batch, n))
+        return fail(DNB_ERR_ARG, "%s: batch %lld x n %lld does not fit a context of max_n = %lld",
+                    fn, (long long)batch, (long long)n, (long long)c->max_n);
+    CHECK(check_dev(mass, "mass", fn));
+    CHECK(check_dev(tape, "tape", fn));
+    CHECK(check_dev(pos_T, "pos_T", fn));
+    CHECK(check_dev(gpos_T, "gpos_T", fn));
+    CHECK(check_dev(gvel_T, "gvel_T", fn, true));
+    CHECK(check_dev(workspace, "workspace", fn));
+    CHECK(check_dev(gpos_0, "gpos_0", fn));
+    CHECK(check_dev(gvel_0, "gvel_0", fn));
+    CHECK(check_dev(gparams, "gparams", fn));
+    if (gpos_0 == gpos_T || gvel_0 == gvel_T || gpos_0 == gvel_0)
+        return fail(DNB_ERR_ARG, "%s: outputs must not alias inputs", fn);
+    hipStream_t st = (hipStream_t)stream;
+    CHECK(put_batch_params(c, batch, params, true, st, fn, true));
+    const size_t vec = sizeof(double) * 3 * n * batch;
+    HIP_TRY(hipMemcpyAsync(gpos_0, gpos_T, vec, hipMemcpyDeviceToDevice, st));
+    if (gvel_T) HIP_TRY(hipMemcpyAsync(gvel_0, gvel_T, vec, hipMemcpyDeviceToDevice, st));
+    else HIP_TRY(hipMemsetAsync(gvel_0, 0, vec, st));
+    HIP_TRY(hipMemsetAsync(workspace, 0, sizeof(double) * 4 * n * batch, st));
+    HIP_TRY(launch_simulate_batch_vjp(c, batch, n, mass, c->bparams, n_steps, tape, pos_T,
+                                      workspace, gpos_0, gvel_0, gparams, st));
     return DNB_OK;
 }
 

@@ -10,6 +10,7 @@
 // accumulation (the FP32C path), drift FP64, exactly as for a single system; the
 // per-target slice sums reuse the single-system device code.
 #include "dnb_internal.h"
+#include "kdk_common.h"
 #include "pair_common.h"
 
 namespace dnb {
@@ -21,6 +22,16 @@ struct BatchGeom {
     int nblk;         // target blocks per member (BS targets each)
     int64_t npad;     // partial row stride per member
     int nb;           // O(N) blocks per member
+};
+
+// Tape of a batched run (every step kept): the states (x, v) of steps
+// 0 .. T-1 as [T][batch][6][n], then the internal accelerations of steps 0 .. T
+// as [T+1][batch][3][n].
+struct BatchTape {
+    double* base;
+    int64_t batch, n, T;
+    double* state(int64_t s) const { return base + s * batch * 6 * n; }
+    double* aint(int64_t s) const { return base + T * batch * 6 * n + s * batch * 3 * n; }
 };
 
 constexpr float BFAR32 = 1.0e18f;
@@ -141,7 +152,9 @@ __global__ __launch_bounds__(BS) void k_batch_kdk(double* __restrict__ pos,
                                                   const float* __restrict__ part,
                                                   const double* __restrict__ cp_in,
                                                   double* __restrict__ cp_out,
-                                                  float4* __restrict__ js) {
+                                                  float4* __restrict__ js,
+                                                  double* __restrict__ tape_state,
+                                                  double* __restrict__ aint_out) {
     __shared__ double sh[3 * BS];
     const int b = blockIdx.y;
     const int n = g.n;
@@ -164,6 +177,10 @@ __global__ __launch_bounds__(BS) void k_batch_kdk(double* __restrict__ pos,
         az += (double)q[2 * g.npad]; az += (double)q[5 * g.npad];
     }
     ax *= pot.G; ay *= pot.G; az *= pot.G;
+    if (aint_out && ok) {
+        double* t = aint_out + (int64_t)b * 3 * n;
+        t[i] = ax; t[n + i] = ay; t[2 * n + i] = az;
+    }
     const double x0 = x[k], y0 = x[n + k], z0 = x[2 * n + k];
     const Ext e = ext_accel(pot, x0, y0, z0);
     ax += e.ax; ay += e.ay; az += e.az;
@@ -177,6 +194,11 @@ __global__ __launch_bounds__(BS) void k_batch_kdk(double* __restrict__ pos,
             double vx, vy, vz;
             if (MODE == 0) { vx = v[i]; vy = v[n + i]; vz = v[2 * n + i]; }
             else { vx = fma(hdt, ax, w[i]); vy = fma(hdt, ay, w[n + i]); vz = fma(hdt, az, w[2 * n + i]); }
+            if (tape_state) {
+                double* t = tape_state + (int64_t)b * 6 * n;
+                t[i] = x0; t[n + i] = y0; t[2 * n + i] = z0;
+                t[3 * n + i] = vx; t[4 * n + i] = vy; t[5 * n + i] = vz;
+            }
             const double hx = fma(hdt, ax, vx), hy = fma(hdt, ay, vy), hz = fma(hdt, az, vz);
             xn = fma(dt, hx, x0); yn = fma(dt, hy, y0); zn = fma(dt, hz, z0);
             w[i] = hx; w[n + i] = hy; w[2 * n + i] = hz;
@@ -280,7 +302,7 @@ bool batch_fits(const dnb_ctx* c, int64_t batch, int64_t n) {
 
 hipError_t launch_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* pos, double* vel,
                                  const double* mass, const double* params_dev, int64_t n_steps,
-                                 hipStream_t st) {
+                                 double* tape, hipStream_t st) {
     if (n_steps == 0) return hipSuccess;
     const BatchGeom g = batch_geom(c, batch, n);
     float4* js = (float4*)c->js;
@@ -291,21 +313,245 @@ hipError_t launch_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* p
                        c->muni);
     hipLaunchKernelGGL(k_batch_block_sums, on, dim3(BS), 0, st, pos, g.n, g.nb, cp[0]);
     hipLaunchKernelGGL(k_batch_stage, on, dim3(BS), 0, st, pos, mass, g, cp[0], js);
+    const BatchTape tp{tape, batch, n, n_steps};
     int q = 0;
     for (int64_t s = 0; s <= n_steps; ++s) {
         hipLaunchKernelGGL(k_batch_pair_fwd, dim3(g.nblk, g.S, (unsigned)batch), dim3(BS), 0, st,
                            js, g, params_dev, c->muni, part);
+        double* ts = (tape && s < n_steps) ? tp.state(s) : nullptr;
+        double* ta = tape ? tp.aint(s) : nullptr;
         if (s == 0)
             hipLaunchKernelGGL(k_batch_kdk<0>, on, dim3(BS), 0, st, pos, vel, c->vh, mass, g,
-                               params_dev, part, cp[q], cp[1 - q], js);
+                               params_dev, part, cp[q], cp[1 - q], js, ts, ta);
         else if (s == n_steps)
             hipLaunchKernelGGL(k_batch_kdk<2>, on, dim3(BS), 0, st, pos, vel, c->vh, mass, g,
-                               params_dev, part, cp[q], cp[1 - q], js);
+                               params_dev, part, cp[q], cp[1 - q], js, ts, ta);
         else
             hipLaunchKernelGGL(k_batch_kdk<1>, on, dim3(BS), 0, st, pos, vel, c->vh, mass, g,
-                               params_dev, part, cp[q], cp[1 - q], js);
+                               params_dev, part, cp[q], cp[1 - q], js, ts, ta);
         q = 1 - q;
     }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ batched VJP --
+// The reverse sweep of dnb_simulate_vjp (every step on the tape, FP32C), member by
+// member with the same arithmetic and reduction order, so a member's gradient
+// equals that of a single-system run with the same source slicing bit for bit.
+
+// Stage the final positions and the velocity cotangent.  grid (nb, batch).
+__global__ __launch_bounds__(BS) void k_batch_rev_stage(const double* __restrict__ pos,
+                                                        const double* __restrict__ mass,
+                                                        const double* __restrict__ w, BatchGeom g,
+                                                        const double* __restrict__ cpart,
+                                                        float4* __restrict__ jsv,
+                                                        double* __restrict__ cpart_out,
+                                                        double* __restrict__ wscale) {
+    __shared__ double sh[3 * BS];
+    const int64_t b = blockIdx.y;
+    const int64_t n = g.n;
+    const double* cp = cpart + b * g.nb * 4;
+    double cx, cy, cz;
+    centre_from(cp, g.nb, n, sh, cx, cy, cz);
+    const double S = scale_from(cp, g.nb, sh);
+    const double* x = pos + b * 3 * n;
+    const double* wb = w + b * 3 * n;
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    const bool ok = i < n;
+    const int64_t k = ok ? i : 0;
+    const double x0 = x[k], y0 = x[n + k], z0 = x[2 * n + k];
+    const double wx = wb[k], wy = wb[n + k], wz = wb[2 * n + k];
+    if (i < g.nj)
+        put_source_w<true>(jsv + b * g.nj * 2, i, ok, x0, y0, z0, mass[b * n + k], cx, cy, cz,
+                           wx * S, wy * S, wz * S);
+    double* co = cpart_out + b * g.nb * 4;
+    write_block_sums(x0, y0, z0, ok, sh, co);
+    write_block_max(ok ? absmax3(wx, wy, wz) : 0.0, sh, co);
+    if (blockIdx.x == 0 && threadIdx.x == 0) wscale[2 * b] = S;
+}
+
+// Block sums of positions with the block maxima of w (slot 3).  grid (nb, batch).
+__global__ __launch_bounds__(BS) void k_batch_block_sums_w(const double* __restrict__ pos,
+                                                           const double* __restrict__ w,
+                                                           BatchGeom g,
+                                                           double* __restrict__ cpart) {
+    __shared__ double sh[3 * BS];
+    const int64_t b = blockIdx.y;
+    const int64_t n = g.n;
+    const double* x = pos + b * 3 * n;
+    const double* wb = w + b * 3 * n;
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    const bool ok = i < n;
+    const int64_t k = ok ? i : 0;
+    double* co = cpart + b * g.nb * 4;
+    write_block_sums(x[k], x[n + k], x[2 * n + k], ok, sh, co);
+    write_block_max(ok ? absmax3(wb[k], wb[n + k], wb[2 * n + k]) : 0.0, sh, co);
+}
+
+// Pair VJP of every member.  grid (nblk, S, batch).
+__global__ __launch_bounds__(BS) void k_batch_pair_vjp(const float4* __restrict__ jsv,
+                                                       BatchGeom g,
+                                                       const double* __restrict__ params,
+                                                       const float* __restrict__ muni,
+                                                       float* __restrict__ part) {
+    const int64_t b = blockIdx.z;
+    const float4* jb = jsv + b * g.nj * 2;
+    const int i = blockIdx.x * BS + threadIdx.x;
+    const int j0 = blockIdx.y * g.jslice;
+    const int j1 = min(g.nj, j0 + g.jslice);
+    const int ii = min(i, g.n - 1);
+    const float4 me = jb[2 * ii];
+    const float4 mw = jb[2 * ii + 1];
+    const double eps = params[8 * b + 1];
+    const float eps2 = (float)(eps * eps);
+    float h[4] = {0.f, 0.f, 0.f, 0.f};
+    float l[4] = {0.f, 0.f, 0.f, 0.f};
+    if (muni[2 * b] != 0.f) {
+        vjp_f32c_slice<false, false, true>(jb, i, j0, j1, eps2, me, mw, h, l);
+        const float m = muni[2 * b + 1];
+        for (int c = 0; c < 3; ++c) { h[c] *= m; l[c] *= m; }
+    } else {
+        vjp_f32c_slice<false, false, false>(jb, i, j0, j1, eps2, me, mw, h, l);
+    }
+    if (i < g.n) {
+        float* p = part + (b * g.S + blockIdx.y) * 8 * g.npad + i;
+        for (int c = 0; c < 3; ++c) {
+            p[c * g.npad] = h[c];
+            p[(3 + c) * g.npad] = l[c];
+        }
+    }
+}
+
+// One merged kick of the reverse sweep for every member (k_rev_kick, FP32C,
+// without per-particle mass cotangents).  x_n / x_prev / aint are the positions,
+// the previous positions (null: the last reverse step) and the internal
+// accelerations of the step, each with its own member stride.  half: the kick
+// coefficient is dt/2 (first and last steps) rather than dt.  grid (nb, batch).
+__global__ __launch_bounds__(BS) void k_batch_rev_kick(
+    BatchGeom g, const double* __restrict__ params, const double* __restrict__ mass,
+    const float* __restrict__ part, const double* __restrict__ xn_base, int64_t xn_stride,
+    const double* __restrict__ xp_base, int64_t xp_stride, const double* __restrict__ aint_base,
+    int half, double* __restrict__ lx_base, double* __restrict__ lv_base,
+    double* __restrict__ accum_base, const double* __restrict__ cpart_in,
+    double* __restrict__ cpart_out, double* __restrict__ wscale, int wq,
+    float4* __restrict__ jsv) {
+    __shared__ double sh[3 * BS];
+    const int64_t b = blockIdx.y;
+    const int64_t n = g.n;
+    const double* P = params + 8 * b;
+    const Pot pot = pot_row(P);
+    const double dt = P[7];
+    const double coef = half ? 0.5 * dt : dt;
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    const bool ok = i < n;
+    const int64_t k = ok ? i : 0;
+    const bool drift = xp_base != nullptr;
+    const double* cpi = cpart_in + b * g.nb * 4;
+    const double* xnb = xn_base + b * xn_stride;
+    const double* ai_b = aint_base + b * 3 * n;
+    double* lx = lx_base + b * 3 * n;
+    double* lv = lv_base + b * 3 * n;
+    double* accum = accum_base + b * 4 * n;
+
+    double cx = 0.0, cy = 0.0, cz = 0.0;
+    if (drift) centre_from(cpi, g.nb, n, sh, cx, cy, cz);
+    double gg[3], gm;
+    vjp_sum<true>(part + b * g.S * 8 * g.npad, g.S, g.npad, k, pot.G, false, gg, gm);
+    const double inv_s = 1.0 / wscale[2 * b + wq];
+    gg[0] *= inv_s; gg[1] *= inv_s; gg[2] *= inv_s;
+    const double ai[3] = {ai_b[k], ai_b[n + k], ai_b[2 * n + k]};
+    const double x = xnb[k], y = xnb[n + k], z = xnb[2 * n + k];
+    const double wx = lv[k], wy = lv[n + k], wz = lv[2 * n + k];
+    Ext e = ext_accel(pot, x, y, z);
+    double hx, hy, hz;
+    ext_hvp(pot, x, y, z, wx, wy, wz, hx, hy, hz);
+
+    const double lxx = fma(coef, gg[0] + hx, lx[k]);
+    const double lxy = fma(coef, gg[1] + hy, lx[n + k]);
+    const double lxz = fma(coef, gg[2] + hz, lx[2 * n + k]);
+    const double kc = coef / dt;
+    const double aw_int = ai[0] * wx + ai[1] * wy + ai[2] * wz;
+    const double aw_ext = e.ax * wx + e.ay * wy + e.az * wz;
+    double d_dt = kc * (aw_int + aw_ext);
+    const double d_nfw = coef * (e.nx * wx + e.ny * wy + e.nz * wz);
+    const double d_mn = coef * (e.mx * wx + e.my * wy + e.mz * wz);
+    const double d_ms = coef * aw_int;
+
+    double px = 0.0, py = 0.0, pz = 0.0;
+    double nwx = wx, nwy = wy, nwz = wz;
+    if (drift) {
+        const double* xpb = xp_base + b * xp_stride;
+        px = xpb[k]; py = xpb[n + k]; pz = xpb[2 * n + k];
+        const double inv = 1.0 / dt;
+        const double vx = (x - px) * inv, vy = (y - py) * inv, vz = (z - pz) * inv;
+        d_dt += vx * lxx + vy * lxy + vz * lxz;
+        nwx = fma(dt, lxx, wx); nwy = fma(dt, lxy, wy); nwz = fma(dt, lxz, wz);
+    }
+    if (ok) {
+        lx[i] = lxx; lx[n + i] = lxy; lx[2 * n + i] = lxz;
+        accum[i] += d_nfw;
+        accum[n + i] += d_mn;
+        accum[2 * n + i] += d_dt;
+        accum[3 * n + i] += d_ms;
+        if (drift) { lv[i] = nwx; lv[n + i] = nwy; lv[2 * n + i] = nwz; }
+    }
+    if (drift) {
+        const double Sn = scale_from(cpi, g.nb, sh);
+        if (i < g.nj)
+            put_source_w<true>(jsv + b * g.nj * 2, i, ok, px, py, pz, mass[b * n + k], cx, cy,
+                               cz, nwx * Sn, nwy * Sn, nwz * Sn);
+        double* co = cpart_out + b * g.nb * 4;
+        write_block_sums(px, py, pz, ok, sh, co);
+        write_block_max(ok ? absmax3(nwx, nwy, nwz) : 0.0, sh, co);
+        if (blockIdx.x == 0 && threadIdx.x == 0) wscale[2 * b + (1 - wq)] = Sn;
+    }
+}
+
+// Per-member sums of the four per-particle cotangent accumulators (the order of
+// k_reduce_rows5).  One block per member.
+__global__ __launch_bounds__(BS) void k_batch_reduce4(const double* __restrict__ accum, int64_t n,
+                                                      double* __restrict__ out) {
+    __shared__ double sh[5 * BS];
+    const double* v = accum + (int64_t)blockIdx.x * 4 * n;
+    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = threadIdx.x; i < n; i += BS)
+        for (int t = 0; t < 4; ++t) s[t] += v[t * n + i];
+    block_sum<5>(s, sh);
+    if (threadIdx.x == 0)
+        for (int t = 0; t < 4; ++t) out[4 * blockIdx.x + t] = s[t];
+}
+
+hipError_t launch_simulate_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const double* mass,
+                                     const double* params_dev, int64_t T, const double* tape,
+                                     const double* pos_T, double* accum, double* lx, double* lv,
+                                     double* gparams, hipStream_t st) {
+    const BatchGeom g = batch_geom(c, batch, n);
+    const BatchTape tp{const_cast<double*>(tape), batch, n, T};
+    float4* jsv = (float4*)c->jsv;
+    float* part = (float*)c->partv;
+    double* cpv[2] = {c->cpartv, c->cpartv + 4 * c->nbmax};
+    const dim3 on(g.nb, (unsigned)batch);
+    hipLaunchKernelGGL(k_batch_mass_info, dim3((unsigned)batch), dim3(BS), 0, st, mass, g.n,
+                       c->muni);
+    hipLaunchKernelGGL(k_batch_block_sums_w, on, dim3(BS), 0, st, pos_T, lv, g, cpv[0]);
+    hipLaunchKernelGGL(k_batch_rev_stage, on, dim3(BS), 0, st, pos_T, mass, lv, g, cpv[0], jsv,
+                       cpv[1], c->bwscale);
+    int q = 1, wq = 0;
+    for (int64_t m = T; m >= 0; --m) {
+        hipLaunchKernelGGL(k_batch_pair_vjp, dim3(g.nblk, g.S, (unsigned)batch), dim3(BS), 0, st,
+                           (const float4*)jsv, g, params_dev, c->muni, part);
+        const double* xn = (m == T) ? pos_T : tp.state(m);
+        const int64_t xs = (m == T) ? 3 * n : 6 * n;
+        const double* xp = (m > 0) ? tp.state(m - 1) : nullptr;
+        hipLaunchKernelGGL(k_batch_rev_kick, on, dim3(BS), 0, st, g, params_dev, mass,
+                           (const float*)part, xn, xs, xp, (int64_t)6 * n, tp.aint(m),
+                           (int)(m == T || m == 0), lx, lv, accum, cpv[q], cpv[1 - q], c->bwscale,
+                           wq, jsv);
+        q = 1 - q;
+        wq = 1 - wq;
+    }
+    hipLaunchKernelGGL(k_batch_reduce4, dim3((unsigned)batch), dim3(BS), 0, st, accum, n,
+                       gparams);
     return hipGetLastError();
 }
 

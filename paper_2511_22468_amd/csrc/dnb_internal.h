@@ -212,6 +212,7 @@ struct dnb_ctx {
     float* muni;             // [DNB_BATCH_MAX][2] (flag, m): all masses of the system (or of
                              // ensemble member b) equal m (FP32C fast path)
     double* bparams;         // [DNB_BATCH_MAX][8] parameter table of a batched ensemble
+    double* bwscale;         // [DNB_BATCH_MAX][2] cotangent staging scales of a batched sweep
     double* red;             // [nbmax][8] reduction scratch
     void* prof;              // host-side event pool of dnb_profile (null when off)
 };
@@ -320,7 +321,11 @@ hipError_t launch_place_vjp(dnb_ctx* c, int64_t n, const double* zeta, double m_
 bool batch_fits(const dnb_ctx* c, int64_t batch, int64_t n);
 hipError_t launch_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* pos, double* vel,
                                  const double* mass, const double* params_dev, int64_t n_steps,
-                                 hipStream_t st);
+                                 double* tape, hipStream_t st);
+hipError_t launch_simulate_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const double* mass,
+                                     const double* params_dev, int64_t T, const double* tape,
+                                     const double* pos_T, double* accum, double* lx, double* lv,
+                                     double* gparams, hipStream_t st);
 hipError_t launch_orbit_batch(int64_t batch, const double* w0, const double* params_dev,
                               int64_t n_steps, double* w_out, hipStream_t st);
 hipError_t launch_place_batch(int64_t batch, int64_t n, const double* w, const double* xi,

@@ -1,4 +1,5 @@
-// Device code shared by the single-system and the batched pair kernels.
+// Device code shared by the single-system and the batched pair kernels: the
+// slice sums of the forward pair kernel and of the pair VJP.
 #pragma once
 
 #include "dnb_internal.h"
@@ -59,6 +60,65 @@ __device__ __forceinline__ void fwd_f32c_slice(const float4* __restrict__ js, in
         two_sum_acc(h[0], l[0], ax);
         two_sum_acc(h[1], l[1], ay);
         two_sum_acc(h[2], l[2], az);
+    }
+}
+
+// For target k and cotangent w, with d = x_j - x_k, s = |d|^2 + eps^2:
+//   (J^T w)_k / G = sum_j [s^-3/2 u - 3 s^-5/2 (d.u) d],  u = m_k w_j - m_j w_k
+//   gm_k / G      = sum_j (d.w_j) s^-3/2          (mass cotangent, negated later)
+// The internal acceleration the dt and mass-scale terms need is not summed here:
+// the forward pass stores it with the tape.
+// jsv: interleaved [2 j] = (x, y, z, m), [2 j + 1] = (wx, wy, wz, 0), padded.
+// part: [S][8][npad] floats: JTw hi(3) lo(3), gm hi, lo.
+// The two terms of J^T w are accumulated apart (A = sum s^-3/2 u,
+// B = sum s^-5/2 (d.u) d) and combined as A - 3 B once per sub-tile, which takes
+// the factor -3 out of the pair loop.  With UNI (all masses equal to m)
+// u = m (w_j - w_k): the mass leaves the pair term and is applied once per
+// target, 22 VALU operations and one v_rsq_f32 per pair.
+template <bool EPS0, bool MASS, bool UNI>
+__device__ __forceinline__ void vjp_f32c_slice(const float4* __restrict__ jsv, int i, int j0,
+                                               int j1, float eps2, float4 me, float4 mw,
+                                               float (&h)[4], float (&l)[4]) {
+    constexpr int PB = 4;
+    float4 pa[PB], wa[PB];
+#pragma unroll
+    for (int u = 0; u < PB; ++u) { pa[u] = jsv[2 * (j0 + u)]; wa[u] = jsv[2 * (j0 + u) + 1]; }
+    for (int jt = j0; jt < j1; jt += SUBTILE) {
+        float A[3] = {0.f, 0.f, 0.f}, B[3] = {0.f, 0.f, 0.f}, gm = 0.f;
+        for (int k = 0; k < SUBTILE; k += PB) {
+            const int nx = next_batch(jt, k, PB, j1);
+            float4 pb[PB], wb[PB];
+#pragma unroll
+            for (int u = 0; u < PB; ++u) { pb[u] = jsv[2 * (nx + u)]; wb[u] = jsv[2 * (nx + u) + 1]; }
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                const float4 q = pa[u];
+                const float4 qw = wa[u];
+                const float dx = q.x - me.x, dy = q.y - me.y, dz = q.z - me.z;
+                const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+                float r = __builtin_amdgcn_rsqf(s);
+                if (EPS0) r = (jt + k + u == i) ? 0.f : r;
+                const float r2 = r * r;
+                const float r3 = r2 * r;
+                const float r5 = r3 * r2;
+                const float ux = UNI ? qw.x - mw.x : fmaf(me.w, qw.x, -(q.w * mw.x));
+                const float uy = UNI ? qw.y - mw.y : fmaf(me.w, qw.y, -(q.w * mw.y));
+                const float uz = UNI ? qw.z - mw.z : fmaf(me.w, qw.z, -(q.w * mw.z));
+                const float t = r5 * fmaf(dx, ux, fmaf(dy, uy, dz * uz));
+                A[0] = fmaf(r3, ux, A[0]);
+                A[1] = fmaf(r3, uy, A[1]);
+                A[2] = fmaf(r3, uz, A[2]);
+                B[0] = fmaf(t, dx, B[0]);
+                B[1] = fmaf(t, dy, B[1]);
+                B[2] = fmaf(t, dz, B[2]);
+                if (MASS) gm = fmaf(fmaf(dx, qw.x, fmaf(dy, qw.y, dz * qw.z)), r3, gm);
+            }
+#pragma unroll
+            for (int u = 0; u < PB; ++u) { pa[u] = pb[u]; wa[u] = wb[u]; }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) two_sum_acc(h[c], l[c], fmaf(-3.f, B[c], A[c]));
+        if (MASS) two_sum_acc(h[3], l[3], gm);
     }
 }
 

@@ -186,16 +186,39 @@ class Context:
                                             _lib.ptr(gpar), _lib.stream_handle()))
         return gw0, gpar
 
-    def simulate_batch(self, pos, vel, mass, pots, dts, n_steps):
+    def simulate_batch(self, pos, vel, mass, pots, dts, n_steps, tape=False):
         """In-place integration of an ensemble: pos, vel (B, 3, n), mass (B, n),
-        pots a sequence of B Potential, dts a sequence of B step sizes."""
+        pots a sequence of B Potential, dts a sequence of B step sizes.  With
+        tape=True every step is recorded and the tape returned (for
+        simulate_batch_vjp)."""
         B, n = mass.shape
         _arr(pos, (B, 3, n), "pos"); _arr(vel, (B, 3, n), "vel"); _arr(mass, (B, n), "mass")
         table = batch_table(pots, dts, B)
+        t = None
+        if tape and n_steps > 0:
+            t = self._new(int(_lib.lib().dnb_batch_tape_doubles(B, n, int(n_steps))))
         _lib.check(_lib.lib().dnb_simulate_batch(
             self._h, B, n, _lib.ptr(pos), _lib.ptr(vel), _lib.ptr(mass),
-            table.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(n_steps),
+            table.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(n_steps), _lib.ptr(t),
             _lib.stream_handle()))
+        return t
+
+    def simulate_batch_vjp(self, mass, pots, dts, n_steps, tape, pos_T, gpos_T, gvel_T=None):
+        """Returns (gpos_0 (B, 3, n), gvel_0 (B, 3, n), gparams (B, 4)) with gparams[b] =
+        (dL/dm_nfw, dL/dm_mn, dL/ddt, sum_k m_k dL/dm_k) of member b."""
+        B, n = mass.shape
+        _arr(mass, (B, n), "mass"); _arr(pos_T, (B, 3, n), "pos_T")
+        _arr(gpos_T, (B, 3, n), "gpos_T")
+        if gvel_T is not None:
+            _arr(gvel_T, (B, 3, n), "gvel_T")
+        table = batch_table(pots, dts, B)
+        work = self._new(4 * B * n)
+        g0, gv0, gpar = self._new(B, 3, n), self._new(B, 3, n), self._new(B, 4)
+        _lib.check(_lib.lib().dnb_simulate_batch_vjp(
+            self._h, B, n, _lib.ptr(mass), table.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            int(n_steps), _lib.ptr(tape), _lib.ptr(pos_T), _lib.ptr(gpos_T), _lib.ptr(gvel_T),
+            _lib.ptr(work), _lib.ptr(g0), _lib.ptr(gv0), _lib.ptr(gpar), _lib.stream_handle()))
+        return g0, gv0, gpar
 
     def mmd_batch(self, pos, tgt, h):
         """Loss of each member pos[b] (B, 3, n) against tgt (3, m): a (B,) tensor."""
