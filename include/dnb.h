@@ -228,10 +228,11 @@ dnb_status dnb_simulate_batch_vjp(dnb_ctx* ctx, int64_t batch, int64_t n, const 
  * of the inference pipeline, Sec. 2.2.1: the MMD between simulated and observed
  * streams at many parameter combinations).  pos [batch][3][n] (device), tgt
  * [3][m], loss [batch] (device): loss[b] = the squared MMD of dnb_mmd between
- * pos[b] and tgt.  No gradient.  Requires n, m <= max_n, h > 0, batch <=
+ * pos[b] and tgt; gpos [batch][3][n] (nullable) = dL_b/dpos[b] (the gradient of
+ * dnb_mmd for every member).  Requires n, m <= max_n, h > 0, batch <=
  * DNB_BATCH_MAX and the partial sums to fit the context (DNB_ERR_ARG otherwise). */
 dnb_status dnb_mmd_batch(dnb_ctx* ctx, int64_t batch, int64_t n, const double* pos, int64_t m,
-                         const double* tgt, double h, double* loss, void* stream);
+                         const double* tgt, double h, double* loss, double* gpos, void* stream);
 
 /* Plummer spheres for every member of an ensemble (the batched form of
  * dnb_place_plummer, Fig. 2 step 3): member b is centred on w[b] ([batch][6],
@@ -249,9 +250,25 @@ int64_t dnb_batch_capacity(const dnb_ctx* ctx, int64_t n);
 
 /* Test-particle orbits of a batch (the batched form of dnb_orbit): w0, w_out
  * [batch][6] (device), params the same HOST table as dnb_simulate_batch (eps
- * is unused).  batch <= DNB_BATCH_MAX. */
+ * is unused); traj (nullable) receives [batch][n_steps+1][3] positions for
+ * dnb_orbit_batch_vjp.  batch <= DNB_BATCH_MAX. */
 dnb_status dnb_orbit_batch(dnb_ctx* ctx, int64_t batch, const double* w0, const double* params,
-                           int64_t n_steps, double* w_out, void* stream);
+                           int64_t n_steps, double* w_out, double* traj, void* stream);
+
+/* Adjoint of dnb_orbit_batch for every member (the batched form of
+ * dnb_orbit_vjp): gw_out [batch][6] in; gw0 [batch][6] and gparams [batch][3] =
+ * (dL/dm_nfw, dL/dm_mn, dL/ddt) out (device).  Every dt must be non-zero. */
+dnb_status dnb_orbit_batch_vjp(dnb_ctx* ctx, int64_t batch, const double* traj,
+                               const double* params, int64_t n_steps, const double* gw_out,
+                               double* gw0, double* gparams, void* stream);
+
+/* Adjoint of dnb_place_plummer_batch: gpos, gvel [batch][3][n] in; gw [batch][6]
+ * = (sum_i gpos_i, sum_i gvel_i) and gm_tot [batch] = dL/dm_tot through the
+ * velocity scale (device).  Requires batch ceil(n / 256) <= ceil(max_n / 256). */
+dnb_status dnb_place_plummer_batch_vjp(dnb_ctx* ctx, int64_t batch, int64_t n,
+                                       const double* zeta, const double* m_tot, double a_p,
+                                       double G, const double* gpos, const double* gvel,
+                                       double* gw, double* gm_tot, void* stream);
 
 /* Instrumentation (not part of the method).  With enable != 0, every launch of
  * the two O(N^2) kernels (forward pair sum, pair VJP) issued through this

@@ -65,8 +65,10 @@ def load_library(path=LIB_PATH):
                                     P, P, P, P, P, P], I),
         "dnb_batch_capacity": ([P, I64], I64),
         "dnb_place_plummer_batch": ([P, I64, I64, P, P, P, P, D, D, P, P, P, P], I),
-        "dnb_mmd_batch": ([P, I64, I64, P, I64, P, D, P, P], I),
-        "dnb_orbit_batch": ([P, I64, P, ctypes.POINTER(ctypes.c_double), I64, P, P], I),
+        "dnb_mmd_batch": ([P, I64, I64, P, I64, P, D, P, P, P], I),
+        "dnb_orbit_batch": ([P, I64, P, ctypes.POINTER(ctypes.c_double), I64, P, P, P], I),
+        "dnb_orbit_batch_vjp": ([P, I64, P, ctypes.POINTER(ctypes.c_double), I64, P, P, P, P], I),
+        "dnb_place_plummer_batch_vjp": ([P, I64, I64, P, P, D, D, P, P, P, P, P], I),
         "dnb_profile": ([P, I], I),
         "dnb_profile_read": ([P, ctypes.POINTER(ctypes.c_double)], I),
         # learned surrogate (include/dnb_surrogate.h)

@@ -571,17 +571,43 @@ dnb_status dnb_simulate_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const do
 }
 
 dnb_status dnb_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* pos, int64_t m,
-                         const double* tgt, double h, double* loss, void* stream) {
+                         const double* tgt, double h, double* loss, double* gpos, void* stream) {
     const char* fn = "dnb_mmd_batch";
     CHECK(check_ctx(c, 1, fn));
     if (!(h > 0) || !is_fin(h)) return fail(DNB_ERR_ARG, "%s: h must be finite and > 0", fn);
-    if (!mmd_batch_fits(c, batch, n, m))
+    if (!mmd_batch_fits(c, batch, n, m, gpos != nullptr))
         return fail(DNB_ERR_ARG, "%s: batch %lld, n %lld, m %lld do not fit a context of max_n = %lld",
                     fn, (long long)batch, (long long)n, (long long)m, (long long)c->max_n);
     CHECK(check_dev(pos, "pos", fn));
     CHECK(check_dev(tgt, "tgt", fn));
     CHECK(check_dev(loss, "loss", fn));
-    HIP_TRY(launch_mmd_batch(c, batch, n, pos, m, tgt, h, loss, (hipStream_t)stream));
+    CHECK(check_dev(gpos, "gpos", fn, true));
+    if (gpos && gpos == pos) return fail(DNB_ERR_ARG, "%s: gpos must not alias pos", fn);
+    HIP_TRY(launch_mmd_batch(c, batch, n, pos, m, tgt, h, loss, gpos, (hipStream_t)stream));
+    return DNB_OK;
+}
+
+dnb_status dnb_place_plummer_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const double* zeta,
+                                       const double* m_tot, double a_p, double G,
+                                       const double* gpos, const double* gvel, double* gw,
+                                       double* gm_tot, void* stream) {
+    const char* fn = "dnb_place_plummer_batch_vjp";
+    CHECK(check_ctx(c, 1, fn));
+    if (batch < 1 || batch > DNB_BATCH_MAX || n < 1)
+        return fail(DNB_ERR_ARG, "%s: batch or n out of range", fn);
+    if (batch * cdiv(n, BS) > c->nbmax)
+        return fail(DNB_ERR_ARG, "%s: batch %lld x n %lld does not fit a context of max_n = %lld",
+                    fn, (long long)batch, (long long)n, (long long)c->max_n);
+    if (!(a_p > 0) || !(G > 0) || !is_fin(a_p) || !is_fin(G))
+        return fail(DNB_ERR_ARG, "%s: a_p and G must be finite and > 0", fn);
+    CHECK(check_dev(zeta, "zeta", fn));
+    CHECK(check_dev(m_tot, "m_tot", fn));
+    CHECK(check_dev(gpos, "gpos", fn));
+    CHECK(check_dev(gvel, "gvel", fn));
+    CHECK(check_dev(gw, "gw", fn));
+    CHECK(check_dev(gm_tot, "gm_tot", fn));
+    HIP_TRY(launch_place_batch_vjp(c, batch, n, zeta, m_tot, a_p, G, gpos, gvel, gw, gm_tot,
+                                   (hipStream_t)stream));
     return DNB_OK;
 }
 
@@ -618,15 +644,32 @@ int64_t dnb_batch_capacity(const dnb_ctx* c, int64_t n) {
 }
 
 dnb_status dnb_orbit_batch(dnb_ctx* c, int64_t batch, const double* w0, const double* params,
-                           int64_t n_steps, double* w_out, void* stream) {
+                           int64_t n_steps, double* w_out, double* traj, void* stream) {
     const char* fn = "dnb_orbit_batch";
     CHECK(check_ctx(c, 1, fn));
     if (n_steps < 0) return fail(DNB_ERR_ARG, "%s: n_steps < 0", fn);
     CHECK(check_dev(w0, "w0", fn));
     CHECK(check_dev(w_out, "w_out", fn));
+    CHECK(check_dev(traj, "traj", fn, true));
     hipStream_t st = (hipStream_t)stream;
     CHECK(put_batch_params(c, batch, params, false, st, fn));
-    HIP_TRY(launch_orbit_batch(batch, w0, c->bparams, n_steps, w_out, st));
+    HIP_TRY(launch_orbit_batch(batch, w0, c->bparams, n_steps, w_out, traj, st));
+    return DNB_OK;
+}
+
+dnb_status dnb_orbit_batch_vjp(dnb_ctx* c, int64_t batch, const double* traj, const double* params,
+                               int64_t n_steps, const double* gw_out, double* gw0, double* gparams,
+                               void* stream) {
+    const char* fn = "dnb_orbit_batch_vjp";
+    CHECK(check_ctx(c, 1, fn));
+    if (n_steps < 0) return fail(DNB_ERR_ARG, "%s: n_steps < 0", fn);
+    CHECK(check_dev(traj, "traj", fn));
+    CHECK(check_dev(gw_out, "gw_out", fn));
+    CHECK(check_dev(gw0, "gw0", fn));
+    CHECK(check_dev(gparams, "gparams", fn));
+    hipStream_t st = (hipStream_t)stream;
+    CHECK(put_batch_params(c, batch, params, false, st, fn, true));
+    HIP_TRY(launch_orbit_batch_vjp(batch, traj, c->bparams, n_steps, gw_out, gw0, gparams, st));
     return DNB_OK;
 }
 

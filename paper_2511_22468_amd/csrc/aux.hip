@@ -138,23 +138,24 @@ hipError_t launch_mmd(dnb_ctx* c, int64_t n, const double* pos, int64_t m, const
     return hipGetLastError();
 }
 
-// Loss of every member of an ensemble against one target (no gradient).
-// pxx, pxy: [batch][S][npad] kernel sums per target; red[8 q + 2] holds the block
-// sums of sum_ab k(y_a, y_b) from k_mmd_y.  One block per member.
+// Loss of every member of an ensemble against one target.  pxx, pxy:
+// [batch][S][rows][npad] kernel sums per target (rows = 1, or 4 with the gradient
+// terms; sstride = rows npad); red[8 q + 2] holds the block sums of
+// sum_ab k(y_a, y_b) from k_mmd_y.  One block per member.
 __global__ __launch_bounds__(BS) void k_mmd_batch_final(const double* __restrict__ pxx, int S,
                                                         const double* __restrict__ pxy, int Sxy,
-                                                        int64_t npad, int n, int m,
+                                                        int64_t sstride, int n, int m,
                                                         const double* __restrict__ red, int nby,
                                                         double* __restrict__ loss) {
     __shared__ double sh[3 * BS];
     const int b = blockIdx.x;
-    const double* qx = pxx + (int64_t)b * S * npad;
-    const double* qy = pxy + (int64_t)b * Sxy * npad;
+    const double* qx = pxx + (int64_t)b * S * sstride;
+    const double* qy = pxy + (int64_t)b * Sxy * sstride;
     double v[3] = {0.0, 0.0, 0.0};
     for (int s = 0; s < S; ++s)
-        for (int i = threadIdx.x; i < n; i += BS) v[0] += qx[(int64_t)s * npad + i];
+        for (int i = threadIdx.x; i < n; i += BS) v[0] += qx[(int64_t)s * sstride + i];
     for (int s = 0; s < Sxy; ++s)
-        for (int i = threadIdx.x; i < n; i += BS) v[1] += qy[(int64_t)s * npad + i];
+        for (int i = threadIdx.x; i < n; i += BS) v[1] += qy[(int64_t)s * sstride + i];
     for (int q = threadIdx.x; q < nby; q += BS) v[2] += red[8 * q + 2];
     block_sum<3>(v, sh);
     if (threadIdx.x == 0)
@@ -177,37 +178,69 @@ static void mmd_batch_slices(const dnb_ctx* c, int64_t batch, int64_t n, int64_t
     Sxy = (int)cdiv(m, jslice_xy);
 }
 
-bool mmd_batch_fits(const dnb_ctx* c, int64_t batch, int64_t n, int64_t m) {
+bool mmd_batch_fits(const dnb_ctx* c, int64_t batch, int64_t n, int64_t m, bool grad) {
     if (batch < 1 || batch > DNB_BATCH_MAX || n < 1 || m < 1 || n > c->max_n || m > c->max_n)
         return false;
     int S, js, Sxy, jsxy;
     mmd_batch_slices(c, batch, n, m, S, js, Sxy, jsxy);
     const int64_t npad = cdiv(n, BS) * BS;
-    return batch * (S + Sxy) * npad <= 8 * c->slice_rows;
+    return batch * (S + Sxy) * npad * (grad ? 4 : 1) <= 8 * c->slice_rows;
+}
+
+// Gradient rows of every member (the arithmetic and order of k_mmd_x).
+// grid (nblk, batch).
+__global__ __launch_bounds__(BS) void k_mmd_batch_grad(const double* __restrict__ pxx, int S,
+                                                       const double* __restrict__ pxy, int Sxy,
+                                                       int64_t npad, int n, int m, double h,
+                                                       double* __restrict__ gpos) {
+    const int64_t b = blockIdx.y;
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    const double* px = pxx + b * S * 4 * npad;
+    const double* py = pxy + b * Sxy * 4 * npad;
+    double gx[3] = {0, 0, 0}, gy[3] = {0, 0, 0};
+    for (int s = 0; s < S; ++s) {
+        const double* q = px + (int64_t)s * 4 * npad + i;
+        for (int c = 0; c < 3; ++c) gx[c] += q[(1 + c) * npad];
+    }
+    for (int s = 0; s < Sxy; ++s) {
+        const double* q = py + (int64_t)s * 4 * npad + i;
+        for (int c = 0; c < 3; ++c) gy[c] += q[(1 + c) * npad];
+    }
+    const double cxx = -2.0 / ((double)n * n * h * h);
+    const double cxy = 2.0 / ((double)n * m * h * h);
+    double* g = gpos + b * 3 * n;
+    for (int c = 0; c < 3; ++c) g[(int64_t)c * n + i] = cxx * gx[c] + cxy * gy[c];
 }
 
 hipError_t launch_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* pos, int64_t m,
-                            const double* tgt, double h, double* loss, hipStream_t st) {
+                            const double* tgt, double h, double* loss, double* gpos,
+                            hipStream_t st) {
     const double inv2h2 = 1.0 / (2.0 * h * h);
     int S, jslice, Sxy, jslice_xy;
     mmd_batch_slices(c, batch, n, m, S, jslice, Sxy, jslice_xy);
     const int nblk = (int)cdiv(n, BS);
     const int64_t npad = (int64_t)nblk * BS;
+    const int wg = gpos != nullptr;
+    const int64_t ss = (wg ? 4 : 1) * npad;      // stride of one slice's rows
     double* pxx = (double*)c->partv;
-    double* pxy = pxx + batch * S * npad;
+    double* pxy = pxx + batch * S * ss;
     double* pyy = (double*)c->part;
     const Slicing sy = plain_slicing(c, m);
     hipLaunchKernelGGL(k_mmd_rows, dim3(nblk, S, (unsigned)batch), dim3(BS), 0, st, pos, (int)n,
-                       pos, (int)n, inv2h2, jslice, 0, pxx, npad, npad, 3 * n, 3 * n, S * npad);
+                       pos, (int)n, inv2h2, jslice, wg, pxx, npad, ss, 3 * n, 3 * n, S * ss);
     hipLaunchKernelGGL(k_mmd_rows, dim3(nblk, Sxy, (unsigned)batch), dim3(BS), 0, st, pos, (int)n,
-                       tgt, (int)m, inv2h2, jslice_xy, 0, pxy, npad, npad, 3 * n, (int64_t)0,
-                       Sxy * npad);
+                       tgt, (int)m, inv2h2, jslice_xy, wg, pxy, npad, ss, 3 * n, (int64_t)0,
+                       Sxy * ss);
     hipLaunchKernelGGL(k_mmd_rows, dim3(sy.nblk, sy.S), dim3(BS), 0, st, tgt, (int)m, tgt, (int)m,
                        inv2h2, sy.jslice, 0, pyy, sy.npad, 4 * sy.npad, 0, 0, 0);
     hipLaunchKernelGGL(k_mmd_y, dim3(sy.nblk), dim3(BS), 0, st, pyy, sy.S, sy.npad, (int)m,
                        c->red);
     hipLaunchKernelGGL(k_mmd_batch_final, dim3((unsigned)batch), dim3(BS), 0, st, pxx, S, pxy, Sxy,
-                       npad, (int)n, (int)m, c->red, sy.nblk, loss);
+                       ss, (int)n, (int)m, c->red, sy.nblk, loss);
+    if (wg)
+        hipLaunchKernelGGL(k_mmd_batch_grad, dim3(nblk, (unsigned)batch), dim3(BS), 0, st, pxx, S,
+                           pxy, Sxy, npad, (int)n, (int)m, h, gpos);
     return hipGetLastError();
 }
 

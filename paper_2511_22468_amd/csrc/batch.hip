@@ -221,25 +221,135 @@ __global__ __launch_bounds__(BS) void k_batch_kdk(double* __restrict__ pos,
     }
 }
 
-// Test-particle orbits of every member, one lane each (the batched form of k_orbit).
+// Test-particle orbits of every member, one lane each (the batched form of k_orbit);
+// traj (nullable) receives member b's positions x_0 .. x_T at traj + b (T+1) 3.
 __global__ void k_batch_orbit(const double* __restrict__ w0, const double* __restrict__ params,
-                              int batch, int64_t n_steps, double* __restrict__ w_out) {
+                              int batch, int64_t n_steps, double* __restrict__ w_out,
+                              double* __restrict__ traj) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
     const double* P = params + 8 * b;
     const Pot p = pot_row(P);
     const double dt = P[7], hdt = 0.5 * dt;
     const double* w = w0 + 6 * b;
+    double* tr = traj ? traj + (int64_t)b * (n_steps + 1) * 3 : nullptr;
     double x = w[0], y = w[1], z = w[2], vx = w[3], vy = w[4], vz = w[5];
     Ext e = ext_accel(p, x, y, z);
+    if (tr) { tr[0] = x; tr[1] = y; tr[2] = z; }
     for (int64_t s = 0; s < n_steps; ++s) {
         const double hx = fma(hdt, e.ax, vx), hy = fma(hdt, e.ay, vy), hz = fma(hdt, e.az, vz);
         x = fma(dt, hx, x); y = fma(dt, hy, y); z = fma(dt, hz, z);
         e = ext_accel(p, x, y, z);
         vx = fma(hdt, e.ax, hx); vy = fma(hdt, e.ay, hy); vz = fma(hdt, e.az, hz);
+        if (tr) { tr[3 * (s + 1)] = x; tr[3 * (s + 1) + 1] = y; tr[3 * (s + 1) + 2] = z; }
     }
     double* o = w_out + 6 * b;
     o[0] = x; o[1] = y; o[2] = z; o[3] = vx; o[4] = vy; o[5] = vz;
+}
+
+// Reverse sweep of every member's orbit (the batched form of k_orbit_vjp, same
+// arithmetic): gw0 [batch][6], gparams [batch][3] = (dL/dm_nfw, dL/dm_mn, dL/ddt).
+__global__ void k_batch_orbit_vjp(const double* __restrict__ traj, const double* __restrict__ params,
+                                  int batch, int64_t n_steps, const double* __restrict__ gw_out,
+                                  double* __restrict__ gw0, double* __restrict__ gparams) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const double* P = params + 8 * b;
+    const Pot p = pot_row(P);
+    const double dt = P[7];
+    const double* tr = traj + (int64_t)b * (n_steps + 1) * 3;
+    const double* go = gw_out + 6 * b;
+    double lx = go[0], ly = go[1], lz = go[2];
+    double wx = go[3], wy = go[4], wz = go[5];
+    double g_nfw = 0.0, g_mn = 0.0, g_dt = 0.0;
+    const double inv = 1.0 / dt;
+    for (int64_t s = n_steps; s >= 0 && n_steps > 0; --s) {
+        const double coef = (s == n_steps || s == 0) ? 0.5 * dt : dt;
+        const double kc = (s == n_steps || s == 0) ? 0.5 : 1.0;
+        const double x = tr[3 * s], y = tr[3 * s + 1], z = tr[3 * s + 2];
+        Ext e = ext_accel(p, x, y, z);
+        double hx, hy, hz;
+        ext_hvp(p, x, y, z, wx, wy, wz, hx, hy, hz);
+        lx += coef * hx; ly += coef * hy; lz += coef * hz;
+        g_dt += kc * (e.ax * wx + e.ay * wy + e.az * wz);
+        g_nfw += coef * (e.nx * wx + e.ny * wy + e.nz * wz);
+        g_mn += coef * (e.mx * wx + e.my * wy + e.mz * wz);
+        if (s > 0) {
+            const double vx = (x - tr[3 * (s - 1)]) * inv;
+            const double vy = (y - tr[3 * (s - 1) + 1]) * inv;
+            const double vz = (z - tr[3 * (s - 1) + 2]) * inv;
+            g_dt += vx * lx + vy * ly + vz * lz;
+            wx += dt * lx; wy += dt * ly; wz += dt * lz;
+        }
+    }
+    double* o = gw0 + 6 * b;
+    o[0] = lx; o[1] = ly; o[2] = lz; o[3] = wx; o[4] = wy; o[5] = wz;
+    gparams[3 * b] = g_nfw; gparams[3 * b + 1] = g_mn; gparams[3 * b + 2] = g_dt;
+}
+
+// Adjoint of the batched Plummer placement: per member the sums over particles of
+// gpos, gvel and gvel . zeta (the order of k_place_vjp_rows / k_place_vjp_final).
+__global__ __launch_bounds__(BS) void k_batch_place_vjp_rows(int64_t n, const double* __restrict__ zeta,
+                                                             const double* __restrict__ gpos,
+                                                             const double* __restrict__ gvel,
+                                                             double* __restrict__ red) {
+    __shared__ double sh[8 * BS];
+    const int64_t b = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    const double* gp = gpos + b * 3 * n;
+    const double* gv = gvel + b * 3 * n;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < n) {
+        for (int c = 0; c < 3; ++c) {
+            v[c] = gp[c * n + i];
+            v[3 + c] = gv[c * n + i];
+            v[6] += gv[c * n + i] * zeta[c * n + i];
+        }
+    }
+    block_sum<8>(v, sh);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 8; ++c) red[(b * gridDim.x + blockIdx.x) * 8 + c] = v[c];
+}
+
+__global__ __launch_bounds__(BS) void k_batch_place_vjp_final(const double* __restrict__ red,
+                                                              int nb, int64_t n,
+                                                              const double* __restrict__ m_tot,
+                                                              double a_p, double G,
+                                                              double* __restrict__ gw,
+                                                              double* __restrict__ gm_tot) {
+    __shared__ double sh[8 * BS];
+    const int64_t b = blockIdx.x;
+    const double* r = red + b * nb * 8;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int q = threadIdx.x; q < nb; q += BS)
+        for (int c = 0; c < 8; ++c) v[c] += r[8 * q + c];
+    block_sum<8>(v, sh);
+    if (threadIdx.x == 0) {
+        // d sqrt(G M / a_p) / dM = sqrt(G / (a_p M)) / 2
+        const double dvs_dm = 0.5 * sqrt(G / (a_p * m_tot[b]));
+        for (int c = 0; c < 6; ++c) gw[6 * b + c] = v[c];
+        gm_tot[b] = v[6] * dvs_dm + v[7] / (double)n;
+    }
+}
+
+hipError_t launch_place_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const double* zeta,
+                                  const double* m_tot, double a_p, double G, const double* gpos,
+                                  const double* gvel, double* gw, double* gm_tot,
+                                  hipStream_t st) {
+    const int nb = (int)cdiv(n, BS);
+    hipLaunchKernelGGL(k_batch_place_vjp_rows, dim3((unsigned)nb, (unsigned)batch), dim3(BS), 0,
+                       st, n, zeta, gpos, gvel, c->red);
+    hipLaunchKernelGGL(k_batch_place_vjp_final, dim3((unsigned)batch), dim3(BS), 0, st, c->red, nb,
+                       n, m_tot, a_p, G, gw, gm_tot);
+    return hipGetLastError();
+}
+
+hipError_t launch_orbit_batch_vjp(int64_t batch, const double* traj, const double* params_dev,
+                                  int64_t n_steps, const double* gw_out, double* gw0,
+                                  double* gparams, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_orbit_vjp, dim3((unsigned)cdiv(batch, 64)), dim3(64), 0, st, traj,
+                       params_dev, (int)batch, n_steps, gw_out, gw0, gparams);
+    return hipGetLastError();
 }
 
 // Plummer spheres of every member placed at their own phase-space points (the
@@ -556,9 +666,9 @@ hipError_t launch_simulate_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const
 }
 
 hipError_t launch_orbit_batch(int64_t batch, const double* w0, const double* params_dev,
-                              int64_t n_steps, double* w_out, hipStream_t st) {
+                              int64_t n_steps, double* w_out, double* traj, hipStream_t st) {
     hipLaunchKernelGGL(k_batch_orbit, dim3((unsigned)cdiv(batch, 64)), dim3(64), 0, st, w0,
-                       params_dev, (int)batch, n_steps, w_out);
+                       params_dev, (int)batch, n_steps, w_out, traj);
     return hipGetLastError();
 }
 

@@ -327,11 +327,18 @@ hipError_t launch_simulate_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const
                                      const double* pos_T, double* accum, double* lx, double* lv,
                                      double* gparams, hipStream_t st);
 hipError_t launch_orbit_batch(int64_t batch, const double* w0, const double* params_dev,
-                              int64_t n_steps, double* w_out, hipStream_t st);
+                              int64_t n_steps, double* w_out, double* traj, hipStream_t st);
+hipError_t launch_orbit_batch_vjp(int64_t batch, const double* traj, const double* params_dev,
+                                  int64_t n_steps, const double* gw_out, double* gw0,
+                                  double* gparams, hipStream_t st);
+hipError_t launch_place_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const double* zeta,
+                                  const double* m_tot, double a_p, double G, const double* gpos,
+                                  const double* gvel, double* gw, double* gm_tot,
+                                  hipStream_t st);
 hipError_t launch_place_batch(int64_t batch, int64_t n, const double* w, const double* xi,
                               const double* zeta, const double* m_tot, double a_p, double G,
                               double* pos, double* vel, double* mass, hipStream_t st);
-bool mmd_batch_fits(const dnb_ctx* c, int64_t batch, int64_t n, int64_t m);
+bool mmd_batch_fits(const dnb_ctx* c, int64_t batch, int64_t n, int64_t m, bool grad);
 
 // Orbit fit (orbitfit.hip).  The model struct is declared in dnb_orbitfit.h.
 }  // namespace dnb
@@ -349,6 +356,7 @@ hipError_t launch_track_lm(const dnb_track_model& md, const double* trk, int K, 
                            double* p, int64_t n_iter, double lam0, double* chi2, void* work,
                            hipStream_t st);
 hipError_t launch_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* pos, int64_t m,
-                            const double* tgt, double h, double* loss, hipStream_t st);
+                            const double* tgt, double h, double* loss, double* gpos,
+                            hipStream_t st);
 
 }  // namespace dnb

@@ -226,8 +226,19 @@ class Context:
         _arr(pos, (B, 3, n), "pos"); _vec(tgt, m, "tgt")
         loss = self._new(B)
         _lib.check(_lib.lib().dnb_mmd_batch(self._h, B, n, _lib.ptr(pos), m, _lib.ptr(tgt),
-                                            float(h), _lib.ptr(loss), _lib.stream_handle()))
+                                            float(h), _lib.ptr(loss), None,
+                                            _lib.stream_handle()))
         return loss
+
+    def mmd_batch_grad(self, pos, tgt, h):
+        """Losses (B,) and their gradients (B, 3, n) for every member pos[b]."""
+        B, n, m = pos.shape[0], pos.shape[2], tgt.shape[1]
+        _arr(pos, (B, 3, n), "pos"); _vec(tgt, m, "tgt")
+        loss, g = self._new(B), self._new(B, 3, n)
+        _lib.check(_lib.lib().dnb_mmd_batch(self._h, B, n, _lib.ptr(pos), m, _lib.ptr(tgt),
+                                            float(h), _lib.ptr(loss), _lib.ptr(g),
+                                            _lib.stream_handle()))
+        return loss, g
 
     def place_plummer_batch(self, w, xi, zeta, m_tot, a_p, G=G_DEFAULT):
         """Plummer spheres at w (B, 6) with masses m_tot (B,), shared unit samples
@@ -245,16 +256,40 @@ class Context:
         """Largest ensemble of n-particle systems that simulate_batch accepts."""
         return int(_lib.lib().dnb_batch_capacity(self._h, int(n)))
 
-    def orbit_batch(self, w0, pots, dts, n_steps):
-        """Test-particle orbits w0 (B, 6) -> w_out (B, 6), member b in pots[b] with dts[b]."""
+    def orbit_batch(self, w0, pots, dts, n_steps, keep=False):
+        """Test-particle orbits w0 (B, 6) -> w_out (B, 6), member b in pots[b] with
+        dts[b]; with keep=True also the positions (B, n_steps + 1, 3) for orbit_batch_vjp."""
         B = w0.shape[0]
         _arr(w0, (B, 6), "w0")
         table = batch_table(pots, dts, B)
         w_out = self._new(B, 6)
+        traj = self._new(B, int(n_steps) + 1, 3) if keep else None
         _lib.check(_lib.lib().dnb_orbit_batch(
             self._h, B, _lib.ptr(w0), table.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-            int(n_steps), _lib.ptr(w_out), _lib.stream_handle()))
-        return w_out
+            int(n_steps), _lib.ptr(w_out), _lib.ptr(traj), _lib.stream_handle()))
+        return (w_out, traj) if keep else w_out
+
+    def orbit_batch_vjp(self, traj, pots, dts, n_steps, gw_out):
+        """(gw0 (B, 6), gparams (B, 3) = dL/dm_nfw, dL/dm_mn, dL/ddt) per member."""
+        B = traj.shape[0]
+        _arr(traj, (B, int(n_steps) + 1, 3), "traj"); _arr(gw_out, (B, 6), "gw_out")
+        table = batch_table(pots, dts, B)
+        gw0, gpar = self._new(B, 6), self._new(B, 3)
+        _lib.check(_lib.lib().dnb_orbit_batch_vjp(
+            self._h, B, _lib.ptr(traj), table.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            int(n_steps), _lib.ptr(gw_out), _lib.ptr(gw0), _lib.ptr(gpar), _lib.stream_handle()))
+        return gw0, gpar
+
+    def place_plummer_batch_vjp(self, zeta, m_tot, a_p, gpos, gvel, G=G_DEFAULT):
+        """(gw (B, 6), gm_tot (B,)) of the batched placement."""
+        B, n = gpos.shape[0], zeta.shape[1]
+        _vec(zeta, n, "zeta"); _arr(m_tot, (B,), "m_tot")
+        _arr(gpos, (B, 3, n), "gpos"); _arr(gvel, (B, 3, n), "gvel")
+        gw, gm = self._new(B, 6), self._new(B)
+        _lib.check(_lib.lib().dnb_place_plummer_batch_vjp(
+            self._h, B, n, _lib.ptr(zeta), _lib.ptr(m_tot), float(a_p), float(G), _lib.ptr(gpos),
+            _lib.ptr(gvel), _lib.ptr(gw), _lib.ptr(gm), _lib.stream_handle()))
+        return gw, gm
 
     def place_plummer(self, w, xi, zeta, m_tot, a_p, G=G_DEFAULT):
         n = xi.shape[1]
