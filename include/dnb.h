@@ -224,15 +224,19 @@ dnb_status dnb_simulate_batch_vjp(dnb_ctx* ctx, int64_t batch, int64_t n, const 
                                   double* workspace, double* gpos_0, double* gvel_0,
                                   double* gparams, void* stream);
 
-/* Loss of every member of an ensemble against one target (the grid-search stage
- * of the inference pipeline, Sec. 2.2.1: the MMD between simulated and observed
- * streams at many parameter combinations).  pos [batch][3][n] (device), tgt
- * [3][m], loss [batch] (device): loss[b] = the squared MMD of dnb_mmd between
- * pos[b] and tgt; gpos [batch][3][n] (nullable) = dL_b/dpos[b] (the gradient of
- * dnb_mmd for every member).  Requires n, m <= max_n, h > 0, batch <=
- * DNB_BATCH_MAX and the partial sums to fit the context (DNB_ERR_ARG otherwise). */
+/* Loss of every member of an ensemble (the grid-search stage of the inference
+ * pipeline, Sec. 2.2.1: the MMD between simulated and observed streams at many
+ * parameter combinations; with a target per member, the bootstrap of Fig. 2
+ * step 6, where every member is compared with its own resampled stream).
+ * pos [batch][3][n] (device); tgt [3][m] shared by all members
+ * (tgt_per_member = 0) or [batch][3][m] (tgt_per_member = 1); loss [batch]
+ * (device): loss[b] = the squared MMD of dnb_mmd between pos[b] and its target;
+ * gpos [batch][3][n] (nullable) = dL_b/dpos[b] (the gradient of dnb_mmd for
+ * every member).  Requires n, m <= max_n, h > 0, batch <= DNB_BATCH_MAX and the
+ * partial sums to fit the context (DNB_ERR_ARG otherwise). */
 dnb_status dnb_mmd_batch(dnb_ctx* ctx, int64_t batch, int64_t n, const double* pos, int64_t m,
-                         const double* tgt, double h, double* loss, double* gpos, void* stream);
+                         const double* tgt, int tgt_per_member, double h, double* loss,
+                         double* gpos, void* stream);
 
 /* Plummer spheres for every member of an ensemble (the batched form of
  * dnb_place_plummer, Fig. 2 step 3): member b is centred on w[b] ([batch][6],

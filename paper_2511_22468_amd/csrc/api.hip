@@ -571,11 +571,14 @@ dnb_status dnb_simulate_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const do
 }
 
 dnb_status dnb_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* pos, int64_t m,
-                         const double* tgt, double h, double* loss, double* gpos, void* stream) {
+                         const double* tgt, int tgt_per_member, double h, double* loss,
+                         double* gpos, void* stream) {
     const char* fn = "dnb_mmd_batch";
     CHECK(check_ctx(c, 1, fn));
     if (!(h > 0) || !is_fin(h)) return fail(DNB_ERR_ARG, "%s: h must be finite and > 0", fn);
-    if (!mmd_batch_fits(c, batch, n, m, gpos != nullptr))
+    if (tgt_per_member != 0 && tgt_per_member != 1)
+        return fail(DNB_ERR_ARG, "%s: tgt_per_member must be 0 or 1", fn);
+    if (!mmd_batch_fits(c, batch, n, m, gpos != nullptr, tgt_per_member != 0))
         return fail(DNB_ERR_ARG, "%s: batch %lld, n %lld, m %lld do not fit a context of max_n = %lld",
                     fn, (long long)batch, (long long)n, (long long)m, (long long)c->max_n);
     CHECK(check_dev(pos, "pos", fn));
@@ -583,7 +586,8 @@ dnb_status dnb_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* pos
     CHECK(check_dev(loss, "loss", fn));
     CHECK(check_dev(gpos, "gpos", fn, true));
     if (gpos && gpos == pos) return fail(DNB_ERR_ARG, "%s: gpos must not alias pos", fn);
-    HIP_TRY(launch_mmd_batch(c, batch, n, pos, m, tgt, h, loss, gpos, (hipStream_t)stream));
+    HIP_TRY(launch_mmd_batch(c, batch, n, pos, m, tgt, tgt_per_member, h, loss, gpos,
+                             (hipStream_t)stream));
     return DNB_OK;
 }
 

@@ -138,14 +138,18 @@ hipError_t launch_mmd(dnb_ctx* c, int64_t n, const double* pos, int64_t m, const
     return hipGetLastError();
 }
 
-// Loss of every member of an ensemble against one target.  pxx, pxy:
-// [batch][S][rows][npad] kernel sums per target (rows = 1, or 4 with the gradient
-// terms; sstride = rows npad); red[8 q + 2] holds the block sums of
-// sum_ab k(y_a, y_b) from k_mmd_y.  One block per member.
+// Loss of every member of an ensemble.  pxx, pxy: [batch][S][rows][npad] kernel
+// sums per target (rows = 1, or 4 with the gradient terms; sstride = rows npad).
+// The target term sum_ab k(y_a, y_b) comes, for one shared target, from the
+// block sums red[8 q + 2] of k_mmd_y (pyy NULL), or, for a target per member,
+// from pyy [batch][Syy][npad_y] (the slice sums of each member's target).  One
+// block per member.
 __global__ __launch_bounds__(BS) void k_mmd_batch_final(const double* __restrict__ pxx, int S,
                                                         const double* __restrict__ pxy, int Sxy,
                                                         int64_t sstride, int n, int m,
                                                         const double* __restrict__ red, int nby,
+                                                        const double* __restrict__ pyy, int Syy,
+                                                        int64_t npad_y,
                                                         double* __restrict__ loss) {
     __shared__ double sh[3 * BS];
     const int b = blockIdx.x;
@@ -156,7 +160,13 @@ __global__ __launch_bounds__(BS) void k_mmd_batch_final(const double* __restrict
         for (int i = threadIdx.x; i < n; i += BS) v[0] += qx[(int64_t)s * sstride + i];
     for (int s = 0; s < Sxy; ++s)
         for (int i = threadIdx.x; i < n; i += BS) v[1] += qy[(int64_t)s * sstride + i];
-    for (int q = threadIdx.x; q < nby; q += BS) v[2] += red[8 * q + 2];
+    if (pyy) {
+        const double* qq = pyy + (int64_t)b * Syy * npad_y;
+        for (int s = 0; s < Syy; ++s)
+            for (int a = threadIdx.x; a < m; a += BS) v[2] += qq[(int64_t)s * npad_y + a];
+    } else {
+        for (int q = threadIdx.x; q < nby; q += BS) v[2] += red[8 * q + 2];
+    }
     block_sum<3>(v, sh);
     if (threadIdx.x == 0)
         loss[b] = v[0] / ((double)n * n) + v[2] / ((double)m * m) - 2.0 * v[1] / ((double)n * m);
@@ -178,13 +188,25 @@ static void mmd_batch_slices(const dnb_ctx* c, int64_t batch, int64_t n, int64_t
     Sxy = (int)cdiv(m, jslice_xy);
 }
 
-bool mmd_batch_fits(const dnb_ctx* c, int64_t batch, int64_t n, int64_t m, bool grad) {
-    if (batch < 1 || batch > DNB_BATCH_MAX || n < 1 || m < 1 || n > c->max_n || m > c->max_n)
-        return false;
+// Partial-sum doubles of the batched loss: the target-source sums of every
+// member, plus, with a target per member, the slice sums of each target.
+static int64_t mmd_batch_doubles(const dnb_ctx* c, int64_t batch, int64_t n, int64_t m,
+                                 bool grad, bool per_member) {
     int S, js, Sxy, jsxy;
     mmd_batch_slices(c, batch, n, m, S, js, Sxy, jsxy);
-    const int64_t npad = cdiv(n, BS) * BS;
-    return batch * (S + Sxy) * npad * (grad ? 4 : 1) <= 8 * c->slice_rows;
+    int64_t total = batch * (S + Sxy) * cdiv(n, BS) * BS * (grad ? 4 : 1);
+    if (per_member) {
+        mmd_batch_slices(c, batch, m, m, S, js, Sxy, jsxy);
+        total += batch * S * cdiv(m, BS) * BS;
+    }
+    return total;
+}
+
+bool mmd_batch_fits(const dnb_ctx* c, int64_t batch, int64_t n, int64_t m, bool grad,
+                    bool per_member) {
+    if (batch < 1 || batch > DNB_BATCH_MAX || n < 1 || m < 1 || n > c->max_n || m > c->max_n)
+        return false;
+    return mmd_batch_doubles(c, batch, n, m, grad, per_member) <= 8 * c->slice_rows;
 }
 
 // Gradient rows of every member (the arithmetic and order of k_mmd_x).
@@ -214,8 +236,8 @@ __global__ __launch_bounds__(BS) void k_mmd_batch_grad(const double* __restrict_
 }
 
 hipError_t launch_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* pos, int64_t m,
-                            const double* tgt, double h, double* loss, double* gpos,
-                            hipStream_t st) {
+                            const double* tgt, int per_member, double h, double* loss,
+                            double* gpos, hipStream_t st) {
     const double inv2h2 = 1.0 / (2.0 * h * h);
     int S, jslice, Sxy, jslice_xy;
     mmd_batch_slices(c, batch, n, m, S, jslice, Sxy, jslice_xy);
@@ -229,15 +251,32 @@ hipError_t launch_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* 
     const Slicing sy = plain_slicing(c, m);
     hipLaunchKernelGGL(k_mmd_rows, dim3(nblk, S, (unsigned)batch), dim3(BS), 0, st, pos, (int)n,
                        pos, (int)n, inv2h2, jslice, wg, pxx, npad, ss, 3 * n, 3 * n, S * ss);
+    const int64_t tstride = per_member ? 3 * m : 0;
     hipLaunchKernelGGL(k_mmd_rows, dim3(nblk, Sxy, (unsigned)batch), dim3(BS), 0, st, pos, (int)n,
-                       tgt, (int)m, inv2h2, jslice_xy, wg, pxy, npad, ss, 3 * n, (int64_t)0,
+                       tgt, (int)m, inv2h2, jslice_xy, wg, pxy, npad, ss, 3 * n, tstride,
                        Sxy * ss);
-    hipLaunchKernelGGL(k_mmd_rows, dim3(sy.nblk, sy.S), dim3(BS), 0, st, tgt, (int)m, tgt, (int)m,
-                       inv2h2, sy.jslice, 0, pyy, sy.npad, 4 * sy.npad, 0, 0, 0);
-    hipLaunchKernelGGL(k_mmd_y, dim3(sy.nblk), dim3(BS), 0, st, pyy, sy.S, sy.npad, (int)m,
-                       c->red);
-    hipLaunchKernelGGL(k_mmd_batch_final, dim3((unsigned)batch), dim3(BS), 0, st, pxx, S, pxy, Sxy,
-                       ss, (int)n, (int)m, c->red, sy.nblk, loss);
+    if (per_member) {
+        // each member's own target term, in its own slices after pxy
+        int Syy, jsyy, s2, j2;
+        mmd_batch_slices(c, batch, m, m, Syy, jsyy, s2, j2);
+        const int nblk_y = (int)cdiv(m, BS);
+        const int64_t npad_y = (int64_t)nblk_y * BS;
+        double* pyb = pxy + batch * Sxy * ss;
+        hipLaunchKernelGGL(k_mmd_rows, dim3(nblk_y, Syy, (unsigned)batch), dim3(BS), 0, st, tgt,
+                           (int)m, tgt, (int)m, inv2h2, jsyy, 0, pyb, npad_y, npad_y, 3 * m, 3 * m,
+                           Syy * npad_y);
+        hipLaunchKernelGGL(k_mmd_batch_final, dim3((unsigned)batch), dim3(BS), 0, st, pxx, S, pxy,
+                           Sxy, ss, (int)n, (int)m, (const double*)nullptr, 0,
+                           (const double*)pyb, Syy, npad_y, loss);
+    } else {
+        hipLaunchKernelGGL(k_mmd_rows, dim3(sy.nblk, sy.S), dim3(BS), 0, st, tgt, (int)m, tgt,
+                           (int)m, inv2h2, sy.jslice, 0, pyy, sy.npad, 4 * sy.npad, 0, 0, 0);
+        hipLaunchKernelGGL(k_mmd_y, dim3(sy.nblk), dim3(BS), 0, st, pyy, sy.S, sy.npad, (int)m,
+                           c->red);
+        hipLaunchKernelGGL(k_mmd_batch_final, dim3((unsigned)batch), dim3(BS), 0, st, pxx, S, pxy,
+                           Sxy, ss, (int)n, (int)m, (const double*)c->red, sy.nblk,
+                           (const double*)nullptr, 0, (int64_t)0, loss);
+    }
     if (wg)
         hipLaunchKernelGGL(k_mmd_batch_grad, dim3(nblk, (unsigned)batch), dim3(BS), 0, st, pxx, S,
                            pxy, Sxy, npad, (int)n, (int)m, h, gpos);

@@ -338,7 +338,8 @@ hipError_t launch_place_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const do
 hipError_t launch_place_batch(int64_t batch, int64_t n, const double* w, const double* xi,
                               const double* zeta, const double* m_tot, double a_p, double G,
                               double* pos, double* vel, double* mass, hipStream_t st);
-bool mmd_batch_fits(const dnb_ctx* c, int64_t batch, int64_t n, int64_t m, bool grad);
+bool mmd_batch_fits(const dnb_ctx* c, int64_t batch, int64_t n, int64_t m, bool grad,
+                    bool per_member);
 
 // Orbit fit (orbitfit.hip).  The model struct is declared in dnb_orbitfit.h.
 }  // namespace dnb
@@ -356,7 +357,7 @@ hipError_t launch_track_lm(const dnb_track_model& md, const double* trk, int K, 
                            double* p, int64_t n_iter, double lam0, double* chi2, void* work,
                            hipStream_t st);
 hipError_t launch_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* pos, int64_t m,
-                            const double* tgt, double h, double* loss, double* gpos,
-                            hipStream_t st);
+                            const double* tgt, int per_member, double h, double* loss,
+                            double* gpos, hipStream_t st);
 
 }  // namespace dnb

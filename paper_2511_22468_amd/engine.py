@@ -220,25 +220,30 @@ class Context:
             _lib.ptr(work), _lib.ptr(g0), _lib.ptr(gv0), _lib.ptr(gpar), _lib.stream_handle()))
         return g0, gv0, gpar
 
-    def mmd_batch(self, pos, tgt, h):
-        """Loss of each member pos[b] (B, 3, n) against tgt (3, m): a (B,) tensor."""
-        B, n, m = pos.shape[0], pos.shape[2], tgt.shape[1]
-        _arr(pos, (B, 3, n), "pos"); _vec(tgt, m, "tgt")
+    def _mmd_batch(self, pos, tgt, h, grad):
+        B, n, m = pos.shape[0], pos.shape[2], tgt.shape[-1]
+        _arr(pos, (B, 3, n), "pos")
+        per = tgt.dim() == 3
+        if per:
+            _arr(tgt, (B, 3, m), "tgt")
+        else:
+            _vec(tgt, m, "tgt")
         loss = self._new(B)
+        g = self._new(B, 3, n) if grad else None
         _lib.check(_lib.lib().dnb_mmd_batch(self._h, B, n, _lib.ptr(pos), m, _lib.ptr(tgt),
-                                            float(h), _lib.ptr(loss), None,
-                                            _lib.stream_handle()))
-        return loss
-
-    def mmd_batch_grad(self, pos, tgt, h):
-        """Losses (B,) and their gradients (B, 3, n) for every member pos[b]."""
-        B, n, m = pos.shape[0], pos.shape[2], tgt.shape[1]
-        _arr(pos, (B, 3, n), "pos"); _vec(tgt, m, "tgt")
-        loss, g = self._new(B), self._new(B, 3, n)
-        _lib.check(_lib.lib().dnb_mmd_batch(self._h, B, n, _lib.ptr(pos), m, _lib.ptr(tgt),
-                                            float(h), _lib.ptr(loss), _lib.ptr(g),
+                                            int(per), float(h), _lib.ptr(loss), _lib.ptr(g),
                                             _lib.stream_handle()))
         return loss, g
+
+    def mmd_batch(self, pos, tgt, h):
+        """Loss of each member pos[b] (B, 3, n) against tgt: one target (3, m) for
+        all members, or tgt[b] (B, 3, m) for member b.  A (B,) tensor."""
+        return self._mmd_batch(pos, tgt, h, False)[0]
+
+    def mmd_batch_grad(self, pos, tgt, h):
+        """Losses (B,) and their gradients (B, 3, n) for every member pos[b]
+        (targets as in mmd_batch)."""
+        return self._mmd_batch(pos, tgt, h, True)
 
     def place_plummer_batch(self, w, xi, zeta, m_tot, a_p, G=G_DEFAULT):
         """Plummer spheres at w (B, 6) with masses m_tot (B,), shared unit samples

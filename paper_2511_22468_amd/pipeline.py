@@ -92,3 +92,60 @@ def grid_search(engine_ctx, thetas, xi, zeta, target, n_steps, pot=None, h=0.2, 
     for s, pos in run_ensemble(engine_ctx, th, xi, zeta, n_steps, pot, a_p, w_now):
         out[s:s + pos.shape[0]] = engine_ctx.mmd_batch(pos, target, h)
     return out.cpu().numpy()
+
+
+def batch_loss_and_grad(engine_ctx, thetas, xi, zeta, target, n_steps, pot=None, h=0.2,
+                        a_p=0.01, w_now=W_NOW, chunk=None):
+    """MMD loss and its gradient with respect to theta = (t_end, M_Plummer, M_NFW,
+    M_MN) at every parameter row, one batched pass per chunk (the gradient of
+    StreamModel.loss for many theta at once).  Each chunk runs the backward orbit
+    (keeping its trajectory), the placement, the N-body run (keeping its tape),
+    the MMD with its position gradient, then the three adjoints in reverse.
+    target is one observed stream (3, m) for every row or one per row (M, 3, m);
+    w_now one present-day centre (6 values) or one per row ((M, 6) host array).
+    Returns host arrays (losses (M,), grads (M, 4)).
+
+    With dt = t_end / n, the orbit runs with -dt and the N-body run with +dt, so
+    dL/dt_end = (dL/ddt_sim - dL/ddt_orb) / n; the particle masses are M / n each,
+    so the mass term of the N-body adjoint, sum_k m_k dL/dm_k, enters dL/dM
+    divided by M beside the placement's own dL/dM."""
+    pot = pot if pot is not None else Potential()
+    dev = xi.device
+    th = np.asarray(thetas, float).reshape(-1, 4)
+    M, n = th.shape[0], xi.shape[1]
+    T = int(n_steps)
+    pots = [pot.replace(m_nfw=r[2], m_mn=r[3]) for r in th]
+    dts = [r[0] / T for r in th]
+    cap = engine_ctx.batch_capacity(n)
+    if cap < 1:
+        raise ValueError(f"the context cannot hold one system of {n} particles")
+    cap = min(cap, M, int(chunk) if chunk else M)
+    w_rows = np.broadcast_to(np.asarray(w_now, float).reshape(-1, 6), (M, 6))
+    w_now_t = torch.tensor(np.ascontiguousarray(w_rows), dtype=torch.float64, device=dev)
+    per_target = target.dim() == 3
+    m_prog = torch.tensor(th[:, 1], dtype=torch.float64, device=dev)
+    losses = np.empty(M)
+    grads = np.empty((M, 4))
+    for s in range(0, M, cap):
+        e = min(M, s + cap)
+        B = e - s
+        odts = [-d for d in dts[s:e]]
+        w_init, traj = engine_ctx.orbit_batch(w_now_t[s:e].contiguous(), pots[s:e], odts, T,
+                                              keep=True)
+        mp = m_prog[s:e].contiguous()
+        pos, vel, mass = engine_ctx.place_plummer_batch(w_init, xi, zeta, mp, a_p, pot.G)
+        tape = engine_ctx.simulate_batch(pos, vel, mass, pots[s:e], dts[s:e], T, tape=True)
+        tgt = target[s:e].contiguous() if per_target else target
+        loss, gpos_T = engine_ctx.mmd_batch_grad(pos, tgt, h)
+        g0, gv0, gsim = engine_ctx.simulate_batch_vjp(mass, pots[s:e], dts[s:e], T, tape, pos,
+                                                      gpos_T)
+        del tape
+        gw, gm_place = engine_ctx.place_plummer_batch_vjp(zeta, mp, a_p, g0, gv0, pot.G)
+        _, gorb = engine_ctx.orbit_batch_vjp(traj, pots[s:e], odts, T, gw)
+        g = torch.stack([(gsim[:, 2] - gorb[:, 2]) / T,
+                         gm_place + gsim[:, 3] / mp,
+                         gsim[:, 0] + gorb[:, 0],
+                         gsim[:, 1] + gorb[:, 1]], dim=1)
+        losses[s:e] = loss.cpu().numpy()
+        grads[s:e] = g.cpu().numpy()
+    return losses, grads

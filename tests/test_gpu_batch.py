@@ -271,3 +271,88 @@ def test_batched_adjoint_equals_single_system_adjoints(eng):
     ref = oadj.simulate_vjp(traj, m, ops[2], dts[2], gx[2].cpu().numpy().T, gv[2].cpu().numpy().T)
     got = g0[2].cpu().numpy().T
     assert np.sqrt(((got - ref["x0"]) ** 2).sum()) <= 1e-3 * np.sqrt((ref["x0"] ** 2).sum())
+
+
+def test_batched_pipeline_gradient_matches_single_model_and_oracle(eng):
+    """pipeline.batch_loss_and_grad (orbit, placement, N-body run, MMD and their
+    three adjoints, all batched) against StreamModel.loss_and_grad member by member
+    and, for one member, against the oracle pipeline's exact gradient."""
+    pk, engine, ctx = eng
+    from oracle import pipeline as opipe
+    from paper_2511_22468_amd.pipeline import StreamModel, batch_loss_and_grad
+    n, T, B = 300, 30, 4
+    say(f"[batch-grad] B={B} n={n} T={T}")
+    xi, zeta = plummer_unit(n, 31)
+    Y = W_X + 0.05 * np.random.default_rng(32).normal(size=(128, 3))
+    op = OPot()
+    thetas = np.array([[pk.myr(30.0 * (1 + 0.1 * b)), 3e4 * (1 - 0.1 * b), 1.1e12 * (1 + 0.03 * b),
+                        6.0e10 * (1 + 0.05 * b)] for b in range(B)])
+    t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device="cuda")
+    losses, grads = batch_loss_and_grad(ctx, thetas, t3(xi), t3(zeta), t3(Y), T,
+                                        gpu_pot(engine, op), h=0.2, chunk=3)
+    model = StreamModel(ctx, t3(xi), t3(zeta), t3(Y), T, pot=gpu_pot(engine, op), h=0.2,
+                        ckpt_every=1)
+    for b in range(B):
+        L, g = model.loss_and_grad(torch.tensor(thetas[b], device="cuda"))
+        assert abs(losses[b] / L.item() - 1) <= 1e-12, b
+        # same trajectories bit for bit; the MMD gradient sums are ordered
+        # differently, which moves FP32 roundings of the adjoint's pair terms
+        sg, sr = grads[b] * thetas[b], g.cpu().numpy() * thetas[b]
+        assert np.abs(sg - sr).max() <= 1e-6 * np.abs(sr).max(), (b, sg, sr)
+    L_ref, g = opipe.loss_and_grad(thetas[0], xi, zeta, op, T, Y, 0.2)
+    g_ref = np.array([g["t_end"], g["m_prog"], g["m_nfw"], g["m_mn"]])
+    assert abs(losses[0] / L_ref - 1) <= 1e-3
+    sg, sr = grads[0] * thetas[0], g_ref * thetas[0]
+    assert np.abs(sg - sr).max() <= 1e-3 * np.abs(sr).max()
+
+
+def test_batched_component_adjoints_equal_single_ones(eng):
+    """The three per-member adjoints the batched pipeline gradient chains: the MMD
+    position gradient (against dnb_mmd and the oracle), the test-particle orbit VJP
+    and the Plummer placement VJP (against their single-system entries)."""
+    pk, engine, ctx = eng
+    from oracle import mmd as ommd
+    B, n, m, T = 3, 300, 200, 40
+    say(f"[batch-vjp] B={B} n={n} m={m} T={T}")
+    rng = np.random.default_rng(90)
+    pos = torch.tensor(W_X[None, :, None] + 0.1 * rng.normal(size=(B, 3, n)), device="cuda")
+    Y = W_X + 0.1 * rng.normal(size=(m, 3))
+    tgt = torch.tensor(np.ascontiguousarray(Y.T), device="cuda")
+    loss, g = ctx.mmd_batch_grad(pos, tgt, 0.2)
+    for b in range(B):
+        sl, sg = ctx.mmd(pos[b].contiguous(), tgt, 0.2)
+        assert abs(loss[b].item() / sl.item() - 1) <= 1e-13
+        # per-row errors against the largest row: rows near a kernel-sum cancellation
+        # have small gradients with few correct digits in any summation order
+        got, single = g[b].cpu().numpy().T, sg.cpu().numpy().T
+        scale = np.sqrt((single ** 2).sum(1)).max()
+        assert np.sqrt(((got - single) ** 2).sum(1)).max() <= 1e-13 * scale, b
+        ref = ommd.mmd2_grad(pos[b].cpu().numpy().T, Y, 0.2)
+        assert np.sqrt(((got - ref) ** 2).sum(1)).max() <= 1e-12 * scale, b
+    # orbits: each member its own potential and signed step
+    ops = [member_pot(b) for b in range(B)]
+    pots = [gpu_pot(engine, o) for o in ops]
+    dts = [pk.myr(2.0) * (1 + 0.2 * b) * (-1 if b == 1 else 1) for b in range(B)]
+    w0 = torch.tensor(np.concatenate([W_X, W_V])[None, :] + rng.normal(size=(B, 6)),
+                      device="cuda")
+    w_out, traj = ctx.orbit_batch(w0, pots, dts, T, keep=True)
+    gw_out = torch.tensor(rng.normal(size=(B, 6)), device="cuda")
+    gw0, gpar = ctx.orbit_batch_vjp(traj, pots, dts, T, gw_out)
+    for b in range(B):
+        s_out, s_traj = ctx.orbit(w0[b].contiguous(), pots[b], dts[b], T)
+        assert torch.equal(s_traj, traj[b])
+        s0, sp = ctx.orbit_vjp(s_traj, pots[b], dts[b], T, gw_out[b].contiguous())
+        np.testing.assert_allclose(gw0[b].cpu().numpy(), s0.cpu().numpy(), rtol=1e-13, atol=0)
+        np.testing.assert_allclose(gpar[b].cpu().numpy(), sp.cpu().numpy(), rtol=1e-13, atol=0)
+    # placement: shared unit samples, per-member centre and mass
+    xi, zeta = plummer_unit(n, 91)
+    t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device="cuda")
+    m_tot = torch.tensor([2e4, 3.5e4, 5e3], device="cuda", dtype=torch.float64)
+    gpos = torch.tensor(rng.normal(size=(B, 3, n)), device="cuda")
+    gvel = torch.tensor(rng.normal(size=(B, 3, n)), device="cuda")
+    gw, gm = ctx.place_plummer_batch_vjp(t3(zeta), m_tot, 0.01, gpos, gvel)
+    for b in range(B):
+        sw, sm = ctx.place_plummer_vjp(t3(zeta), m_tot[b].item(), 0.01, gpos[b].contiguous(),
+                                       gvel[b].contiguous())
+        np.testing.assert_allclose(gw[b].cpu().numpy(), sw.cpu().numpy(), rtol=1e-12, atol=0)
+        assert abs(gm[b].item() / sm.item() - 1) <= 1e-12, b
