@@ -242,6 +242,72 @@ def grid(n=1000, T=1000, per_axis=10):
                             "rank_of_true_point": int((losses < losses[k_true]).sum())}}
 
 
+def bootstrap(B=64, n=1000, T=1000, iters=10, n_seq=2):
+    """The refinement stage of the stream inference for a bootstrap of B
+    realisations of the observed stream (Fig. 2, steps 5-6): iters descent steps
+    of the full pipeline gradient for each, n = 1000 particles and 1000 steps,
+    all realisations advanced together by the batched gradient; against the
+    same descent for n_seq realisations one at a time (StreamModel), scaled to B.
+    Softening at the Plummer scale radius (the fit's setting, under which the
+    gradient of the 1000-step map is informative)."""
+    import torch
+
+    from paper_2511_22468_amd import bootstrap as BS, engine
+    from paper_2511_22468_amd.fit import EPS_FIT
+    from paper_2511_22468_amd.pipeline import StreamModel, make_target
+    from synth import plummer_unit
+
+    dev = torch.device("cuda", 0)
+    t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device=dev)
+    pot = engine.Potential(eps=EPS_FIT)
+    ctx = engine.Context(max(B, 4) * 1024, "fp32c")
+    u_true = np.array([-0.5, 0.0, 0.0, 0.0])
+    xt, zt = plummer_unit(n, 81)
+    xi, zeta = plummer_unit(n, 82)
+    target = make_target(ctx, t3(xt), t3(zt),
+                         torch.tensor(BS.theta_rows(u_true[None])[0], device=dev), T, pot=pot)
+    noise = torch.tensor(np.random.default_rng(83).normal(size=(B, 3, n)), device=dev)
+    targets = BS.resample(target, 0.05, noise)
+    u0 = np.repeat((u_true + np.array([0.1, -0.15, 0.1, -0.1]))[None], B, 0)
+    lr = 0.05
+    BS.refine(ctx, u0[:2], t3(xi), t3(zeta), targets[:2].contiguous(), T, lr, 1, pot=pot)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u_best, L_best, hist = BS.refine(ctx, u0, t3(xi), t3(zeta), targets, T, lr, iters, pot=pot)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    # the same descent one realisation at a time
+    t0 = time.perf_counter()
+    for b in range(n_seq):
+        model = StreamModel(ctx, t3(xi), t3(zeta), targets[b].contiguous(), T, pot=pot,
+                            ckpt_every=1)
+        u = u0[b].copy()
+        for it in range(iters + 1):
+            th = torch.tensor(BS.theta_rows(u[None])[0], device=dev)
+            if it == iters:
+                with torch.no_grad():
+                    model.loss(th).item()
+                break
+            _, g = model.loss_and_grad(th)
+            gu = g.cpu().numpy() * BS.dtheta_du_rows(u[None])[0]
+            u = np.clip(u - lr * gu / np.sqrt((gu * gu).sum()), -1, 1)
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / n_seq * B
+    ctx.close()
+    th_best = BS.theta_rows(u_best)
+    th_true = BS.theta_rows(u_true[None])[0]
+    return {"bootstrap_refinement": {
+        "realisations": B, "n": n, "steps": T, "descent_steps": iters,
+        "gradient_evaluations": B * iters, "seconds_batched": t_batch,
+        "seconds_one_at_a_time_scaled": t_seq, "sequential_realisations_timed": n_seq,
+        "speedup": t_seq / t_batch,
+        "pair_interactions_per_s": B * iters * 2 * (T + 1) * n * n / t_batch,
+        "loss_first_mean": float(hist[0].mean()), "loss_best_mean": float(L_best.mean()),
+        "u_true": u_true.tolist(), "u_start": u0[0].tolist(),
+        "u_best_mean": u_best.mean(0).tolist(), "u_best_std": u_best.std(0).tolist(),
+        "theta_best_over_true_mean": (th_best / th_true).mean(0).tolist()}}
+
+
 def configs():
     """End-to-end wall time of the three smaller workloads (HIP events, after one
     warm-up): N = 1024 FP64, 400 steps of 0.5 Myr; N = 16384 FP32C, 4000 steps;
@@ -407,6 +473,10 @@ def main():
     ap.add_argument("--grid", action="store_true",
                     help="grid-search stage of the stream inference: the pipeline loss at "
                          "10^4 parameter combinations (N = 1000, 1000 steps), one JSON line")
+    ap.add_argument("--bootstrap", action="store_true",
+                    help="bootstrap refinement of the stream inference: 10 descent steps of "
+                         "the pipeline gradient for 64 resampled streams at once vs one at a "
+                         "time (N = 1000, 1000 steps), one JSON line")
     ap.add_argument("--configs", action="store_true",
                     help="end-to-end time of the N = 1024, 16384 and 8192 (gradient) workloads, "
                          "one JSON line each")
@@ -417,8 +487,8 @@ def main():
     if args.cpu_sweep:
         print(json.dumps(cpu_sweep()), flush=True)
         return
-    if (args.sweep or args.ensemble or args.orbit_fit or args.configs or args.grid) \
-            and args.gpus != 1:
+    if (args.sweep or args.ensemble or args.orbit_fit or args.configs or args.grid
+            or args.bootstrap) and args.gpus != 1:
         print("bench.py measures one GPU only (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.sweep:
@@ -432,6 +502,9 @@ def main():
         return
     if args.grid:
         print(json.dumps(grid()), flush=True)
+        return
+    if args.bootstrap:
+        print(json.dumps(bootstrap()), flush=True)
         return
     if args.configs:
         for row in configs():

@@ -86,11 +86,15 @@ def run_ensemble(engine_ctx, thetas, xi, zeta, n_steps, pot=None, a_p=0.01, w_no
 def grid_search(engine_ctx, thetas, xi, zeta, target, n_steps, pot=None, h=0.2, a_p=0.01,
                 w_now=W_NOW):
     """MMD loss of the pipeline at every parameter row (the grid-search stage of
-    the inference, Sec. 2.2.1): a host array of M losses."""
+    the inference, Sec. 2.2.1): a host array of M losses.  target is one observed
+    stream (3, m) or one per row (M, 3, m)."""
     th = np.asarray(thetas, float).reshape(-1, 4)
     out = torch.empty(th.shape[0], dtype=torch.float64, device=xi.device)
+    per_target = target.dim() == 3
     for s, pos in run_ensemble(engine_ctx, th, xi, zeta, n_steps, pot, a_p, w_now):
-        out[s:s + pos.shape[0]] = engine_ctx.mmd_batch(pos, target, h)
+        e = s + pos.shape[0]
+        tgt = target[s:e].contiguous() if per_target else target
+        out[s:e] = engine_ctx.mmd_batch(pos, tgt, h)
     return out.cpu().numpy()
 
 

@@ -29,3 +29,13 @@ def test_orbit_frame_matches_oracle():
     e1, e2, n = S.frame((12.0, 0, 0), (0, -180.0, 60.0))
     np.testing.assert_allclose(orbit_frame((12.0, 0, 0), (0, -180.0, 60.0)),
                                np.concatenate([e1, e2, n]), atol=1e-15)
+
+
+def test_bootstrap_row_maps_match_the_single_row_maps():
+    from paper_2511_22468_amd import bootstrap as B, fit
+    rng = np.random.default_rng(4)
+    u = rng.uniform(-1, 1, (6, 4))
+    th, J = B.theta_rows(u), B.dtheta_du_rows(u)
+    for r in range(6):
+        np.testing.assert_allclose(th[r], fit.theta_internal(u[r][None]), rtol=1e-15)
+        np.testing.assert_allclose(J[r], fit.dtheta_du(u[r][None]), rtol=1e-15)

@@ -356,3 +356,64 @@ def test_batched_component_adjoints_equal_single_ones(eng):
                                        gvel[b].contiguous())
         np.testing.assert_allclose(gw[b].cpu().numpy(), sw.cpu().numpy(), rtol=1e-12, atol=0)
         assert abs(gm[b].item() / sm.item() - 1) <= 1e-12, b
+
+
+def test_mmd_batch_with_a_target_per_member(eng):
+    """Bootstrap form of the batched loss: member b against its own target tgt[b]
+    (loss and gradient equal dnb_mmd on that pair; a member whose target is its
+    own positions has zero loss and gradient)."""
+    pk, engine, ctx = eng
+    B, n, m = 4, 300, 260
+    say(f"[mmd-per-member] B={B} n={n} m={m}")
+    rng = np.random.default_rng(95)
+    pos = torch.tensor(W_X[None, :, None] + 0.1 * rng.normal(size=(B, 3, n)), device="cuda")
+    tgt = torch.tensor(W_X[None, :, None] + 0.1 * rng.normal(size=(B, 3, m)), device="cuda")
+    loss, g = ctx.mmd_batch_grad(pos, tgt, 0.2)
+    assert torch.equal(ctx.mmd_batch(pos, tgt, 0.2), loss)
+    for b in range(B):
+        sl, sg = ctx.mmd(pos[b].contiguous(), tgt[b].contiguous(), 0.2)
+        assert abs(loss[b].item() / sl.item() - 1) <= 1e-13, b
+        got, single = g[b].cpu().numpy().T, sg.cpu().numpy().T
+        scale = np.sqrt((single ** 2).sum(1)).max()
+        assert np.sqrt(((got - single) ** 2).sum(1)).max() <= 1e-13 * scale, b
+    # targets equal to the members' own positions (m = n)
+    l0, g0 = ctx.mmd_batch_grad(pos, pos.clone(), 0.2)
+    assert l0.abs().max().item() <= 1e-14
+    assert g0.abs().max().item() <= 1e-12
+    with pytest.raises(ValueError):
+        ctx.mmd_batch(pos, tgt[:2].contiguous(), 0.2)
+
+
+def test_bootstrap_refinement_equals_row_by_row_descent(eng):
+    """bootstrap.refine advances every realisation with one batched gradient per
+    step; the same descent row by row through StreamModel.loss_and_grad must
+    visit the same points (up to the FP32 roundings of the adjoint) and the loss
+    must not end above its start."""
+    pk, engine, ctx = eng
+    from paper_2511_22468_amd import bootstrap as BS
+    from paper_2511_22468_amd.pipeline import StreamModel, make_target
+    n, T, B, iters, lr = 300, 30, 3, 3, 0.05
+    say(f"[bootstrap] B={B} n={n} T={T} iters={iters}")
+    xi, zeta = plummer_unit(n, 61)
+    xt, zt = plummer_unit(n, 62)
+    t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device="cuda")
+    pot = engine.Potential()
+    u_true = np.array([-0.9, 0.2, 0.0, 0.1])
+    target = make_target(ctx, t3(xt), t3(zt), torch.tensor(BS.theta_rows(u_true[None])[0],
+                                                           device="cuda"), T, pot=pot)
+    noise = torch.tensor(np.random.default_rng(63).normal(size=(B, 3, n)), device="cuda")
+    targets = BS.resample(target, 0.005, noise)
+    u0 = u_true[None] + np.array([[0.05, -0.1, 0.1, 0.0], [0.0, 0.1, -0.05, 0.05],
+                                  [-0.05, 0.0, 0.05, -0.1]])
+    u_best, L_best, hist = BS.refine(ctx, u0, t3(xi), t3(zeta), targets, T, lr, iters, pot=pot)
+    assert hist.shape == (iters + 1, B)
+    for b in range(B):
+        model = StreamModel(ctx, t3(xi), t3(zeta), targets[b].contiguous(), T, pot=pot,
+                            ckpt_every=1)
+        u = u0[b].copy()
+        for it in range(iters + 1):
+            L, g = model.loss_and_grad(torch.tensor(BS.theta_rows(u[None])[0], device="cuda"))
+            assert abs(hist[it, b] / L.item() - 1) <= 1e-6, (b, it, hist[it, b], L.item())
+            gu = g.cpu().numpy() * BS.dtheta_du_rows(u[None])[0]
+            u = np.clip(u - lr * gu / np.sqrt((gu * gu).sum()), -1, 1)
+        assert L_best[b] == hist[:, b].min() and L_best[b] <= hist[0, b]
