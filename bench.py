@@ -269,11 +269,12 @@ def bootstrap(B=64, n=1000, T=1000, iters=10, n_seq=2):
     noise = torch.tensor(np.random.default_rng(83).normal(size=(B, 3, n)), device=dev)
     targets = BS.resample(target, 0.05, noise)
     u0 = np.repeat((u_true + np.array([0.1, -0.15, 0.1, -0.1]))[None], B, 0)
-    lr = 0.05
+    lr = 0.1
     BS.refine(ctx, u0[:2], t3(xi), t3(zeta), targets[:2].contiguous(), T, lr, 1, pot=pot)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    u_best, L_best, hist = BS.refine(ctx, u0, t3(xi), t3(zeta), targets, T, lr, iters, pot=pot)
+    u_best, L_best, hist, acc = BS.refine(ctx, u0, t3(xi), t3(zeta), targets, T, lr, iters,
+                                          pot=pot)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     # the same descent one realisation at a time
@@ -281,16 +282,20 @@ def bootstrap(B=64, n=1000, T=1000, iters=10, n_seq=2):
     for b in range(n_seq):
         model = StreamModel(ctx, t3(xi), t3(zeta), targets[b].contiguous(), T, pot=pot,
                             ckpt_every=1)
-        u = u0[b].copy()
-        for it in range(iters + 1):
-            th = torch.tensor(BS.theta_rows(u[None])[0], device=dev)
-            if it == iters:
-                with torch.no_grad():
-                    model.loss(th).item()
-                break
-            _, g = model.loss_and_grad(th)
-            gu = g.cpu().numpy() * BS.dtheta_du_rows(u[None])[0]
-            u = np.clip(u - lr * gu / np.sqrt((gu * gu).sum()), -1, 1)
+
+        def ev(u):
+            L, g = model.loss_and_grad(torch.tensor(BS.theta_rows(u[None])[0], device=dev))
+            return L.item(), g.cpu().numpy() * BS.dtheta_du_rows(u[None])[0]
+
+        u, step = u0[b].copy(), lr
+        L, gu = ev(u)
+        for it in range(iters):
+            cand = np.clip(u - step * gu / np.sqrt((gu * gu).sum()), -1, 1)
+            Lc, gc = ev(cand)
+            if Lc <= L:
+                u, L, gu = cand, Lc, gc
+            else:
+                step *= 0.5
     torch.cuda.synchronize()
     t_seq = (time.perf_counter() - t0) / n_seq * B
     ctx.close()
@@ -298,11 +303,12 @@ def bootstrap(B=64, n=1000, T=1000, iters=10, n_seq=2):
     th_true = BS.theta_rows(u_true[None])[0]
     return {"bootstrap_refinement": {
         "realisations": B, "n": n, "steps": T, "descent_steps": iters,
-        "gradient_evaluations": B * iters, "seconds_batched": t_batch,
+        "gradient_evaluations": B * (iters + 1), "seconds_batched": t_batch,
         "seconds_one_at_a_time_scaled": t_seq, "sequential_realisations_timed": n_seq,
         "speedup": t_seq / t_batch,
-        "pair_interactions_per_s": B * iters * 2 * (T + 1) * n * n / t_batch,
+        "pair_interactions_per_s": B * (iters + 1) * 2 * (T + 1) * n * n / t_batch,
         "loss_first_mean": float(hist[0].mean()), "loss_best_mean": float(L_best.mean()),
+        "accepted_steps_mean": float(acc.sum(0).mean()),
         "u_true": u_true.tolist(), "u_start": u0[0].tolist(),
         "u_best_mean": u_best.mean(0).tolist(), "u_best_std": u_best.std(0).tolist(),
         "theta_best_over_true_mean": (th_best / th_true).mean(0).tolist()}}

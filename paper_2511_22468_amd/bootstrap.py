@@ -9,15 +9,15 @@ batched pipeline gradient (pipeline.batch_loss_and_grad) per descent step serves
 all of them.
 
 Steps are taken in the normalised coordinates u of the prior box (t_end linear,
-masses logarithmic, as in the surrogate and the time-to-fit experiment), each of
-fixed length lr along its realisation's negative gradient direction: the paper
-quotes its learning rate without the coordinates it applies to, and a
-normalised step serves every horizon and mass scale alike.
+masses logarithmic, as in the surrogate and the time-to-fit experiment) along
+each realisation's negative gradient direction, with a step length that is
+halved whenever a step would raise the loss: the paper quotes its learning rate
+without the coordinates it applies to, and a normalised step serves every
+horizon and mass scale alike.
 """
 import numpy as np
-import torch
 
-from .pipeline import W_NOW, batch_loss_and_grad, grid_search
+from .pipeline import W_NOW, batch_loss_and_grad
 from .surrogate import PRIOR, denormalise
 from .units import gyr
 
@@ -50,27 +50,31 @@ def resample(target, sigma, noise):
 def refine(engine_ctx, u0, xi, zeta, targets, n_steps, lr, iters=10, pot=None, h=0.2,
            a_p=0.01, w_now=W_NOW, chunk=None):
     """iters descent steps for every row of u0 (B, 4) against targets[b]
-    (B, 3, m), then the loss at the last point.  Returns (u_best (B, 4),
-    L_best (B,), history (iters + 1, B) of losses)."""
+    (B, 3, m).  Each step moves a realisation by its current step length along
+    its negative gradient direction; a step that would raise that realisation's
+    loss is not taken and its length is halved (the descent of the time-to-fit
+    experiment).  Every step costs one batched pipeline gradient for all rows.
+    Returns (u (B, 4) at the lowest loss met, that loss (B,), history
+    (iters + 1, B) of the losses at the evaluated points, accepted (iters, B))."""
     u = np.clip(np.array(u0, float).reshape(-1, 4), -1.0, 1.0)
-    hist = []
-    best_u, best_L = u.copy(), np.full(u.shape[0], np.inf)
-    for it in range(iters + 1):
-        th = theta_rows(u)
-        if it < iters:
-            L, g = batch_loss_and_grad(engine_ctx, th, xi, zeta, targets, n_steps, pot, h, a_p,
-                                       w_now, chunk)
-        else:
-            L = grid_search(engine_ctx, th, xi, zeta, targets, n_steps, pot, h, a_p, w_now)
-        better = L < best_L
-        best_u[better], best_L[better] = u[better], L[better]
-        hist.append(L)
-        if it == iters:
-            break
-        gu = g * dtheta_du_rows(u)
-        gn = np.sqrt((gu * gu).sum(1, keepdims=True))
-        ok = np.isfinite(gn[:, 0]) & (gn[:, 0] > 0)
-        step = np.zeros_like(u)
-        step[ok] = lr * gu[ok] / gn[ok]
-        u = np.clip(u - step, -1.0, 1.0)
-    return best_u, best_L, np.array(hist)
+
+    def evaluate(uu):
+        L, g = batch_loss_and_grad(engine_ctx, theta_rows(uu), xi, zeta, targets, n_steps, pot,
+                                   h, a_p, w_now, chunk)
+        return L, g * dtheta_du_rows(uu)
+
+    L, gu = evaluate(u)
+    hist, accepted = [L.copy()], []
+    step = np.full(u.shape[0], float(lr))
+    for _ in range(iters):
+        gn = np.sqrt((gu * gu).sum(1))
+        ok = np.isfinite(gn) & (gn > 0)
+        cand = u.copy()
+        cand[ok] = np.clip(u[ok] - step[ok, None] * gu[ok] / gn[ok, None], -1.0, 1.0)
+        Lc, gc = evaluate(cand)
+        acc = ok & (Lc <= L)
+        u[acc], L[acc], gu[acc] = cand[acc], Lc[acc], gc[acc]
+        step[~acc] *= 0.5
+        hist.append(Lc)
+        accepted.append(acc)
+    return u, L, np.array(hist), np.array(accepted)
