@@ -38,9 +38,9 @@ FLOPS_VJP = 41                    # per pair of the vector-Jacobian product
 # profiles/pair_kernels_n65536_traffic.md (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the
 # factors measured on a 256 MiB copy), valid only for the kernel source they were
 # measured on (sha256 prefix of pair.hip followed by pair_common.h) and for N = 65536.
-TRAFFIC_SRC_SHA = "d13988065d2b249d"
+TRAFFIC_SRC_SHA = "14ab207d90b035f4"
 TRAFFIC_N = 65536
-TRAFFIC_KIB = {"k_pair_fwd_f32c": (7703.0, 49152.0), "k_pair_vjp_f32c": (15445.3, 49152.0)}
+TRAFFIC_KIB = {"k_pair_fwd_f32c": (7702.6, 49152.0), "k_pair_vjp_f32c": (15423.4, 49152.0)}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
@@ -242,41 +242,47 @@ def grid(n=1000, T=1000, per_axis=10):
                             "rank_of_true_point": int((losses < losses[k_true]).sum())}}
 
 
-def bootstrap(B=64, n=1000, T=1000, iters=10, n_seq=2):
+def bootstrap(sizes=(64, 256), n=1000, T=1000, iters=10, n_seq=2):
     """The refinement stage of the stream inference for a bootstrap of B
     realisations of the observed stream (Fig. 2, steps 5-6): iters descent steps
     of the full pipeline gradient for each, n = 1000 particles and 1000 steps,
-    all realisations advanced together by the batched gradient; against the
-    same descent for n_seq realisations one at a time (StreamModel), scaled to B.
-    Softening at the Plummer scale radius (the fit's setting, under which the
-    gradient of the 1000-step map is informative)."""
+    all realisations advanced together by the batched gradient (B = 64 and 256);
+    against the same descent for n_seq realisations one at a time (StreamModel),
+    scaled to B.  Softening at the Plummer scale radius (the fit's setting, under
+    which the gradient of the 1000-step map is informative)."""
     import torch
 
     from paper_2511_22468_amd import bootstrap as BS, engine
     from paper_2511_22468_amd.fit import EPS_FIT
-    from paper_2511_22468_amd.pipeline import StreamModel, make_target
+    from paper_2511_22468_amd.pipeline import StreamModel, grid_search, make_target
     from synth import plummer_unit
 
     dev = torch.device("cuda", 0)
     t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device=dev)
     pot = engine.Potential(eps=EPS_FIT)
-    ctx = engine.Context(max(B, 4) * 1024, "fp32c")
+    Bmax = max(sizes)
+    ctx = engine.Context(Bmax * 1024, "fp32c")
     u_true = np.array([-0.5, 0.0, 0.0, 0.0])
     xt, zt = plummer_unit(n, 81)
     xi, zeta = plummer_unit(n, 82)
     target = make_target(ctx, t3(xt), t3(zt),
                          torch.tensor(BS.theta_rows(u_true[None])[0], device=dev), T, pot=pot)
-    noise = torch.tensor(np.random.default_rng(83).normal(size=(B, 3, n)), device=dev)
+    noise = torch.tensor(np.random.default_rng(83).normal(size=(Bmax, 3, n)), device=dev)
     targets = BS.resample(target, 0.05, noise)
-    u0 = np.repeat((u_true + np.array([0.1, -0.15, 0.1, -0.1]))[None], B, 0)
+    u0 = np.repeat((u_true + np.array([0.1, -0.15, 0.1, -0.1]))[None], Bmax, 0)
     lr = 0.1
     BS.refine(ctx, u0[:2], t3(xi), t3(zeta), targets[:2].contiguous(), T, lr, 1, pot=pot)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    u_best, L_best, hist, acc = BS.refine(ctx, u0, t3(xi), t3(zeta), targets, T, lr, iters,
-                                          pot=pot)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
+    runs = {}
+    for B in sizes:
+        t0 = time.perf_counter()
+        u_best, L_best, hist, acc = BS.refine(ctx, u0[:B], t3(xi), t3(zeta),
+                                              targets[:B].contiguous(), T, lr, iters, pot=pot)
+        torch.cuda.synchronize()
+        runs[B] = (time.perf_counter() - t0, u_best, L_best, hist, acc)
+    # the loss at the true parameters: the floor set by the finite samples
+    L_true = grid_search(ctx, BS.theta_rows(np.repeat(u_true[None], Bmax, 0)), t3(xi), t3(zeta),
+                         targets, T, pot)
     # the same descent one realisation at a time
     t0 = time.perf_counter()
     for b in range(n_seq):
@@ -297,21 +303,23 @@ def bootstrap(B=64, n=1000, T=1000, iters=10, n_seq=2):
             else:
                 step *= 0.5
     torch.cuda.synchronize()
-    t_seq = (time.perf_counter() - t0) / n_seq * B
+    t_one = (time.perf_counter() - t0) / n_seq
     ctx.close()
-    th_best = BS.theta_rows(u_best)
     th_true = BS.theta_rows(u_true[None])[0]
-    return {"bootstrap_refinement": {
-        "realisations": B, "n": n, "steps": T, "descent_steps": iters,
-        "gradient_evaluations": B * (iters + 1), "seconds_batched": t_batch,
-        "seconds_one_at_a_time_scaled": t_seq, "sequential_realisations_timed": n_seq,
-        "speedup": t_seq / t_batch,
-        "pair_interactions_per_s": B * (iters + 1) * 2 * (T + 1) * n * n / t_batch,
-        "loss_first_mean": float(hist[0].mean()), "loss_best_mean": float(L_best.mean()),
-        "accepted_steps_mean": float(acc.sum(0).mean()),
-        "u_true": u_true.tolist(), "u_start": u0[0].tolist(),
-        "u_best_mean": u_best.mean(0).tolist(), "u_best_std": u_best.std(0).tolist(),
-        "theta_best_over_true_mean": (th_best / th_true).mean(0).tolist()}}
+    out = {"n": n, "steps": T, "descent_steps": iters, "gradient_evaluations_per_realisation":
+           iters + 1, "seconds_per_realisation_one_at_a_time": t_one,
+           "sequential_realisations_timed": n_seq, "u_true": u_true.tolist(),
+           "u_start": u0[0].tolist(), "loss_at_truth_mean": float(L_true.mean())}
+    for B, (t_b, u_best, L_best, hist, acc) in runs.items():
+        out[f"B{B}"] = {
+            "seconds_batched": t_b, "seconds_one_at_a_time_scaled": t_one * B,
+            "speedup": t_one * B / t_b,
+            "pair_interactions_per_s": B * (iters + 1) * 2 * (T + 1) * n * n / t_b,
+            "loss_first_mean": float(hist[0].mean()), "loss_best_mean": float(L_best.mean()),
+            "accepted_steps_mean": float(acc.sum(0).mean()),
+            "u_best_mean": u_best.mean(0).tolist(), "u_best_std": u_best.std(0).tolist(),
+            "theta_best_over_true_mean": (BS.theta_rows(u_best) / th_true).mean(0).tolist()}
+    return {"bootstrap_refinement": out}
 
 
 def configs():
@@ -481,8 +489,8 @@ def main():
                          "10^4 parameter combinations (N = 1000, 1000 steps), one JSON line")
     ap.add_argument("--bootstrap", action="store_true",
                     help="bootstrap refinement of the stream inference: 10 descent steps of "
-                         "the pipeline gradient for 64 resampled streams at once vs one at a "
-                         "time (N = 1000, 1000 steps), one JSON line")
+                         "the pipeline gradient for 64 and 256 resampled streams at once vs one "
+                         "at a time (N = 1000, 1000 steps), one JSON line")
     ap.add_argument("--configs", action="store_true",
                     help="end-to-end time of the N = 1024, 16384 and 8192 (gradient) workloads, "
                          "one JSON line each")
