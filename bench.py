@@ -133,14 +133,31 @@ def sweep(prec, sizes=(1024, 4096, 8192, 16384, 65536), reps=20):
             ctx.simulate_vjp(m, pot, myr(0.5), T, 1, tape, xx, w)
             torch.cuda.synchronize()
             p = ctx.profile_read()
+        shard = None
+        if n >= 65536:
+            # one device's block of the system split over 8: n / 8 targets x n sources
+            ni = n // 8
+            for _ in range(2):
+                ctx.profile(True)
+                ctx.profile_read()
+                for _ in range(reps):
+                    ctx.accelerations_rows(x, m, pot, 3 * ni, ni)
+                torch.cuda.synchronize()
+                q = ctx.profile_read()
+            s_ms = q["fwd_ms"] / q["fwd_launches"]
+            shard = {"targets": ni, "sources": n, "fwd_us": s_ms * 1e3,
+                     "fwd_pairs_per_s": ni * n / (s_ms * 1e-3)}
         ctx.close()
         f_ms = p["fwd_ms"] / p["fwd_launches"]
         v_ms = p["vjp_ms"] / p["vjp_launches"]
-        rows.append({"n": n, "fwd_us": f_ms * 1e3, "vjp_us": v_ms * 1e3,
-                     "fwd_pairs_per_s": n * n / (f_ms * 1e-3),
-                     "vjp_pairs_per_s": n * n / (v_ms * 1e-3),
-                     "fwd_frac_of_157.3TF": FLOPS_FWD * n * n / (f_ms * 1e-3) / 157.3e12,
-                     "vjp_frac_of_157.3TF": FLOPS_VJP * n * n / (v_ms * 1e-3) / 157.3e12})
+        row = {"n": n, "fwd_us": f_ms * 1e3, "vjp_us": v_ms * 1e3,
+               "fwd_pairs_per_s": n * n / (f_ms * 1e-3),
+               "vjp_pairs_per_s": n * n / (v_ms * 1e-3),
+               "fwd_frac_of_157.3TF": FLOPS_FWD * n * n / (f_ms * 1e-3) / 157.3e12,
+               "vjp_frac_of_157.3TF": FLOPS_VJP * n * n / (v_ms * 1e-3) / 157.3e12}
+        if shard:
+            row["shard_rows"] = shard
+        rows.append(row)
     return {"sweep": rows, "prec": prec}
 
 

@@ -92,6 +92,17 @@ const char* dnb_version(void);
 dnb_status dnb_accelerations(dnb_ctx* ctx, int64_t n, const double* pos, const double* mass,
                              const dnb_pot* pot, int with_ext, double* acc, void* stream);
 
+/* Accelerations of the targets i_begin .. i_begin + i_count - 1 only, each summed
+ * over all n sources (the rectangular block one device computes when the targets
+ * are split over several devices, Sec. 2 and Fig. 1).  pos [3][n] and mass [n]
+ * hold the whole system; acc [3][i_count] (device, must not alias pos) receives
+ * row r = target i_begin + r, with the arithmetic of dnb_accelerations (equal
+ * to it bit for bit when both split the sources into the same slices).  Requires
+ * 0 <= i_begin and 1 <= i_count <= n - i_begin (DNB_ERR_ARG otherwise). */
+dnb_status dnb_accelerations_rows(dnb_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                                  const dnb_pot* pot, int with_ext, int64_t i_begin,
+                                  int64_t i_count, double* acc, void* stream);
+
 /* One kick-drift-kick step of size dt (Sec. 2.2.1, Velocity-Verlet), in place on
  * pos [3][n] and vel [3][n]; the step evaluates a(x_n) and a(x_{n+1}). */
 dnb_status dnb_step(dnb_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,

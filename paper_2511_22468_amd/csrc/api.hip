@@ -269,6 +269,32 @@ dnb_status dnb_accelerations(dnb_ctx* c, int64_t n, const double* pos, const dou
     return DNB_OK;
 }
 
+dnb_status dnb_accelerations_rows(dnb_ctx* c, int64_t n, const double* pos, const double* mass,
+                                  const dnb_pot* pot, int with_ext, int64_t i_begin,
+                                  int64_t i_count, double* acc, void* stream) {
+    const char* fn = "dnb_accelerations_rows";
+    CHECK(check_ctx(c, n, fn));
+    CHECK(check_pot(pot, fn));
+    if (i_begin < 0 || i_count < 1 || i_begin > n - i_count)
+        return fail(DNB_ERR_ARG, "%s: rows [%lld, %lld + %lld) are not inside [0, %lld)", fn,
+                    (long long)i_begin, (long long)i_begin, (long long)i_count, (long long)n);
+    CHECK(check_dev(pos, "pos", fn));
+    CHECK(check_dev(mass, "mass", fn));
+    CHECK(check_dev(acc, "acc", fn));
+    if (acc == pos) return fail(DNB_ERR_ARG, "%s: acc must not alias pos", fn);
+    hipStream_t st = (hipStream_t)stream;
+    Pot p = to_pot(*pot);
+    const int nb = (int)cdiv(n, BS);
+    HIP_TRY(launch_mass_info(c, mass, n, st));
+    if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(pos, n, c->cpart, st));
+    HIP_TRY(launch_stage(c, pos, mass, n, c->cpart, nb, nullptr, nullptr, st));
+    HIP_TRY(profiled(c, 0, st, [&] {
+        return launch_pair_fwd_rows(c, n, i_begin, i_count, p.eps, st);
+    }));
+    HIP_TRY(launch_acc_rows(c, pos, n, i_begin, i_count, p, with_ext ? 1 : 0, acc, st));
+    return DNB_OK;
+}
+
 int64_t dnb_tape_doubles(int64_t n, int64_t n_steps, int64_t ckpt_every) {
     if (n < 1 || n_steps < 0 || ckpt_every < 1) return -1;
     if (n_steps == 0) return 0;

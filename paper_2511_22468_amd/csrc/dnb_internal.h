@@ -233,6 +233,20 @@ inline Slicing vjp_slicing(const dnb_ctx* c, int64_t n) {
 inline Slicing plain_slicing(const dnb_ctx* c, int64_t n) {
     return slicing_for(n, BS, c->target_blocks);
 }
+// Rectangular block: ni targets against n sources (ni = n gives fwd_slicing).
+inline Slicing rows_slicing(const dnb_ctx* c, int64_t ni, int64_t n) {
+    Slicing s;
+    s.nblk = (int)cdiv(ni, BS);
+    s.npad = (int64_t)s.nblk * BS;
+    int64_t want = c->target_blocks / s.nblk;
+    const int64_t max_by_tiles = cdiv(n, TILE);
+    if (want > max_by_tiles) want = max_by_tiles;
+    if (want > S_MAX) want = S_MAX;
+    if (want < 1) want = 1;
+    s.jslice = (int)(cdiv(cdiv(n, want), TILE) * TILE);
+    s.S = (int)cdiv(n, s.jslice);
+    return s;
+}
 
 // Kernel launchers (defined in the .hip files).  All return hipError_t of the launch.
 enum KdkMode { KDK_FIRST = 0, KDK_MID = 1, KDK_LAST = 2, KDK_ACC = 3 };
@@ -272,6 +286,10 @@ hipError_t launch_stage(dnb_ctx* c, const double* x, const double* mass, int64_t
                         const double* cpart, int nb, const double* centre_override,
                         double* centre_out, hipStream_t st);
 hipError_t launch_pair_fwd(dnb_ctx* c, int64_t n, double eps, hipStream_t st);
+hipError_t launch_pair_fwd_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, double eps,
+                                hipStream_t st);
+hipError_t launch_acc_rows(dnb_ctx* c, const double* x, int64_t n, int64_t i0, int64_t ni,
+                           const Pot& pot, int with_ext, double* acc, hipStream_t st);
 // Sets c->muni = (1, m) if all n masses equal m, else (0, 0); one block.
 hipError_t launch_mass_info(dnb_ctx* c, const double* mass, int64_t n, hipStream_t st);
 hipError_t launch_kdk(dnb_ctx* c, KdkMode mode, const FwdArgs& a, hipStream_t st);

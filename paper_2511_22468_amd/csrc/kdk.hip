@@ -201,6 +201,37 @@ hipError_t launch_kdk(dnb_ctx* c, KdkMode mode, const FwdArgs& a, hipStream_t st
     return hipGetLastError();
 }
 
+// Accelerations of targets [i0, i0 + ni) from the partials of launch_pair_fwd_rows
+// (the arithmetic of the KDK_ACC mode): acc [3][ni].
+template <bool F32>
+__global__ __launch_bounds__(BS) void k_acc_rows(const double* __restrict__ x, int64_t n,
+                                                 int64_t i0, int64_t ni, Pot pot, int with_ext,
+                                                 const void* __restrict__ part, int S,
+                                                 int64_t npad, double* __restrict__ acc) {
+    const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (r >= ni) return;
+    const int64_t i = i0 + r;
+    double ax, ay, az;
+    pair_sum<F32>(part, S, npad, r, pot.G, ax, ay, az);
+    if (with_ext) {
+        Ext e = ext_accel(pot, x[i], x[n + i], x[2 * n + i]);
+        ax += e.ax; ay += e.ay; az += e.az;
+    }
+    acc[r] = ax; acc[ni + r] = ay; acc[2 * ni + r] = az;
+}
+
+hipError_t launch_acc_rows(dnb_ctx* c, const double* x, int64_t n, int64_t i0, int64_t ni,
+                           const Pot& pot, int with_ext, double* acc, hipStream_t st) {
+    const Slicing sl = rows_slicing(c, ni, n);
+    if (c->prec == DNB_FP32C)
+        hipLaunchKernelGGL(k_acc_rows<true>, dim3(sl.nblk), dim3(BS), 0, st, x, n, i0, ni, pot,
+                           with_ext, (const void*)c->part, sl.S, sl.npad, acc);
+    else
+        hipLaunchKernelGGL(k_acc_rows<false>, dim3(sl.nblk), dim3(BS), 0, st, x, n, i0, ni, pot,
+                           with_ext, (const void*)c->part, sl.S, sl.npad, acc);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ reverse --
 
 template <bool F32>

@@ -50,10 +50,11 @@ __device__ __forceinline__ double rsqrt_f64(double s) {
 // k_mass_info); the branch on it is uniform over the grid.
 template <bool EPS0>
 __global__ __launch_bounds__(BS) void k_pair_fwd_f32c(const float4* __restrict__ js, int n,
-                                                      int nj, int jslice, float eps2,
-                                                      float* __restrict__ part, int64_t npad,
+                                                      int i0, int iend, int nj, int jslice,
+                                                      float eps2, float* __restrict__ part,
+                                                      int64_t npad,
                                                       const float* __restrict__ muni) {
-    const int i = blockIdx.x * BS + threadIdx.x;
+    const int i = i0 + blockIdx.x * BS + threadIdx.x;
     const int j0 = blockIdx.y * jslice;
     const int j1 = min(nj, j0 + jslice);
     const float4 me = js[min(i, n - 1)];
@@ -67,8 +68,8 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f32c(const float4* __restrict__
         fwd_f32c_slice<EPS0, false>(js, i, j0, j1, eps2, me, h, l);
     }
     const float hx = h[0], hy = h[1], hz = h[2], lx = l[0], ly = l[1], lz = l[2];
-    if (i < n) {
-        float* p = part + (int64_t)blockIdx.y * 6 * npad + i;
+    if (i < iend) {
+        float* p = part + (int64_t)blockIdx.y * 6 * npad + (i - i0);
         p[0 * npad] = hx; p[1 * npad] = hy; p[2 * npad] = hz;
         p[3 * npad] = lx; p[4 * npad] = ly; p[5 * npad] = lz;
     }
@@ -79,10 +80,11 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f32c(const float4* __restrict__
 // part: [S][3][npad] doubles.
 template <bool EPS0>
 __global__ __launch_bounds__(BS) void k_pair_fwd_f64(const double4* __restrict__ js, int n,
-                                                     int nj, int jslice, double eps2,
-                                                     double* __restrict__ part, int64_t npad) {
+                                                     int i0, int iend, int nj, int jslice,
+                                                     double eps2, double* __restrict__ part,
+                                                     int64_t npad) {
     constexpr int PB = 4;
-    const int i = blockIdx.x * BS + threadIdx.x;
+    const int i = i0 + blockIdx.x * BS + threadIdx.x;
     const int j0 = blockIdx.y * jslice;
     const int j1 = min(nj, j0 + jslice);
     const double4 me = js[min(i, n - 1)];
@@ -112,8 +114,8 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f64(const double4* __restrict__
             for (int u = 0; u < PB; ++u) qa[u] = qb[u];
         }
     }
-    if (i < n) {
-        double* p = part + (int64_t)blockIdx.y * 3 * npad + i;
+    if (i < iend) {
+        double* p = part + (int64_t)blockIdx.y * 3 * npad + (i - i0);
         p[0] = ax; p[npad] = ay; p[2 * npad] = az;
     }
 }
@@ -216,30 +218,38 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__
 }
 
 // ---------------------------------------------------------------- launchers --
-hipError_t launch_pair_fwd(dnb_ctx* c, int64_t n, double eps, hipStream_t st) {
-    const Slicing sl = fwd_slicing(c, n);
+// Targets [i0, i0 + ni) against all n staged sources; slice partials of target
+// i at row i - i0 (the whole system: i0 = 0, ni = n).
+hipError_t launch_pair_fwd_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, double eps,
+                                hipStream_t st) {
+    const Slicing sl = rows_slicing(c, ni, n);
     const int nj = (int)pad_sources(n);
+    const int a = (int)i0, e = (int)(i0 + ni);
     dim3 grid(sl.nblk, sl.S);
     if (c->prec == DNB_FP32C) {
         const float eps2 = (float)(eps * eps);
         const float4* js = (const float4*)c->js;
         if (eps == 0.0)
-            hipLaunchKernelGGL(k_pair_fwd_f32c<true>, grid, dim3(BS), 0, st, js, (int)n, nj,
+            hipLaunchKernelGGL(k_pair_fwd_f32c<true>, grid, dim3(BS), 0, st, js, (int)n, a, e, nj,
                                sl.jslice, eps2, (float*)c->part, sl.npad, c->muni);
         else
-            hipLaunchKernelGGL(k_pair_fwd_f32c<false>, grid, dim3(BS), 0, st, js, (int)n, nj,
-                               sl.jslice, eps2, (float*)c->part, sl.npad, c->muni);
+            hipLaunchKernelGGL(k_pair_fwd_f32c<false>, grid, dim3(BS), 0, st, js, (int)n, a, e,
+                               nj, sl.jslice, eps2, (float*)c->part, sl.npad, c->muni);
     } else {
         const double eps2 = eps * eps;
         const double4* js = (const double4*)c->js;
         if (eps == 0.0)
-            hipLaunchKernelGGL(k_pair_fwd_f64<true>, grid, dim3(BS), 0, st, js, (int)n, nj,
+            hipLaunchKernelGGL(k_pair_fwd_f64<true>, grid, dim3(BS), 0, st, js, (int)n, a, e, nj,
                                sl.jslice, eps2, (double*)c->part, sl.npad);
         else
-            hipLaunchKernelGGL(k_pair_fwd_f64<false>, grid, dim3(BS), 0, st, js, (int)n, nj,
-                               sl.jslice, eps2, (double*)c->part, sl.npad);
+            hipLaunchKernelGGL(k_pair_fwd_f64<false>, grid, dim3(BS), 0, st, js, (int)n, a, e,
+                               nj, sl.jslice, eps2, (double*)c->part, sl.npad);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_pair_fwd(dnb_ctx* c, int64_t n, double eps, hipStream_t st) {
+    return launch_pair_fwd_rows(c, n, 0, n, eps, st);
 }
 
 template <bool EPS0, bool MASS>

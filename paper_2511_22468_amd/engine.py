@@ -108,6 +108,17 @@ class Context:
                                                 _lib.stream_handle()))
         return acc
 
+    def accelerations_rows(self, pos, mass, pot, i_begin, i_count, with_ext=True):
+        """Accelerations (3, i_count) of targets i_begin .. i_begin + i_count - 1
+        against all n sources (one device's block of a target-split system)."""
+        n = mass.shape[0]
+        _vec(pos, n, "pos"); _arr(mass, (n,), "mass")
+        acc = self._new(3, int(i_count))
+        _lib.check(_lib.lib().dnb_accelerations_rows(
+            self._h, n, _lib.ptr(pos), _lib.ptr(mass), pot.c(), int(bool(with_ext)),
+            int(i_begin), int(i_count), _lib.ptr(acc), _lib.stream_handle()))
+        return acc
+
     def step(self, pos, vel, mass, pot, dt):
         n = mass.shape[0]
         _vec(pos, n, "pos"); _vec(vel, n, "vel"); _arr(mass, (n,), "mass")

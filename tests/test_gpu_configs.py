@@ -248,3 +248,27 @@ def test_pair_vjp_n65536_sampled_rows():
             f"median {np.median(err):.2e} (relative to the summed term magnitudes)")
         assert err.max() <= tol
         c.close()
+
+
+def test_shard_shaped_rows_n65536():
+    """One device's share of the N = 65536 system split over 8 devices: the 8192
+    targets of block 3 against all 65536 sources (dnb_accelerations_rows) on 256
+    sampled rows of the block against the oracle (FP32C <= 1e-5, FP64 <= 1e-12
+    relative per particle), and against the full call at FP32C rounding (the
+    block's launch splits the sources into more slices than the full one)."""
+    from paper_2511_22468_amd import engine
+    n, i0, ni = 65536, 3 * 8192, 8192
+    x, v, m = plummer_state(n, 4, 1e5)
+    op = OPot(eps=5e-4)
+    pot = gpot(engine, op)
+    rows = i0 + sample_rows(ni, 256, 45)
+    ref = of.pair_accel(x, m, G, op.eps, rows=rows) + of.ext_accel(x[rows], op)
+    for prec, tol in (("fp32c", 1e-5), ("fp64", 1e-12)):
+        c = engine.Context(n, prec)
+        say(f"[cfg] N=65536 rows [{i0}, {i0 + ni}) {prec}")
+        got = c.accelerations_rows(to_dev(x), to_dev(m), pot, i0, ni)
+        err = rel_rows(to_host(got)[rows - i0], ref)
+        assert err.max() <= tol, err.max()
+        full = to_host(c.accelerations(to_dev(x), to_dev(m), pot))[i0:i0 + ni]
+        assert rel_rows(to_host(got), full).max() <= (2e-7 if prec == "fp32c" else 1e-14)
+        c.close()

@@ -74,6 +74,36 @@ def test_accelerations_match_oracle(dnb, n, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("eps", [1e-3, 0.0])
+def test_accelerations_rows_equal_the_full_call(dnb, prec, eps):
+    """Row blocks (one device's share of a target-split system): with the same
+    source slicing (n = 2048: 8 slices either way) every row equals the full
+    dnb_accelerations bit for bit, for ragged blocks, a single row and the last
+    rows; bad ranges are refused."""
+    from paper_2511_22468_amd._lib import DnbError
+    pk, engine, ctx = dnb
+    n = 2048
+    say(f"[accel-rows] n={n} prec={prec} eps={eps}")
+    rng = np.random.default_rng(71)
+    x = W_X + rng.normal(scale=0.02, size=(n, 3))
+    m = rng.uniform(1.0, 5.0, n)
+    pot = gpu_pot(engine, OPot(eps=eps))
+    full = ctx[prec].accelerations(to_dev(x), to_dev(m), pot)
+    for i0, ni in [(0, n), (777, 300), (5, 1), (n - 1, 1), (1024, 1024), (0, 255)]:
+        got = ctx[prec].accelerations_rows(to_dev(x), to_dev(m), pot, i0, ni)
+        assert torch.equal(got, full[:, i0:i0 + ni]), (i0, ni)
+        got_i = ctx[prec].accelerations_rows(to_dev(x), to_dev(m), pot, i0, ni, with_ext=False)
+        ref_i = of.pair_accel(x, m, G, eps)[i0:i0 + ni] if ni <= 300 else None
+        if ref_i is not None:
+            sc = internal_scale(x, m, eps, np.arange(i0, i0 + ni))
+            err = np.sqrt(((to_host(got_i) - ref_i) ** 2).sum(1)) / sc
+            assert err.max() <= (1e-13 if prec == "fp64" else 1e-5), (i0, ni, err.max())
+    for i0, ni in [(-1, 5), (0, 0), (n - 4, 5), (n, 1)]:
+        with pytest.raises(DnbError):
+            ctx[prec].accelerations_rows(to_dev(x), to_dev(m), pot, i0, ni)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
 def test_zero_softening_masks_self_term(dnb, prec):
     pk, engine, ctx = dnb
     rng = np.random.default_rng(3)
