@@ -233,7 +233,11 @@ inline Slicing vjp_slicing(const dnb_ctx* c, int64_t n) {
 inline Slicing plain_slicing(const dnb_ctx* c, int64_t n) {
     return slicing_for(n, BS, c->target_blocks);
 }
-// Rectangular block: ni targets against n sources (ni = n gives fwd_slicing).
+// Rectangular block: ni targets against n sources.  A block of few targets
+// against many sources (one device's share of a split system) needs more slices
+// than a square launch to fill the chip, so the cap is S_MAX_ROWS; S * npad stays
+// below target_blocks * BS (the partial buffer's bound).
+constexpr int S_MAX_ROWS = 256;
 inline Slicing rows_slicing(const dnb_ctx* c, int64_t ni, int64_t n) {
     Slicing s;
     s.nblk = (int)cdiv(ni, BS);
@@ -241,7 +245,7 @@ inline Slicing rows_slicing(const dnb_ctx* c, int64_t ni, int64_t n) {
     int64_t want = c->target_blocks / s.nblk;
     const int64_t max_by_tiles = cdiv(n, TILE);
     if (want > max_by_tiles) want = max_by_tiles;
-    if (want > S_MAX) want = S_MAX;
+    if (want > S_MAX_ROWS) want = S_MAX_ROWS;
     if (want < 1) want = 1;
     s.jslice = (int)(cdiv(cdiv(n, want), TILE) * TILE);
     s.S = (int)cdiv(n, s.jslice);

@@ -218,11 +218,10 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__
 }
 
 // ---------------------------------------------------------------- launchers --
-// Targets [i0, i0 + ni) against all n staged sources; slice partials of target
-// i at row i - i0 (the whole system: i0 = 0, ni = n).
-hipError_t launch_pair_fwd_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, double eps,
-                                hipStream_t st) {
-    const Slicing sl = rows_slicing(c, ni, n);
+// Targets [i0, i0 + ni) against all n staged sources with the slicing sl; slice
+// partials of target i at row i - i0 (the whole system: i0 = 0, ni = n).
+static hipError_t launch_pair_fwd_sliced(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni,
+                                         const Slicing& sl, double eps, hipStream_t st) {
     const int nj = (int)pad_sources(n);
     const int a = (int)i0, e = (int)(i0 + ni);
     dim3 grid(sl.nblk, sl.S);
@@ -249,7 +248,12 @@ hipError_t launch_pair_fwd_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, d
 }
 
 hipError_t launch_pair_fwd(dnb_ctx* c, int64_t n, double eps, hipStream_t st) {
-    return launch_pair_fwd_rows(c, n, 0, n, eps, st);
+    return launch_pair_fwd_sliced(c, n, 0, n, fwd_slicing(c, n), eps, st);
+}
+
+hipError_t launch_pair_fwd_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, double eps,
+                                hipStream_t st) {
+    return launch_pair_fwd_sliced(c, n, i0, ni, rows_slicing(c, ni, n), eps, st);
 }
 
 template <bool EPS0, bool MASS>
