@@ -107,6 +107,8 @@ def batch_loss_and_grad(engine_ctx, thetas, xi, zeta, target, n_steps, pot=None,
     the MMD with its position gradient, then the three adjoints in reverse.
     target is one observed stream (3, m) for every row or one per row (M, 3, m);
     w_now one present-day centre (6 values) or one per row ((M, 6) host array).
+    chunk bounds the members per pass (default: as many as the context holds and
+    half of the free device memory takes, the tape being 72 n T bytes per member).
     Returns host arrays (losses (M,), grads (M, 4)).
 
     With dt = t_end / n, the orbit runs with -dt and the N-body run with +dt, so
@@ -123,7 +125,14 @@ def batch_loss_and_grad(engine_ctx, thetas, xi, zeta, target, n_steps, pot=None,
     cap = engine_ctx.batch_capacity(n)
     if cap < 1:
         raise ValueError(f"the context cannot hold one system of {n} particles")
-    cap = min(cap, M, int(chunk) if chunk else M)
+    if not chunk:
+        # every member keeps its whole trajectory for the adjoint (9 n doubles per
+        # step, plus the orbit and the per-member buffers): take at most half of
+        # the free device memory
+        free, _ = torch.cuda.mem_get_info(dev)
+        per_member = 8 * (9 * n * T + 3 * n + 3 * (T + 1) + 40 * n)
+        chunk = max(1, int(0.5 * free // per_member))
+    cap = min(cap, M, int(chunk))
     w_rows = np.broadcast_to(np.asarray(w_now, float).reshape(-1, 6), (M, 6))
     w_now_t = torch.tensor(np.ascontiguousarray(w_rows), dtype=torch.float64, device=dev)
     per_target = target.dim() == 3
