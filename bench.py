@@ -145,8 +145,18 @@ def sweep(prec, sizes=(1024, 4096, 8192, 16384, 65536), reps=20):
                 torch.cuda.synchronize()
                 q = ctx.profile_read()
             s_ms = q["fwd_ms"] / q["fwd_launches"]
+            for _ in range(2):
+                ctx.profile(True)
+                ctx.profile_read()
+                for _ in range(reps):
+                    ctx.accelerations_vjp(x, m, pot, w, i_begin=3 * ni, i_count=ni,
+                                          with_mass=False)
+                torch.cuda.synchronize()
+                q = ctx.profile_read()
+            sv_ms = q["vjp_ms"] / q["vjp_launches"]
             shard = {"targets": ni, "sources": n, "fwd_us": s_ms * 1e3,
-                     "fwd_pairs_per_s": ni * n / (s_ms * 1e-3)}
+                     "fwd_pairs_per_s": ni * n / (s_ms * 1e-3), "vjp_us": sv_ms * 1e3,
+                     "vjp_pairs_per_s": ni * n / (sv_ms * 1e-3)}
         ctx.close()
         f_ms = p["fwd_ms"] / p["fwd_launches"]
         v_ms = p["vjp_ms"] / p["vjp_launches"]

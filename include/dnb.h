@@ -103,6 +103,22 @@ dnb_status dnb_accelerations_rows(dnb_ctx* ctx, int64_t n, const double* pos, co
                                   const dnb_pot* pot, int with_ext, int64_t i_begin,
                                   int64_t i_count, double* acc, void* stream);
 
+/* Vector-Jacobian product of dnb_accelerations (the derivatives the paper's
+ * gradients with respect to initial conditions and particle masses are built
+ * from, Sec. 2), for the rows i_begin .. i_begin + i_count - 1.  With w [3][n]
+ * (device) the cotangent of the accelerations of all n particles, row r of
+ * gpos [3][i_count] receives d(sum_j w_j . a_j)/dx_k and gmass [i_count]
+ * (nullable) d(sum_j w_j . a_j)/dm_k, for k = i_begin + r; the external field
+ * enters gpos through its Hessian when with_ext is nonzero.  pos [3][n] and
+ * mass [n] hold the whole system.  The pair part runs in the precision of the
+ * context (FP32C: the cotangent is staged with a power-of-two scale, undone in
+ * FP64).  Outputs must not alias inputs; 0 <= i_begin and 1 <= i_count <=
+ * n - i_begin (DNB_ERR_ARG otherwise). */
+dnb_status dnb_accelerations_vjp(dnb_ctx* ctx, int64_t n, const double* pos, const double* mass,
+                                 const dnb_pot* pot, int with_ext, const double* w,
+                                 int64_t i_begin, int64_t i_count, double* gpos, double* gmass,
+                                 void* stream);
+
 /* One kick-drift-kick step of size dt (Sec. 2.2.1, Velocity-Verlet), in place on
  * pos [3][n] and vel [3][n]; the step evaluates a(x_n) and a(x_{n+1}). */
 dnb_status dnb_step(dnb_ctx* ctx, int64_t n, double* pos, double* vel, const double* mass,

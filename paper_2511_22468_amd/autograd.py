@@ -116,6 +116,30 @@ class PlacePlummer(torch.autograd.Function):
         return gw, gm[0], None, None, None, None, None
 
 
+class Accelerations(torch.autograd.Function):
+    """(pos, mass) -> a = a_int + a_ext (3, n) at fixed potential parameters;
+    the backward is dnb_accelerations_vjp (gradients of both inputs)."""
+
+    @staticmethod
+    def forward(ctx, pos, mass, engine_ctx, pot, with_ext):
+        p, m = pos.detach().contiguous(), mass.detach().contiguous()
+        ctx.save_for_backward(p, m)
+        ctx.engine_ctx, ctx.pot, ctx.with_ext = engine_ctx, pot, with_ext
+        return engine_ctx.accelerations(p, m, pot, with_ext=with_ext)
+
+    @staticmethod
+    def backward(ctx, gacc):
+        p, m = ctx.saved_tensors
+        g, gm = ctx.engine_ctx.accelerations_vjp(p, m, ctx.pot, gacc.contiguous(),
+                                                 with_ext=ctx.with_ext,
+                                                 with_mass=ctx.needs_input_grad[1])
+        return g, gm, None, None, None
+
+
+def accelerations(engine_ctx, pos, mass, pot: Potential, with_ext=True):
+    return Accelerations.apply(pos, mass, engine_ctx, pot, with_ext)
+
+
 def simulate(engine_ctx, pos0, vel0, mass, m_nfw, m_mn, dt, pot: Potential, n_steps,
              ckpt_every=1, m_scale=None):
     return Simulate.apply(pos0, vel0, mass, m_nfw, m_mn, dt, m_scale, engine_ctx, pot, n_steps,

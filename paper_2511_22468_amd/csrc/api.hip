@@ -295,6 +295,38 @@ dnb_status dnb_accelerations_rows(dnb_ctx* c, int64_t n, const double* pos, cons
     return DNB_OK;
 }
 
+dnb_status dnb_accelerations_vjp(dnb_ctx* c, int64_t n, const double* pos, const double* mass,
+                                 const dnb_pot* pot, int with_ext, const double* w,
+                                 int64_t i_begin, int64_t i_count, double* gpos, double* gmass,
+                                 void* stream) {
+    const char* fn = "dnb_accelerations_vjp";
+    CHECK(check_ctx(c, n, fn));
+    CHECK(check_pot(pot, fn));
+    if (i_begin < 0 || i_count < 1 || i_begin > n - i_count)
+        return fail(DNB_ERR_ARG, "%s: rows [%lld, %lld + %lld) are not inside [0, %lld)", fn,
+                    (long long)i_begin, (long long)i_begin, (long long)i_count, (long long)n);
+    CHECK(check_dev(pos, "pos", fn));
+    CHECK(check_dev(mass, "mass", fn));
+    CHECK(check_dev(w, "w", fn));
+    CHECK(check_dev(gpos, "gpos", fn));
+    CHECK(check_dev(gmass, "gmass", fn, true));
+    if (gpos == pos || gpos == w || (gmass && gmass == mass))
+        return fail(DNB_ERR_ARG, "%s: outputs must not alias inputs", fn);
+    hipStream_t st = (hipStream_t)stream;
+    Pot p = to_pot(*pot);
+    const int nb = (int)cdiv(n, BS);
+    double* cpv[2] = {c->cpartv, c->cpartv + 4 * c->nbmax};
+    HIP_TRY(launch_mass_info(c, mass, n, st));
+    if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(pos, n, cpv[0], st, w));
+    HIP_TRY(launch_rev_stage(c, n, pos, mass, w, cpv[0], nb, cpv[1], c->wscale, st));
+    HIP_TRY(profiled(c, 1, st, [&] {
+        return launch_pair_vjp_rows(c, n, i_begin, i_count, gmass != nullptr, p.eps, st);
+    }));
+    HIP_TRY(launch_acc_vjp_rows(c, pos, w, n, i_begin, i_count, p, with_ext ? 1 : 0, gpos, gmass,
+                                st));
+    return DNB_OK;
+}
+
 int64_t dnb_tape_doubles(int64_t n, int64_t n_steps, int64_t ckpt_every) {
     if (n < 1 || n_steps < 0 || ckpt_every < 1) return -1;
     if (n_steps == 0) return 0;

@@ -320,6 +320,11 @@ hipError_t launch_rev_stage(dnb_ctx* c, int64_t n, const double* x, const double
                             const double* w, const double* cpart, int nb, double* cpart_out,
                             double* wscale_out, hipStream_t st);
 hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, int with_mass, double eps, hipStream_t st);
+hipError_t launch_pair_vjp_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, int with_mass,
+                                double eps, hipStream_t st);
+hipError_t launch_acc_vjp_rows(dnb_ctx* c, const double* x, const double* w, int64_t n,
+                               int64_t i0, int64_t ni, const Pot& pot, int with_ext,
+                               double* gpos, double* gmass, hipStream_t st);
 hipError_t launch_rev_kick(dnb_ctx* c, const RevArgs& a, hipStream_t st);
 hipError_t launch_reduce_accum(const double* accum, int64_t n, int nterms, double* out,
                                double* scratch, hipStream_t st);

@@ -347,6 +347,53 @@ hipError_t launch_rev_stage(dnb_ctx* c, int64_t n, const double* x, const double
     return hipGetLastError();
 }
 
+// Vector-Jacobian product of the accelerations for targets [i0, i0 + ni): with
+// the cotangent w [3][n] of all accelerations, gpos[r] = (J^T w)_k (pair part
+// from the partials of launch_pair_vjp_rows, plus H_ext(x_k) w_k) and
+// gmass[r] = d(w . a)/dm_k, for k = i0 + r.
+template <bool F32>
+__global__ __launch_bounds__(BS) void k_acc_vjp_rows(const double* __restrict__ x,
+                                                     const double* __restrict__ w, int64_t n,
+                                                     int64_t i0, int64_t ni, Pot pot,
+                                                     int with_ext, const void* __restrict__ part,
+                                                     int S, int64_t npad,
+                                                     const double* __restrict__ wscale,
+                                                     double* __restrict__ gpos,
+                                                     double* __restrict__ gmass) {
+    const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (r >= ni) return;
+    const int64_t k = i0 + r;
+    double g[3], gm;
+    vjp_sum<F32>(part, S, npad, r, pot.G, gmass != nullptr, g, gm);
+    if (F32) {
+        const double inv_s = 1.0 / wscale[0];
+        g[0] *= inv_s; g[1] *= inv_s; g[2] *= inv_s;
+        gm *= inv_s;
+    }
+    if (with_ext) {
+        double hx, hy, hz;
+        ext_hvp(pot, x[k], x[n + k], x[2 * n + k], w[k], w[n + k], w[2 * n + k], hx, hy, hz);
+        g[0] += hx; g[1] += hy; g[2] += hz;
+    }
+    gpos[r] = g[0]; gpos[ni + r] = g[1]; gpos[2 * ni + r] = g[2];
+    if (gmass) gmass[r] = -gm;
+}
+
+hipError_t launch_acc_vjp_rows(dnb_ctx* c, const double* x, const double* w, int64_t n,
+                               int64_t i0, int64_t ni, const Pot& pot, int with_ext,
+                               double* gpos, double* gmass, hipStream_t st) {
+    const Slicing sl = rows_slicing(c, ni, n);
+    if (c->prec == DNB_FP32C)
+        hipLaunchKernelGGL(k_acc_vjp_rows<true>, dim3(sl.nblk), dim3(BS), 0, st, x, w, n, i0, ni,
+                           pot, with_ext, (const void*)c->partv, sl.S, sl.npad,
+                           (const double*)c->wscale, gpos, gmass);
+    else
+        hipLaunchKernelGGL(k_acc_vjp_rows<false>, dim3(sl.nblk), dim3(BS), 0, st, x, w, n, i0,
+                           ni, pot, with_ext, (const void*)c->partv, sl.S, sl.npad,
+                           (const double*)c->wscale, gpos, gmass);
+    return hipGetLastError();
+}
+
 hipError_t launch_rev_kick(dnb_ctx* c, const RevArgs& a, hipStream_t st) {
     Slicing sl = vjp_slicing(c, a.n);
     dim3 grid(onblocks(a.n));

@@ -124,10 +124,11 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f64(const double4* __restrict__
 // The slice sum is vjp_f32c_slice (pair_common.h).
 template <bool EPS0, bool MASS>
 __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__ jsv, int n,
-                                                      int nj, int jslice, float eps2,
-                                                      float* __restrict__ part, int64_t npad,
+                                                      int i0, int iend, int nj, int jslice,
+                                                      float eps2, float* __restrict__ part,
+                                                      int64_t npad,
                                                       const float* __restrict__ muni) {
-    const int i = blockIdx.x * BS + threadIdx.x;
+    const int i = i0 + blockIdx.x * BS + threadIdx.x;
     const int j0 = blockIdx.y * jslice;
     const int j1 = min(nj, j0 + jslice);
     const int ii = min(i, n - 1);
@@ -143,8 +144,8 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__
     } else {
         vjp_f32c_slice<EPS0, MASS, false>(jsv, i, j0, j1, eps2, me, mw, h, l);
     }
-    if (i < n) {
-        float* p = part + (int64_t)blockIdx.y * 8 * npad + i;
+    if (i < iend) {
+        float* p = part + (int64_t)blockIdx.y * 8 * npad + (i - i0);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             p[c * npad] = h[c];
@@ -162,10 +163,11 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__
 // part: [S][4][npad] doubles: JTw(3), gm.
 template <bool EPS0, bool MASS>
 __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__ jsv, int n,
-                                                     int nj, int jslice, double eps2,
-                                                     double* __restrict__ part, int64_t npad) {
+                                                     int i0, int iend, int nj, int jslice,
+                                                     double eps2, double* __restrict__ part,
+                                                     int64_t npad) {
     constexpr int PB = 2;
-    const int i = blockIdx.x * BS + threadIdx.x;
+    const int i = i0 + blockIdx.x * BS + threadIdx.x;
     const int j0 = blockIdx.y * jslice;
     const int j1 = min(nj, j0 + jslice);
     const int ii = min(i, n - 1);
@@ -209,8 +211,8 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__
             for (int u = 0; u < PB; ++u) { pa[u] = pb[u]; wa[u] = wb[u]; }
         }
     }
-    if (i < n) {
-        double* p = part + (int64_t)blockIdx.y * 4 * npad + i;
+    if (i < iend) {
+        double* p = part + (int64_t)blockIdx.y * 4 * npad + (i - i0);
 #pragma unroll
         for (int c = 0; c < 3; ++c) p[c * npad] = acc[c];
         if (MASS) p[3 * npad] = acc[3];
@@ -257,31 +259,42 @@ hipError_t launch_pair_fwd_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, d
 }
 
 template <bool EPS0, bool MASS>
-static void vjp_dispatch(dnb_ctx* c, const Slicing& sl, int64_t n, int nj, double eps2,
-                         hipStream_t st) {
+static void vjp_dispatch(dnb_ctx* c, const Slicing& sl, int64_t n, int i0, int iend, int nj,
+                         double eps2, hipStream_t st) {
     dim3 grid(sl.nblk, sl.S);
     if (c->prec == DNB_FP32C)
         hipLaunchKernelGGL((k_pair_vjp_f32c<EPS0, MASS>), grid, dim3(BS), 0, st,
-                           (const float4*)c->jsv, (int)n, nj, sl.jslice, (float)eps2,
+                           (const float4*)c->jsv, (int)n, i0, iend, nj, sl.jslice, (float)eps2,
                            (float*)c->partv, sl.npad, c->muni);
     else
         hipLaunchKernelGGL((k_pair_vjp_f64<EPS0, MASS>), grid, dim3(BS), 0, st,
-                           (const double4*)c->jsv, (int)n, nj, sl.jslice, eps2,
+                           (const double4*)c->jsv, (int)n, i0, iend, nj, sl.jslice, eps2,
                            (double*)c->partv, sl.npad);
 }
 
-hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, int with_mass, double eps, hipStream_t st) {
-    const Slicing sl = vjp_slicing(c, n);
+static hipError_t launch_pair_vjp_sliced(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni,
+                                         const Slicing& sl, int with_mass, double eps,
+                                         hipStream_t st) {
     const int nj = (int)pad_sources(n);
+    const int a = (int)i0, e = (int)(i0 + ni);
     const double eps2 = eps * eps;
     if (eps == 0.0) {
-        if (with_mass) vjp_dispatch<true, true>(c, sl, n, nj, eps2, st);
-        else vjp_dispatch<true, false>(c, sl, n, nj, eps2, st);
+        if (with_mass) vjp_dispatch<true, true>(c, sl, n, a, e, nj, eps2, st);
+        else vjp_dispatch<true, false>(c, sl, n, a, e, nj, eps2, st);
     } else {
-        if (with_mass) vjp_dispatch<false, true>(c, sl, n, nj, eps2, st);
-        else vjp_dispatch<false, false>(c, sl, n, nj, eps2, st);
+        if (with_mass) vjp_dispatch<false, true>(c, sl, n, a, e, nj, eps2, st);
+        else vjp_dispatch<false, false>(c, sl, n, a, e, nj, eps2, st);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, int with_mass, double eps, hipStream_t st) {
+    return launch_pair_vjp_sliced(c, n, 0, n, vjp_slicing(c, n), with_mass, eps, st);
+}
+
+hipError_t launch_pair_vjp_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, int with_mass,
+                                double eps, hipStream_t st) {
+    return launch_pair_vjp_sliced(c, n, i0, ni, rows_slicing(c, ni, n), with_mass, eps, st);
 }
 
 }  // namespace dnb

@@ -119,6 +119,21 @@ class Context:
             int(i_begin), int(i_count), _lib.ptr(acc), _lib.stream_handle()))
         return acc
 
+    def accelerations_vjp(self, pos, mass, pot, w, with_ext=True, i_begin=0, i_count=None,
+                          with_mass=True):
+        """(gpos (3, i_count), gmass (i_count,) or None): the derivatives of
+        sum_j w_j . a_j with respect to the positions and masses of targets
+        i_begin .. i_begin + i_count - 1 (all n by default)."""
+        n = mass.shape[0]
+        _vec(pos, n, "pos"); _arr(mass, (n,), "mass"); _vec(w, n, "w")
+        ni = n - int(i_begin) if i_count is None else int(i_count)
+        g = self._new(3, ni)
+        gm = self._new(ni) if with_mass else None
+        _lib.check(_lib.lib().dnb_accelerations_vjp(
+            self._h, n, _lib.ptr(pos), _lib.ptr(mass), pot.c(), int(bool(with_ext)),
+            _lib.ptr(w), int(i_begin), ni, _lib.ptr(g), _lib.ptr(gm), _lib.stream_handle()))
+        return g, gm
+
     def step(self, pos, vel, mass, pot, dt):
         n = mass.shape[0]
         _vec(pos, n, "pos"); _vec(vel, n, "vel"); _arr(mass, (n,), "mass")

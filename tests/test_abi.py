@@ -85,6 +85,8 @@ def test_arguments_rejected_before_any_device_work(lib):
     assert lib.dnb_mmd(None, 1, None, 1, None, 0.2, None, None, None) == _lib.DNB_ERR_ARG
     assert lib.dnb_accelerations_rows(None, 10, None, None, ctypes.byref(pot), 1, 0, 5, None,
                                       None) == _lib.DNB_ERR_ARG
+    assert lib.dnb_accelerations_vjp(None, 10, None, None, ctypes.byref(pot), 1, None, 0, 5,
+                                     None, None, None) == _lib.DNB_ERR_ARG
     table = (ctypes.c_double * 8)(4.3e-6, 1e-3, 1e12, 16.0, 6.5e10, 3.0, 0.28, 0.01)
     assert lib.dnb_simulate_batch(None, 1, 10, None, None, None, table, 5, None,
                                   None) == _lib.DNB_ERR_ARG

@@ -272,3 +272,27 @@ def test_shard_shaped_rows_n65536():
         full = to_host(c.accelerations(to_dev(x), to_dev(m), pot))[i0:i0 + ni]
         assert rel_rows(to_host(got), full).max() <= (2e-7 if prec == "fp32c" else 1e-14)
         c.close()
+
+
+def test_shard_shaped_vjp_rows_n65536():
+    """The adjoint block of one device (8192 targets of N = 65536 against all
+    sources): dnb_accelerations_vjp rows against the oracle's J^T w + H_ext w on
+    256 sampled rows (FP32C <= 1e-5 of the summed term magnitudes, FP64 <= 1e-11)."""
+    from oracle import adjoint as oadj
+    from paper_2511_22468_amd import engine
+    n, i0, ni = 65536, 5 * 8192, 8192
+    x, v, m = plummer_state(n, 4, 1e5)
+    op = OPot(eps=5e-4)
+    pot = gpot(engine, op)
+    w = random_directions(n, 46)
+    rows = i0 + sample_rows(ni, 256, 47)
+    ref = oadj.pair_vjp(x, m, G, op.eps, w, rows=rows) + of.ext_hvp(x[rows], w[rows], op)
+    scale = _vjp_scale(x, m, op.eps, w, rows)
+    for prec, tol in (("fp32c", 1e-5), ("fp64", 1e-11)):
+        c = engine.Context(n, prec)
+        say(f"[cfg] N=65536 VJP rows [{i0}, {i0 + ni}) {prec}")
+        g, _ = c.accelerations_vjp(to_dev(x), to_dev(m), pot, to_dev(w), i_begin=i0, i_count=ni,
+                                   with_mass=False)
+        err = np.sqrt(((to_host(g)[rows - i0] - ref) ** 2).sum(1)) / scale
+        assert err.max() <= tol, err.max()
+        c.close()

@@ -104,6 +104,56 @@ def test_accelerations_rows_equal_the_full_call(dnb, prec, eps):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("eps", [1e-3, 0.0])
+@pytest.mark.parametrize("masses", ["equal", "unequal"])
+def test_accelerations_vjp_matches_oracle(dnb, prec, eps, masses):
+    """dnb_accelerations_vjp against the oracle's (J^T w, dL/dm) of the same
+    accelerations, for all rows and for row blocks (bitwise equal to the full call
+    when the source slicing matches: n = 300 and n = 2048 either way)."""
+    pk, engine, ctx = dnb
+    say(f"[accel-vjp] prec={prec} eps={eps} masses={masses}")
+    for n in (300, 2048):
+        rng = np.random.default_rng(81 + n)
+        x = W_X + rng.normal(scale=0.02, size=(n, 3))
+        m = np.full(n, 3.0) if masses == "equal" else rng.uniform(1.0, 5.0, n)
+        w = rng.normal(size=(n, 3))
+        op = OPot(eps=eps)
+        pot = gpu_pot(engine, op)
+        c = ctx[prec]
+        g, gm = c.accelerations_vjp(to_dev(x), to_dev(m), pot, to_dev(w))
+        if n == 300:
+            gx_ref, gm_ref, _, _ = oadj.accel_vjp(x, m, op, w)
+            tol = 1e-12 if prec == "fp64" else 1e-5
+            assert rel_norm(to_host(g), gx_ref) <= tol
+            assert rel_norm(gm.cpu().numpy(), gm_ref) <= tol
+            # the pair part alone, per row against its own magnitude scale
+            gi, _ = c.accelerations_vjp(to_dev(x), to_dev(m), pot, to_dev(w), with_ext=False)
+            ref_i = oadj.pair_vjp(x, m, G, eps, w)
+            scale = np.abs(ref_i).max()
+            assert np.abs(to_host(gi) - ref_i).max() <= tol * 10 * scale
+        for i0, ni in [(0, n), (17, 200), (n - 1, 1), (256, 44)]:
+            gr, gmr = c.accelerations_vjp(to_dev(x), to_dev(m), pot, to_dev(w), i_begin=i0,
+                                          i_count=ni)
+            assert torch.equal(gr, g[:, i0:i0 + ni]) and torch.equal(gmr, gm[i0:i0 + ni]), (n, i0)
+        gn, none = c.accelerations_vjp(to_dev(x), to_dev(m), pot, to_dev(w), with_mass=False)
+        assert none is None and torch.equal(gn, g)
+
+
+def test_accelerations_autograd_matches_finite_differences(dnb):
+    """The Accelerations autograd Function (FP64 context) against central finite
+    differences of the accelerations themselves (torch.autograd.gradcheck)."""
+    from paper_2511_22468_amd import autograd as AG
+    pk, engine, ctx = dnb
+    rng = np.random.default_rng(91)
+    n = 12
+    x = to_dev(W_X + rng.normal(scale=0.02, size=(n, 3))).requires_grad_(True)
+    m = to_dev(rng.uniform(1.0, 5.0, n)).requires_grad_(True)
+    pot = gpu_pot(engine, OPot())
+    f = lambda xx, mm: AG.accelerations(ctx["fp64"], xx, mm, pot)
+    assert torch.autograd.gradcheck(f, (x, m), eps=1e-7, atol=1e-4, rtol=1e-4)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
 def test_zero_softening_masks_self_term(dnb, prec):
     pk, engine, ctx = dnb
     rng = np.random.default_rng(3)
