@@ -15,6 +15,7 @@ constexpr int TILE = 256;            // sources staged in LDS per tile
 constexpr int SUBTILE = 128;         // sources summed in plain FP32 before a TwoSum
 constexpr int TARGET_BLOCKS = 8192;  // pair-kernel blocks wanted per launch (32 per CU)
 constexpr int S_MAX = 64;            // maximum number of source slices
+constexpr int SLICE_GRAIN = 32;      // pair-kernel source slices are multiples of this
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -28,7 +29,7 @@ inline int64_t pad_sources(int64_t n) { return cdiv(n, SUBTILE) * SUBTILE; }
 // compute units with about `target` blocks.
 struct Slicing {
     int S;          // number of slices
-    int jslice;     // sources per slice (a multiple of TILE)
+    int jslice;     // sources per slice (a multiple of TILE, SLICE_GRAIN for the pair kernels)
     int nblk;       // target blocks
     int64_t npad;   // row stride of the partial buffers (n rounded up to tpb)
 };
@@ -43,6 +44,24 @@ inline Slicing slicing_for(int64_t n, int tpb, int target) {
     if (want > S_MAX) want = S_MAX;
     if (want < 1) want = 1;
     s.jslice = (int)(cdiv(cdiv(n, want), TILE) * TILE);
+    s.S = (int)cdiv(n, s.jslice);
+    return s;
+}
+
+// Source slicing of the pair kernels: ni targets (blocks of BS) against n
+// sources in slices of a multiple of SLICE_GRAIN sources (a slice shorter than a
+// sub-tile is summed as one short sub-tile), S <= smax.  A small system gets
+// short slices so that its launch still spreads over many compute units.
+inline Slicing pair_slicing(int64_t ni, int64_t n, int target, int smax) {
+    Slicing s;
+    s.nblk = (int)cdiv(ni, BS);
+    s.npad = (int64_t)s.nblk * BS;
+    int64_t want = target / s.nblk;
+    const int64_t max_by_grain = cdiv(n, SLICE_GRAIN);
+    if (want > max_by_grain) want = max_by_grain;
+    if (want > smax) want = smax;
+    if (want < 1) want = 1;
+    s.jslice = (int)(cdiv(cdiv(n, want), SLICE_GRAIN) * SLICE_GRAIN);
     s.S = (int)cdiv(n, s.jslice);
     return s;
 }
@@ -225,10 +244,10 @@ void set_error(const char* msg);
 // Geometry of the forward and VJP pair kernels for this context (FP64 uses one
 // target per lane).
 inline Slicing fwd_slicing(const dnb_ctx* c, int64_t n) {
-    return slicing_for(n, BS, c->target_blocks);
+    return pair_slicing(n, n, c->target_blocks, S_MAX);
 }
 inline Slicing vjp_slicing(const dnb_ctx* c, int64_t n) {
-    return slicing_for(n, BS, c->target_blocks);
+    return pair_slicing(n, n, c->target_blocks, S_MAX);
 }
 inline Slicing plain_slicing(const dnb_ctx* c, int64_t n) {
     return slicing_for(n, BS, c->target_blocks);
@@ -239,17 +258,7 @@ inline Slicing plain_slicing(const dnb_ctx* c, int64_t n) {
 // below target_blocks * BS (the partial buffer's bound).
 constexpr int S_MAX_ROWS = 256;
 inline Slicing rows_slicing(const dnb_ctx* c, int64_t ni, int64_t n) {
-    Slicing s;
-    s.nblk = (int)cdiv(ni, BS);
-    s.npad = (int64_t)s.nblk * BS;
-    int64_t want = c->target_blocks / s.nblk;
-    const int64_t max_by_tiles = cdiv(n, TILE);
-    if (want > max_by_tiles) want = max_by_tiles;
-    if (want > S_MAX_ROWS) want = S_MAX_ROWS;
-    if (want < 1) want = 1;
-    s.jslice = (int)(cdiv(cdiv(n, want), TILE) * TILE);
-    s.S = (int)cdiv(n, s.jslice);
-    return s;
+    return pair_slicing(ni, n, c->target_blocks, S_MAX_ROWS);
 }
 
 // Kernel launchers (defined in the .hip files).  All return hipError_t of the launch.

@@ -93,8 +93,9 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f64(const double4* __restrict__
 #pragma unroll
     for (int u = 0; u < PB; ++u) qa[u] = js[j0 + u];
     for (int jt = j0; jt < j1; jt += SUBTILE) {
-        for (int k = 0; k < SUBTILE; k += PB) {
-            const int nx = next_batch(jt, k, PB, j1);
+        const int kend = min(SUBTILE, j1 - jt);
+        for (int k = 0; k < kend; k += PB) {
+            const int nx = next_batch(jt, k, PB, kend, j1);
             double4 qb[PB];
 #pragma unroll
             for (int u = 0; u < PB; ++u) qb[u] = js[nx + u];
@@ -178,8 +179,9 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__
 #pragma unroll
     for (int u = 0; u < PB; ++u) { pa[u] = jsv[2 * (j0 + u)]; wa[u] = jsv[2 * (j0 + u) + 1]; }
     for (int jt = j0; jt < j1; jt += SUBTILE) {
-        for (int k = 0; k < SUBTILE; k += PB) {
-            const int nx = next_batch(jt, k, PB, j1);
+        const int kend = min(SUBTILE, j1 - jt);
+        for (int k = 0; k < kend; k += PB) {
+            const int nx = next_batch(jt, k, PB, kend, j1);
             double4 pb[PB], wb[PB];
 #pragma unroll
             for (int u = 0; u < PB; ++u) { pb[u] = jsv[2 * (nx + u)]; wb[u] = jsv[2 * (nx + u) + 1]; }

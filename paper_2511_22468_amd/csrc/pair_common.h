@@ -15,10 +15,11 @@ __device__ __forceinline__ void two_sum_acc(float& hi, float& lo, float x) {
     lo += e;
 }
 
-// Start index of the batch loaded ahead of batch k of a sub-tile starting at jt;
-// on the last batch of the slice it re-reads the slice's last batch (in bounds).
-__device__ __forceinline__ int next_batch(int jt, int k, int PB, int j1) {
-    return (k + PB < SUBTILE) ? jt + k + PB : min(jt + SUBTILE, j1 - PB);
+// Start index of the batch loaded ahead of batch k of a sub-tile that starts at
+// jt and holds kend sources (SUBTILE, or fewer at the end of a short slice); on
+// the last batch of the slice it re-reads the slice's last batch (in bounds).
+__device__ __forceinline__ int next_batch(int jt, int k, int PB, int kend, int j1) {
+    return (k + PB < kend) ? jt + k + PB : min(jt + SUBTILE, j1 - PB);
 }
 
 // Sum over the slice [j0, j1) of the staged sources js for target i (position
@@ -37,8 +38,9 @@ __device__ __forceinline__ void fwd_f32c_slice(const float4* __restrict__ js, in
     for (int u = 0; u < PB; ++u) qa[u] = js[j0 + u];
     for (int jt = j0; jt < j1; jt += SUBTILE) {
         float ax = 0.f, ay = 0.f, az = 0.f;
-        for (int k = 0; k < SUBTILE; k += PB) {
-            const int nx = next_batch(jt, k, PB, j1);
+        const int kend = min(SUBTILE, j1 - jt);
+        for (int k = 0; k < kend; k += PB) {
+            const int nx = next_batch(jt, k, PB, kend, j1);
             float4 qb[PB];
 #pragma unroll
             for (int u = 0; u < PB; ++u) qb[u] = js[nx + u];
@@ -85,8 +87,9 @@ __device__ __forceinline__ void vjp_f32c_slice(const float4* __restrict__ jsv, i
     for (int u = 0; u < PB; ++u) { pa[u] = jsv[2 * (j0 + u)]; wa[u] = jsv[2 * (j0 + u) + 1]; }
     for (int jt = j0; jt < j1; jt += SUBTILE) {
         float A[3] = {0.f, 0.f, 0.f}, B[3] = {0.f, 0.f, 0.f}, gm = 0.f;
-        for (int k = 0; k < SUBTILE; k += PB) {
-            const int nx = next_batch(jt, k, PB, j1);
+        const int kend = min(SUBTILE, j1 - jt);
+        for (int k = 0; k < kend; k += PB) {
+            const int nx = next_batch(jt, k, PB, kend, j1);
             float4 pb[PB], wb[PB];
 #pragma unroll
             for (int u = 0; u < PB; ++u) { pb[u] = jsv[2 * (nx + u)]; wb[u] = jsv[2 * (nx + u) + 1]; }

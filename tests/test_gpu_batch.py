@@ -5,8 +5,8 @@ grid search built on them) against the oracle and against single-system runs
 Every member of an ensemble is an independent system with its own potential,
 softening and step size.  Members are checked against the FP64 oracle at the
 FP32C tolerance of the single-system tests and, where the source slicing of the
-ensemble equals that of a lone system (n = 300: two 256-target tiles, two
-slices in both), bitwise against dnb_simulate in FP32C.
+ensemble equals that of a lone system (n = 300: ten 32-source slices in both
+for up to 64 members), bitwise against dnb_simulate in FP32C.
 """
 import numpy as np
 import pytest

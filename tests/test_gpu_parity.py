@@ -77,7 +77,7 @@ def test_accelerations_match_oracle(dnb, n, prec):
 @pytest.mark.parametrize("eps", [1e-3, 0.0])
 def test_accelerations_rows_equal_the_full_call(dnb, prec, eps):
     """Row blocks (one device's share of a target-split system): with the same
-    source slicing (n = 2048: 8 slices either way) every row equals the full
+    source slicing (n = 2048: 64 slices either way) every row equals the full
     dnb_accelerations bit for bit, for ragged blocks, a single row and the last
     rows; bad ranges are refused."""
     from paper_2511_22468_amd._lib import DnbError
