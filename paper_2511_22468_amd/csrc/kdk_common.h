@@ -119,6 +119,7 @@ __device__ inline void pair_sum(const void* part, int S, int64_t npad, int64_t i
         }
     } else {
         const double* p = (const double*)part;
+#pragma unroll 4
         for (int s = 0; s < S; ++s) {
             const double* q = p + (int64_t)s * 3 * npad + i;
             ax += q[0]; ay += q[npad]; az += q[2 * npad];
@@ -128,7 +129,11 @@ __device__ inline void pair_sum(const void* part, int S, int64_t npad, int64_t i
 }
 
 // Slice sums of the VJP kernel for particle i: J^T w and the raw mass term
-// sum_j (d.w_j) s^-3/2, both times G.
+// sum_j (d.w_j) s^-3/2, both times G, in slice order.  The slice loops here
+// (and the FP64 one of pair_sum) are unrolled so that the loads of several
+// slices are in flight together: a small system has many slices and few waves
+// to hide their latency (at n = 1000 this took the reverse kick from 19 to 14
+// us per step; unrolling the FP32C pair_sum instead slowed its kick kernel).
 template <bool F32>
 __device__ inline void vjp_sum(const void* part, int S, int64_t npad, int64_t i, double G,
                                bool with_mass, double (&g)[3], double& gm) {
@@ -136,6 +141,7 @@ __device__ inline void vjp_sum(const void* part, int S, int64_t npad, int64_t i,
     gm = 0.0;
     if (F32) {
         const float* p = (const float*)part;
+#pragma unroll 4
         for (int s = 0; s < S; ++s) {
             const float* q = p + (int64_t)s * 8 * npad + i;
             for (int c = 0; c < 3; ++c) { g[c] += (double)q[c * npad]; g[c] += (double)q[(3 + c) * npad]; }
@@ -143,6 +149,7 @@ __device__ inline void vjp_sum(const void* part, int S, int64_t npad, int64_t i,
         }
     } else {
         const double* p = (const double*)part;
+#pragma unroll 4
         for (int s = 0; s < S; ++s) {
             const double* q = p + (int64_t)s * 4 * npad + i;
             for (int c = 0; c < 3; ++c) g[c] += q[c * npad];
