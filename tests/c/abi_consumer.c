@@ -1,7 +1,8 @@
 /* A plain C program that uses libdnb through the headers alone (no torch, no
- * C++): it checks the two-body accelerations against Newton's closed form, runs
- * a short integration with its gradient, and checks that a bad call is refused
- * with a message.  Exit status 0 on success. */
+ * C++): it checks the two-body accelerations, a row block of them and their
+ * vector-Jacobian product against Newton's closed forms, runs a short
+ * integration with its gradient, and checks that a bad call is refused with a
+ * message.  Exit status 0 on success. */
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -45,6 +46,29 @@ int main(void) {
     const double a = G * m / (d * d);
     if (fabs(acc[0] - a) > 1e-14 * a || fabs(acc[1] + a) > 1e-14 * a || acc[2] != 0.0)
         FAIL("two-body acceleration %.17g %.17g, expected +-%.17g", acc[0], acc[1], a);
+
+    /* one row of the same accelerations, and their vector-Jacobian product with
+     * w = unit x on particle 0: d(a_0x)/dx_0 = 2 G m / d^3 = -d(a_0x)/dx_1 and
+     * d(a_0x)/dm_1 = G / d^2 (a_0 does not depend on m_0) */
+    double row[3], gx[6], gm[2], w0[6] = {1, 0, 0, 0, 0, 0};
+    double *drow, *dw0, *dgx, *dgm;
+    if (hipMalloc((void**)&drow, sizeof row) || hipMalloc((void**)&dw0, sizeof w0) ||
+        hipMalloc((void**)&dgx, sizeof gx) || hipMalloc((void**)&dgm, sizeof gm))
+        FAIL("hipMalloc failed");
+    hipMemcpy(dw0, w0, sizeof w0, hipMemcpyHostToDevice);
+    if (dnb_accelerations_rows(ctx, n, dpos, dmass, &pot, 1, 1, 1, drow, NULL) != DNB_OK)
+        FAIL("accelerations_rows: %s", dnb_last_error());
+    hipMemcpy(row, drow, sizeof row, hipMemcpyDeviceToHost);
+    if (row[0] != acc[1] || row[1] != acc[3] || row[2] != acc[5])
+        FAIL("row 1: %.17g, full call %.17g", row[0], acc[1]);
+    if (dnb_accelerations_vjp(ctx, n, dpos, dmass, &pot, 1, dw0, 0, n, dgx, dgm, NULL) != DNB_OK)
+        FAIL("accelerations_vjp: %s", dnb_last_error());
+    hipMemcpy(gx, dgx, sizeof gx, hipMemcpyDeviceToHost);
+    hipMemcpy(gm, dgm, sizeof gm, hipMemcpyDeviceToHost);
+    const double h = 2.0 * G * m / (d * d * d);
+    if (fabs(gx[0] - h) > 1e-13 * h || fabs(gx[1] + h) > 1e-13 * h || gm[0] != 0.0 ||
+        fabs(gm[1] - G / (d * d)) > 1e-13 * G / (d * d))
+        FAIL("accelerations vjp %.17g %.17g %.17g %.17g", gx[0], gx[1], gm[0], gm[1]);
 
     if (dnb_simulate(ctx, n, dpos, dvel, dmass, &pot, 0.01, T, K, tape, NULL) != DNB_OK)
         FAIL("simulate: %s", dnb_last_error());
