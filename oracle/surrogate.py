@@ -3,7 +3,7 @@
 The paper names coupling the N-body code with a neural network as future work
 (Sec. 3); the surrogate here maps the four inference parameters of Sec. 2.2.1
 to a smoothed density image of the final stream, and the plain N-body gradient
-fit remains the judge of it.  Nothing in this module is given by the paper;
+fit remains the test of it.  Nothing in this module is given by the paper;
 the readings taken are:
 
 Grid.  A fixed orbit-aligned frame built from the present-day phase-space

@@ -1,7 +1,8 @@
 """GPU-vs-oracle parity of every C-ABI entry point (run on an MI355X).
 
-Tolerances: accelerations <= 1e-5 relative per particle in FP32C (the
-spec bound) and <= 1e-12 in FP64; short-horizon positions and gradients
+Tolerances: accelerations <= 1e-5 relative per particle in FP32C (the bound
+stated for the compensated FP32 pair sum) and <= 1e-12 in FP64; short-horizon
+positions and gradients
 as stated per test.  Sizes span several 256-particle tiles, several source
 slices and a ragged tail.
 """
