@@ -462,3 +462,28 @@ def test_batched_adjoint_of_single_particle_members(eng):
         assert rel(gv0[b].cpu().numpy().T, ref["v0"]) <= 1e-10, b
         got = gpar[b].cpu().numpy()
         np.testing.assert_allclose(got[:3], [ref["m_nfw"], ref["m_mn"], ref["dt"]], rtol=1e-9)
+
+
+def test_batched_pipeline_gradient_with_a_centre_per_row(eng):
+    """Rows with their own present-day centre (a bootstrap realisation's centre
+    of mass, Fig. 2 step 1) equal StreamModel built on that centre."""
+    pk, engine, ctx = eng
+    from paper_2511_22468_amd.pipeline import StreamModel, batch_loss_and_grad
+    n, T = 300, 20
+    say(f"[batch-grad-centres] n={n} T={T}")
+    xi, zeta = plummer_unit(n, 33)
+    Y = W_X + 0.05 * np.random.default_rng(34).normal(size=(100, 3))
+    op = OPot()
+    theta = np.array([pk.myr(20.0), 3e4, 1.1e12, 6.0e10])
+    w_rows = np.array([[12.0, 0.0, 0.0, 0.0, -180.0, 60.0], [12.05, 0.02, -0.01, 1.0, -179.0, 60.5]])
+    t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device="cuda")
+    losses, grads = batch_loss_and_grad(ctx, np.repeat(theta[None], 2, 0), t3(xi), t3(zeta), t3(Y),
+                                        T, gpu_pot(engine, op), w_now=w_rows)
+    assert abs(losses[0] - losses[1]) > 1e-6 * abs(losses[0])
+    for b in range(2):
+        model = StreamModel(ctx, t3(xi), t3(zeta), t3(Y), T, pot=gpu_pot(engine, op),
+                            ckpt_every=1, w_now=tuple(w_rows[b]))
+        L, g = model.loss_and_grad(torch.tensor(theta, device="cuda"))
+        assert abs(losses[b] / L.item() - 1) <= 1e-12, b
+        sg, sr = grads[b] * theta, g.cpu().numpy() * theta
+        assert np.abs(sg - sr).max() <= 1e-6 * np.abs(sr).max(), (b, sg, sr)

@@ -369,3 +369,28 @@ def test_autograd_mass_and_initial_condition_gradients(dnb):
     assert rel_norm(pm.grad.cpu().numpy(), ref["mass"]) <= 1e-10
     for t, k in ((mn, "m_nfw"), (md, "m_mn"), (tdt, "dt")):
         assert abs(t.grad.item() / ref[k] - 1) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_runs_are_deterministic(dnb, prec):
+    """No atomics and fixed reduction orders: a gradient computed twice (forward
+    with tape, MMD, reverse sweep) is the same bit for bit, and so are two
+    accelerations calls separated by other work on the context."""
+    pk, engine, ctx = dnb
+    say(f"[determinism] n=1300 prec={prec}")
+    x, v, m = plummer_state(1300, 61)
+    op = OPot()
+    pot = gpu_pot(engine, op)
+    c = ctx[prec]
+    tgt = to_dev(W_X + 0.05 * np.random.default_rng(62).normal(size=(200, 3)))
+    outs = []
+    for _ in range(2):
+        px, pv, pm = to_dev(x), to_dev(v), to_dev(m)
+        a0 = c.accelerations(px, pm, pot)
+        tape = c.simulate(px, pv, pm, pot, pk.myr(0.5), 30, ckpt_every=4)
+        L, gpos = c.mmd(px, tgt, 0.2)
+        g0, gv0, gm, gp = c.simulate_vjp(pm, pot, pk.myr(0.5), 30, 4, tape, px, gpos,
+                                         with_mass=True)
+        outs.append((a0, px, L, g0, gv0, gm, gp))
+    for u, w in zip(*outs):
+        assert torch.equal(u, w)
