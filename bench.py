@@ -518,6 +518,10 @@ def main():
                     help="bootstrap refinement of the stream inference: 10 descent steps of "
                          "the pipeline gradient for 64 and 256 resampled streams at once vs one "
                          "at a time (N = 1000, 1000 steps), one JSON line")
+    ap.add_argument("--infer", action="store_true",
+                    help="the whole inference pipeline: grid search over 10^4 points for 64 "
+                         "bootstrap realisations, then their batched refinement (N = 1000, "
+                         "1000 steps), one JSON line")
     ap.add_argument("--configs", action="store_true",
                     help="end-to-end time of the N = 1024, 16384 and 8192 (gradient) workloads, "
                          "one JSON line each")
@@ -529,7 +533,7 @@ def main():
         print(json.dumps(cpu_sweep()), flush=True)
         return
     if (args.sweep or args.ensemble or args.orbit_fit or args.configs or args.grid
-            or args.bootstrap) and args.gpus != 1:
+            or args.bootstrap or args.infer) and args.gpus != 1:
         print("bench.py measures one GPU only (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.sweep:
@@ -546,6 +550,10 @@ def main():
         return
     if args.bootstrap:
         print(json.dumps(bootstrap()), flush=True)
+        return
+    if args.infer:
+        from paper_2511_22468_amd import infer
+        print(json.dumps(infer.main()), flush=True)
         return
     if args.configs:
         for row in configs():

@@ -39,3 +39,12 @@ def test_bootstrap_row_maps_match_the_single_row_maps():
     for r in range(6):
         np.testing.assert_allclose(th[r], fit.theta_internal(u[r][None]), rtol=1e-15)
         np.testing.assert_allclose(J[r], fit.dtheta_du(u[r][None]), rtol=1e-15)
+
+
+def test_inference_grid_covers_the_prior_box():
+    from paper_2511_22468_amd.infer import grid_points
+    g = grid_points(4)
+    assert g.shape == (256, 4) and len({tuple(r) for r in g}) == 256
+    assert g.min() == -1.0 and g.max() == 1.0
+    for k in range(4):
+        np.testing.assert_allclose(np.unique(g[:, k]), np.linspace(-1, 1, 4))

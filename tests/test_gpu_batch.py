@@ -487,3 +487,36 @@ def test_batched_pipeline_gradient_with_a_centre_per_row(eng):
         assert abs(losses[b] / L.item() - 1) <= 1e-12, b
         sg, sr = grads[b] * theta, g.cpu().numpy() * theta
         assert np.abs(sg - sr).max() <= 1e-6 * np.abs(sr).max(), (b, sg, sr)
+
+
+def test_inference_pipeline_end_to_end(eng):
+    """infer.run: the grid losses of every realisation equal grid_search against
+    that realisation's target, each refinement starts at its realisation's best
+    grid point and ends no worse than it."""
+    pk, engine, ctx = eng
+    from paper_2511_22468_amd import bootstrap as BS, infer
+    from paper_2511_22468_amd.pipeline import grid_search
+    n, T, B, per_axis, iters = 300, 30, 3, 3, 2
+    say(f"[infer] n={n} T={T} B={B} grid={per_axis}^4")
+    xi, zeta = plummer_unit(n, 91)
+    xt, zt = plummer_unit(n, 92)
+    t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device="cuda")
+    pot = engine.Potential()
+    noise = torch.tensor(np.random.default_rng(93).normal(size=(B, 3, n)), device="cuda")
+    u_true = np.array([-0.9, 0.1, 0.0, 0.2])
+    res = infer.run(ctx, u_true, t3(xi), t3(zeta), t3(xt), t3(zt), T, noise, 0.005, per_axis,
+                    iters, 0.05, pot)
+    L = res["grid_losses"]
+    assert L.shape == (per_axis ** 4, B)
+    th = BS.theta_rows(infer.grid_points(per_axis))
+    target = infer.make_target(ctx, t3(xt), t3(zt), torch.tensor(BS.theta_rows(u_true[None])[0],
+                                                                  device="cuda"), T, pot=pot)
+    targets = BS.resample(target, 0.005, noise)
+    for b in range(B):
+        ref = grid_search(ctx, th, t3(xi), t3(zeta), targets[b].contiguous(), T, pot)
+        assert np.array_equal(L[:, b], ref), b
+        k = int(np.argmin(L[:, b]))
+        np.testing.assert_array_equal(res["u_grid_best"][b], infer.grid_points(per_axis)[k])
+        assert res["L_fit"][b] <= L[k, b] * (1 + 1e-6), b
+    s = infer.summary(res, u_true)
+    assert len(s["fit_mean"]) == 4 and np.all(np.isfinite(s["fit_std"]))
