@@ -134,9 +134,8 @@ __global__ __launch_bounds__(BS) void k_batch_pair_fwd(const float4* __restrict_
         fwd_f32c_slice<false, false>(jb, i, j0, j1, eps2, me, h, l);
     }
     if (i < g.n) {
-        float* p = part + ((int64_t)b * g.S + blockIdx.y) * 6 * g.npad + i;
-        p[0] = h[0]; p[g.npad] = h[1]; p[2 * g.npad] = h[2];
-        p[3 * g.npad] = l[0]; p[4 * g.npad] = l[1]; p[5 * g.npad] = l[2];
+        float2* p = (float2*)part + ((int64_t)b * g.S + blockIdx.y) * 3 * g.npad + i;
+        for (int c = 0; c < 3; ++c) p[c * g.npad] = make_float2(h[c], l[c]);
     }
 }
 
@@ -169,14 +168,8 @@ __global__ __launch_bounds__(BS) void k_batch_kdk(double* __restrict__ pos,
     const int k = ok ? i : 0;
     double cx = 0.0, cy = 0.0, cz = 0.0;
     if (MODE != 2) member_centre(cp_in + (int64_t)b * g.nb * 4, g.nb, n, sh, cx, cy, cz);
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    for (int s = 0; s < g.S; ++s) {
-        const float* q = part + ((int64_t)b * g.S + s) * 6 * g.npad + k;
-        ax += (double)q[0]; ax += (double)q[3 * g.npad];
-        ay += (double)q[g.npad]; ay += (double)q[4 * g.npad];
-        az += (double)q[2 * g.npad]; az += (double)q[5 * g.npad];
-    }
-    ax *= pot.G; ay *= pot.G; az *= pot.G;
+    double ax, ay, az;
+    pair_sum<true>(part + (int64_t)b * g.S * 6 * g.npad, g.S, g.npad, k, pot.G, ax, ay, az);
     if (aint_out && ok) {
         double* t = aint_out + (int64_t)b * 3 * n;
         t[i] = ax; t[n + i] = ay; t[2 * n + i] = az;
@@ -527,11 +520,8 @@ __global__ __launch_bounds__(BS) void k_batch_pair_vjp(const float4* __restrict_
         vjp_f32c_slice<false, false, false>(jb, i, j0, j1, eps2, me, mw, h, l);
     }
     if (i < g.n) {
-        float* p = part + (b * g.S + blockIdx.y) * 8 * g.npad + i;
-        for (int c = 0; c < 3; ++c) {
-            p[c * g.npad] = h[c];
-            p[(3 + c) * g.npad] = l[c];
-        }
+        float2* p = (float2*)part + (b * g.S + blockIdx.y) * 4 * g.npad + i;
+        for (int c = 0; c < 3; ++c) p[c * g.npad] = make_float2(h[c], l[c]);
     }
 }
 

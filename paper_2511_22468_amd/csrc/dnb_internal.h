@@ -219,13 +219,13 @@ struct dnb_ctx {
     // forward path
     void* js;                // staged sources: FP32C float4 (x, y, z relative to a centre; m),
                              // FP64 double4 (x, y, z, m); padded to pad_sources(n)
-    void* part;              // slice partials: FP32C float [S][6][npad], FP64 double [S][3][npad]
+    void* part;              // slice partials: FP32C float2 (hi, lo) [S][3][npad], FP64 double [S][3][npad]
     double* cpart;           // [2][nbmax][4] block sums of positions (centre), double buffered
     double* vh;              // [3][max_n] half-step velocities of the running integration
     // reverse path
     void* jsv;               // staged VJP sources, interleaved per particle:
                              // [2 j] = (x, y, z, m), [2 j + 1] = (w, 0); float4 or double4
-    void* partv;             // VJP partials: FP32C float [S][8][npad], FP64 double [S][4][npad]
+    void* partv;             // VJP partials: FP32C float2 (hi, lo) [S][4][npad], FP64 double [S][4][npad]
     double* cpartv;          // [2][nbmax][4]
     double* wscale;          // [2] cotangent staging scales of the reverse sweep
     float* muni;             // [DNB_BATCH_MAX][2] (flag, m): all masses of the system (or of

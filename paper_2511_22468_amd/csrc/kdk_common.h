@@ -104,18 +104,20 @@ __device__ inline void put_source_w(void* jsv, int64_t i, bool real, double x, d
     }
 }
 
-// Sum of the slice partials of the forward pair kernel for particle i (times G).
+// Sum of the slice partials of the forward pair kernel for particle i (times G):
+// FP32C (hi, lo) float2 [S][3][npad], FP64 double [S][3][npad], in slice order.
 template <bool F32>
 __device__ inline void pair_sum(const void* part, int S, int64_t npad, int64_t i, double G,
                                 double& ax, double& ay, double& az) {
     ax = ay = az = 0.0;
     if (F32) {
-        const float* p = (const float*)part;
+        const float2* p = (const float2*)part;
         for (int s = 0; s < S; ++s) {
-            const float* q = p + (int64_t)s * 6 * npad + i;
-            ax += (double)q[0]; ax += (double)q[3 * npad];
-            ay += (double)q[npad]; ay += (double)q[4 * npad];
-            az += (double)q[2 * npad]; az += (double)q[5 * npad];
+            const float2* q = p + (int64_t)s * 3 * npad + i;
+            const float2 vx = q[0], vy = q[npad], vz = q[2 * npad];
+            ax += (double)vx.x; ax += (double)vx.y;
+            ay += (double)vy.x; ay += (double)vy.y;
+            az += (double)vz.x; az += (double)vz.y;
         }
     } else {
         const double* p = (const double*)part;
@@ -140,12 +142,18 @@ __device__ inline void vjp_sum(const void* part, int S, int64_t npad, int64_t i,
     for (int c = 0; c < 3; ++c) g[c] = 0.0;
     gm = 0.0;
     if (F32) {
-        const float* p = (const float*)part;
+        const float2* p = (const float2*)part;
 #pragma unroll 4
         for (int s = 0; s < S; ++s) {
-            const float* q = p + (int64_t)s * 8 * npad + i;
-            for (int c = 0; c < 3; ++c) { g[c] += (double)q[c * npad]; g[c] += (double)q[(3 + c) * npad]; }
-            if (with_mass) { gm += (double)q[6 * npad]; gm += (double)q[7 * npad]; }
+            const float2* q = p + (int64_t)s * 4 * npad + i;
+            for (int c = 0; c < 3; ++c) {
+                const float2 v = q[c * npad];
+                g[c] += (double)v.x; g[c] += (double)v.y;
+            }
+            if (with_mass) {
+                const float2 v = q[3 * npad];
+                gm += (double)v.x; gm += (double)v.y;
+            }
         }
     } else {
         const double* p = (const double*)part;

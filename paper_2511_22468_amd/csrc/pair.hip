@@ -44,8 +44,9 @@ __device__ __forceinline__ double rsqrt_f64(double s) {
 
 // ------------------------------------------------------------ forward FP32C --
 // js: staged sources (x, y, z, m), padded to nj = roundup(n, 128).
-// part: [S][6][npad] = (hi_x, hi_y, hi_z, lo_x, lo_y, lo_z) of
-// sum_j m_j d_ij s_ij^-3/2 over the block's slice.
+// part: [S][3][npad] float2 = (hi, lo) of the x, y and z components of
+// sum_j m_j d_ij s_ij^-3/2 over the block's slice (one 8-byte store per
+// component, one 8-byte load for the consumer).
 // muni: [flag, m] -- flag != 0 when every particle has mass m (set per call by
 // k_mass_info); the branch on it is uniform over the grid.
 template <bool EPS0>
@@ -67,11 +68,10 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f32c(const float4* __restrict__
     } else {
         fwd_f32c_slice<EPS0, false>(js, i, j0, j1, eps2, me, h, l);
     }
-    const float hx = h[0], hy = h[1], hz = h[2], lx = l[0], ly = l[1], lz = l[2];
     if (i < iend) {
-        float* p = part + (int64_t)blockIdx.y * 6 * npad + (i - i0);
-        p[0 * npad] = hx; p[1 * npad] = hy; p[2 * npad] = hz;
-        p[3 * npad] = lx; p[4 * npad] = ly; p[5 * npad] = lz;
+        float2* p = (float2*)part + (int64_t)blockIdx.y * 3 * npad + (i - i0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p[c * npad] = make_float2(h[c], l[c]);
     }
 }
 
@@ -146,16 +146,10 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__
         vjp_f32c_slice<EPS0, MASS, false>(jsv, i, j0, j1, eps2, me, mw, h, l);
     }
     if (i < iend) {
-        float* p = part + (int64_t)blockIdx.y * 8 * npad + (i - i0);
+        float2* p = (float2*)part + (int64_t)blockIdx.y * 4 * npad + (i - i0);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            p[c * npad] = h[c];
-            p[(3 + c) * npad] = l[c];
-        }
-        if (MASS) {
-            p[6 * npad] = h[3];
-            p[7 * npad] = l[3];
-        }
+        for (int c = 0; c < 3; ++c) p[c * npad] = make_float2(h[c], l[c]);
+        if (MASS) p[3 * npad] = make_float2(h[3], l[3]);
     }
 }
 

@@ -71,7 +71,7 @@ __device__ __forceinline__ void fwd_f32c_slice(const float4* __restrict__ js, in
 // The internal acceleration the dt and mass-scale terms need is not summed here:
 // the forward pass stores it with the tape.
 // jsv: interleaved [2 j] = (x, y, z, m), [2 j + 1] = (wx, wy, wz, 0), padded.
-// part: [S][8][npad] floats: JTw hi(3) lo(3), gm hi, lo.
+// part: [S][4][npad] float2 = (hi, lo) of the three J^T w components and of gm.
 // The two terms of J^T w are accumulated apart (A = sum s^-3/2 u,
 // B = sum s^-5/2 (d.u) d) and combined as A - 3 B once per sub-tile, which takes
 // the factor -3 out of the pair loop.  With UNI (all masses equal to m)
