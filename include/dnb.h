@@ -265,6 +265,19 @@ dnb_status dnb_mmd_batch(dnb_ctx* ctx, int64_t batch, int64_t n, const double* p
                          const double* tgt, int tgt_per_member, double h, double* loss,
                          double* gpos, void* stream);
 
+/* Loss of every member of an ensemble against each of n_tgt targets (the grid
+ * stage of a bootstrap, Fig. 2: every realisation of the observed stream
+ * compared with every grid run, the runs made once).  pos [batch][3][n], tgts
+ * [n_tgt][3][m] (device); loss [batch][n_tgt] (device): loss[b][t] = the squared
+ * MMD of dnb_mmd between pos[b] and tgts[t], equal bit for bit to dnb_mmd_batch
+ * with tgt_per_member = 1 and every member's target tgts[t].  The member-member
+ * sums are computed once for all targets.  Requires n, m <= max_n, h > 0,
+ * batch and n_tgt <= DNB_BATCH_MAX and the partial sums to fit the context
+ * (DNB_ERR_ARG otherwise). */
+dnb_status dnb_mmd_batch_targets(dnb_ctx* ctx, int64_t batch, int64_t n, const double* pos,
+                                 int64_t n_tgt, int64_t m, const double* tgts, double h,
+                                 double* loss, void* stream);
+
 /* Plummer spheres for every member of an ensemble (the batched form of
  * dnb_place_plummer, Fig. 2 step 3): member b is centred on w[b] ([batch][6],
  * device) with total mass m_tot[b] ([batch], device, > 0); the unit samples xi,

@@ -68,6 +68,7 @@ def load_library(path=LIB_PATH):
         "dnb_batch_capacity": ([P, I64], I64),
         "dnb_place_plummer_batch": ([P, I64, I64, P, P, P, P, D, D, P, P, P, P], I),
         "dnb_mmd_batch": ([P, I64, I64, P, I64, P, ctypes.c_int, D, P, P, P], I),
+        "dnb_mmd_batch_targets": ([P, I64, I64, P, I64, I64, P, D, P, P], I),
         "dnb_orbit_batch": ([P, I64, P, ctypes.POINTER(ctypes.c_double), I64, P, P, P], I),
         "dnb_orbit_batch_vjp": ([P, I64, P, ctypes.POINTER(ctypes.c_double), I64, P, P, P, P], I),
         "dnb_place_plummer_batch_vjp": ([P, I64, I64, P, P, D, D, P, P, P, P, P], I),

@@ -649,6 +649,26 @@ dnb_status dnb_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* pos
     return DNB_OK;
 }
 
+dnb_status dnb_mmd_batch_targets(dnb_ctx* c, int64_t batch, int64_t n, const double* pos,
+                                 int64_t n_tgt, int64_t m, const double* tgts, double h,
+                                 double* loss, void* stream) {
+    const char* fn = "dnb_mmd_batch_targets";
+    CHECK(check_ctx(c, 1, fn));
+    if (!(h > 0) || !is_fin(h)) return fail(DNB_ERR_ARG, "%s: h must be finite and > 0", fn);
+    if (!mmd_batch_targets_fits(c, batch, n, n_tgt, m))
+        return fail(DNB_ERR_ARG,
+                    "%s: batch %lld, n %lld, %lld targets of m %lld do not fit a context of "
+                    "max_n = %lld",
+                    fn, (long long)batch, (long long)n, (long long)n_tgt, (long long)m,
+                    (long long)c->max_n);
+    CHECK(check_dev(pos, "pos", fn));
+    CHECK(check_dev(tgts, "tgts", fn));
+    CHECK(check_dev(loss, "loss", fn));
+    HIP_TRY(launch_mmd_batch_targets(c, batch, n, pos, n_tgt, m, tgts, h, loss,
+                                     (hipStream_t)stream));
+    return DNB_OK;
+}
+
 dnb_status dnb_place_plummer_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const double* zeta,
                                        const double* m_tot, double a_p, double G,
                                        const double* gpos, const double* gvel, double* gw,

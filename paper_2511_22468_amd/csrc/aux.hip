@@ -142,15 +142,17 @@ hipError_t launch_mmd(dnb_ctx* c, int64_t n, const double* pos, int64_t m, const
 // sums per target (rows = 1, or 4 with the gradient terms; sstride = rows npad).
 // The target term sum_ab k(y_a, y_b) comes, for one shared target, from the
 // block sums red[8 q + 2] of k_mmd_y (pyy NULL), or, for a target per member,
-// from pyy [batch][Syy][npad_y] (the slice sums of each member's target).  One
-// block per member.
+// from pyy [batch][Syy][npad_y] (the slice sums of each member's target; with
+// pyy_bstride = 0 one target's sums serve every member).  loss[b * lstride].
+// One block per member.
 __global__ __launch_bounds__(BS) void k_mmd_batch_final(const double* __restrict__ pxx, int S,
                                                         const double* __restrict__ pxy, int Sxy,
                                                         int64_t sstride, int n, int m,
                                                         const double* __restrict__ red, int nby,
                                                         const double* __restrict__ pyy, int Syy,
-                                                        int64_t npad_y,
-                                                        double* __restrict__ loss) {
+                                                        int64_t npad_y, int64_t pyy_bstride,
+                                                        double* __restrict__ loss,
+                                                        int64_t lstride) {
     __shared__ double sh[3 * BS];
     const int b = blockIdx.x;
     const double* qx = pxx + (int64_t)b * S * sstride;
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(BS) void k_mmd_batch_final(const double* __restrict
     for (int s = 0; s < Sxy; ++s)
         for (int i = threadIdx.x; i < n; i += BS) v[1] += qy[(int64_t)s * sstride + i];
     if (pyy) {
-        const double* qq = pyy + (int64_t)b * Syy * npad_y;
+        const double* qq = pyy + (int64_t)b * pyy_bstride;
         for (int s = 0; s < Syy; ++s)
             for (int a = threadIdx.x; a < m; a += BS) v[2] += qq[(int64_t)s * npad_y + a];
     } else {
@@ -169,7 +171,8 @@ __global__ __launch_bounds__(BS) void k_mmd_batch_final(const double* __restrict
     }
     block_sum<3>(v, sh);
     if (threadIdx.x == 0)
-        loss[b] = v[0] / ((double)n * n) + v[2] / ((double)m * m) - 2.0 * v[1] / ((double)n * m);
+        loss[b * lstride] =
+            v[0] / ((double)n * n) + v[2] / ((double)m * m) - 2.0 * v[1] / ((double)n * m);
 }
 
 // Source slicing of the batched loss: slices of whole tiles, about target_blocks
@@ -267,7 +270,8 @@ hipError_t launch_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* 
                            Syy * npad_y);
         hipLaunchKernelGGL(k_mmd_batch_final, dim3((unsigned)batch), dim3(BS), 0, st, pxx, S, pxy,
                            Sxy, ss, (int)n, (int)m, (const double*)nullptr, 0,
-                           (const double*)pyb, Syy, npad_y, loss);
+                           (const double*)pyb, Syy, npad_y, (int64_t)Syy * npad_y, loss,
+                           (int64_t)1);
     } else {
         hipLaunchKernelGGL(k_mmd_rows, dim3(sy.nblk, sy.S), dim3(BS), 0, st, tgt, (int)m, tgt,
                            (int)m, inv2h2, sy.jslice, 0, pyy, sy.npad, 4 * sy.npad, 0, 0, 0);
@@ -275,11 +279,52 @@ hipError_t launch_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* 
                            c->red);
         hipLaunchKernelGGL(k_mmd_batch_final, dim3((unsigned)batch), dim3(BS), 0, st, pxx, S, pxy,
                            Sxy, ss, (int)n, (int)m, (const double*)c->red, sy.nblk,
-                           (const double*)nullptr, 0, (int64_t)0, loss);
+                           (const double*)nullptr, 0, (int64_t)0, (int64_t)0, loss, (int64_t)1);
     }
     if (wg)
         hipLaunchKernelGGL(k_mmd_batch_grad, dim3(nblk, (unsigned)batch), dim3(BS), 0, st, pxx, S,
                            pxy, Sxy, npad, (int)n, (int)m, h, gpos);
+    return hipGetLastError();
+}
+
+// Loss of every member against each of n_tgt targets: loss [batch][n_tgt].  The
+// member-member sums are made once; per target, the member-target sums, the
+// target's own sums (the slicing of the per-member-target mode, so that the
+// result equals it bit for bit) and the losses of all members.
+bool mmd_batch_targets_fits(const dnb_ctx* c, int64_t batch, int64_t n, int64_t n_tgt,
+                            int64_t m) {
+    if (n_tgt < 1 || n_tgt > DNB_BATCH_MAX) return false;
+    return mmd_batch_fits(c, batch, n, m, false, true);
+}
+
+hipError_t launch_mmd_batch_targets(dnb_ctx* c, int64_t batch, int64_t n, const double* pos,
+                                    int64_t n_tgt, int64_t m, const double* tgts, double h,
+                                    double* loss, hipStream_t st) {
+    const double inv2h2 = 1.0 / (2.0 * h * h);
+    int S, jslice, Sxy, jslice_xy, Syy, jsyy, s2, j2;
+    mmd_batch_slices(c, batch, n, m, S, jslice, Sxy, jslice_xy);
+    mmd_batch_slices(c, batch, m, m, Syy, jsyy, s2, j2);
+    const int nblk = (int)cdiv(n, BS);
+    const int64_t npad = (int64_t)nblk * BS;
+    const int nblk_y = (int)cdiv(m, BS);
+    const int64_t npad_y = (int64_t)nblk_y * BS;
+    double* pxx = (double*)c->partv;
+    double* pxy = pxx + batch * S * npad;
+    double* pyy = pxy + batch * Sxy * npad;
+    hipLaunchKernelGGL(k_mmd_rows, dim3(nblk, S, (unsigned)batch), dim3(BS), 0, st, pos, (int)n,
+                       pos, (int)n, inv2h2, jslice, 0, pxx, npad, npad, 3 * n, 3 * n, S * npad);
+    for (int64_t t = 0; t < n_tgt; ++t) {
+        const double* tgt = tgts + t * 3 * m;
+        hipLaunchKernelGGL(k_mmd_rows, dim3(nblk, Sxy, (unsigned)batch), dim3(BS), 0, st, pos,
+                           (int)n, tgt, (int)m, inv2h2, jslice_xy, 0, pxy, npad, npad, 3 * n,
+                           (int64_t)0, Sxy * npad);
+        hipLaunchKernelGGL(k_mmd_rows, dim3(nblk_y, Syy, 1), dim3(BS), 0, st, tgt, (int)m, tgt,
+                           (int)m, inv2h2, jsyy, 0, pyy, npad_y, npad_y, (int64_t)0, (int64_t)0,
+                           (int64_t)0);
+        hipLaunchKernelGGL(k_mmd_batch_final, dim3((unsigned)batch), dim3(BS), 0, st, pxx, S, pxy,
+                           Sxy, npad, (int)n, (int)m, (const double*)nullptr, 0,
+                           (const double*)pyy, Syy, npad_y, (int64_t)0, loss + t, n_tgt);
+    }
     return hipGetLastError();
 }
 

@@ -376,6 +376,11 @@ hipError_t launch_place_batch(int64_t batch, int64_t n, const double* w, const d
                               double* pos, double* vel, double* mass, hipStream_t st);
 bool mmd_batch_fits(const dnb_ctx* c, int64_t batch, int64_t n, int64_t m, bool grad,
                     bool per_member);
+bool mmd_batch_targets_fits(const dnb_ctx* c, int64_t batch, int64_t n, int64_t n_tgt,
+                            int64_t m);
+hipError_t launch_mmd_batch_targets(dnb_ctx* c, int64_t batch, int64_t n, const double* pos,
+                                    int64_t n_tgt, int64_t m, const double* tgts, double h,
+                                    double* loss, hipStream_t st);
 
 // Orbit fit (orbitfit.hip).  The model struct is declared in dnb_orbitfit.h.
 }  // namespace dnb

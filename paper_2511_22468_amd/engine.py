@@ -266,6 +266,17 @@ class Context:
         all members, or tgt[b] (B, 3, m) for member b.  A (B,) tensor."""
         return self._mmd_batch(pos, tgt, h, False)[0]
 
+    def mmd_batch_targets(self, pos, tgts, h):
+        """Loss of every member pos[b] (B, 3, n) against every target tgts[t]
+        (T, 3, m): a (B, T) tensor."""
+        B, n, T, m = pos.shape[0], pos.shape[2], tgts.shape[0], tgts.shape[2]
+        _arr(pos, (B, 3, n), "pos"); _arr(tgts, (T, 3, m), "tgts")
+        loss = self._new(B, T)
+        _lib.check(_lib.lib().dnb_mmd_batch_targets(self._h, B, n, _lib.ptr(pos), T, m,
+                                                    _lib.ptr(tgts), float(h), _lib.ptr(loss),
+                                                    _lib.stream_handle()))
+        return loss
+
     def mmd_batch_grad(self, pos, tgt, h):
         """Losses (B,) and their gradients (B, 3, n) for every member pos[b]
         (targets as in mmd_batch)."""

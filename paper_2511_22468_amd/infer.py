@@ -7,7 +7,8 @@
 3. Grid search (stage one of Sec. 2.2.1): the pipeline at every point of a
    regular grid over the prior box.  The runs do not depend on the realisation,
    so they are made once, as batched ensembles, and every realisation's MMD is
-   taken against each run.
+   taken against each run (dnb_mmd_batch_targets: the run-run kernel sums once
+   per run, the run-realisation sums per realisation).
 4. Refinement (stage two, Fig. 2 step 5): from each realisation's best grid
    point, descent steps on the batched pipeline gradient, all realisations
    together (bootstrap.refine).
@@ -40,9 +41,7 @@ def grid_losses(engine_ctx, u_grid, xi, zeta, targets, n_steps, pot, h=0.2, a_p=
     G, B = th.shape[0], targets.shape[0]
     out = torch.empty(G, B, dtype=torch.float64, device=xi.device)
     for s, pos in run_ensemble(engine_ctx, th, xi, zeta, n_steps, pot, a_p, w_now):
-        e = s + pos.shape[0]
-        for b in range(B):
-            out[s:e, b] = engine_ctx.mmd_batch(pos, targets[b], h)
+        out[s:s + pos.shape[0]] = engine_ctx.mmd_batch_targets(pos, targets, h)
     return out.cpu().numpy()
 
 

@@ -93,6 +93,8 @@ def test_arguments_rejected_before_any_device_work(lib):
     assert lib.dnb_orbit_batch(None, 1, None, table, 5, None, None, None) == _lib.DNB_ERR_ARG
     assert lib.dnb_mmd_batch(None, 1, 10, None, 10, None, 0, 0.2, None, None,
                              None) == _lib.DNB_ERR_ARG
+    assert lib.dnb_mmd_batch_targets(None, 1, 10, None, 2, 10, None, 0.2, None,
+                                     None) == _lib.DNB_ERR_ARG
     assert lib.dnb_batch_capacity(None, 10) == 0
     model = _lib.dnb_track_model()
     assert lib.dnb_track_chi2(None, ctypes.byref(model), 4, None, 1, None, None, None, None,
