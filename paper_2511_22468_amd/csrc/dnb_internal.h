@@ -24,9 +24,11 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t pad_sources(int64_t n) { return cdiv(n, SUBTILE) * SUBTILE; }
 
 // Source slicing of the O(N^2) kernels: the grid is (target blocks) x S, each
-// block owns tpb = BS * RI targets (RI per lane) and sums one contiguous slice of
+// block owns tpb targets (one per lane) and sums one contiguous slice of
 // sources.  Small N gets more slices so that the launch still fills the 256
-// compute units with about `target` blocks.
+// compute units with about `target` blocks.  slicing_for serves the MMD and
+// energy kernels (slices of whole LDS tiles); pair_slicing below the pair
+// kernels.
 struct Slicing {
     int S;          // number of slices
     int jslice;     // sources per slice (a multiple of TILE, SLICE_GRAIN for the pair kernels)
