@@ -37,13 +37,22 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
     return fmaf(z, pdf, cdf);
 }
 
-enum Epi { EPI_PLAIN = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_BWD = 3 };
+enum Epi { EPI_PLAIN = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_BWD = 3, EPI_PARTIAL = 4 };
+
+// Split of the inner dimension for products with few output tiles and a long
+// inner dimension (the backward pass through the 2048-wide output layer): each
+// block sums a K-slice into its own FP32 partial tile, k_splitk_epi adds the
+// slices in order and applies the epilogue.
+constexpr int KSPLIT_MAX = 16;
+constexpr int KSPLIT_MIN_K = 1024;
 
 // C[M x N] = A[M x K] . B[K x N];  A(m, k) = A[m * sam + k * sak], B(k, n) = B[k * sbk + n * sbn].
 // EPI_PLAIN:     outf = C
 // EPI_BIAS:      outf = C + bias
 // EPI_BIAS_GELU: outf = z = C + bias, outb = bf16(gelu(z))
 // EPI_GELU_BWD:  g = C * gelu'(zin), outf = g, outb = bf16(g)
+// EPI_PARTIAL:   outf[z][M][ldo] = the product over the K-slice z (blockIdx.z) of
+//                length kchunk
 // Outputs are row-major with leading dimension ldo.
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K,
@@ -53,7 +62,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K,
                                                    const float* __restrict__ bias,
                                                    const float* __restrict__ zin,
                                                    float* __restrict__ outf,
-                                                   uint16_t* __restrict__ outb, int64_t ldo) {
+                                                   uint16_t* __restrict__ outb, int64_t ldo,
+                                                   int kchunk) {
     __shared__ uint16_t As[64][16];
     __shared__ uint16_t Bs[16][64];
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
@@ -64,15 +74,17 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K,
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    for (int k0 = kbeg; k0 < kend; k0 += 16) {
 #pragma unroll
         for (int e = t; e < 1024; e += 256) {
             const int r = e >> 4, kk = e & 15;
             const int gm = m0 + r, gk = k0 + kk;
-            As[r][kk] = (gm < M && gk < K) ? A[gm * sam + gk * sak] : (uint16_t)0;
+            As[r][kk] = (gm < M && gk < kend) ? A[gm * sam + gk * sak] : (uint16_t)0;
             const int kb = e >> 6, c = e & 63;
             const int gk2 = k0 + kb, gn = n0 + c;
-            Bs[kb][c] = (gk2 < K && gn < N) ? B[gk2 * sbk + gn * sbn] : (uint16_t)0;
+            Bs[kb][c] = (gk2 < kend && gn < N) ? B[gk2 * sbk + gn * sbn] : (uint16_t)0;
         }
         __syncthreads();
         const int kq = 4 * (lane >> 4);
@@ -102,7 +114,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K,
                 if (row >= M || col >= N) continue;
                 const float c = acc[i][j][q];
                 const int64_t o = (int64_t)row * ldo + col;
-                if (EPI == EPI_PLAIN) {
+                if (EPI == EPI_PARTIAL) {
+                    outf[(int64_t)blockIdx.z * M * ldo + o] = c;
+                } else if (EPI == EPI_PLAIN) {
                     outf[o] = c;
                 } else if (EPI == EPI_BIAS) {
                     outf[o] = c + bias[col];
@@ -118,13 +132,48 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K,
             }
 }
 
+// Sum of the K-slice partials part[splits][M][N] in slice order, then the
+// epilogue EPI (EPI_PLAIN or EPI_GELU_BWD) into row-major outputs (ldo = N).
+template <int EPI>
+__global__ void k_splitk_epi(int M, int N, int splits, const float* __restrict__ part,
+                             const float* __restrict__ zin, float* __restrict__ outf,
+                             uint16_t* __restrict__ outb) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= (int64_t)M * N) return;
+    float c = 0.f;
+    for (int z = 0; z < splits; ++z) c += part[(int64_t)z * M * N + o];
+    if (EPI == EPI_PLAIN) {
+        outf[o] = c;
+    } else {
+        const float g = c * gelu_grad_f(zin[o]);
+        outf[o] = g;
+        outb[o] = f2bf(g);
+    }
+}
+
+// kpart: room for KSPLIT_MAX partial products of M x N (null: no split).
 template <int EPI>
 static void gemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak,
                  const uint16_t* B, int64_t sbk, int64_t sbn, const float* bias, const float* zin,
-                 float* outf, uint16_t* outb, int64_t ldo, hipStream_t st) {
+                 float* outf, uint16_t* outb, int64_t ldo, hipStream_t st,
+                 float* kpart = nullptr) {
     dim3 grid((unsigned)cdiv(N, 64), (unsigned)cdiv(M, 64));
+    const int64_t tiles = (int64_t)grid.x * grid.y;
+    if ((EPI == EPI_PLAIN || EPI == EPI_GELU_BWD) && kpart && K >= KSPLIT_MIN_K && tiles < 64 &&
+        ldo == N) {
+        int splits = K / 128;
+        if (splits > KSPLIT_MAX) splits = KSPLIT_MAX;
+        const int kchunk = (int)(cdiv(cdiv(K, splits), 16) * 16);
+        splits = (int)cdiv(K, kchunk);
+        hipLaunchKernelGGL(k_gemm_bf16<EPI_PARTIAL>, dim3(grid.x, grid.y, (unsigned)splits),
+                           dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, bias, zin, kpart,
+                           (uint16_t*)nullptr, ldo, kchunk);
+        hipLaunchKernelGGL(k_splitk_epi<EPI>, dim3((unsigned)cdiv((int64_t)M * N, 256)),
+                           dim3(256), 0, st, M, N, splits, (const float*)kpart, zin, outf, outb);
+        return;
+    }
     hipLaunchKernelGGL(k_gemm_bf16<EPI>, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk,
-                       sbn, bias, zin, outf, outb, ldo);
+                       sbn, bias, zin, outf, outb, ldo, K);
 }
 
 __global__ void k_to_bf16(int64_t n, const float* __restrict__ x, uint16_t* __restrict__ y) {
@@ -132,28 +181,40 @@ __global__ void k_to_bf16(int64_t n, const float* __restrict__ x, uint16_t* __re
     if (i < n) y[i] = f2bf(x[i]);
 }
 
-// Column sums of g [rows][cols] (bias gradient), one thread per column, fixed order.
+// Column sums of g [rows][cols] (bias gradient), one thread per column, fixed
+// order; four rows' loads in flight.
 __global__ void k_colsum(int rows, int cols, const float* __restrict__ g, float* __restrict__ out) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cols) return;
     float s = 0.f;
+#pragma unroll 4
     for (int r = 0; r < rows; ++r) s += g[(int64_t)r * cols + c];
     out[c] = s;
 }
 
-__global__ __launch_bounds__(BS) void k_mse(int64_t n, const float* __restrict__ y,
-                                            const float* __restrict__ t, double* __restrict__ loss,
-                                            float* __restrict__ dy) {
-    __shared__ double sh[BS];
-    double s[1] = {0.0};
+// Mean squared error and its gradient in one block of 1024 threads; thread t
+// takes elements t, t + 1024, ... (coalesced, four loads in flight, fixed order).
+constexpr int MSE_T = 1024;
+__global__ __launch_bounds__(MSE_T) void k_mse(int64_t n, const float* __restrict__ y,
+                                               const float* __restrict__ t,
+                                               double* __restrict__ loss,
+                                               float* __restrict__ dy) {
+    __shared__ double sh[MSE_T];
+    double s = 0.0;
     const float sc = (float)(2.0 / (double)n);
-    for (int64_t i = threadIdx.x; i < n; i += BS) {
+#pragma unroll 4
+    for (int64_t i = threadIdx.x; i < n; i += MSE_T) {
         const float d = y[i] - t[i];
-        s[0] += (double)d * (double)d;
+        s += (double)d * (double)d;
         dy[i] = sc * d;
     }
-    block_sum<1>(s, sh);
-    if (threadIdx.x == 0) loss[0] = s[0] / (double)n;
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = MSE_T / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = sh[0] / (double)n;
 }
 
 __global__ void k_adam(int64_t n, float* __restrict__ p, uint16_t* __restrict__ pb,
@@ -192,6 +253,7 @@ struct MlpWs {
     uint16_t* gb;        // gradient, BF16 [B][2048]
     float* h;            // gradient, FP32 [B][256]
     uint16_t* hb;        // gradient, BF16 [B][256]
+    float* kpart;        // split-K partial products, FP32 [KSPLIT_MAX][B][256]
 };
 
 inline int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
@@ -206,6 +268,7 @@ inline int64_t mlp_ws_layout(int64_t B, char* base, MlpWs* w) {
     p = take(2 * B * 2048); if (w) w->gb = (uint16_t*)p;
     p = take(4 * B * 256); if (w) w->h = (float*)p;
     p = take(2 * B * 256); if (w) w->hb = (uint16_t*)p;
+    p = take(4 * (int64_t)KSPLIT_MAX * B * 256); if (w) w->kpart = (float*)p;
     return off;
 }
 
@@ -357,11 +420,12 @@ dnb_status dnb_mlp_backward(const uint16_t* pb, int64_t B, const float* dy, void
             uint16_t* hb = (l % 2 == 1) ? w.hb : w.gb;
             if (l == NL - 1) { hf = w.h; hb = w.hb; }
             gemm<EPI_GELU_BWD>((int)B, K, N, gbf, N, 1, W, 1, N, nullptr, w.z[l - 1], hf, hb, K,
-                               st);
+                               st, w.kpart);
             gf = hf;
             gbf = hb;
         } else if (dx) {
-            gemm<EPI_PLAIN>((int)B, K, N, gbf, N, 1, W, 1, N, nullptr, nullptr, dx, nullptr, K, st);
+            gemm<EPI_PLAIN>((int)B, K, N, gbf, N, 1, W, 1, N, nullptr, nullptr, dx, nullptr, K, st,
+                            w.kpart);
         }
     }
     return hip_status("dnb_mlp_backward");
@@ -371,7 +435,8 @@ dnb_status dnb_mlp_mse(int64_t count, const float* y, const float* t, double* lo
                        void* stream) {
     if (count < 1 || !is_dev(y) || !is_dev(t) || !is_dev(loss) || !is_dev(dy))
         return sfail("dnb_mlp_mse: bad argument");
-    hipLaunchKernelGGL(k_mse, dim3(1), dim3(BS), 0, (hipStream_t)stream, count, y, t, loss, dy);
+    hipLaunchKernelGGL(k_mse, dim3(1), dim3(MSE_T), 0, (hipStream_t)stream, count, y, t, loss,
+                       dy);
     return hip_status("dnb_mlp_mse");
 }
 
