@@ -56,7 +56,8 @@ dnb_status dnb_mlp_forward(const float* params, const uint16_t* params_bf16, int
 
 /* Gradients of a loss with output cotangent dy [batch][2048] for the batch last
  * passed to dnb_mlp_forward with the same workspace: grads [param_count]
- * (overwritten) and, if dx is not NULL, the input cotangent dx [batch][4]. */
+ * (overwritten; NULL skips the parameter gradients) and, if dx is not NULL, the
+ * input cotangent dx [batch][4].  At least one of grads and dx is non-null. */
 dnb_status dnb_mlp_backward(const uint16_t* params_bf16, int64_t batch, const float* dy,
                             void* workspace, float* grads, float* dx, void* stream);
 
@@ -70,6 +71,22 @@ dnb_status dnb_mlp_mse(int64_t count, const float* y, const float* t, double* lo
 dnb_status dnb_mlp_adam(int64_t count, float* params, uint16_t* params_bf16, float* m, float* v,
                         const float* grads, double lr, double beta1, double beta2, double eps,
                         int64_t t, void* stream);
+
+/* Bytes of the workspace of dnb_mlp_invert for a batch of starts. */
+int64_t dnb_mlp_invert_workspace_bytes(int64_t batch);
+
+/* Inversion of the network on a target image (the warm start of the fit):
+ * iters Adam steps (beta 0.9, 0.999, eps 1e-8, step size lr) on the inputs u
+ * [batch][4] (device, updated in place) of mean((MLP(u) - target)^2) over the
+ * batch, with target [2048] (device) the same for every row, each step followed
+ * by clamping u to [-1, 1].  The same kernels and order as the loop of
+ * dnb_mlp_forward, dnb_mlp_mse, dnb_mlp_backward (dx only) and dnb_mlp_adam,
+ * issued from the library with no host round trip.  workspace:
+ * dnb_mlp_invert_workspace_bytes(batch) bytes (device).  batch must be a
+ * multiple of 16, at most 65536. */
+dnb_status dnb_mlp_invert(const float* params, const uint16_t* params_bf16, int64_t batch,
+                          const float* target, float* u, int64_t iters, double lr,
+                          void* workspace, void* stream);
 
 /* Bytes of the workspace of dnb_density_grid. */
 int64_t dnb_grid_workspace_bytes(void);

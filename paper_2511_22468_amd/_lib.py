@@ -82,6 +82,8 @@ def load_library(path=LIB_PATH):
         "dnb_mlp_backward": ([P, I64, P, P, P, P, P], I),
         "dnb_mlp_mse": ([I64, P, P, P, P, P], I),
         "dnb_mlp_adam": ([I64, P, P, P, P, P, D, D, D, D, I64, P], I),
+        "dnb_mlp_invert_workspace_bytes": ([I64], I64),
+        "dnb_mlp_invert": ([P, P, I64, P, P, I64, D, P, P], I),
         "dnb_grid_workspace_bytes": ([], I64),
         # orbit fit (include/dnb_orbitfit.h)
         "dnb_track_observe": ([P, TM, I64, P, P, P, P], I),

@@ -176,6 +176,22 @@ static void gemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sa
                        sbn, bias, zin, outf, outb, ldo, K);
 }
 
+__global__ void k_bcast_rows(int64_t n, int cols, const float* __restrict__ row,
+                             float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = row[i % cols];
+}
+
+__global__ void k_fill0(int64_t n, float* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.f;
+}
+
+__global__ void k_clamp(int64_t n, float* __restrict__ x, float lo, float hi) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = fminf(hi, fmaxf(lo, x[i]));
+}
+
 __global__ void k_to_bf16(int64_t n, const float* __restrict__ x, uint16_t* __restrict__ y) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] = f2bf(x[i]);
@@ -396,8 +412,9 @@ dnb_status dnb_mlp_forward(const float* params, const uint16_t* pb, int64_t B, c
 dnb_status dnb_mlp_backward(const uint16_t* pb, int64_t B, const float* dy, void* workspace,
                             float* grads, float* dx, void* stream) {
     if (B < 16 || B > 65536 || B % 16 != 0) return sfail("dnb_mlp_backward: bad batch");
-    if (!is_dev(pb) || !is_dev(dy) || !is_dev(workspace) || !is_dev(grads) || (dx && !is_dev(dx)))
-        return sfail("dnb_mlp_backward: every pointer must be device memory");
+    if (!is_dev(pb) || !is_dev(dy) || !is_dev(workspace) || (grads && !is_dev(grads)) ||
+        (dx && !is_dev(dx)) || (!grads && !dx))
+        return sfail("dnb_mlp_backward: every pointer must be device memory, grads or dx non-null");
     hipStream_t st = (hipStream_t)stream;
     MlpWs w;
     mlp_ws_layout(B, (char*)workspace, &w);
@@ -408,11 +425,13 @@ dnb_status dnb_mlp_backward(const uint16_t* pb, int64_t B, const float* dy, void
     const uint16_t* gbf = w.gb;      // its BF16 copy
     for (int l = NL - 1; l >= 0; --l) {
         const int K = LIN[l], N = LOUT[l];
-        // dW_l = a_l^T . g  (M = K, N = N, inner dimension = batch)
-        gemm<EPI_PLAIN>(K, N, (int)B, w.a[l], 1, K, gbf, N, 1, nullptr, nullptr,
-                        grads + w_off(l), nullptr, N, st);
-        hipLaunchKernelGGL(k_colsum, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, st, (int)B, N,
-                           gf, grads + b_off(l));
+        if (grads) {
+            // dW_l = a_l^T . g  (M = K, N = N, inner dimension = batch)
+            gemm<EPI_PLAIN>(K, N, (int)B, w.a[l], 1, K, gbf, N, 1, nullptr, nullptr,
+                            grads + w_off(l), nullptr, N, st);
+            hipLaunchKernelGGL(k_colsum, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, st, (int)B,
+                               N, gf, grads + b_off(l));
+        }
         const uint16_t* W = pb + w_off(l);
         if (l > 0) {
             // g_{l-1} = (g . W_l^T) * gelu'(z_{l-1})
@@ -451,6 +470,54 @@ dnb_status dnb_mlp_adam(int64_t count, float* params, uint16_t* pb, float* m, fl
                        count, params, pb, m, v, grads, (float)lr, (float)beta1, (float)beta2,
                        (float)eps, (float)c1, (float)c2);
     return hip_status("dnb_mlp_adam");
+}
+
+int64_t dnb_mlp_invert_workspace_bytes(int64_t batch) {
+    if (batch < 1) return -1;
+    // network workspace, y and dy [B][2048], the broadcast target [B][2048],
+    // dx [B][4], the BF16 copy of u and the Adam moments of u, the loss
+    return mlp_ws_layout(batch, nullptr, nullptr) + 3 * align256(4 * batch * 2048) +
+           align256(4 * batch * 4) + align256(2 * batch * 4) + 2 * align256(4 * batch * 4) +
+           align256(8);
+}
+
+dnb_status dnb_mlp_invert(const float* params, const uint16_t* pb, int64_t B, const float* target,
+                          float* u, int64_t iters, double lr, void* workspace, void* stream) {
+    if (B < 16 || B > 65536 || B % 16 != 0) return sfail("dnb_mlp_invert: batch must be a multiple of 16 in [16, 65536]");
+    if (iters < 1) return sfail("dnb_mlp_invert: iters must be >= 1");
+    if (!(lr > 0)) return sfail("dnb_mlp_invert: lr must be > 0");
+    if (!is_dev(params) || !is_dev(pb) || !is_dev(target) || !is_dev(u) || !is_dev(workspace))
+        return sfail("dnb_mlp_invert: every pointer must be device memory");
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)workspace;
+    int64_t off = mlp_ws_layout(B, nullptr, nullptr);
+    auto take = [&](int64_t bytes) { char* p = base + off; off += align256(bytes); return p; };
+    float* y = (float*)take(4 * B * 2048);
+    float* dy = (float*)take(4 * B * 2048);
+    float* tgt = (float*)take(4 * B * 2048);
+    float* dx = (float*)take(4 * B * 4);
+    uint16_t* ub = (uint16_t*)take(2 * B * 4);
+    float* mu = (float*)take(4 * B * 4);
+    float* vu = (float*)take(4 * B * 4);
+    double* loss = (double*)take(8);
+    const int64_t nu = 4 * B, ny = 2048 * B;
+    hipLaunchKernelGGL(k_bcast_rows, dim3((unsigned)cdiv(ny, 256)), dim3(256), 0, st, ny, 2048,
+                       target, tgt);
+    hipLaunchKernelGGL(k_fill0, dim3((unsigned)cdiv(nu, 256)), dim3(256), 0, st, nu, mu);
+    hipLaunchKernelGGL(k_fill0, dim3((unsigned)cdiv(nu, 256)), dim3(256), 0, st, nu, vu);
+    for (int64_t it = 1; it <= iters; ++it) {
+        dnb_status s = dnb_mlp_forward(params, pb, B, u, y, workspace, stream);
+        if (s != DNB_OK) return s;
+        hipLaunchKernelGGL(k_mse, dim3(1), dim3(MSE_T), 0, st, ny, (const float*)y,
+                           (const float*)tgt, loss, dy);
+        s = dnb_mlp_backward(pb, B, dy, workspace, nullptr, dx, stream);
+        if (s != DNB_OK) return s;
+        s = dnb_mlp_adam(nu, u, ub, mu, vu, dx, lr, 0.9, 0.999, 1e-8, it, stream);
+        if (s != DNB_OK) return s;
+        hipLaunchKernelGGL(k_clamp, dim3((unsigned)cdiv(nu, 256)), dim3(256), 0, st, nu, u, -1.f,
+                           1.f);
+    }
+    return hip_status("dnb_mlp_invert");
 }
 
 int64_t dnb_grid_workspace_bytes(void) { return 2048 * sizeof(unsigned int); }

@@ -97,12 +97,14 @@ class MLP:
                                               _lib.stream_handle()))
         return y
 
-    def backward(self, dy, want_dx=False):
-        """After forward(x) on the same batch size: fills self.grads; returns dx or None."""
+    def backward(self, dy, want_dx=False, want_grads=True):
+        """After forward(x) on the same batch size: fills self.grads (unless
+        want_grads is False); returns dx or None."""
         B = dy.shape[0]
         dx = torch.empty(B, 4, dtype=torch.float32, device=self.device) if want_dx else None
+        grads = self.grads if want_grads else None
         _lib.check(_lib.lib().dnb_mlp_backward(_lib.ptr(self.pb), B, _lib.ptr(dy),
-                                               _lib.ptr(self.ws(B)), _lib.ptr(self.grads),
+                                               _lib.ptr(self.ws(B)), _lib.ptr(grads),
                                                _lib.ptr(dx), _lib.stream_handle()))
         return dx
 
@@ -149,18 +151,13 @@ class MLP:
         B = ((n_starts + 15) // 16) * 16
         u = torch.tensor(rng.uniform(-0.9, 0.9, size=(B, 4)), dtype=torch.float32,
                          device=self.device)
-        tgt = target.reshape(1, NPIX).expand(B, NPIX).contiguous()
-        ub = torch.empty(B * 4, dtype=torch.int16, device=self.device)
-        mu = torch.zeros(B * 4, dtype=torch.float32, device=self.device)
-        vu = torch.zeros(B * 4, dtype=torch.float32, device=self.device)
-        for it in range(1, iters + 1):
-            y = self.forward(u)
-            _, dy = self.mse(y, tgt)
-            dx = self.backward(dy, want_dx=True)
-            _lib.check(_lib.lib().dnb_mlp_adam(B * 4, _lib.ptr(u), _lib.ptr(ub), _lib.ptr(mu),
-                                               _lib.ptr(vu), _lib.ptr(dx), lr, 0.9, 0.999, 1e-8,
-                                               it, _lib.stream_handle()))
-            u.clamp_(-1.0, 1.0)
+        tgt = target.reshape(NPIX).contiguous()
+        ws = torch.empty(int(_lib.lib().dnb_mlp_invert_workspace_bytes(B)), dtype=torch.uint8,
+                         device=self.device)
+        _lib.check(_lib.lib().dnb_mlp_invert(_lib.ptr(self.p), _lib.ptr(self.pb), B,
+                                             _lib.ptr(tgt), _lib.ptr(u), int(iters), float(lr),
+                                             _lib.ptr(ws), _lib.stream_handle()))
+        tgt = tgt.reshape(1, NPIX).expand(B, NPIX)
         y = self.forward(u)
         err = ((y - tgt) ** 2).mean(dim=1)
         k = int(torch.argmin(err[:n_starts]).item())

@@ -94,3 +94,40 @@ def test_training_reduces_loss():
     losses = net.train(X, Y.contiguous(), epochs=30, batch=64, lr=1e-3)
     say(f"[mlp] training loss {losses[0]:.3e} -> {losses[-1]:.3e}")
     assert losses[-1] < 0.2 * losses[0]
+
+
+def test_inversion_entry_equals_the_step_by_step_loop():
+    """dnb_mlp_invert runs the same kernels in the same order as the loop of
+    forward, mse, backward (input cotangent only), Adam on the inputs and the
+    clamp to [-1, 1]: its inputs after 25 steps equal the loop's bit for bit, and
+    the parameter gradients skipped by the backward leave dx unchanged."""
+    from paper_2511_22468_amd import _lib
+    from paper_2511_22468_amd.surrogate import NPIX
+    _, net = _mlp(8)
+    rng = np.random.default_rng(9)
+    B, iters, lr = 32, 25, 0.05
+    u0 = torch.tensor(rng.uniform(-0.9, 0.9, size=(B, 4)), dtype=torch.float32, device="cuda")
+    target = torch.tensor(rng.normal(scale=0.01, size=NPIX), dtype=torch.float32, device="cuda")
+    # the library loop
+    u = u0.clone()
+    ws = torch.empty(int(_lib.lib().dnb_mlp_invert_workspace_bytes(B)), dtype=torch.uint8,
+                     device="cuda")
+    _lib.check(_lib.lib().dnb_mlp_invert(_lib.ptr(net.p), _lib.ptr(net.pb), B, _lib.ptr(target),
+                                         _lib.ptr(u), iters, lr, _lib.ptr(ws),
+                                         _lib.stream_handle()))
+    # the same steps through the single-call bindings
+    v = u0.clone()
+    tgt = target.reshape(1, NPIX).expand(B, NPIX).contiguous()
+    vb = torch.empty(B * 4, dtype=torch.int16, device="cuda")
+    mv = torch.zeros(B * 4, dtype=torch.float32, device="cuda")
+    vv = torch.zeros(B * 4, dtype=torch.float32, device="cuda")
+    for it in range(1, iters + 1):
+        y = net.forward(v)
+        _, dy = net.mse(y, tgt)
+        dx = net.backward(dy, want_dx=True, want_grads=(it % 2 == 0))
+        _lib.check(_lib.lib().dnb_mlp_adam(B * 4, _lib.ptr(v), _lib.ptr(vb), _lib.ptr(mv),
+                                           _lib.ptr(vv), _lib.ptr(dx), lr, 0.9, 0.999, 1e-8,
+                                           it, _lib.stream_handle()))
+        v.clamp_(-1.0, 1.0)
+    assert torch.equal(u, v)
+    assert float((u - u0).abs().max().item()) > 0
