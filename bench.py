@@ -519,9 +519,9 @@ def main():
                          "the pipeline gradient for 64 and 256 resampled streams at once vs one "
                          "at a time (N = 1000, 1000 steps), one JSON line")
     ap.add_argument("--infer", action="store_true",
-                    help="the whole inference pipeline: grid search over 10^4 points for 64 "
-                         "bootstrap realisations, then their batched refinement (N = 1000, "
-                         "1000 steps), one JSON line")
+                    help="the whole inference pipeline at the paper's scale: grid search over "
+                         "10^4 points for 1000 bootstrap realisations, then their batched "
+                         "refinement (N = 1000, 1000 steps), one JSON line")
     ap.add_argument("--configs", action="store_true",
                     help="end-to-end time of the N = 1024, 16384 and 8192 (gradient) workloads, "
                          "one JSON line each")

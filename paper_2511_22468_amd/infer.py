@@ -14,7 +14,8 @@
    together (bootstrap.refine).
 5. The spread of the refined estimates over the realisations.
 
-Usage: python -m paper_2511_22468_amd.infer [--quick]   (prints one JSON line)
+Usage: python -m paper_2511_22468_amd.infer [--quick] [--realisations B]
+(prints one JSON line)
 """
 import argparse
 import json
@@ -26,6 +27,13 @@ import torch
 from . import bootstrap as BS
 from .pipeline import W_NOW, make_target, run_ensemble
 from .surrogate import denormalise, normalise
+
+
+# The paper's inference setup (Sec. 2.2.1; Fig. 2): 1000 Plummer particles,
+# 1000 fixed steps, 1000 bootstrap realisations of the observed stream, a grid of
+# 10^4 parameter points, then 10 gradient refinement steps.
+FULL = {"n": 1000, "steps": 1000, "realisations": 1000, "per_axis": 10, "iters": 10}
+QUICK = {"n": 300, "steps": 200, "realisations": 8, "per_axis": 5, "iters": 4}
 
 
 def grid_points(per_axis):
@@ -88,15 +96,16 @@ def summary(res, u_true):
             "accepted_steps_mean": float(res["accepted"].sum(0).mean())}
 
 
-def main(quick=False, seed=90):
+def main(quick=False, seed=90, realisations=None):
     from . import engine
     from .fit import EPS_FIT
     from synth import plummer_unit
 
     dev = torch.device("cuda", 0)
     t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device=dev)
-    n, T = (300, 200) if quick else (1000, 1000)
-    B, per_axis, iters = (8, 5, 4) if quick else (64, 10, 10)
+    cfg = QUICK if quick else FULL
+    n, T, per_axis, iters = cfg["n"], cfg["steps"], cfg["per_axis"], cfg["iters"]
+    B = int(realisations) if realisations else cfg["realisations"]
     pot = engine.Potential(eps=EPS_FIT)
     ctx = engine.Context(4096 * 1024, "fp32c")
     u_true = normalise(np.array([[1.75, 10 ** 4.5, 1.0e12, 6.5e10]]))[0]
@@ -118,5 +127,7 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--seed", type=int, default=90)
+    ap.add_argument("--realisations", type=int, default=None,
+                    help="bootstrap realisations (default: the paper's 1000; 8 with --quick)")
     a = ap.parse_args()
-    print(json.dumps(main(a.quick, a.seed)), flush=True)
+    print(json.dumps(main(a.quick, a.seed, a.realisations)), flush=True)

@@ -18,6 +18,9 @@ from .units import G as G_DEFAULT, gyr
 
 NPAR = 5
 TRACK_MAX = 64
+# Starts of the fit are drawn between p_true / START_FACTOR and p_true * START_FACTOR
+# (Sec. 2.2.2: from half to twice the true parameters).
+START_FACTOR = 2.0
 
 
 @dataclass(frozen=True)
@@ -110,7 +113,7 @@ def fit(ctx, model, track, p_true, n_starts=1000, n_iter=60, seed=0, lambda0=1e-
     p_true, Levenberg-Marquardt from each, the lowest chi2 kept, and the Fisher
     covariance there.  Returns (best p, its chi2, covariance, all fits, all chi2)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    half = np.log10(2.0)
+    half = np.log10(START_FACTOR)
     starts = np.asarray(p_true, float)[None, :] + rng.uniform(-half, half, (n_starts, NPAR))
     p0 = torch.tensor(starts, dtype=torch.float64, device=track.device)
     fits, c = lm(ctx, model, track, p0, n_iter, lambda0)
