@@ -15,7 +15,6 @@ import torch
 
 from . import autograd as AG
 from .engine import Potential
-from .units import G as G_DEFAULT
 
 W_NOW = (12.0, 0.0, 0.0, 0.0, -180.0, 60.0)
 

@@ -8,7 +8,6 @@ the MMD by its identities and by the closed-form expectation for Gaussian
 samples.
 """
 import numpy as np
-import pytest
 
 from oracle import adjoint, constants as C, forces, integrate, mmd, pipeline
 from oracle.forces import Potential

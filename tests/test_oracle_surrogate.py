@@ -1,6 +1,5 @@
 """Pins of the oracle's density grid and MLP against independent library routes."""
 import numpy as np
-import pytest
 import torch
 from scipy.ndimage import gaussian_filter1d
 
