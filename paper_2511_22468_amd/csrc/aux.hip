@@ -7,14 +7,43 @@
 namespace dnb {
 
 // ---------------------------------------------------------------------- MMD --
+// 2^x for x <= 0 (the Gaussian kernel is exp(-s / (2 h^2)) = 2^(-s c) with
+// c = log2(e) / (2 h^2)).  x = n + f with n = rint(x) and |f| <= 1/2; 2^f =
+// e^(f ln 2) is summed from its Taylor series to degree 13, whose first omitted
+// term, (ln 2 / 2)^14 / 14!, is below 5e-18; ldexp then scales by 2^n, with
+// gradual underflow to exactly 0 for any n (v_ldexp_f64 takes the whole int
+// range, and the conversion of n saturates).  Maximum error 0.57 ulp against a
+// long-double 2^x over [-1080, 0].  A NaN argument gives NaN; so does -inf,
+// which would need |p - q| beyond 1e154.
+struct Exp2Taylor { double c[14]; };
+constexpr Exp2Taylor exp2_taylor() {
+    constexpr double LN2 = 0.69314718055994530942;
+    Exp2Taylor t{};
+    double term = 1.0;
+    for (int k = 0; k < 14; ++k) { t.c[k] = term; term = term * LN2 / (k + 1); }
+    return t;
+}
+
+__device__ __forceinline__ double exp2_nonpos(double x) {
+    constexpr Exp2Taylor T = exp2_taylor();
+    const double n = rint(x);
+    const double f = x - n;
+    double p = T.c[13];
+#pragma unroll
+    for (int k = 12; k >= 0; --k) p = fma(p, f, T.c[k]);
+    return ldexp(p, (int)n);
+}
+
 // For targets p_i and sources q_j of one slice:
 //   part[s][0][i] = sum_j k(p_i, q_j),  part[s][1..3][i] = sum_j k(p_i, q_j) (p_i - q_j)
 // with k(p, q) = exp(-|p - q|^2 / (2 h^2)); slice s starts at part + s * sstride
 // (4 npad with the gradient terms, npad without).  blockIdx.z selects a member of
 // an ensemble: P, Q and part advance by the given member strides (0 for one system).
+// neg_c = -log2(e) / (2 h^2).  Without GRAD only the kernel sums are formed.
+template <bool GRAD>
 __global__ __launch_bounds__(BS) void k_mmd_rows(const double* __restrict__ P, int np,
                                                  const double* __restrict__ Q, int nq,
-                                                 double inv2h2, int jslice, int with_grad,
+                                                 double neg_c, int jslice,
                                                  double* __restrict__ part, int64_t npad,
                                                  int64_t sstride, int64_t p_bstride,
                                                  int64_t q_bstride, int64_t part_bstride) {
@@ -37,19 +66,35 @@ __global__ __launch_bounds__(BS) void k_mmd_rows(const double* __restrict__ P, i
         for (int k = 0; k < cnt; ++k) {
             const double4 q = tile[k];
             const double dx = px - q.x, dy = py - q.y, dz = pz - q.z;
-            const double e = exp(-(dx * dx + dy * dy + dz * dz) * inv2h2);
+            const double e = exp2_nonpos(fma(dx, dx, fma(dy, dy, dz * dz)) * neg_c);
             s0 += e;
-            gx = fma(e, dx, gx);
-            gy = fma(e, dy, gy);
-            gz = fma(e, dz, gz);
+            if (GRAD) {
+                gx = fma(e, dx, gx);
+                gy = fma(e, dy, gy);
+                gz = fma(e, dz, gz);
+            }
         }
         __syncthreads();
     }
     if (i < np) {
         double* p = part + (int64_t)blockIdx.y * sstride + i;
         p[0] = s0;
-        if (with_grad) { p[npad] = gx; p[2 * npad] = gy; p[3 * npad] = gz; }
+        if (GRAD) { p[npad] = gx; p[2 * npad] = gy; p[3 * npad] = gz; }
     }
+}
+
+// Launch of k_mmd_rows with the kernel width h given as inv2h2 = 1 / (2 h^2).
+static void mmd_rows(dim3 grid, hipStream_t st, const double* P, int np, const double* Q, int nq,
+                     double inv2h2, int jslice, int with_grad, double* part, int64_t npad,
+                     int64_t sstride, int64_t p_bstride, int64_t q_bstride,
+                     int64_t part_bstride) {
+    const double neg_c = -1.44269504088896340736 * inv2h2;
+    if (with_grad)
+        hipLaunchKernelGGL(k_mmd_rows<true>, grid, dim3(BS), 0, st, P, np, Q, nq, neg_c, jslice,
+                           part, npad, sstride, p_bstride, q_bstride, part_bstride);
+    else
+        hipLaunchKernelGGL(k_mmd_rows<false>, grid, dim3(BS), 0, st, P, np, Q, nq, neg_c, jslice,
+                           part, npad, sstride, p_bstride, q_bstride, part_bstride);
 }
 
 // Per-target slice sums -> gradient rows and per-block sums of the kernel sums.
@@ -123,11 +168,11 @@ hipError_t launch_mmd(dnb_ctx* c, int64_t n, const double* pos, int64_t m, const
     double* pxx = pv;
     double* pxy = pv + (int64_t)4 * sx.S * sx.npad;
     double* pyy = (double*)c->part;
-    hipLaunchKernelGGL(k_mmd_rows, dim3(sx.nblk, sx.S), dim3(BS), 0, st, pos, (int)n, pos, (int)n,
+    mmd_rows(dim3(sx.nblk, sx.S), st, pos, (int)n, pos, (int)n,
                        inv2h2, sx.jslice, wg, pxx, sx.npad, 4 * sx.npad, 0, 0, 0);
-    hipLaunchKernelGGL(k_mmd_rows, dim3(sxy.nblk, sxy.S), dim3(BS), 0, st, pos, (int)n, tgt,
+    mmd_rows(dim3(sxy.nblk, sxy.S), st, pos, (int)n, tgt,
                        (int)m, inv2h2, sxy.jslice, wg, pxy, sxy.npad, 4 * sxy.npad, 0, 0, 0);
-    hipLaunchKernelGGL(k_mmd_rows, dim3(sy.nblk, sy.S), dim3(BS), 0, st, tgt, (int)m, tgt, (int)m,
+    mmd_rows(dim3(sy.nblk, sy.S), st, tgt, (int)m, tgt, (int)m,
                        inv2h2, sy.jslice, 0, pyy, sy.npad, 4 * sy.npad, 0, 0, 0);
     hipLaunchKernelGGL(k_mmd_x, dim3(sx.nblk), dim3(BS), 0, st, pxx, sx.S, pxy, sxy.S, sx.npad,
                        (int)n, (int)m, h, gpos, c->red);
@@ -252,10 +297,10 @@ hipError_t launch_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* 
     double* pxy = pxx + batch * S * ss;
     double* pyy = (double*)c->part;
     const Slicing sy = plain_slicing(c, m);
-    hipLaunchKernelGGL(k_mmd_rows, dim3(nblk, S, (unsigned)batch), dim3(BS), 0, st, pos, (int)n,
+    mmd_rows(dim3(nblk, S, (unsigned)batch), st, pos, (int)n,
                        pos, (int)n, inv2h2, jslice, wg, pxx, npad, ss, 3 * n, 3 * n, S * ss);
     const int64_t tstride = per_member ? 3 * m : 0;
-    hipLaunchKernelGGL(k_mmd_rows, dim3(nblk, Sxy, (unsigned)batch), dim3(BS), 0, st, pos, (int)n,
+    mmd_rows(dim3(nblk, Sxy, (unsigned)batch), st, pos, (int)n,
                        tgt, (int)m, inv2h2, jslice_xy, wg, pxy, npad, ss, 3 * n, tstride,
                        Sxy * ss);
     if (per_member) {
@@ -265,7 +310,7 @@ hipError_t launch_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* 
         const int nblk_y = (int)cdiv(m, BS);
         const int64_t npad_y = (int64_t)nblk_y * BS;
         double* pyb = pxy + batch * Sxy * ss;
-        hipLaunchKernelGGL(k_mmd_rows, dim3(nblk_y, Syy, (unsigned)batch), dim3(BS), 0, st, tgt,
+        mmd_rows(dim3(nblk_y, Syy, (unsigned)batch), st, tgt,
                            (int)m, tgt, (int)m, inv2h2, jsyy, 0, pyb, npad_y, npad_y, 3 * m, 3 * m,
                            Syy * npad_y);
         hipLaunchKernelGGL(k_mmd_batch_final, dim3((unsigned)batch), dim3(BS), 0, st, pxx, S, pxy,
@@ -273,7 +318,7 @@ hipError_t launch_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* 
                            (const double*)pyb, Syy, npad_y, (int64_t)Syy * npad_y, loss,
                            (int64_t)1);
     } else {
-        hipLaunchKernelGGL(k_mmd_rows, dim3(sy.nblk, sy.S), dim3(BS), 0, st, tgt, (int)m, tgt,
+        mmd_rows(dim3(sy.nblk, sy.S), st, tgt, (int)m, tgt,
                            (int)m, inv2h2, sy.jslice, 0, pyy, sy.npad, 4 * sy.npad, 0, 0, 0);
         hipLaunchKernelGGL(k_mmd_y, dim3(sy.nblk), dim3(BS), 0, st, pyy, sy.S, sy.npad, (int)m,
                            c->red);
@@ -311,14 +356,14 @@ hipError_t launch_mmd_batch_targets(dnb_ctx* c, int64_t batch, int64_t n, const 
     double* pxx = (double*)c->partv;
     double* pxy = pxx + batch * S * npad;
     double* pyy = pxy + batch * Sxy * npad;
-    hipLaunchKernelGGL(k_mmd_rows, dim3(nblk, S, (unsigned)batch), dim3(BS), 0, st, pos, (int)n,
+    mmd_rows(dim3(nblk, S, (unsigned)batch), st, pos, (int)n,
                        pos, (int)n, inv2h2, jslice, 0, pxx, npad, npad, 3 * n, 3 * n, S * npad);
     for (int64_t t = 0; t < n_tgt; ++t) {
         const double* tgt = tgts + t * 3 * m;
-        hipLaunchKernelGGL(k_mmd_rows, dim3(nblk, Sxy, (unsigned)batch), dim3(BS), 0, st, pos,
+        mmd_rows(dim3(nblk, Sxy, (unsigned)batch), st, pos,
                            (int)n, tgt, (int)m, inv2h2, jslice_xy, 0, pxy, npad, npad, 3 * n,
                            (int64_t)0, Sxy * npad);
-        hipLaunchKernelGGL(k_mmd_rows, dim3(nblk_y, Syy, 1), dim3(BS), 0, st, tgt, (int)m, tgt,
+        mmd_rows(dim3(nblk_y, Syy, 1), st, tgt, (int)m, tgt,
                            (int)m, inv2h2, jsyy, 0, pyy, npad_y, npad_y, (int64_t)0, (int64_t)0,
                            (int64_t)0);
         hipLaunchKernelGGL(k_mmd_batch_final, dim3((unsigned)batch), dim3(BS), 0, st, pxx, S, pxy,

@@ -321,12 +321,15 @@ def test_batched_component_adjoints_equal_single_ones(eng):
     loss, g = ctx.mmd_batch_grad(pos, tgt, 0.2)
     for b in range(B):
         sl, sg = ctx.mmd(pos[b].contiguous(), tgt, 0.2)
-        assert abs(loss[b].item() / sl.item() - 1) <= 1e-13
+        # the batched and single entries sum in different orders; MMD^2 (~1e-3) is a
+        # difference of kernel means of order 0.1-1, so one ulp of those sums is
+        # ~1e-13 of the loss
+        assert abs(loss[b].item() / sl.item() - 1) <= 1e-12
         # per-row errors against the largest row: rows near a kernel-sum cancellation
         # have small gradients with few correct digits in any summation order
         got, single = g[b].cpu().numpy().T, sg.cpu().numpy().T
         scale = np.sqrt((single ** 2).sum(1)).max()
-        assert np.sqrt(((got - single) ** 2).sum(1)).max() <= 1e-13 * scale, b
+        assert np.sqrt(((got - single) ** 2).sum(1)).max() <= 1e-12 * scale, b
         ref = ommd.mmd2_grad(pos[b].cpu().numpy().T, Y, 0.2)
         assert np.sqrt(((got - ref) ** 2).sum(1)).max() <= 1e-12 * scale, b
     # orbits: each member its own potential and signed step
@@ -372,10 +375,10 @@ def test_mmd_batch_with_a_target_per_member(eng):
     assert torch.equal(ctx.mmd_batch(pos, tgt, 0.2), loss)
     for b in range(B):
         sl, sg = ctx.mmd(pos[b].contiguous(), tgt[b].contiguous(), 0.2)
-        assert abs(loss[b].item() / sl.item() - 1) <= 1e-13, b
+        assert abs(loss[b].item() / sl.item() - 1) <= 1e-12, b
         got, single = g[b].cpu().numpy().T, sg.cpu().numpy().T
         scale = np.sqrt((single ** 2).sum(1)).max()
-        assert np.sqrt(((got - single) ** 2).sum(1)).max() <= 1e-13 * scale, b
+        assert np.sqrt(((got - single) ** 2).sum(1)).max() <= 1e-12 * scale, b
     # targets equal to the members' own positions (m = n)
     l0, g0 = ctx.mmd_batch_grad(pos, pos.clone(), 0.2)
     assert l0.abs().max().item() <= 1e-14
