@@ -271,6 +271,31 @@ def test_mmd_matches_oracle(dnb):
     assert abs(loss.item()) <= 1e-14
 
 
+def test_mmd_kernel_range_ends(dnb):
+    """The Gaussian kernel over its whole range: clouds far apart (cross-kernel
+    values underflow to exactly 0, so MMD^2 = the two self terms), clouds whose
+    pair distances span the denormal range, and a NaN position (propagates)."""
+    pk, engine, ctx = dnb
+    rng = np.random.default_rng(12)
+    X = W_X + rng.normal(scale=0.2, size=(300, 3))
+    h = 0.2
+    for shift in (60.0, 7.5, 7.8):
+        Y = X[:250] + np.array([shift, 0.0, 0.0])
+        loss, g = ctx["fp64"].mmd(to_dev(X), to_dev(Y), h)
+        ref = ommd.mmd2(X, Y, h)
+        assert abs(loss.item() / ref - 1) <= 1e-12, shift
+        assert rel_norm(to_host(g), ommd.mmd2_grad(X, Y, h)) <= 1e-12, shift
+    Y = X[:250] + np.array([60.0, 0.0, 0.0])
+    kxx = np.exp(-((X[:, None, :] - X[None, :, :]) ** 2).sum(-1) / (2 * h * h)).mean()
+    kyy = np.exp(-((Y[:, None, :] - Y[None, :, :]) ** 2).sum(-1) / (2 * h * h)).mean()
+    loss, _ = ctx["fp64"].mmd(to_dev(X), to_dev(Y), h, grad=False)
+    assert abs(loss.item() / (kxx + kyy) - 1) <= 1e-12
+    Xn = X.copy()
+    Xn[5, 1] = np.nan
+    loss, _ = ctx["fp64"].mmd(to_dev(Xn), to_dev(X[:250]), h, grad=False)
+    assert np.isnan(loss.item())
+
+
 def test_energy_matches_oracle(dnb):
     pk, engine, ctx = dnb
     x, v, m = plummer_state(777, 12)
