@@ -83,12 +83,20 @@ def descend(model, u0, lr, max_iter, stop_loss=None, clock0=None):
     return u, L, hist
 
 
-def run(quick=False, seed=50):
+def run(quick=False, seed=50, n_train=None, n_draws=None, train_steps=None):
+    """Both arms for one held-out target.  n_train, n_draws and train_steps set
+    the surrogate's training set (particles per run, runs, KDK steps per run over
+    the same t_end).  By default it is 512 runs of 2048 particles with 1000 steps,
+    the step count of the paper's inference runs (Sec. 2.2.1); the fit itself
+    runs 8192 particles with 4000 steps.  The density images are normalised to sum
+    1, so runs of another size map to the same image."""
     dev = torch.device("cuda", 0)
     from synth import draw_theta, mlp_init, flatten, plummer_unit
 
-    n_fit, n_train, T = (2048, 1024, 1000) if quick else (8192, 4096, 4000)
-    n_draws = 64 if quick else 512
+    n_fit, T = (2048, 1000) if quick else (8192, 4000)
+    n_train = int(n_train or (1024 if quick else 2048))
+    n_draws = int(n_draws or (64 if quick else 512))
+    T_train = int(train_steps or 1000)
     iters = 8 if quick else 20
     pot = engine.Potential(eps=EPS_FIT)
     t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device=dev)
@@ -118,7 +126,7 @@ def run(quick=False, seed=50):
     t0 = time.perf_counter()
     thetas = draw_theta(n_draws, seed)
     xs, zs = plummer_unit(n_train, seed + 4)
-    X, Y = generate_dataset(gen_ctx, thetas, t3(xs), t3(zs), T, pot, f9)
+    X, Y = generate_dataset(gen_ctx, thetas, t3(xs), t3(zs), T_train, pot, f9)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -142,6 +150,7 @@ def run(quick=False, seed=50):
     out = {
         "metric": "time-to-fit: surrogate warm start vs plain N-body gradient descent",
         "n_fit": n_fit, "n_steps": T, "n_train_runs": n_draws, "n_train_particles": n_train,
+        "n_train_steps": T_train,
         "theta_star": th_star.tolist(),
         "plain": {"seconds": t_plain, "iterations": len(hist_plain) - 1, "L_star": L_star,
                   "u": u_plain.tolist(), "loss_curve": [h[1] for h in hist_plain]},
