@@ -522,6 +522,10 @@ def main():
                     help="the whole inference pipeline at the paper's scale: grid search over "
                          "10^4 points for 1000 bootstrap realisations, then their batched "
                          "refinement (N = 1000, 1000 steps), one JSON line")
+    ap.add_argument("--time-to-fit", action="store_true",
+                    help="the second half of the headline metric: surrogate-warm-started vs "
+                         "plain N-body gradient descent on a held-out target (fit N = 8192, "
+                         "4000 steps), one JSON line")
     ap.add_argument("--configs", action="store_true",
                     help="end-to-end time of the N = 1024, 16384 and 8192 (gradient) workloads, "
                          "one JSON line each")
@@ -533,7 +537,7 @@ def main():
         print(json.dumps(cpu_sweep()), flush=True)
         return
     if (args.sweep or args.ensemble or args.orbit_fit or args.configs or args.grid
-            or args.bootstrap or args.infer) and args.gpus != 1:
+            or args.bootstrap or args.infer or args.time_to_fit) and args.gpus != 1:
         print("bench.py measures one GPU only (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.sweep:
@@ -550,6 +554,10 @@ def main():
         return
     if args.bootstrap:
         print(json.dumps(bootstrap()), flush=True)
+        return
+    if args.time_to_fit:
+        from paper_2511_22468_amd import fit
+        print(json.dumps(fit.run()), flush=True)
         return
     if args.infer:
         from paper_2511_22468_amd import infer
