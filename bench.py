@@ -570,7 +570,7 @@ def main():
     if args.profile_run:
         args.n_steps, args.steps, args.warmup, args.no_cpu_baseline = 20, 1, 0, True
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 

@@ -365,7 +365,7 @@ def test_pipeline_gradient_matches_oracle(dnb, prec, K):
     if prec == "fp64":
         np.testing.assert_allclose(gg.cpu().numpy(), g_ref, rtol=tol)
     else:
-        # judged on theta * dL/dtheta against its largest component: the host-mass
+        # compared on theta * dL/dtheta against its largest component: the host-mass
         # sensitivities are ~100x smaller than the t_end and M_Plummer ones
         sg, sr = gg.cpu().numpy() * theta, g_ref * theta
         assert np.abs(sg - sr).max() <= tol * np.abs(sr).max()
