@@ -10,6 +10,8 @@
   differences (h = 1e-4 relative) of the same FP64 GPU forward model.
 * N=65536: FP32C vs FP64-on-GPU vs oracle accelerations on 1024 sampled
   particles, and FP32C vs FP64 final positions after 1000 steps.
+* N=65536, the headline workload's pipeline gradient over 20 steps: FP32C vs
+  the FP64 path.
 """
 import numpy as np
 import pytest
@@ -296,3 +298,40 @@ def test_shard_shaped_vjp_rows_n65536():
         err = np.sqrt(((to_host(g)[rows - i0] - ref) ** 2).sum(1)) / scale
         assert err.max() <= tol, err.max()
         c.close()
+
+
+def test_headline_workload_gradient_n65536_fp32c_against_fp64():
+    """The headline workload's pipeline gradient in its own launch configuration
+    (N = 65536, FP32C pair terms, a tape every step, MMD against a 4096-point mock
+    stream; the seeds and parameters of the benchmark) over 20 steps, where the
+    map is still linear on the scale of FP32 rounding (the gradient of the bound
+    core grows by e every ~17 steps), against the FP64 path on the GPU, which the
+    oracle pins at smaller N."""
+    import paper_2511_22468_amd as pk
+    from paper_2511_22468_amd import engine
+    from paper_2511_22468_amd.pipeline import StreamModel, make_target
+    n, T = 65536, 20
+    say(f"[cfg] headline workload gradient N={n} T={T}: FP32C vs FP64")
+    theta = torch.tensor([T * pk.myr(0.5), 1.0e5, 1.0e12, 6.5e10], dtype=torch.float64,
+                         device="cuda")
+    pot = engine.Potential(eps=5e-4)
+    ctx = {p: engine.Context(n, p) for p in ("fp64", "fp32c")}
+    xt, zt = plummer_unit(4096, 41)
+    theta_t = theta * torch.tensor([1.0, 0.8, 1.05, 0.95], dtype=torch.float64, device="cuda")
+    target = make_target(ctx["fp64"], to_dev(xt), to_dev(zt), theta_t, T, pot=pot)
+    xi, zeta = plummer_unit(n, 40)
+    res = {}
+    for p, c in ctx.items():
+        model = StreamModel(c, to_dev(xi), to_dev(zeta), target, T, pot=pot, h=0.2,
+                            ckpt_every=1)
+        L, g = model.loss_and_grad(theta)
+        res[p] = (L.item(), (g * theta).cpu().numpy())
+    (L32, s32), (L64, s64) = res["fp32c"], res["fp64"]
+    d = np.abs(s32 - s64).max() / np.abs(s64).max()
+    say(f"  loss FP32C {L32:.9e} FP64 {L64:.9e}; theta*dL/dtheta max difference {d:.2e} "
+        f"of the largest component")
+    assert np.isfinite(s32).all() and np.isfinite(s64).all()
+    # after 20 steps MMD^2 is ~1.5e-7, a difference of kernel means of order 0.1-1,
+    # so the loss is also compared in absolute terms (measured 1e-13)
+    assert abs(L32 - L64) <= 1e-6 * abs(L64) + 1e-11
+    assert d <= 1e-3
