@@ -172,10 +172,11 @@ def sweep(prec, sizes=(1024, 4096, 8192, 16384, 65536), reps=20):
 
 
 def ensemble(B=512, n=4096, T=200, n_single=8):
-    """Training-set generation of the surrogate: B independent runs of n particles
-    (priors as for the surrogate), T kick-drift-kick steps, advanced as one batched
-    ensemble, against the same runs one system at a time (n_single of them, the
-    rate extrapolated).  Pair interactions per second of each."""
+    """A batched ensemble of the kind the surrogate's training set and the grid
+    search run: B independent runs of n particles (parameters drawn from the
+    priors), T kick-drift-kick steps, advanced as one batched ensemble, against
+    the same runs one system at a time (n_single of them, the rate extrapolated).
+    Pair interactions per second of each."""
     import torch
 
     from paper_2511_22468_amd import engine, gyr
@@ -506,8 +507,8 @@ def main():
                     help="kernel rates of the forward and VJP pair kernels at every workload "
                          "size (N = 1024 ... 65536), one JSON line")
     ap.add_argument("--ensemble", action="store_true",
-                    help="surrogate training-set generation (512 runs of N = 4096) as one "
-                         "batched ensemble vs one run at a time, one JSON line")
+                    help="512 runs of N = 4096 (parameters from the priors) as one batched "
+                         "ensemble vs one run at a time, one JSON line")
     ap.add_argument("--orbit-fit", action="store_true",
                     help="orbit fit of the progenitor: Levenberg-Marquardt from 1000 starts, "
                          "exact Hessian and Fisher covariance, one JSON line")
