@@ -170,8 +170,10 @@ dnb_status dnb_simulate_vjp(dnb_ctx* ctx, int64_t n, const double* mass, const d
  * tgt [3][m] (Sec. 2.2.1 and Fig. 2, step 4), with the Gaussian kernel
  * k(x, y) = exp(-|x - y|^2 / (2 h^2)) and the biased (V-statistic) estimate:
  *   L = mean_ij k(x_i,x_j) + mean_ab k(y_a,y_b) - 2 mean_ia k(x_i,y_a).
- * loss: device scalar.  gpos [3][n] (nullable): dL/dpos.  FP64 throughout.
- * Requires n, m <= max_n of the context and h > 0. */
+ * loss: device scalar.  gpos [3][n] (nullable): dL/dpos.  FP64 throughout; each
+ * kernel value is within 0.6 ulp of exp at the rounded argument, and a NaN
+ * position makes the loss NaN.  Requires n, m <= max_n of the context and
+ * h > 0. */
 dnb_status dnb_mmd(dnb_ctx* ctx, int64_t n, const double* pos, int64_t m, const double* tgt,
                    double h, double* loss, double* gpos, void* stream);
 
