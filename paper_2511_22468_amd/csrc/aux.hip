@@ -11,10 +11,11 @@ namespace dnb {
 // c = log2(e) / (2 h^2)).  x = n + f with n = rint(x) and |f| <= 1/2; 2^f =
 // e^(f ln 2) is summed from its Taylor series to degree 13, whose first omitted
 // term, (ln 2 / 2)^14 / 14!, is below 5e-18; ldexp then scales by 2^n, with
-// gradual underflow to exactly 0 for any n (v_ldexp_f64 takes the whole int
-// range, and the conversion of n saturates).  Maximum error 0.57 ulp against a
-// long-double 2^x over [-1080, 0].  A NaN argument gives NaN; so does -inf,
-// which would need |p - q| beyond 1e154.
+// gradual underflow to exactly 0.  n is clamped at -2000 before its conversion
+// to int (2^-2000 p is 0 in FP64), which keeps the conversion defined for any
+// finite x.  Maximum error 0.57 ulp against a long-double 2^x over [-1080, 0].
+// A NaN argument gives NaN through p; so does -inf, which would need |p - q|
+// beyond 1e154.
 struct Exp2Taylor { double c[14]; };
 constexpr Exp2Taylor exp2_taylor() {
     constexpr double LN2 = 0.69314718055994530942;
@@ -31,7 +32,7 @@ __device__ __forceinline__ double exp2_nonpos(double x) {
     double p = T.c[13];
 #pragma unroll
     for (int k = 12; k >= 0; --k) p = fma(p, f, T.c[k]);
-    return ldexp(p, (int)n);
+    return ldexp(p, (int)fmax(n, -2000.0));
 }
 
 // For targets p_i and sources q_j of one slice:
