@@ -21,8 +21,10 @@ integrate  kick-drift-kick (Velocity-Verlet) integrator
 mmd        Gaussian-kernel maximum mean discrepancy and its gradient
 adjoint    discrete adjoint of the integrator (exact gradient of the map)
 pipeline   back-integration of the progenitor, IC assembly, forward model
-grid       orbit-frame density grid
-mlp        4-256-256-256-2048 surrogate network with BF16 emulation
+surrogate  orbit-frame density grid and the 4-256-256-256-2048 surrogate network
+           with BF16 emulation, GELU, MSE and Adam
+orbitfit   orbit-aligned frame, track observables, chi^2, its Hessian and
+           Levenberg-Marquardt
 
 Parity unpinned: absolute energy-drift levels and stream morphology have no
 value in the paper to compare against (its figures are not available), so

@@ -11,6 +11,7 @@ import pytest
 import torch
 
 from oracle import adjoint as oadj, forces as of, integrate as oint, mmd as ommd
+from oracle import pipeline as opipe
 from oracle.forces import Potential as OPot
 from synth import plummer_unit, sample_rows
 
@@ -333,9 +334,10 @@ def test_place_plummer_and_adjoint(dnb):
     w = np.array([1.0, 2.0, 3.0, 4.0, 5.0, 6.0])
     c = ctx["fp64"]
     pos, vel, mass = c.place_plummer(torch.tensor(w, device="cuda"), to_dev(xi), to_dev(zeta), 3e4, 0.01)
-    np.testing.assert_allclose(to_host(pos), w[:3] + 0.01 * xi, rtol=1e-15)
-    np.testing.assert_allclose(to_host(vel), w[3:] + np.sqrt(G * 3e4 / 0.01) * zeta, rtol=1e-14)
-    np.testing.assert_allclose(mass.cpu().numpy(), 3e4 / n, rtol=1e-15)
+    x0, v0, m0 = opipe.assemble_ic(w[:3], w[3:], 3e4, xi, zeta, G, 0.01)
+    np.testing.assert_allclose(to_host(pos), x0, rtol=1e-15)
+    np.testing.assert_allclose(to_host(vel), v0, rtol=1e-14)
+    np.testing.assert_allclose(mass.cpu().numpy(), m0, rtol=1e-15)
     rng = np.random.default_rng(15)
     gp, gv, gm = rng.normal(size=(n, 3)), rng.normal(size=(n, 3)), rng.normal(size=n)
     gw, gM = c.place_plummer_vjp(to_dev(zeta), 3e4, 0.01, to_dev(gp), to_dev(gv), to_dev(gm))
@@ -347,7 +349,6 @@ def test_place_plummer_and_adjoint(dnb):
 @pytest.mark.parametrize("prec,K", [("fp64", 1), ("fp64", 7), ("fp32c", 1)])
 def test_pipeline_gradient_matches_oracle(dnb, prec, K):
     """Fig. 2 steps 2-4 end to end: loss and dL/dtheta against the oracle pipeline."""
-    from oracle import pipeline as opipe
     from paper_2511_22468_amd.pipeline import StreamModel
     pk, engine, ctx = dnb
     say(f"[pipeline] n=300 T=30 K={K} prec={prec}")
