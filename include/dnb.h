@@ -126,9 +126,10 @@ dnb_status dnb_step(dnb_ctx* ctx, int64_t n, double* pos, double* vel, const dou
 
 /* Number of doubles of the checkpoint tape that dnb_simulate writes for
  * (n, n_steps, ckpt_every): for each of the ceil(n_steps / ckpt_every)
- * checkpoints the state (6n), the staging centre (4) and the internal (pair)
- * acceleration (3n), plus the internal acceleration at the final positions
- * (3n); 0 for n_steps = 0. */
+ * checkpoints the state (6n), two FP32C staging centres (8: those of the
+ * checkpoint's positions and of the positions one step later) and the internal
+ * (pair) acceleration (3n), plus the internal acceleration at the final
+ * positions (3n); 0 for n_steps = 0. */
 int64_t dnb_tape_doubles(int64_t n, int64_t n_steps, int64_t ckpt_every);
 
 /* Number of doubles of the segment workspace that dnb_simulate_vjp needs:
@@ -153,13 +154,25 @@ dnb_status dnb_simulate(dnb_ctx* ctx, int64_t n, double* pos, double* vel, const
  * then the sweep runs newest step first with one pair-VJP per step.
  *
  * Inputs: the same n, mass, pot, dt, n_steps, ckpt_every and tape as the
- * forward call; pos_T [3][n], the final positions the forward call produced;
- * gpos_T, gvel_T [3][n], the loss cotangents of the final state (gvel_T may be
- * NULL for zero).  workspace holds dnb_vjp_workspace_doubles(n, ckpt_every).
- * Outputs: gpos_0, gvel_0 [3][n]; gmass [n] (nullable): dL/dm_k; gparams [4]
- * (device): dL/dm_nfw, dL/dm_mn, dL/ddt, and sum_k m_k dL/dm_k (the derivative
- * with respect to a common log-scale of all particle masses, which is what a
- * progenitor-mass parameter needs).  Outputs must not alias inputs. */
+ * forward call; pos_T [3][n], the final positions the forward call produced
+ * (the position array that call moved in place); gpos_T, gvel_T [3][n], the
+ * loss cotangents of the final state (gvel_T may be NULL for zero).  workspace
+ * holds dnb_vjp_workspace_doubles(n, ckpt_every).  Outputs: gpos_0, gvel_0
+ * [3][n]; gmass [n] (nullable): dL/dm_k; gparams [4] (device): dL/dm_nfw,
+ * dL/dm_mn, dL/ddt, and sum_k m_k dL/dm_k (the derivative with respect to a
+ * common log-scale of all particle masses, which is what a progenitor-mass
+ * parameter needs).  Outputs must not alias inputs.
+ *
+ * Call sequence: the context records each tape that dnb_simulate writes (its
+ * address, the position and mass arrays, n, n_steps, ckpt_every, dt and pot;
+ * the 16 most recent).  With n_steps > 0 this call returns DNB_ERR_STATE,
+ * enqueueing nothing, unless tape is such a record and every one of those
+ * arguments matches it.  A later dnb_simulate, dnb_step or dnb_place_plummer
+ * on this context that writes the recorded position array, or a dnb_simulate
+ * that writes a tape over the recorded one, retires the record (the library
+ * cannot see writes made by other code).  DNB_ERR_STATE is also returned when
+ * the allocation holding workspace or tape ends before the length these
+ * arguments need (checked through the HIP runtime's allocation ranges). */
 dnb_status dnb_simulate_vjp(dnb_ctx* ctx, int64_t n, const double* mass, const dnb_pot* pot,
                             double dt, int64_t n_steps, int64_t ckpt_every, const double* tape,
                             const double* pos_T, const double* gpos_T, const double* gvel_T,
@@ -246,7 +259,9 @@ int64_t dnb_batch_tape_doubles(int64_t batch, int64_t n, int64_t n_steps);
  * be NULL).  workspace: 4 batch n doubles.  Outputs gpos_0, gvel_0 [batch][3][n]
  * and gparams [batch][4] (device) = per member (dL/dm_nfw, dL/dm_mn, dL/ddt,
  * sum_k m_k dL/dm_k).  No per-particle mass gradient.  Outputs must not alias
- * inputs. */
+ * inputs.  As for dnb_simulate_vjp, the tape must be one the context recorded
+ * (here with the batch size and the parameter table's contents) and pos_T the
+ * position array of that forward call, else DNB_ERR_STATE. */
 dnb_status dnb_simulate_batch_vjp(dnb_ctx* ctx, int64_t batch, int64_t n, const double* mass,
                                   const double* params, int64_t n_steps, const double* tape,
                                   const double* pos_T, const double* gpos_T, const double* gvel_T,

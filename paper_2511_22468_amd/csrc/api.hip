@@ -91,6 +91,115 @@ dnb_status check_dev(const void* p, const char* name, const char* fn, bool nulla
     return DNB_OK;
 }
 
+// A device buffer must hold `bytes` bytes from p to the end of its allocation.
+// The allocation's range is known to the HIP runtime; a pointer it does not know
+// (for instance managed memory) is not checked.
+dnb_status check_extent(const void* p, size_t bytes, const char* name, const char* fn) {
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess) {
+        (void)hipGetLastError();
+        return DNB_OK;
+    }
+    const size_t avail = size - (size_t)((const char*)p - (const char*)base);
+    if (bytes > avail)
+        return fail(DNB_ERR_STATE, "%s: %s needs %zu bytes but only %zu remain in its allocation",
+                    fn, name, bytes, avail);
+    return DNB_OK;
+}
+
+// Tape descriptors (dnb_ctx::tapes).  A dnb_simulate or dnb_step that moves the
+// positions pos in place makes every tape whose final positions are pos stale;
+// a tape written over another one's memory replaces it.
+void forget_tapes(dnb_ctx* c, const double* pos, const double* tape, int64_t tape_len) {
+    for (int k = 0; k < c->tape_count; ++k) {
+        dnb_ctx::TapeDesc& d = c->tapes[k];
+        if (!d.tape) continue;
+        const int64_t dl = d.batch ? dnb_batch_tape_doubles(d.batch, d.n, d.n_steps)
+                                   : dnb_tape_doubles(d.n, d.n_steps, d.ckpt_every);
+        const bool overlap = tape && tape < d.tape + dl && d.tape < tape + tape_len;
+        if (d.pos == pos || overlap) d.tape = nullptr;
+    }
+}
+
+void remember_tape(dnb_ctx* c, const dnb_ctx::TapeDesc& d) {
+    c->tapes[c->tape_head] = d;
+    c->tape_head = (c->tape_head + 1) % dnb_ctx::TAPE_RING;
+    if (c->tape_count < dnb_ctx::TAPE_RING) ++c->tape_count;
+}
+
+dnb_ctx::TapeDesc single_desc(const double* tape, const double* pos, const double* mass,
+                              int64_t n, int64_t T, int64_t K, double dt, const dnb_pot& p) {
+    return dnb_ctx::TapeDesc{tape, pos, mass, n, T, K, dt,
+                             {p.G, p.eps, p.m_nfw, p.rs_nfw, p.m_mn, p.a_mn, p.b_mn}, 0, 0};
+}
+
+// FNV-1a over the bytes of a batch's host parameter table [batch][8].
+uint64_t table_hash(const double* params, int64_t batch) {
+    const unsigned char* b = (const unsigned char*)params;
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < sizeof(double) * 8 * (size_t)batch; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// The descriptor of a batched tape, checked against the arguments of
+// dnb_simulate_batch_vjp.
+dnb_status match_batch_tape(dnb_ctx* c, const double* tape, const double* pos_T,
+                            const double* mass, int64_t batch, int64_t n, int64_t T,
+                            const double* params, const char* fn) {
+    for (int k = 0; k < c->tape_count; ++k) {
+        const dnb_ctx::TapeDesc& d = c->tapes[k];
+        if (!d.tape || d.tape != tape) continue;
+        if (d.batch != batch || d.n != n || d.n_steps != T)
+            return fail(DNB_ERR_STATE,
+                        "%s: the tape was written for batch = %lld, n = %lld, n_steps = %lld "
+                        "(called with %lld, %lld, %lld)", fn, (long long)d.batch, (long long)d.n,
+                        (long long)d.n_steps, (long long)batch, (long long)n, (long long)T);
+        if (d.pos != pos_T)
+            return fail(DNB_ERR_STATE, "%s: pos_T is not the position array the tape's forward "
+                        "run moved", fn);
+        if (d.mass != mass || d.table != table_hash(params, batch))
+            return fail(DNB_ERR_STATE, "%s: mass or the parameter table differ from the tape's "
+                        "forward run", fn);
+        return DNB_OK;
+    }
+    return fail(DNB_ERR_STATE, "%s: no current tape at this address (no dnb_simulate_batch wrote "
+                "it on this context, or a later call moved its final positions or overwrote it)",
+                fn);
+}
+
+// The descriptor of `tape`, checked against the arguments of a reverse sweep.
+dnb_status match_tape(dnb_ctx* c, const double* tape, const double* pos_T, const double* mass,
+                      int64_t n, int64_t T, int64_t K, double dt, const dnb_pot& p,
+                      const char* fn) {
+    const double pv[7] = {p.G, p.eps, p.m_nfw, p.rs_nfw, p.m_mn, p.a_mn, p.b_mn};
+    for (int k = 0; k < c->tape_count; ++k) {
+        const dnb_ctx::TapeDesc& d = c->tapes[k];
+        if (!d.tape || d.tape != tape) continue;
+        if (d.batch != 0)
+            return fail(DNB_ERR_STATE, "%s: the tape was written by dnb_simulate_batch", fn);
+        if (d.n != n || d.n_steps != T || d.ckpt_every != K)
+            return fail(DNB_ERR_STATE,
+                        "%s: the tape was written for n = %lld, n_steps = %lld, ckpt_every = %lld "
+                        "(called with %lld, %lld, %lld)", fn, (long long)d.n,
+                        (long long)d.n_steps, (long long)d.ckpt_every, (long long)n,
+                        (long long)T, (long long)K);
+        if (d.pos != pos_T)
+            return fail(DNB_ERR_STATE, "%s: pos_T is not the position array the tape's forward "
+                        "run moved", fn);
+        if (d.mass != mass || d.dt != dt || std::memcmp(d.pot, pv, sizeof pv) != 0)
+            return fail(DNB_ERR_STATE, "%s: mass, dt or pot differ from the tape's forward run",
+                        fn);
+        return DNB_OK;
+    }
+    return fail(DNB_ERR_STATE, "%s: no current tape at this address (no dnb_simulate wrote it on "
+                "this context, or a later dnb_simulate/dnb_step moved its final positions or "
+                "overwrote it)", fn);
+}
+
 // Event pool of dnb_profile: one (start, stop) pair per profiled launch.
 struct Prof {
     bool on = false;
@@ -131,16 +240,20 @@ hipError_t profiled(dnb_ctx* c, int kind, hipStream_t st, F launch) {
     } while (0)
 
 // Tape of one integration, in order: the states (x, v) at the checkpoints
-// [n_ckpt][6][n], the staging centres [n_ckpt][4], the internal accelerations
+// [n_ckpt][6][n], the staging centres [n_ckpt][8], the internal accelerations
 // at the checkpoints [n_ckpt][3][n], and the internal acceleration at the final
 // positions [3][n].  The reverse sweep reads the accelerations instead of
-// summing them again in the pair VJP.
+// summing them again in the pair VJP.  A checkpoint's two centres (4 doubles
+// each) are the ones the run staged the checkpoint's positions with and the
+// positions one step later: with them a recomputation from the checkpoint
+// repeats the run's FP32 staging exactly.
 struct Tape {
     double* base;
     int64_t n, n_ckpt;
     double* state(int64_t c) const { return base + c * 6 * n; }
-    double* centre(int64_t c) const { return base + n_ckpt * 6 * n + 4 * c; }
-    double* aint(int64_t c) const { return base + n_ckpt * (6 * n + 4) + c * 3 * n; }
+    double* centre(int64_t c) const { return base + n_ckpt * 6 * n + 8 * c; }
+    double* centre_next(int64_t c) const { return centre(c) + 4; }
+    double* aint(int64_t c) const { return base + n_ckpt * (6 * n + 8) + c * 3 * n; }
     double* aint_final() const { return aint(n_ckpt); }
 };
 
@@ -151,15 +264,18 @@ dnb_status run_forward(dnb_ctx* c, int64_t n, double* pos, double* vel, const do
                        hipStream_t st) {
     if (T == 0) return DNB_OK;
     const int nb = (int)cdiv(n, BS);
-    double* cp[2] = {c->cpart, c->cpart + 4 * c->nbmax};
+    double* cp[2] = {c->cpart, c->cpart + REC * c->nbmax};
     HIP_TRY(launch_mass_info(c, mass, n, st));
-    if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(pos, n, cp[0], st));
+    if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(pos, n, cp[0], st, nullptr, vel, dt));
     HIP_TRY(launch_stage(c, pos, mass, n, cp[0], nb, nullptr, tape ? tape->centre(0) : nullptr, st));
     int q = 0;
+    const bool f32 = c->prec == DNB_FP32C;
     for (int64_t s = 0; s <= T; ++s) {
         HIP_TRY(profiled(c, 0, st, [&] { return launch_pair_fwd(c, n, p.eps, st); }));
+        if (f32) HIP_TRY(launch_fwd_reduce(c, n, mass, p.G, st));
         FwdArgs a{};
         a.n = n; a.mass = mass; a.pot = p; a.dt = dt;
+        if (f32) { a.ared = c->ared; a.arec = c->arec; a.nr = red_blocks(n); }
         a.x = pos; a.x_out = pos; a.v = vel; a.vh = c->vh; a.with_ext = 1;
         a.cpart_in = cp[q]; a.cpart_out = cp[1 - q]; a.nb_in = nb;
         if (tape && s < T && s % K == 0) {
@@ -168,6 +284,7 @@ dnb_status run_forward(dnb_ctx* c, int64_t n, double* pos, double* vel, const do
         }
         if (tape && s == T) a.aint_out = tape->aint_final();
         if (tape && s + 1 < T && (s + 1) % K == 0) a.tape_centre_next = tape->centre((s + 1) / K);
+        if (tape && s < T && s % K == 0) a.tape_centre_cur = tape->centre_next(s / K);
         KdkMode mode = (s == 0) ? KDK_FIRST : (s == T ? KDK_LAST : KDK_MID);
         HIP_TRY(launch_kdk(c, mode, a, st));
         q = 1 - q;
@@ -209,16 +326,20 @@ dnb_status dnb_create(dnb_ctx** out, int64_t max_n, dnb_prec prec) {
     struct A { void** p; size_t bytes; } allocs[] = {
         {&c->js, sizeof(double4) * npadmax},
         {&c->part, 32 * (size_t)c->slice_rows},
-        {(void**)&c->cpart, sizeof(double) * 8 * c->nbmax},
+        {(void**)&c->cpart, sizeof(double) * 2 * REC * c->nbmax},
         {(void**)&c->vh, sizeof(double) * 3 * npadmax},
         {&c->jsv, sizeof(double4) * 2 * npadmax},
         {&c->partv, 64 * (size_t)c->slice_rows},
-        {(void**)&c->cpartv, sizeof(double) * 8 * c->nbmax},
+        {(void**)&c->cpartv, sizeof(double) * 2 * REC * c->nbmax},
         {(void**)&c->wscale, sizeof(double) * 2},
         {(void**)&c->muni, sizeof(float) * 2 * DNB_BATCH_MAX},
         {(void**)&c->bparams, sizeof(double) * 8 * DNB_BATCH_MAX},
         {(void**)&c->bwscale, sizeof(double) * 2 * DNB_BATCH_MAX},
         {(void**)&c->red, sizeof(double) * 8 * (c->nbmax + 8)},
+        {(void**)&c->ared, sizeof(double) * 3 * npadmax},
+        {(void**)&c->gred, sizeof(double) * 4 * npadmax},
+        {(void**)&c->arec, sizeof(double) * 4 * (cdiv(npadmax, RT) + DNB_BATCH_MAX)},
+        {(void**)&c->grec, sizeof(double) * 4 * (cdiv(npadmax, RT) + DNB_BATCH_MAX)},
     };
     for (auto& a : allocs) {
         if (hipMalloc(a.p, a.bytes) != hipSuccess) {
@@ -241,7 +362,7 @@ void dnb_destroy(dnb_ctx* c) {
         delete pf;
     }
     void* ps[] = {c->js, c->part, c->cpart, c->vh, c->jsv, c->partv, c->cpartv, c->wscale, c->muni,
-                  c->bparams, c->bwscale, c->red};
+                  c->bparams, c->bwscale, c->red, c->ared, c->gred, c->arec, c->grec};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     delete c;
@@ -315,7 +436,7 @@ dnb_status dnb_accelerations_vjp(dnb_ctx* c, int64_t n, const double* pos, const
     hipStream_t st = (hipStream_t)stream;
     Pot p = to_pot(*pot);
     const int nb = (int)cdiv(n, BS);
-    double* cpv[2] = {c->cpartv, c->cpartv + 4 * c->nbmax};
+    double* cpv[2] = {c->cpartv, c->cpartv + REC * c->nbmax};
     HIP_TRY(launch_mass_info(c, mass, n, st));
     if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(pos, n, cpv[0], st, w));
     HIP_TRY(launch_rev_stage(c, n, pos, mass, w, cpv[0], nb, cpv[1], c->wscale, st));
@@ -330,7 +451,7 @@ dnb_status dnb_accelerations_vjp(dnb_ctx* c, int64_t n, const double* pos, const
 int64_t dnb_tape_doubles(int64_t n, int64_t n_steps, int64_t ckpt_every) {
     if (n < 1 || n_steps < 0 || ckpt_every < 1) return -1;
     if (n_steps == 0) return 0;
-    return cdiv(n_steps, ckpt_every) * (9 * n + 4) + 3 * n;
+    return cdiv(n_steps, ckpt_every) * (9 * n + 8) + 3 * n;
 }
 
 int64_t dnb_vjp_workspace_doubles(int64_t n, int64_t ckpt_every) {
@@ -355,6 +476,7 @@ static dnb_status check_sim_args(dnb_ctx* c, int64_t n, const void* pos, const v
 dnb_status dnb_step(dnb_ctx* c, int64_t n, double* pos, double* vel, const double* mass,
                     const dnb_pot* pot, double dt, void* stream) {
     CHECK(check_sim_args(c, n, pos, vel, mass, pot, dt, 1, 1, "dnb_step"));
+    forget_tapes(c, pos, nullptr, 0);
     return run_forward(c, n, pos, vel, mass, to_pot(*pot), dt, 1, 1, nullptr, (hipStream_t)stream);
 }
 
@@ -364,9 +486,15 @@ dnb_status dnb_simulate(dnb_ctx* c, int64_t n, double* pos, double* vel, const d
     const char* fn = "dnb_simulate";
     CHECK(check_sim_args(c, n, pos, vel, mass, pot, dt, n_steps, ckpt_every, fn));
     CHECK(check_dev(tape, "tape", fn, true));
+    const int64_t tl = dnb_tape_doubles(n, n_steps, ckpt_every);
+    if (tape && n_steps > 0) CHECK(check_extent(tape, sizeof(double) * tl, "tape", fn));
+    forget_tapes(c, pos, tape, tape ? tl : 0);
     Tape tp{tape, n, cdiv(n_steps, ckpt_every)};
-    return run_forward(c, n, pos, vel, mass, to_pot(*pot), dt, n_steps, ckpt_every,
-                       tape ? &tp : nullptr, (hipStream_t)stream);
+    CHECK(run_forward(c, n, pos, vel, mass, to_pot(*pot), dt, n_steps, ckpt_every,
+                      tape ? &tp : nullptr, (hipStream_t)stream));
+    if (tape && n_steps > 0)
+        remember_tape(c, single_desc(tape, pos, mass, n, n_steps, ckpt_every, dt, *pot));
+    return DNB_OK;
 }
 
 dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb_pot* pot,
@@ -386,6 +514,13 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
     if (n_steps > 0) CHECK(check_dev(tape, "tape", fn));
     if (gpos_0 == gpos_T || gvel_0 == gvel_T || gpos_0 == gvel_0)
         return fail(DNB_ERR_ARG, "%s: outputs must not alias inputs", fn);
+    CHECK(check_extent(workspace, sizeof(double) * dnb_vjp_workspace_doubles(n, ckpt_every),
+                       "workspace", fn));
+    if (n_steps > 0) {
+        CHECK(check_extent(tape, sizeof(double) * dnb_tape_doubles(n, n_steps, ckpt_every), "tape",
+                           fn));
+        CHECK(match_tape(c, tape, pos_T, mass, n, n_steps, ckpt_every, dt, *pot, fn));
+    }
     hipStream_t st = (hipStream_t)stream;
     const Pot p = to_pot(*pot);
     const int64_t T = n_steps, K = ckpt_every;
@@ -415,20 +550,26 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
             if (m % K == 0) return tp.aint(m / K);
             return seg_a + (m % K) * 3 * n;
         };
-        double* cpf[2] = {c->cpart, c->cpart + 4 * c->nbmax};
+        double* cpf[2] = {c->cpart, c->cpart + REC * c->nbmax};
         // Positions x_{n0+1} .. x_{n1-1} of segment cs and their internal
-        // accelerations, from its checkpoint, bitwise as in the forward run.
+        // accelerations, from its checkpoint, bitwise as in the forward run (the
+        // first two stagings take the centres the run stored with the checkpoint;
+        // from then on the centres follow from the recomputed positions as they
+        // did in the run).
         auto recompute = [&](int64_t cs) -> dnb_status {
             const int64_t n0 = cs * K, n1 = (n0 + K < T) ? n0 + K : T;
             if (n1 - n0 < 2) return DNB_OK;
             double* x0 = tp.state(cs);
-            if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(x0, n, cpf[0], st));
             HIP_TRY(launch_stage(c, x0, mass, n, nullptr, 0, tp.centre(cs), nullptr, st));
             int q = 0;
             for (int64_t s = n0; s <= n1 - 1; ++s) {
                 double* xc = (s == n0) ? x0 : seg + (s - n0) * 3 * n;
                 HIP_TRY(profiled(c, 0, st, [&] { return launch_pair_fwd(c, n, p.eps, st); }));
                 FwdArgs a{};
+                if (c->prec == DNB_FP32C) {
+                    HIP_TRY(launch_fwd_reduce(c, n, mass, p.G, st));
+                    a.ared = c->ared; a.arec = c->arec; a.nr = red_blocks(n);
+                }
                 a.n = n; a.mass = mass; a.pot = p; a.dt = dt; a.with_ext = 1;
                 a.x = xc;
                 a.aint_out = (s == n0) ? nullptr : seg_a + (s - n0) * 3 * n;
@@ -440,18 +581,26 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
                 a.v = (s == n0) ? x0 + 3 * n : nullptr;
                 a.vh = vrec;
                 a.cpart_in = cpf[q]; a.cpart_out = cpf[1 - q]; a.nb_in = nb;
+                if (s == n0) a.centre_override = tp.centre_next(cs);
                 HIP_TRY(launch_kdk(c, s == n0 ? KDK_FIRST : KDK_MID, a, st));
                 q = 1 - q;
             }
             return DNB_OK;
         };
-        double* cpv[2] = {c->cpartv, c->cpartv + 4 * c->nbmax};
+        double* cpv[2] = {c->cpartv, c->cpartv + REC * c->nbmax};
         int q = 0;
+        int64_t cur = -1;
+        // x_{T-1} first: its displacement from x_T centres the first staging of
+        // the sweep
+        if ((T - 1) % K != 0) {
+            CHECK(recompute((T - 1) / K));
+            cur = (T - 1) / K;
+        }
         if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(pos_T, n, cpv[0], st, lv));
-        HIP_TRY(launch_rev_stage(c, n, pos_T, mass, lv, cpv[0], nb, cpv[1], c->wscale, st));
+        HIP_TRY(launch_rev_stage(c, n, pos_T, mass, lv, cpv[0], nb, cpv[1], c->wscale, st,
+                                 get_pos(T - 1)));
         q = 1;
         int wq = 0;   // c->wscale[wq]: scale of the currently staged cotangent
-        int64_t cur = -1;
         for (int64_t m = T; m >= 0; --m) {
             if (m > 0) {
                 const int64_t cs = (m - 1) / K;
@@ -463,6 +612,10 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
             const double* xm = get_pos(m);
             HIP_TRY(profiled(c, 1, st, [&] { return launch_pair_vjp(c, n, with_mass, p.eps, st); }));
             RevArgs r{};
+            if (c->prec == DNB_FP32C) {
+                HIP_TRY(launch_vjp_reduce(c, n, p.G, with_mass, c->wscale + wq, st));
+                r.gred = c->gred; r.grec = c->grec; r.nr = red_blocks(n);
+            }
             r.n = n; r.mass = mass; r.pot = p; r.dt = dt;
             r.coef = (m == T || m == 0) ? 0.5 * dt : dt;
             r.x_n = xm;
@@ -589,7 +742,13 @@ dnb_status dnb_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* pos,
     CHECK(check_dev(tape, "tape", fn, true));
     hipStream_t st = (hipStream_t)stream;
     CHECK(put_batch_params(c, batch, params, true, st, fn));
+    const int64_t tl = dnb_batch_tape_doubles(batch, n, n_steps);
+    if (tape && n_steps > 0) CHECK(check_extent(tape, sizeof(double) * tl, "tape", fn));
+    forget_tapes(c, pos, tape, tape ? tl : 0);
     HIP_TRY(launch_simulate_batch(c, batch, n, pos, vel, mass, c->bparams, n_steps, tape, st));
+    if (tape && n_steps > 0)
+        remember_tape(c, dnb_ctx::TapeDesc{tape, pos, mass, n, n_steps, 1, 0.0, {}, batch,
+                                           table_hash(params, batch)});
     return DNB_OK;
 }
 
@@ -618,6 +777,10 @@ dnb_status dnb_simulate_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const do
         return fail(DNB_ERR_ARG, "%s: outputs must not alias inputs", fn);
     hipStream_t st = (hipStream_t)stream;
     CHECK(put_batch_params(c, batch, params, true, st, fn, true));
+    CHECK(check_extent(workspace, sizeof(double) * 4 * n * batch, "workspace", fn));
+    CHECK(check_extent(tape, sizeof(double) * dnb_batch_tape_doubles(batch, n, n_steps), "tape",
+                       fn));
+    CHECK(match_batch_tape(c, tape, pos_T, mass, batch, n, n_steps, params, fn));
     const size_t vec = sizeof(double) * 3 * n * batch;
     HIP_TRY(hipMemcpyAsync(gpos_0, gpos_T, vec, hipMemcpyDeviceToDevice, st));
     if (gvel_T) HIP_TRY(hipMemcpyAsync(gvel_0, gvel_T, vec, hipMemcpyDeviceToDevice, st));
@@ -712,6 +875,7 @@ dnb_status dnb_place_plummer_batch(dnb_ctx* c, int64_t batch, int64_t n, const d
     CHECK(check_dev(pos, "pos", fn));
     CHECK(check_dev(vel, "vel", fn));
     CHECK(check_dev(mass, "mass", fn));
+    forget_tapes(c, pos, nullptr, 0);
     HIP_TRY(launch_place_batch(batch, n, w, xi, zeta, m_tot, a_p, G, pos, vel, mass,
                                (hipStream_t)stream));
     return DNB_OK;
@@ -768,6 +932,7 @@ dnb_status dnb_place_plummer(dnb_ctx* c, int64_t n, const double* w, const doubl
     CHECK(check_dev(pos, "pos", fn));
     CHECK(check_dev(vel, "vel", fn));
     CHECK(check_dev(mass, "mass", fn));
+    forget_tapes(c, pos, nullptr, 0);
     HIP_TRY(launch_place(n, w, xi, zeta, m_tot, a_p, G, pos, vel, mass, (hipStream_t)stream));
     return DNB_OK;
 }

@@ -41,7 +41,6 @@ __device__ inline Pot pot_row(const double* __restrict__ P) {
     return Pot{P[0], P[1], P[2], P[3], P[4], P[5], P[6]};
 }
 
-__device__ inline void bsum3(double (&v)[3], double* sh) { block_sum<3>(v, sh); }
 
 __global__ __launch_bounds__(BS) void k_batch_mass_info(const double* __restrict__ mass, int n,
                                                         float* __restrict__ muni) {
@@ -63,32 +62,23 @@ __global__ __launch_bounds__(BS) void k_batch_mass_info(const double* __restrict
     }
 }
 
-// Block sums of member positions (for the staging centre).  grid (nb, batch).
-__global__ __launch_bounds__(BS) void k_batch_block_sums(const double* __restrict__ pos, int n,
-                                                         int nb, double* __restrict__ cpart) {
+// Block records of member positions with the displacement dt v of the first
+// drift (for the staging centre, as k_block_sums).  grid (nb, batch).
+__global__ __launch_bounds__(BS) void k_batch_block_sums(const double* __restrict__ pos,
+                                                         const double* __restrict__ vel,
+                                                         const double* __restrict__ params,
+                                                         int n, int nb,
+                                                         double* __restrict__ cpart) {
     __shared__ double sh[3 * BS];
     const int b = blockIdx.y;
     const double* x = pos + (int64_t)b * 3 * n;
+    const double* v = vel + (int64_t)b * 3 * n;
+    const double dt = params[8 * b + 7];
     const int i = blockIdx.x * BS + threadIdx.x;
     const bool ok = i < n;
     const int k = ok ? i : 0;
-    double v[3] = {ok ? x[k] : 0.0, ok ? x[n + k] : 0.0, ok ? x[2 * n + k] : 0.0};
-    bsum3(v, sh);
-    if (threadIdx.x == 0) {
-        double* c = cpart + ((int64_t)b * nb + blockIdx.x) * 4;
-        c[0] = v[0]; c[1] = v[1]; c[2] = v[2]; c[3] = 0.0;
-    }
-}
-
-__device__ inline void member_centre(const double* __restrict__ cp, int nb, int n, double* sh,
-                                     double& cx, double& cy, double& cz) {
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int q = threadIdx.x; q < nb; q += BS) {
-        v[0] += cp[4 * q]; v[1] += cp[4 * q + 1]; v[2] += cp[4 * q + 2];
-    }
-    bsum3(v, sh);
-    const double inv = 1.0 / (double)n;   // as the single-system centre, so that members match it bitwise
-    cx = v[0] * inv; cy = v[1] * inv; cz = v[2] * inv;
+    write_block_sums(x[k], x[n + k], x[2 * n + k], dt * v[k], dt * v[n + k], dt * v[2 * n + k],
+                     ok, sh, cpart + (int64_t)b * nb * REC);
 }
 
 // Stage member positions relative to their centre.  grid (cdiv(nj, BS), batch).
@@ -99,7 +89,7 @@ __global__ __launch_bounds__(BS) void k_batch_stage(const double* __restrict__ p
     __shared__ double sh[3 * BS];
     const int b = blockIdx.y;
     double cx, cy, cz;
-    member_centre(cpart + (int64_t)b * g.nb * 4, g.nb, g.n, sh, cx, cy, cz);
+    centre_from(cpart + (int64_t)b * g.nb * REC, g.nb, g.n, sh, cx, cy, cz, false);
     const double* x = pos + (int64_t)b * 3 * g.n;
     const int i = blockIdx.x * BS + threadIdx.x;
     if (i < g.nj) {
@@ -153,8 +143,10 @@ __global__ __launch_bounds__(BS) void k_batch_kdk(double* __restrict__ pos,
                                                   double* __restrict__ cp_out,
                                                   float4* __restrict__ js,
                                                   double* __restrict__ tape_state,
-                                                  double* __restrict__ aint_out) {
-    __shared__ double sh[3 * BS];
+                                                  double* __restrict__ aint_out,
+                                                  const double* __restrict__ ared,
+                                                  const double* __restrict__ arec) {
+    __shared__ double sh[4 * BS];
     const int b = blockIdx.y;
     const int n = g.n;
     const double* P = params + 8 * b;
@@ -167,9 +159,17 @@ __global__ __launch_bounds__(BS) void k_batch_kdk(double* __restrict__ pos,
     const bool ok = i < n;
     const int k = ok ? i : 0;
     double cx = 0.0, cy = 0.0, cz = 0.0;
-    if (MODE != 2) member_centre(cp_in + (int64_t)b * g.nb * 4, g.nb, n, sh, cx, cy, cz);
-    double ax, ay, az;
-    pair_sum<true>(part + (int64_t)b * g.S * 6 * g.npad, g.S, g.npad, k, pot.G, ax, ay, az);
+    if (MODE != 2) centre_from(cp_in + (int64_t)b * g.nb * REC, g.nb, n, sh, cx, cy, cz, true);
+    // the member's reduced internal acceleration minus its net internal force
+    // per unit mass (as k_kdk in FP32C)
+    const int nr = red_blocks(n);
+    double tot[4];
+    rec_total(arec + (int64_t)b * nr * 4, nr, sh, tot);
+    const double inv_m = 1.0 / tot[3];
+    const double* ar = ared + (int64_t)b * 3 * n;
+    double ax = ar[k] - tot[0] * inv_m;
+    double ay = ar[n + k] - tot[1] * inv_m;
+    double az = ar[2 * n + k] - tot[2] * inv_m;
     if (aint_out && ok) {
         double* t = aint_out + (int64_t)b * 3 * n;
         t[i] = ax; t[n + i] = ay; t[2 * n + i] = az;
@@ -205,13 +205,39 @@ __global__ __launch_bounds__(BS) void k_batch_kdk(double* __restrict__ pos,
                                   (float)mass[(int64_t)b * n + i])
                     : make_float4(BFAR32, BFAR32, BFAR32, 0.f);
         }
-        double sv[3] = {ok ? xn : 0.0, ok ? yn : 0.0, ok ? zn : 0.0};
-        bsum3(sv, sh);
-        if (threadIdx.x == 0 && blockIdx.x < g.nb) {
-            double* c = cp_out + ((int64_t)b * g.nb + blockIdx.x) * 4;
-            c[0] = sv[0]; c[1] = sv[1]; c[2] = sv[2]; c[3] = 0.0;
-        }
+        write_block_sums(xn, yn, zn, xn - x0, yn - y0, zn - z0, ok, sh,
+                         cp_out + (int64_t)b * g.nb * REC);
     }
+}
+
+// Slice reductions of every member (the batched forms of k_fwd_reduce and
+// k_vjp_reduce, same arithmetic).  grid (cdiv(n, RT), batch).
+__global__ __launch_bounds__(BS) void k_batch_fwd_reduce(const float* __restrict__ part,
+                                                         BatchGeom g,
+                                                         const double* __restrict__ params,
+                                                         const double* __restrict__ mass,
+                                                         double* __restrict__ ared,
+                                                         double* __restrict__ arec) {
+    __shared__ double sh[3 * RG * RT];
+    const int64_t b = blockIdx.y;
+    const int64_t n = g.n;
+    const int nr = red_blocks(n);
+    fwd_reduce_block((const float2*)part + b * g.S * 3 * g.npad, g.S, g.npad, n, params[8 * b],
+                     mass + b * n, ared + b * 3 * n, arec + b * nr * 4, sh);
+}
+
+__global__ __launch_bounds__(BS) void k_batch_vjp_reduce(const float* __restrict__ part,
+                                                         BatchGeom g,
+                                                         const double* __restrict__ params,
+                                                         const double* __restrict__ wscale,
+                                                         int wq, double* __restrict__ gred,
+                                                         double* __restrict__ grec) {
+    __shared__ double sh[4 * RG * RT];
+    const int64_t b = blockIdx.y;
+    const int64_t n = g.n;
+    const int nr = red_blocks(n);
+    vjp_reduce_block((const float2*)part + b * g.S * 4 * g.npad, g.S, g.npad, n, params[8 * b],
+                     false, 1.0 / wscale[2 * b + wq], gred + b * 4 * n, grec + b * nr * 4, sh);
 }
 
 // Test-particle orbits of every member, one lane each (the batched form of k_orbit);
@@ -413,28 +439,32 @@ hipError_t launch_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* p
     const BatchGeom g = batch_geom(c, batch, n);
     float4* js = (float4*)c->js;
     float* part = (float*)c->part;
-    double* cp[2] = {c->cpart, c->cpart + 4 * c->nbmax};
+    double* cp[2] = {c->cpart, c->cpart + REC * c->nbmax};
     const dim3 on(g.nb, (unsigned)batch);
     hipLaunchKernelGGL(k_batch_mass_info, dim3((unsigned)batch), dim3(BS), 0, st, mass, g.n,
                        c->muni);
-    hipLaunchKernelGGL(k_batch_block_sums, on, dim3(BS), 0, st, pos, g.n, g.nb, cp[0]);
+    hipLaunchKernelGGL(k_batch_block_sums, on, dim3(BS), 0, st, pos, vel, params_dev, g.n, g.nb,
+                       cp[0]);
     hipLaunchKernelGGL(k_batch_stage, on, dim3(BS), 0, st, pos, mass, g, cp[0], js);
     const BatchTape tp{tape, batch, n, n_steps};
+    const dim3 red((unsigned)red_blocks(n), (unsigned)batch);
     int q = 0;
     for (int64_t s = 0; s <= n_steps; ++s) {
         hipLaunchKernelGGL(k_batch_pair_fwd, dim3(g.nblk, g.S, (unsigned)batch), dim3(BS), 0, st,
                            js, g, params_dev, c->muni, part);
+        hipLaunchKernelGGL(k_batch_fwd_reduce, red, dim3(BS), 0, st, (const float*)part, g,
+                           params_dev, mass, c->ared, c->arec);
         double* ts = (tape && s < n_steps) ? tp.state(s) : nullptr;
         double* ta = tape ? tp.aint(s) : nullptr;
         if (s == 0)
             hipLaunchKernelGGL(k_batch_kdk<0>, on, dim3(BS), 0, st, pos, vel, c->vh, mass, g,
-                               params_dev, part, cp[q], cp[1 - q], js, ts, ta);
+                               params_dev, part, cp[q], cp[1 - q], js, ts, ta, c->ared, c->arec);
         else if (s == n_steps)
             hipLaunchKernelGGL(k_batch_kdk<2>, on, dim3(BS), 0, st, pos, vel, c->vh, mass, g,
-                               params_dev, part, cp[q], cp[1 - q], js, ts, ta);
+                               params_dev, part, cp[q], cp[1 - q], js, ts, ta, c->ared, c->arec);
         else
             hipLaunchKernelGGL(k_batch_kdk<1>, on, dim3(BS), 0, st, pos, vel, c->vh, mass, g,
-                               params_dev, part, cp[q], cp[1 - q], js, ts, ta);
+                               params_dev, part, cp[q], cp[1 - q], js, ts, ta, c->ared, c->arec);
         q = 1 - q;
     }
     return hipGetLastError();
@@ -452,13 +482,15 @@ __global__ __launch_bounds__(BS) void k_batch_rev_stage(const double* __restrict
                                                         const double* __restrict__ cpart,
                                                         float4* __restrict__ jsv,
                                                         double* __restrict__ cpart_out,
-                                                        double* __restrict__ wscale) {
+                                                        double* __restrict__ wscale,
+                                                        const double* __restrict__ xprev_base,
+                                                        int64_t xprev_stride) {
     __shared__ double sh[3 * BS];
     const int64_t b = blockIdx.y;
     const int64_t n = g.n;
-    const double* cp = cpart + b * g.nb * 4;
+    const double* cp = cpart + b * g.nb * REC;
     double cx, cy, cz;
-    centre_from(cp, g.nb, n, sh, cx, cy, cz);
+    centre_from(cp, g.nb, n, sh, cx, cy, cz, false);
     const double S = scale_from(cp, g.nb, sh);
     const double* x = pos + b * 3 * n;
     const double* wb = w + b * 3 * n;
@@ -470,8 +502,13 @@ __global__ __launch_bounds__(BS) void k_batch_rev_stage(const double* __restrict
     if (i < g.nj)
         put_source_w<true>(jsv + b * g.nj * 2, i, ok, x0, y0, z0, mass[b * n + k], cx, cy, cz,
                            wx * S, wy * S, wz * S);
-    double* co = cpart_out + b * g.nb * 4;
-    write_block_sums(x0, y0, z0, ok, sh, co);
+    double* co = cpart_out + b * g.nb * REC;
+    double dx = 0.0, dy = 0.0, dz = 0.0;
+    if (xprev_base) {
+        const double* xp = xprev_base + b * xprev_stride;
+        dx = xp[k] - x0; dy = xp[n + k] - y0; dz = xp[2 * n + k] - z0;
+    }
+    write_block_sums(x0, y0, z0, dx, dy, dz, ok, sh, co);
     write_block_max(ok ? absmax3(wx, wy, wz) : 0.0, sh, co);
     if (blockIdx.x == 0 && threadIdx.x == 0) wscale[2 * b] = S;
 }
@@ -489,8 +526,8 @@ __global__ __launch_bounds__(BS) void k_batch_block_sums_w(const double* __restr
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
     const bool ok = i < n;
     const int64_t k = ok ? i : 0;
-    double* co = cpart + b * g.nb * 4;
-    write_block_sums(x[k], x[n + k], x[2 * n + k], ok, sh, co);
+    double* co = cpart + b * g.nb * REC;
+    write_block_sums(x[k], x[n + k], x[2 * n + k], 0.0, 0.0, 0.0, ok, sh, co);
     write_block_max(ok ? absmax3(wb[k], wb[n + k], wb[2 * n + k]) : 0.0, sh, co);
 }
 
@@ -537,8 +574,8 @@ __global__ __launch_bounds__(BS) void k_batch_rev_kick(
     int half, double* __restrict__ lx_base, double* __restrict__ lv_base,
     double* __restrict__ accum_base, const double* __restrict__ cpart_in,
     double* __restrict__ cpart_out, double* __restrict__ wscale, int wq,
-    float4* __restrict__ jsv) {
-    __shared__ double sh[3 * BS];
+    float4* __restrict__ jsv, const double* __restrict__ gred, const double* __restrict__ grec) {
+    __shared__ double sh[4 * BS];
     const int64_t b = blockIdx.y;
     const int64_t n = g.n;
     const double* P = params + 8 * b;
@@ -549,7 +586,7 @@ __global__ __launch_bounds__(BS) void k_batch_rev_kick(
     const bool ok = i < n;
     const int64_t k = ok ? i : 0;
     const bool drift = xp_base != nullptr;
-    const double* cpi = cpart_in + b * g.nb * 4;
+    const double* cpi = cpart_in + b * g.nb * REC;
     const double* xnb = xn_base + b * xn_stride;
     const double* ai_b = aint_base + b * 3 * n;
     double* lx = lx_base + b * 3 * n;
@@ -557,11 +594,15 @@ __global__ __launch_bounds__(BS) void k_batch_rev_kick(
     double* accum = accum_base + b * 4 * n;
 
     double cx = 0.0, cy = 0.0, cz = 0.0;
-    if (drift) centre_from(cpi, g.nb, n, sh, cx, cy, cz);
-    double gg[3], gm;
-    vjp_sum<true>(part + b * g.S * 8 * g.npad, g.S, g.npad, k, pot.G, false, gg, gm);
-    const double inv_s = 1.0 / wscale[2 * b + wq];
-    gg[0] *= inv_s; gg[1] *= inv_s; gg[2] *= inv_s;
+    if (drift) centre_from(cpi, g.nb, n, sh, cx, cy, cz, true);
+    // the member's reduced J^T w minus its mean (as k_rev_kick in FP32C)
+    const int nr = red_blocks(n);
+    double tot[4];
+    rec_total(grec + b * nr * 4, nr, sh, tot);
+    const double inv_n = 1.0 / (double)n;
+    const double* gr = gred + b * 4 * n;
+    double gg[3] = {gr[k] - tot[0] * inv_n, gr[n + k] - tot[1] * inv_n,
+                    gr[2 * n + k] - tot[2] * inv_n};
     const double ai[3] = {ai_b[k], ai_b[n + k], ai_b[2 * n + k]};
     const double x = xnb[k], y = xnb[n + k], z = xnb[2 * n + k];
     const double wx = lv[k], wy = lv[n + k], wz = lv[2 * n + k];
@@ -603,8 +644,8 @@ __global__ __launch_bounds__(BS) void k_batch_rev_kick(
         if (i < g.nj)
             put_source_w<true>(jsv + b * g.nj * 2, i, ok, px, py, pz, mass[b * n + k], cx, cy,
                                cz, nwx * Sn, nwy * Sn, nwz * Sn);
-        double* co = cpart_out + b * g.nb * 4;
-        write_block_sums(px, py, pz, ok, sh, co);
+        double* co = cpart_out + b * g.nb * REC;
+        write_block_sums(px, py, pz, px - x, py - y, pz - z, ok, sh, co);
         write_block_max(ok ? absmax3(nwx, nwy, nwz) : 0.0, sh, co);
         if (blockIdx.x == 0 && threadIdx.x == 0) wscale[2 * b + (1 - wq)] = Sn;
     }
@@ -632,24 +673,27 @@ hipError_t launch_simulate_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const
     const BatchTape tp{const_cast<double*>(tape), batch, n, T};
     float4* jsv = (float4*)c->jsv;
     float* part = (float*)c->partv;
-    double* cpv[2] = {c->cpartv, c->cpartv + 4 * c->nbmax};
+    double* cpv[2] = {c->cpartv, c->cpartv + REC * c->nbmax};
     const dim3 on(g.nb, (unsigned)batch);
     hipLaunchKernelGGL(k_batch_mass_info, dim3((unsigned)batch), dim3(BS), 0, st, mass, g.n,
                        c->muni);
     hipLaunchKernelGGL(k_batch_block_sums_w, on, dim3(BS), 0, st, pos_T, lv, g, cpv[0]);
     hipLaunchKernelGGL(k_batch_rev_stage, on, dim3(BS), 0, st, pos_T, mass, lv, g, cpv[0], jsv,
-                       cpv[1], c->bwscale);
+                       cpv[1], c->bwscale, T > 0 ? tp.state(T - 1) : nullptr, (int64_t)6 * n);
     int q = 1, wq = 0;
     for (int64_t m = T; m >= 0; --m) {
         hipLaunchKernelGGL(k_batch_pair_vjp, dim3(g.nblk, g.S, (unsigned)batch), dim3(BS), 0, st,
                            (const float4*)jsv, g, params_dev, c->muni, part);
+        hipLaunchKernelGGL(k_batch_vjp_reduce, dim3((unsigned)red_blocks(n), (unsigned)batch),
+                           dim3(BS), 0, st, (const float*)part, g, params_dev, c->bwscale, wq,
+                           c->gred, c->grec);
         const double* xn = (m == T) ? pos_T : tp.state(m);
         const int64_t xs = (m == T) ? 3 * n : 6 * n;
         const double* xp = (m > 0) ? tp.state(m - 1) : nullptr;
         hipLaunchKernelGGL(k_batch_rev_kick, on, dim3(BS), 0, st, g, params_dev, mass,
                            (const float*)part, xn, xs, xp, (int64_t)6 * n, tp.aint(m),
                            (int)(m == T || m == 0), lx, lv, accum, cpv[q], cpv[1 - q], c->bwscale,
-                           wq, jsv);
+                           wq, jsv, c->gred, c->grec);
         q = 1 - q;
         wq = 1 - wq;
     }

@@ -16,6 +16,12 @@ constexpr int SUBTILE = 128;         // sources summed in plain FP32 before a Tw
 constexpr int TARGET_BLOCKS = 8192;  // pair-kernel blocks wanted per launch (32 per CU)
 constexpr int S_MAX = 64;            // maximum number of source slices
 constexpr int SLICE_GRAIN = 32;      // pair-kernel source slices are multiples of this
+constexpr int REC = 8;               // doubles per block record of the O(N) kernels
+constexpr int RT = 64;               // targets per block of the FP32C slice reductions (a wave)
+constexpr int RG = BS / RT;          // slice groups per block of those reductions
+
+// Number of reduction blocks (and net-force records) of a system of n particles.
+__host__ __device__ inline int red_blocks(int64_t n) { return (int)((n + RT - 1) / RT); }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -222,20 +228,42 @@ struct dnb_ctx {
     void* js;                // staged sources: FP32C float4 (x, y, z relative to a centre; m),
                              // FP64 double4 (x, y, z, m); padded to pad_sources(n)
     void* part;              // slice partials: FP32C float2 (hi, lo) [S][3][npad], FP64 double [S][3][npad]
-    double* cpart;           // [2][nbmax][4] block sums of positions (centre), double buffered
+    double* cpart;           // [2][nbmax][8] block records (positions and displacements, for the
+                             // staging centre), double buffered
     double* vh;              // [3][max_n] half-step velocities of the running integration
     // reverse path
     void* jsv;               // staged VJP sources, interleaved per particle:
                              // [2 j] = (x, y, z, m), [2 j + 1] = (w, 0); float4 or double4
     void* partv;             // VJP partials: FP32C float2 (hi, lo) [S][4][npad], FP64 double [S][4][npad]
-    double* cpartv;          // [2][nbmax][4]
+    double* cpartv;          // [2][nbmax][8]
     double* wscale;          // [2] cotangent staging scales of the reverse sweep
     float* muni;             // [DNB_BATCH_MAX][2] (flag, m): all masses of the system (or of
                              // ensemble member b) equal m (FP32C fast path)
     double* bparams;         // [DNB_BATCH_MAX][8] parameter table of a batched ensemble
     double* bwscale;         // [DNB_BATCH_MAX][2] cotangent staging scales of a batched sweep
     double* red;             // [nbmax][8] reduction scratch
+    double* ared;            // [3][npadmax] FP32C internal accelerations reduced from the slices
+    double* gred;            // [4][npadmax] FP32C J^T w (3 rows) and mass term reduced likewise
+    double* arec;            // [cdiv(npadmax, RT) + DNB_BATCH_MAX][4] net-force records
+    double* grec;            // the same for J^T w
     void* prof;              // host-side event pool of dnb_profile (null when off)
+    // Descriptors of the tapes written by the most recent dnb_simulate calls (a
+    // ring, newest at tape_head - 1): dnb_simulate_vjp accepts only a tape, with
+    // its final positions and the arguments it was written with, listed here.
+    struct TapeDesc {
+        const double* tape;
+        const double* pos;   // the in-place position array: the final positions
+        const double* mass;
+        int64_t n, n_steps, ckpt_every;
+        double dt;
+        double pot[7];       // G, eps, m_nfw, rs_nfw, m_mn, a_mn, b_mn
+        int64_t batch;       // 0: dnb_simulate; else the members of dnb_simulate_batch
+        uint64_t table;      // hash of the batch's host parameter table (0 for a single system)
+    };
+    static constexpr int TAPE_RING = 16;
+    TapeDesc tapes[TAPE_RING];
+    int tape_count;          // valid entries (<= TAPE_RING)
+    int tape_head;           // next slot to write
 };
 
 namespace dnb {
@@ -284,16 +312,28 @@ struct FwdArgs {
     double* cpart_out;        // block sums of x_out
     int nb_in;                // number of blocks that wrote cpart_in
     // checkpoint: write (x, v) of this step to tape_state, and the centre used
-    // for staging x_out to tape_centre_next (if non-null)
+    // for staging x_out to tape_centre_next and tape_centre_cur (each if non-null:
+    // the first record of the next checkpoint, the second of this one)
     double* tape_state;
     double* tape_centre_next;
+    double* tape_centre_cur;
     const double* centre_override;   // if non-null: centre to stage x_out with
+    // FP32C inside the integrator: the internal accelerations reduced by
+    // launch_fwd_reduce ([3][n]) and its net-force records (nr of them), from
+    // which the kernel removes the net internal force; null: sum the slice
+    // partials directly, no correction (dnb_accelerations)
+    const double* ared;
+    const double* arec;
+    int nr;
 };
 
-// Block sums of x into cpart[b][0..2]; with w non-null also the block maximum of
-// |w| components into cpart[b][3] (the cotangent scale of the reverse sweep).
+// Block records of x into cpart (layout REC of kdk_common.h): sums of x in
+// [b][0..2]; with w non-null the block maximum of the |w| components in [b][3]
+// (the cotangent scale of the reverse sweep); with v non-null the sums of the
+// displacement dt v in [b][4..6] (the first drift of a run).
 hipError_t launch_block_sums(const double* x, int64_t n, double* cpart, hipStream_t st,
-                             const double* w = nullptr);
+                             const double* w = nullptr, const double* v = nullptr,
+                             double dt = 0.0);
 // Stage x (and mass) into ctx->js: FP32C relative to the centre (from the block
 // sums cpart over nb blocks, or centre_override), FP64 as absolute positions.
 // Pads the tail to pad_sources(n).  centre_out (nullable) receives the centre.
@@ -308,6 +348,14 @@ hipError_t launch_acc_rows(dnb_ctx* c, const double* x, int64_t n, int64_t i0, i
 // Sets c->muni = (1, m) if all n masses equal m, else (0, 0); one block.
 hipError_t launch_mass_info(dnb_ctx* c, const double* mass, int64_t n, hipStream_t st);
 hipError_t launch_kdk(dnb_ctx* c, KdkMode mode, const FwdArgs& a, hipStream_t st);
+// FP32C: reduce the forward slice partials of the last pair launch into c->ared
+// and c->arec (records of cdiv(n, RT) target blocks).
+hipError_t launch_fwd_reduce(dnb_ctx* c, int64_t n, const double* mass, double G,
+                             hipStream_t st);
+// FP32C: reduce the VJP slice partials into c->gred and c->grec, undoing the
+// cotangent scale wscale[0].
+hipError_t launch_vjp_reduce(dnb_ctx* c, int64_t n, double G, int with_mass,
+                             const double* wscale, hipStream_t st);
 
 struct RevArgs {
     int64_t n;
@@ -325,11 +373,18 @@ struct RevArgs {
     const double* cpart_in; int nb_in; double* cpart_out;
     const double* wscale_in;   // scale the consumed cotangent was staged with (FP32C)
     double* wscale_out;        // scale of the cotangent staged by this kernel (FP32C)
+    // FP32C: J^T w and the mass term reduced by launch_vjp_reduce ([4][n], scale
+    // undone) and its records (nr), from which the kernel removes sum_k (J^T w)_k
+    const double* gred;
+    const double* grec;
+    int nr;
 };
 
+// xprev (nullable): the positions the sweep stages next, whose displacement from
+// x the records in cpart_out carry for the next staging centre.
 hipError_t launch_rev_stage(dnb_ctx* c, int64_t n, const double* x, const double* mass,
                             const double* w, const double* cpart, int nb, double* cpart_out,
-                            double* wscale_out, hipStream_t st);
+                            double* wscale_out, hipStream_t st, const double* xprev = nullptr);
 hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, int with_mass, double eps, hipStream_t st);
 hipError_t launch_pair_vjp_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, int with_mass,
                                 double eps, hipStream_t st);

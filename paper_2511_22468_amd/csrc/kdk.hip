@@ -12,10 +12,13 @@
 // staging centre.
 //
 // Staging centre (FP32C).  Positions x_{n+1} are staged relative to the mean of
-// x_n (the centre lags one step; it only has to lie near the particles).  The
-// centre is a deterministic function of x_n, so a recomputation started from a
-// checkpoint reproduces the forward run bit for bit once the checkpoint also
-// stores the centre its positions were staged with.
+// x_n plus the mean displacement of the drift that produced x_n, i.e. the
+// centre of x_n carried one step on (it only has to lie near the particles, but
+// the closer it lies the more FP32 resolution the pair separations keep; the
+// first step extrapolates with dt v_0).  The centre is a deterministic function
+// of x_n and x_{n-1}, so a recomputation started from a checkpoint reproduces
+// the forward run bit for bit once the checkpoint also stores the two centres
+// that the run staged the checkpoint's positions and the step after with.
 //
 // Reverse (the exact discrete adjoint).  With the two half kicks that meet at x_n
 // merged, the sweep newest-first is, for n = T .. 0,
@@ -30,12 +33,15 @@ namespace dnb {
 
 __global__ __launch_bounds__(BS) void k_block_sums(const double* __restrict__ x, int64_t n,
                                                    double* __restrict__ cpart,
-                                                   const double* __restrict__ w) {
+                                                   const double* __restrict__ w,
+                                                   const double* __restrict__ v, double dt) {
     __shared__ double sh[3 * BS];
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
     const bool ok = i < n;
     const int64_t k = ok ? i : 0;
-    write_block_sums(x[k], x[n + k], x[2 * n + k], ok, sh, cpart);
+    double dx = 0.0, dy = 0.0, dz = 0.0;
+    if (v) { dx = dt * v[k]; dy = dt * v[n + k]; dz = dt * v[2 * n + k]; }
+    write_block_sums(x[k], x[n + k], x[2 * n + k], dx, dy, dz, ok, sh, cpart);
     if (w) write_block_max(ok ? absmax3(w[k], w[n + k], w[2 * n + k]) : 0.0, sh, cpart);
 }
 
@@ -52,7 +58,7 @@ __global__ __launch_bounds__(BS) void k_stage(const double* __restrict__ x,
         if (centre_override) {
             cx = centre_override[0]; cy = centre_override[1]; cz = centre_override[2];
         } else {
-            centre_from(cpart, nb, n, sh, cx, cy, cz);
+            centre_from(cpart, nb, n, sh, cx, cy, cz, false);
         }
     }
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
@@ -69,7 +75,7 @@ __global__ __launch_bounds__(BS) void k_stage(const double* __restrict__ x,
 template <int MODE, bool F32>
 __global__ __launch_bounds__(BS) void k_kdk(FwdArgs a, const void* __restrict__ part, int S,
                                             int64_t npad, int64_t nj, void* __restrict__ js) {
-    __shared__ double sh[3 * BS];
+    __shared__ double sh[4 * BS];
     const int64_t n = a.n;
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
     const bool ok = i < n;
@@ -77,10 +83,26 @@ __global__ __launch_bounds__(BS) void k_kdk(FwdArgs a, const void* __restrict__ 
     const bool drift = (MODE == KDK_FIRST || MODE == KDK_MID);
 
     double cx = 0.0, cy = 0.0, cz = 0.0;
-    if (F32 && drift) centre_from(a.cpart_in, a.nb_in, n, sh, cx, cy, cz);
+    if (F32 && drift) {
+        if (a.centre_override) {
+            cx = a.centre_override[0]; cy = a.centre_override[1]; cz = a.centre_override[2];
+        } else {
+            centre_from(a.cpart_in, a.nb_in, n, sh, cx, cy, cz, true);
+        }
+    }
 
     double ax, ay, az;
-    pair_sum<F32>(part, S, npad, k, a.pot.G, ax, ay, az);
+    if (F32 && a.ared) {
+        // reduced internal acceleration minus the net internal force per unit mass
+        double tot[4];
+        rec_total(a.arec, a.nr, sh, tot);
+        const double inv_m = 1.0 / tot[3];
+        ax = a.ared[k] - tot[0] * inv_m;
+        ay = a.ared[n + k] - tot[1] * inv_m;
+        az = a.ared[2 * n + k] - tot[2] * inv_m;
+    } else {
+        pair_sum<F32>(part, S, npad, k, a.pot.G, ax, ay, az);
+    }
     if (a.aint_out && ok) {
         a.aint_out[i] = ax; a.aint_out[n + i] = ay; a.aint_out[2 * n + i] = az;
     }
@@ -121,10 +143,12 @@ __global__ __launch_bounds__(BS) void k_kdk(FwdArgs a, const void* __restrict__ 
     if (drift) {
         if (i < nj) put_source<F32>(js, i, ok, xn, yn, zn, a.mass[k], cx, cy, cz);
         if (F32) {
-            write_block_sums(xn, yn, zn, ok, sh, a.cpart_out);
-            if (a.tape_centre_next && blockIdx.x == 0 && threadIdx.x == 0) {
-                a.tape_centre_next[0] = cx; a.tape_centre_next[1] = cy;
-                a.tape_centre_next[2] = cz; a.tape_centre_next[3] = 0.0;
+            write_block_sums(xn, yn, zn, xn - x, yn - y, zn - z, ok, sh, a.cpart_out);
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                for (double* t : {a.tape_centre_next, a.tape_centre_cur}) {
+                    if (!t) continue;
+                    t[0] = cx; t[1] = cy; t[2] = cz; t[3] = 0.0;
+                }
             }
         }
     }
@@ -160,8 +184,9 @@ hipError_t launch_mass_info(dnb_ctx* c, const double* mass, int64_t n, hipStream
 static inline unsigned onblocks(int64_t n) { return (unsigned)cdiv(pad_sources(n), BS); }
 
 hipError_t launch_block_sums(const double* x, int64_t n, double* cpart, hipStream_t st,
-                             const double* w) {
-    hipLaunchKernelGGL(k_block_sums, dim3((unsigned)cdiv(n, BS)), dim3(BS), 0, st, x, n, cpart, w);
+                             const double* w, const double* v, double dt) {
+    hipLaunchKernelGGL(k_block_sums, dim3((unsigned)cdiv(n, BS)), dim3(BS), 0, st, x, n, cpart, w,
+                       v, dt);
     return hipGetLastError();
 }
 
@@ -241,12 +266,13 @@ __global__ __launch_bounds__(BS) void k_rev_stage(const double* __restrict__ x,
                                                   int64_t nj, const double* __restrict__ cpart,
                                                   int nb, void* __restrict__ jsv,
                                                   double* __restrict__ cpart_out,
-                                                  double* __restrict__ wscale_out) {
+                                                  double* __restrict__ wscale_out,
+                                                  const double* __restrict__ xprev) {
     __shared__ double sh[3 * BS];
     double cx = 0.0, cy = 0.0, cz = 0.0;
     double S = 1.0;
     if (F32) {
-        centre_from(cpart, nb, n, sh, cx, cy, cz);
+        centre_from(cpart, nb, n, sh, cx, cy, cz, false);
         S = scale_from(cpart, nb, sh);
     }
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
@@ -257,7 +283,10 @@ __global__ __launch_bounds__(BS) void k_rev_stage(const double* __restrict__ x,
     if (i < nj)
         put_source_w<F32>(jsv, i, ok, x0, y0, z0, mass[k], cx, cy, cz, wx * S, wy * S, wz * S);
     if (F32) {
-        write_block_sums(x0, y0, z0, ok, sh, cpart_out);
+        // the displacement to the positions the reverse sweep stages next
+        double dx = 0.0, dy = 0.0, dz = 0.0;
+        if (xprev) { dx = xprev[k] - x0; dy = xprev[n + k] - y0; dz = xprev[2 * n + k] - z0; }
+        write_block_sums(x0, y0, z0, dx, dy, dz, ok, sh, cpart_out);
         write_block_max(ok ? absmax3(wx, wy, wz) : 0.0, sh, cpart_out);
         if (blockIdx.x == 0 && threadIdx.x == 0) wscale_out[0] = S;
     }
@@ -267,7 +296,7 @@ template <bool F32>
 __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restrict__ part, int S,
                                                  int64_t npad, int64_t nj,
                                                  void* __restrict__ jsv) {
-    __shared__ double sh[3 * BS];
+    __shared__ double sh[4 * BS];
     const int64_t n = a.n;
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
     const bool ok = i < n;
@@ -275,17 +304,22 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
     const bool drift = a.x_prev != nullptr;
 
     double cx = 0.0, cy = 0.0, cz = 0.0;
-    if (F32 && drift) centre_from(a.cpart_in, a.nb_in, n, sh, cx, cy, cz);
+    if (F32 && drift) centre_from(a.cpart_in, a.nb_in, n, sh, cx, cy, cz, true);
 
-    double g[3], gm;
-    vjp_sum<F32>(part, S, npad, k, a.pot.G, a.with_mass != 0, g, gm);
-    const double ai[3] = {a.aint[k], a.aint[n + k], a.aint[2 * n + k]};
+    double g[3], gm = 0.0;
     if (F32) {
-        // undo the power-of-two scale the consumed cotangent was staged with
-        const double inv_s = 1.0 / a.wscale_in[0];
-        g[0] *= inv_s; g[1] *= inv_s; g[2] *= inv_s;
-        gm *= inv_s;
+        // reduced J^T w (cotangent scale undone) minus its mean over the particles
+        double tot[4];
+        rec_total(a.grec, a.nr, sh, tot);
+        const double inv_n = 1.0 / (double)n;
+        g[0] = a.gred[k] - tot[0] * inv_n;
+        g[1] = a.gred[n + k] - tot[1] * inv_n;
+        g[2] = a.gred[2 * n + k] - tot[2] * inv_n;
+        if (a.with_mass) gm = a.gred[3 * n + k];
+    } else {
+        vjp_sum<F32>(part, S, npad, k, a.pot.G, a.with_mass != 0, g, gm);
     }
+    const double ai[3] = {a.aint[k], a.aint[n + k], a.aint[2 * n + k]};
     const double x = a.x_n[k], y = a.x_n[n + k], z = a.x_n[2 * n + k];
     const double wx = a.lv[k], wy = a.lv[n + k], wz = a.lv[2 * n + k];
     Ext e = ext_accel(a.pot, x, y, z);
@@ -327,23 +361,59 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
             put_source_w<F32>(jsv, i, ok, px, py, pz, a.mass[k], cx, cy, cz, nwx * Sn, nwy * Sn,
                               nwz * Sn);
         if (F32) {
-            write_block_sums(px, py, pz, ok, sh, a.cpart_out);
+            write_block_sums(px, py, pz, px - x, py - y, pz - z, ok, sh, a.cpart_out);
             write_block_max(ok ? absmax3(nwx, nwy, nwz) : 0.0, sh, a.cpart_out);
             if (blockIdx.x == 0 && threadIdx.x == 0) a.wscale_out[0] = Sn;
         }
     }
 }
 
+__global__ __launch_bounds__(BS) void k_fwd_reduce(const float2* __restrict__ part, int S,
+                                                   int64_t npad, int64_t n, double G,
+                                                   const double* __restrict__ mass,
+                                                   double* __restrict__ ared,
+                                                   double* __restrict__ rec) {
+    __shared__ double sh[3 * RG * RT];
+    fwd_reduce_block(part, S, npad, n, G, mass, ared, rec, sh);
+}
+
+__global__ __launch_bounds__(BS) void k_vjp_reduce(const float2* __restrict__ part, int S,
+                                                   int64_t npad, int64_t n, double G,
+                                                   int with_mass,
+                                                   const double* __restrict__ wscale,
+                                                   double* __restrict__ gred,
+                                                   double* __restrict__ rec) {
+    __shared__ double sh[4 * RG * RT];
+    vjp_reduce_block(part, S, npad, n, G, with_mass != 0, 1.0 / wscale[0], gred, rec, sh);
+}
+
+hipError_t launch_fwd_reduce(dnb_ctx* c, int64_t n, const double* mass, double G,
+                             hipStream_t st) {
+    const Slicing sl = fwd_slicing(c, n);
+    hipLaunchKernelGGL(k_fwd_reduce, dim3((unsigned)red_blocks(n)), dim3(BS), 0, st,
+                       (const float2*)c->part, sl.S, sl.npad, n, G, mass, c->ared, c->arec);
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_reduce(dnb_ctx* c, int64_t n, double G, int with_mass,
+                             const double* wscale, hipStream_t st) {
+    const Slicing sl = vjp_slicing(c, n);
+    hipLaunchKernelGGL(k_vjp_reduce, dim3((unsigned)red_blocks(n)), dim3(BS), 0, st,
+                       (const float2*)c->partv, sl.S, sl.npad, n, G, with_mass, wscale, c->gred,
+                       c->grec);
+    return hipGetLastError();
+}
+
 hipError_t launch_rev_stage(dnb_ctx* c, int64_t n, const double* x, const double* mass,
                             const double* w, const double* cpart, int nb, double* cpart_out,
-                            double* wscale_out, hipStream_t st) {
+                            double* wscale_out, hipStream_t st, const double* xprev) {
     const int64_t nj = pad_sources(n);
     if (c->prec == DNB_FP32C)
         hipLaunchKernelGGL(k_rev_stage<true>, dim3(onblocks(n)), dim3(BS), 0, st, x, mass, w, n,
-                           nj, cpart, nb, c->jsv, cpart_out, wscale_out);
+                           nj, cpart, nb, c->jsv, cpart_out, wscale_out, xprev);
     else
         hipLaunchKernelGGL(k_rev_stage<false>, dim3(onblocks(n)), dim3(BS), 0, st, x, mass, w, n,
-                           nj, cpart, nb, c->jsv, cpart_out, wscale_out);
+                           nj, cpart, nb, c->jsv, cpart_out, wscale_out, xprev);
     return hipGetLastError();
 }
 

@@ -10,28 +10,53 @@ namespace dnb {
 constexpr float FAR32 = 1.0e18f;
 constexpr double FAR64 = 1.0e150;
 
+// Per-block record of the O(N) kernels (FP32C staging), REC doubles:
+//   [0..2] sums of the positions the kernel wrote or staged,
+//   [3]    maximum |w| of the cotangent it staged (reverse sweep; 0 otherwise),
+//   [4..6] sums of the displacement from the positions before them (x_new - x_old),
+//   [7]    0.
+// The displacement sums let the next kernel predict where the particles it is
+// about to move will be.  A progenitor on its orbit travels 0.1-0.25 kpc per
+// step, ten to twenty times its own 0.01 kpc size: staged relative to the mean
+// of the previous positions, the FP32 offsets would carry that drift and lose
+// the same factor in resolution of the pair separations.  (REC is defined with
+// the launch geometry, since the host sizes the record buffers.)
+
+// Staging centre: the mean of the recorded positions, plus, with extrapolate,
+// the mean recorded displacement (the centre of the positions one step on).
 __device__ inline void centre_from(const double* __restrict__ cpart, int nb, int64_t n, double* sh,
-                                   double& cx, double& cy, double& cz) {
+                                   double& cx, double& cy, double& cz, bool extrapolate) {
     double v[3] = {0.0, 0.0, 0.0};
+    double d[3] = {0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nb; b += BS) {
-        v[0] += cpart[4 * b + 0];
-        v[1] += cpart[4 * b + 1];
-        v[2] += cpart[4 * b + 2];
+        v[0] += cpart[REC * b + 0];
+        v[1] += cpart[REC * b + 1];
+        v[2] += cpart[REC * b + 2];
+        if (extrapolate) {
+            d[0] += cpart[REC * b + 4];
+            d[1] += cpart[REC * b + 5];
+            d[2] += cpart[REC * b + 6];
+        }
     }
     block_sum<3>(v, sh);
+    if (extrapolate) block_sum<3>(d, sh);
     const double inv = 1.0 / (double)n;
-    cx = v[0] * inv; cy = v[1] * inv; cz = v[2] * inv;
+    cx = (v[0] + d[0]) * inv; cy = (v[1] + d[1]) * inv; cz = (v[2] + d[2]) * inv;
 }
 
-__device__ inline void write_block_sums(double x, double y, double z, bool valid, double* sh,
+// Record of this block: sums of (x, y, z) and of the displacement (dx, dy, dz)
+// over its valid lanes; slot 3 is cleared (write_block_max fills it).
+__device__ inline void write_block_sums(double x, double y, double z, double dx, double dy,
+                                        double dz, bool valid, double* sh,
                                         double* __restrict__ cpart_out) {
     double v[3] = {valid ? x : 0.0, valid ? y : 0.0, valid ? z : 0.0};
+    double d[3] = {valid ? dx : 0.0, valid ? dy : 0.0, valid ? dz : 0.0};
     block_sum<3>(v, sh);
+    block_sum<3>(d, sh);
     if (threadIdx.x == 0) {
-        cpart_out[4 * blockIdx.x + 0] = v[0];
-        cpart_out[4 * blockIdx.x + 1] = v[1];
-        cpart_out[4 * blockIdx.x + 2] = v[2];
-        cpart_out[4 * blockIdx.x + 3] = 0.0;
+        double* c = cpart_out + REC * blockIdx.x;
+        c[0] = v[0]; c[1] = v[1]; c[2] = v[2]; c[3] = 0.0;
+        c[4] = d[0]; c[5] = d[1]; c[6] = d[2]; c[7] = 0.0;
     }
 }
 
@@ -41,7 +66,7 @@ __device__ inline void write_block_sums(double x, double y, double z, bool valid
 // with S a power of two (exact) chosen so that max |w S| is about 1; the pair VJP
 // is linear in w, so the consumer divides the slice sums by S in FP64.  S is
 // taken from the block maxima of the previous cotangent (slot 3 of the
-// block-sum records), which differs from the staged one by one drift update.
+// block records), which differs from the staged one by one drift update.
 __device__ inline double absmax3(double a, double b, double c) {
     return fmax(fabs(a), fmax(fabs(b), fabs(c)));
 }
@@ -53,14 +78,14 @@ __device__ inline void write_block_max(double v, double* sh, double* __restrict_
         if (threadIdx.x < off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) cpart_out[4 * blockIdx.x + 3] = sh[0];
+    if (threadIdx.x == 0) cpart_out[REC * blockIdx.x + 3] = sh[0];
     __syncthreads();
 }
 
 // Power-of-two scale from the block maxima in slot 3 of cpart (1 if all zero).
 __device__ inline double scale_from(const double* __restrict__ cpart, int nb, double* sh) {
     double m = 0.0;
-    for (int b = threadIdx.x; b < nb; b += BS) m = fmax(m, cpart[4 * b + 3]);
+    for (int b = threadIdx.x; b < nb; b += BS) m = fmax(m, cpart[REC * b + 3]);
     sh[threadIdx.x] = m;
     __syncthreads();
     for (int off = BS / 2; off > 0; off >>= 1) {
@@ -166,6 +191,151 @@ __device__ inline void vjp_sum(const void* part, int S, int64_t npad, int64_t i,
     }
     for (int c = 0; c < 3; ++c) g[c] *= G;
     gm *= G;
+}
+
+// ------------------------------------------------ FP32C slice reductions --
+// Inside the integrator (forward steps and the reverse sweep) the FP32C slice
+// partials are summed by a reduction kernel of their own, which also records the
+// net internal force of the step: sum_k m_k a_k, zero in exact arithmetic
+// (Newton's third law), and for the reverse sweep sum_k (J^T w)_k, zero for the
+// same reason (the pair Jacobian's blocks K(d_kj) are even in d_kj).  The
+// consumer subtracts the mean that restores these identities.  What it removes
+// is the common part of the FP32 rounding of the per-target sums: in exact
+// arithmetic it is zero.  That common part matters because the gradients with
+// respect to the host masses are small differences (about 1e-4 of their terms)
+// between the progenitor's orbit and the response of its particles, and the
+// orbit's part follows the sum of the particles' cotangents, which per-target
+// FP32 rounding would otherwise shift by ~1e-7 per step.
+
+// Sum of the S slice partials of target i (FP32C (hi, lo) float2, STRIDE rows
+// per slice, the first ROWS summed): RG groups of consecutive slices, each
+// summed in slice order (hi, then lo) in FP64 by its own wave, the group sums
+// added in group order.  Returns the sums in the threads of group 0
+// (threadIdx.x < RT).  sh: [RG * ROWS * RT].
+template <int ROWS, int STRIDE>
+__device__ inline void slice_reduce(const float2* __restrict__ part, int S, int64_t npad,
+                                    int64_t i, bool valid, double (&out)[ROWS], double* sh) {
+    const int t = threadIdx.x % RT, g = threadIdx.x / RT;
+    const int per = (S + RG - 1) / RG;
+    const int s0 = g * per;
+    const int s1 = min(S, s0 + per);
+    double v[ROWS];
+#pragma unroll
+    for (int c = 0; c < ROWS; ++c) v[c] = 0.0;
+    if (valid) {
+#pragma unroll 4
+        for (int s = s0; s < s1; ++s) {
+            const float2* q = part + (int64_t)s * STRIDE * npad + i;
+#pragma unroll
+            for (int c = 0; c < ROWS; ++c) {
+                const float2 x = q[c * npad];
+                v[c] += (double)x.x;
+                v[c] += (double)x.y;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < ROWS; ++c) sh[(g * ROWS + c) * RT + t] = v[c];
+    __syncthreads();
+    if (g == 0) {
+#pragma unroll
+        for (int c = 0; c < ROWS; ++c) {
+            double a = sh[c * RT + t];
+            for (int q = 1; q < RG; ++q) a += sh[(q * ROWS + c) * RT + t];
+            out[c] = a;
+        }
+    }
+    __syncthreads();
+}
+
+// Tree sum over the RT lanes of group 0 of NV values (result in every thread).
+template <int NV>
+__device__ inline void rt_sum(double (&v)[NV], double* sh) {
+    const int t = threadIdx.x;
+    if (t < RT) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[k * RT + t] = v[k];
+    }
+    __syncthreads();
+    for (int off = RT / 2; off > 0; off >>= 1) {
+        if (t < off) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) sh[k * RT + t] += sh[k * RT + t + off];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = sh[k * RT];
+    __syncthreads();
+}
+
+// Forward reduction for targets [blockIdx.x RT, +RT) of one system: ared [3][n]
+// = G x (slice sums), rec [4] = (sum m a_x, sum m a_y, sum m a_z, sum m) over
+// the block's targets.  sh: at least 3 RG RT doubles.
+__device__ inline void fwd_reduce_block(const float2* __restrict__ part, int S, int64_t npad,
+                                        int64_t n, double G, const double* __restrict__ mass,
+                                        double* __restrict__ ared, double* __restrict__ rec,
+                                        double* sh) {
+    const int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x % RT;
+    const bool valid = i < n;
+    double a[3] = {0.0, 0.0, 0.0};
+    slice_reduce<3, 3>(part, S, npad, i, valid, a, sh);
+    double m = 0.0;
+    if (threadIdx.x < RT && valid) {
+        for (int c = 0; c < 3; ++c) {
+            a[c] *= G;
+            ared[c * n + i] = a[c];
+        }
+        m = mass[i];
+    } else {
+        a[0] = a[1] = a[2] = 0.0;
+    }
+    double v[4] = {m * a[0], m * a[1], m * a[2], m};
+    rt_sum<4>(v, sh);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 4; ++c) rec[4 * blockIdx.x + c] = v[c];
+}
+
+// Reverse reduction: gred [4][n] = (J^T w (3 rows), raw mass term) x G / S_w
+// (S_w: the power-of-two scale the cotangent was staged with), rec [4] =
+// (sum of the three J^T w rows over the block's targets, 0).
+__device__ inline void vjp_reduce_block(const float2* __restrict__ part, int S, int64_t npad,
+                                        int64_t n, double G, bool with_mass, double inv_s,
+                                        double* __restrict__ gred, double* __restrict__ rec,
+                                        double* sh) {
+    const int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x % RT;
+    const bool valid = i < n;
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
+    if (with_mass) {
+        slice_reduce<4, 4>(part, S, npad, i, valid, g, sh);
+    } else {
+        double g3[3] = {0.0, 0.0, 0.0};
+        slice_reduce<3, 4>(part, S, npad, i, valid, g3, sh);
+        g[0] = g3[0]; g[1] = g3[1]; g[2] = g3[2];
+    }
+    if (threadIdx.x < RT && valid) {
+        for (int c = 0; c < 4; ++c) {
+            g[c] = (g[c] * G) * inv_s;
+            if (c < 3 || with_mass) gred[c * n + i] = g[c];
+        }
+    } else {
+        g[0] = g[1] = g[2] = 0.0;
+    }
+    double v[3] = {g[0], g[1], g[2]};
+    rt_sum<3>(v, sh);
+    if (threadIdx.x == 0) {
+        for (int c = 0; c < 3; ++c) rec[4 * blockIdx.x + c] = v[c];
+        rec[4 * blockIdx.x + 3] = 0.0;
+    }
+}
+
+// Sum of the nr reduction records (fixed order; every thread gets it).
+__device__ inline void rec_total(const double* __restrict__ rec, int nr, double* sh,
+                                 double (&tot)[4]) {
+    for (int c = 0; c < 4; ++c) tot[c] = 0.0;
+    for (int b = threadIdx.x; b < nr; b += BS)
+        for (int c = 0; c < 4; ++c) tot[c] += rec[4 * b + c];
+    block_sum<4>(tot, sh);
 }
 
 }  // namespace dnb

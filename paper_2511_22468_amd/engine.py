@@ -58,6 +58,16 @@ def _arr(t, shape, name):
     return t
 
 
+def _buffer(t, length, name):
+    """A flat float64 CUDA buffer of at least `length` elements."""
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if t.numel() < length:
+        raise ValueError(f"{name} holds {t.numel()} doubles, {length} needed")
+    return t
+
+
 class Context:
     """Owns a dnb_ctx: device workspace for up to max_n particles."""
 
@@ -165,8 +175,12 @@ class Context:
         if gvel_T is not None:
             _vec(gvel_T, n, "gvel_T")
         K = int(ckpt_every)
+        ws_len = int(_lib.lib().dnb_vjp_workspace_doubles(n, K))
         if workspace is None:
-            workspace = self._new(int(_lib.lib().dnb_vjp_workspace_doubles(n, K)))
+            workspace = self._new(ws_len)
+        _buffer(workspace, ws_len, "workspace")
+        if int(n_steps) > 0:
+            _buffer(tape, self.tape_len(n, n_steps, K), "tape")
         gpos0, gvel0 = self._new(3, n), self._new(3, n)
         gmass = self._new(n) if with_mass else None
         gpar = self._new(4)
@@ -238,6 +252,7 @@ class Context:
         if gvel_T is not None:
             _arr(gvel_T, (B, 3, n), "gvel_T")
         table = batch_table(pots, dts, B)
+        _buffer(tape, int(_lib.lib().dnb_batch_tape_doubles(B, n, int(n_steps))), "tape")
         work = self._new(4 * B * n)
         g0, gv0, gpar = self._new(B, 3, n), self._new(B, 3, n), self._new(B, 4)
         _lib.check(_lib.lib().dnb_simulate_batch_vjp(

@@ -63,7 +63,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_version_and_size_queries(lib):
     assert b"gfx950" in lib.dnb_version()
-    assert lib.dnb_tape_doubles(10, 7, 3) == 3 * (90 + 4) + 30
+    assert lib.dnb_tape_doubles(10, 7, 3) == 3 * (90 + 8) + 30
     assert lib.dnb_tape_doubles(10, 0, 3) == 0
     assert lib.dnb_tape_doubles(10, 7, 0) == -1
     assert lib.dnb_vjp_workspace_doubles(10, 4) == 3 * 10 * 5 + 160 + 3 * 10 * 4
