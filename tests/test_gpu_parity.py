@@ -362,14 +362,14 @@ def test_pipeline_gradient_matches_oracle(dnb, prec, K):
                         pot=engine.Potential(), ckpt_every=K)
     L, gg = model.loss_and_grad(torch.tensor(theta, device="cuda"))
     tol = 1e-8 if prec == "fp64" else 1e-3
+    g = gg.cpu().numpy()
+    say(f"  loss rel err {abs(L.item() / L_ref - 1):.2e}, per-component gradient rel err "
+        f"{np.abs(g / g_ref - 1)}")
     assert abs(L.item() / L_ref - 1) <= tol
-    if prec == "fp64":
-        np.testing.assert_allclose(gg.cpu().numpy(), g_ref, rtol=tol)
-    else:
-        # compared on theta * dL/dtheta against its largest component: the host-mass
-        # sensitivities are ~100x smaller than the t_end and M_Plummer ones
-        sg, sr = gg.cpu().numpy() * theta, g_ref * theta
-        assert np.abs(sg - sr).max() <= tol * np.abs(sr).max()
+    # every component on its own scale, the host masses included (their
+    # gradients are differences of ~1e-4 between the orbit's and the particles'
+    # terms; FP32C measured within 1.2e-6)
+    np.testing.assert_allclose(g, g_ref, rtol=tol)
 
 
 def test_autograd_mass_and_initial_condition_gradients(dnb):
