@@ -5,14 +5,25 @@
   initial conditions differ by one ulp), plus energy drift.
 * N=16384 FP32C, 4000 steps: accelerations of 256 sampled particles checked
   against the oracle every 500 steps (relative error <= 1e-5).
-* N=8192, 2000 steps, checkpoints every 100: adjoint gradient of the MMD loss
-  with respect to the four inference parameters against central finite
-  differences (h = 1e-4 relative) of the same FP64 GPU forward model.
+* N=8192, 20 and 50 steps of the 2000-step differentiation workload: adjoint
+  gradient of the MMD loss with respect to the four inference parameters
+  against central finite differences (h = 1e-4 relative) of the same FP64 GPU
+  forward model, and against the oracle's pipeline gradient (stored by
+  tests/golden/make_oracle_gradients.py), each component on its own scale;
+  the full 2000 steps with checkpoints every 100 against the full tape.
 * N=65536: FP32C vs FP64-on-GPU vs oracle accelerations on 1024 sampled
   particles, and FP32C vs FP64 final positions after 1000 steps.
 * N=65536, the headline workload's pipeline gradient over 20 steps: FP32C vs
   the FP64 path.
+
+Full-horizon positions are judged against the chaos floor: the spread of the
+FP64 path itself when its initial positions are rounded as FP32 staging rounds
+them (2^-24 |x - c| in seeded directions), taken as the largest over four draws
+of each statistic, with the multipliers the FP32C path's per-step rounding
+justifies (2x the median, 3x the 99th percentile and the cloud MMD).
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -123,9 +134,61 @@ def test_adjoint_against_finite_differences_n8192(T):
             fd = (model.loss(tp).item() - model.loss(tm).item()) / (2 * h)
         fds.append(fd * theta[k].item())
     fds = np.array(fds)
-    say(f"  theta*dL/dtheta adjoint {sg}  central FD {fds}")
-    assert np.abs(sg - fds).max() <= 2e-3 * np.abs(fds).max()
+    rel = np.abs(sg / fds - 1)
+    say(f"  theta*dL/dtheta adjoint {sg}  central FD {fds}  per-component rel {rel}")
+    # each component on its own scale (the FD quotient's own error, O(h^2) plus
+    # rounding of ~1e-16 L / (h g), is below 1e-6 for all four)
+    assert rel.max() <= 1e-3
     c.close()
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "oracle_gradients_n8192.txt")
+
+
+def golden_gradients():
+    """{(steps, draw): (loss, dL/dtheta)} from the oracle-written fixture."""
+    rows = {}
+    for line in open(GOLDEN):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        rows[(int(f[0]), int(f[1]))] = (float(f[2]), np.array([float(x) for x in f[3:7]]))
+    return rows
+
+
+@pytest.mark.parametrize("T", [20, 50])
+def test_pipeline_gradient_n8192_against_oracle(T):
+    """The differentiation workload at its full particle number (N = 8192, eps =
+    1e-3 kpc, T steps of 1.1 x 2 Gyr / 2000, checkpoints every 10, MMD with h =
+    0.2 kpc against a seeded 4096-point cloud) against the oracle's pipeline
+    gradient stored by tests/golden/make_oracle_gradients.py (which runs the
+    oracle only).  Every component on its own scale: FP64 within 1e-8, FP32C
+    within 1e-3.  The fixture also holds the oracle's own spread when the initial
+    positions are rounded at FP32 scale, printed beside as context."""
+    import paper_2511_22468_amd as pk
+    from paper_2511_22468_amd import engine
+    from paper_2511_22468_amd.pipeline import StreamModel
+    gold = golden_gradients()
+    L_ref, g_ref = gold[(T, -1)]
+    spread = max(np.abs(gold[(T, k)][1] / g_ref - 1).max() for k in (0, 1))
+    xi, zeta = plummer_unit(8192, 3)
+    rng = np.random.Generator(np.random.PCG64(30))
+    target = W_X + 0.02 * rng.normal(size=(4096, 3))
+    theta = torch.tensor([T * 1.1 * pk.gyr(2.0) / 2000, 3e4 * 1.2, 1e12 * 0.9, 6.5e10 * 1.1],
+                         dtype=torch.float64, device="cuda")
+    for prec, tol in (("fp64", 1e-8), ("fp32c", 1e-3)):
+        say(f"[cfg] N=8192 T={T} {prec}: pipeline gradient vs oracle")
+        c = engine.Context(8192, prec)
+        model = StreamModel(c, to_dev(xi), to_dev(zeta), to_dev(target), T,
+                            pot=engine.Potential(eps=1e-3), h=0.2, ckpt_every=10)
+        L, g = model.loss_and_grad(theta)
+        rel = np.abs(g.cpu().numpy() / g_ref - 1)
+        say(f"  loss rel err {abs(L.item() / L_ref - 1):.2e}; per-component rel err {rel}; "
+            f"oracle FP32-rounding spread {spread:.2e}")
+        assert abs(L.item() / L_ref - 1) <= tol
+        assert rel.max() <= tol
+        c.close()
 
 
 def test_full_horizon_checkpointed_adjoint_is_exact_n8192():
@@ -172,14 +235,15 @@ def test_three_way_precision_n65536():
     say(f"[cfg] N=65536 accel vs oracle (1024 sampled): FP32C max {e32.max():.2e} "
         f"median {np.median(e32):.2e}; FP64 max {e64.max():.2e}")
     assert e32.max() <= 1e-5 and e64.max() <= 1e-12
-    # FP64 floors: initial positions moved by one ulp, and by the FP32 rounding
-    # of a position staged relative to the centre (6e-8 of |x - c|, seeded
-    # directions), which is the size of error the FP32C path makes at every step
+    # the chaos floor (module docstring): FP64 runs from initial positions
+    # rounded at FP32 scale relative to the centre (2^-24 |x - c| in seeded
+    # directions), four draws; one run moved by one ulp is printed as context
     rel = x - x.mean(0)
-    x32 = x + 6e-8 * np.sqrt((rel ** 2).sum(1))[:, None] * random_directions(n, 41)
+    runs = [("fp32c", x), ("fp64", x), ("fp64+1ulp", np.nextafter(x, np.inf))]
+    for k in range(4):
+        runs.append((f"fp64+fp32#{k}", x + 2.0 ** -24 * np.sqrt((rel ** 2).sum(1))[:, None]
+                     * random_directions(n, 41 + k)))
     final = {}
-    runs = (("fp32c", x), ("fp64", x), ("fp64+1ulp", np.nextafter(x, np.inf)),
-            ("fp64+fp32", x32))
     for name, x0 in runs:
         c = ctx[name.split("+")[0]]
         px, pv, pm = to_dev(x0), to_dev(v), to_dev(m)
@@ -188,20 +252,23 @@ def test_three_way_precision_n65536():
     d = rel_rows(final["fp32c"], final["fp64"])
     stats = lambda e: f"max {e.max():.2e} p99 {np.quantile(e, 0.99):.2e} median {np.median(e):.2e}"
     fl1 = rel_rows(final["fp64+1ulp"], final["fp64"])
-    fl32 = rel_rows(final["fp64+fp32"], final["fp64"])
+    draws = [rel_rows(final[f"fp64+fp32#{k}"], final["fp64"]) for k in range(4)]
     say(f"[cfg] N=65536 final positions after 1000 steps vs FP64-GPU: FP32C {stats(d)}; "
-        f"FP64 one-ulp floor {stats(fl1)}; FP64 FP32-rounding floor {stats(fl32)}")
+        f"FP64 one-ulp {stats(fl1)}; FP64 FP32-rounding draws: "
+        + "; ".join(stats(e) for e in draws))
     c64 = ctx["fp64"]
     mmd = {k: c64.mmd(to_dev(final[k]), to_dev(final["fp64"]), 0.2, grad=False)[0].item()
-           for k in ("fp32c", "fp64+1ulp", "fp64+fp32")}
-    say(f"[cfg] N=65536 cloud MMD^2 vs FP64: FP32C {mmd['fp32c']:.3e}, one-ulp floor "
-        f"{mmd['fp64+1ulp']:.3e}, FP32-rounding floor {mmd['fp64+fp32']:.3e}")
-    # chaos saturates per-particle differences at the size of the bound core: per
-    # particle (median and p99) and as a cloud (MMD, h = 0.2 kpc) FP32C must be no
-    # further from FP64 than an FP64 run started with FP32-sized rounding errors
-    assert np.median(d) <= 2 * np.median(fl32) + 1e-6
-    assert np.quantile(d, 0.99) <= 3 * np.quantile(fl32, 0.99) + 1e-6
-    assert mmd["fp32c"] <= 3 * mmd["fp64+fp32"] + 1e-9
+           for k in final if k != "fp64"}
+    floor_med = max(np.median(e) for e in draws)
+    floor_p99 = max(np.quantile(e, 0.99) for e in draws)
+    floor_mmd = max(mmd[f"fp64+fp32#{k}"] for k in range(4))
+    say(f"[cfg] N=65536 cloud MMD^2 vs FP64: FP32C {mmd['fp32c']:.3e}, one-ulp "
+        f"{mmd['fp64+1ulp']:.3e}, FP32-rounding floor {floor_mmd:.3e}; ratios to the floor: "
+        f"median {np.median(d) / floor_med:.2f} p99 {np.quantile(d, 0.99) / floor_p99:.2f} "
+        f"MMD {mmd['fp32c'] / floor_mmd:.2f}")
+    assert np.median(d) <= 2 * floor_med + 1e-6
+    assert np.quantile(d, 0.99) <= 3 * floor_p99 + 1e-6
+    assert mmd["fp32c"] <= 3 * floor_mmd + 1e-9
     for c in ctx.values():
         c.close()
 
@@ -327,11 +394,10 @@ def test_headline_workload_gradient_n65536_fp32c_against_fp64():
         L, g = model.loss_and_grad(theta)
         res[p] = (L.item(), (g * theta).cpu().numpy())
     (L32, s32), (L64, s64) = res["fp32c"], res["fp64"]
-    d = np.abs(s32 - s64).max() / np.abs(s64).max()
-    say(f"  loss FP32C {L32:.9e} FP64 {L64:.9e}; theta*dL/dtheta max difference {d:.2e} "
-        f"of the largest component")
+    d = np.abs(s32 / s64 - 1)
+    say(f"  loss FP32C {L32:.9e} FP64 {L64:.9e}; per-component rel difference {d}")
     assert np.isfinite(s32).all() and np.isfinite(s64).all()
     # after 20 steps MMD^2 is ~1.5e-7, a difference of kernel means of order 0.1-1,
     # so the loss is also compared in absolute terms (measured 1e-13)
     assert abs(L32 - L64) <= 1e-6 * abs(L64) + 1e-11
-    assert d <= 1e-3
+    assert d.max() <= 1e-3
