@@ -17,7 +17,8 @@ oracle on a bounded subsample of the same pair work on the host's cores.
 time_to_fit carries the metric's second half, outside the timed region: the
 surrogate-warm-started fit against plain N-body gradient descent on a held-out
 target (fit N = 8192, 4000 steps; 512 training runs of N = 4096), both arms
-descending to convergence and timed to the loss both reach.
+descending to convergence; the plain fit's duration against the time the warm
+arm takes to reach the plain fit's final loss.
 
 Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline]
                        [--no-time-to-fit]
@@ -517,7 +518,8 @@ def orbit_fit(n_starts=1000, n_iter=60, K=32):
 def time_to_fit_summary(seed=50):
     """The metric's second half at its workload (fit N = 8192 with 4000 steps; the
     surrogate trained on 512 runs of N = 4096 with 4000 steps): both arms descend
-    to convergence and are timed to the loss both reach."""
+    to convergence; the plain fit's duration against the warm arm's time to reach
+    the plain fit's final loss."""
     from paper_2511_22468_amd import fit
     r = fit.run(seed=seed)
     p, w = r["plain"], r["warm"]
@@ -526,9 +528,13 @@ def time_to_fit_summary(seed=50):
                      f"{r['n_fit']}, {r['n_steps']} steps, eps {r['eps_kpc']} kpc; surrogate "
                      f"trained on {r['n_train_runs']} runs of N = {r['n_train_particles']} with "
                      f"{r['n_train_steps']} steps; descent stops at {r['stop_rule']}"),
-        "common_loss": r["common_loss"],
-        "plain_seconds": r["plain_seconds_to_common_loss"],
-        "warm_seconds": r["warm_seconds_to_common_loss"],
+        "definition": ("plain_seconds: the plain fit until its descent stops, ending at "
+                       "plain_fit_loss; warm_seconds: the warm arm (inversion, then descent) "
+                       "until it first reaches plain_fit_loss"),
+        "plain_fit_loss": r["plain_fit_loss"],
+        "plain_seconds": r["plain_fit_seconds"],
+        "warm_seconds": r["warm_seconds_to_plain_fit_loss"],
+        "plain_reaches_warm_final_loss": r["plain_reaches_warm_final_loss"],
         "speedup_excl_training": r["speedup_excl_training"],
         "speedup_incl_training": r["speedup_incl_training"],
         "data_seconds": r["surrogate"]["data_seconds"],

@@ -14,10 +14,12 @@ plain arm:  from the prior centre u = 0.
 warm arm:   invert the surrogate on the target's density image (Adam on u through
             the network, many starts), then the same descent from there.
 
-Both arms are timed to the same loss: L_common, the larger of their two final
-losses (the loss both arms reach).  The ratio of those times is reported
+Time-to-fit: the plain method's fit takes as long as its descent runs until it
+stops, and ends at its final loss L_plain.  The warm arm is timed until it first
+reaches L_plain (inversion included).  The ratio of the two is reported
 excluding and including the one-off cost of the surrogate (its training set from
-the engine's own runs, and its training).
+the engine's own runs, and its training).  Both arms' complete descents (time and
+final loss) are reported beside it.
 
 Usage: python -m paper_2511_22468_amd.fit [--quick]   (prints one JSON line)
 """
@@ -168,8 +170,8 @@ def run(quick=False, seed=50, n_train=None, n_draws=None, train_steps=None, max_
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
 
-    L_common = max(L_plain, L_warm)
-    tp, tw = time_to(hist_plain, L_common), time_to(hist_warm, L_common)
+    tp = t_plain                       # the plain fit, until its descent stops
+    tw = time_to(hist_warm, L_plain)   # the warm arm, until it matches the plain fit
     out = {
         "metric": "time-to-fit: surrogate warm start vs plain N-body gradient descent",
         "n_fit": n_fit, "n_steps": T, "n_train_runs": n_draws, "n_train_particles": n_train,
@@ -188,11 +190,12 @@ def run(quick=False, seed=50, n_train=None, n_draws=None, train_steps=None, max_
                       "train_loss_first_last": [losses[0], losses[-1]],
                       "inversion_image_mse": err_w},
         "u_star": u_star.tolist(),
-        "common_loss": L_common,
-        "plain_seconds_to_common_loss": tp,
-        "warm_seconds_to_common_loss": tw,
-        "speedup_excl_training": tp / tw,
-        "speedup_incl_training": tp / (tw + t_data + t_train),
+        "plain_fit_loss": L_plain,
+        "plain_fit_seconds": tp,
+        "warm_seconds_to_plain_fit_loss": tw,
+        "plain_reaches_warm_final_loss": time_to(hist_plain, L_warm) is not None,
+        "speedup_excl_training": (tp / tw) if tw else None,
+        "speedup_incl_training": (tp / (tw + t_data + t_train)) if tw else None,
     }
     ctx.close()
     gen_ctx.close()

@@ -137,20 +137,19 @@ def test_warm_start_gains_over_plain_descent():
     """What the trained network gains over the method without it: the quick
     time-to-fit configuration (fit N = 2048, 1000 steps; 64 training runs of
     N = 1024; the engine's own runs as training data).  Both arms descend until
-    they converge (step length below 1/64 of its start, or 30 iterations); each
-    is timed to the loss both reach (the larger of their final losses), and the
-    warm arm, the surrogate's inversion followed by the same descent, must get
-    there in less wall time than plain descent from the prior centre."""
+    they converge (step length below 1/64 of its start, or 30 iterations).  The
+    warm arm, the surrogate's inversion followed by the same descent, must reach
+    the plain fit's final loss in less wall time than the plain fit takes, and
+    end at a loss no worse than it."""
     from paper_2511_22468_amd import fit
     r = fit.run(quick=True, seed=50)
     p, w = r["plain"], r["warm"]
-    say(f"[fit] plain {p['iterations']} iterations, final loss {p['final_loss']:.3e} "
-        f"(converged {p['converged']}); warm {w['iterations']} iterations, final loss "
-        f"{w['final_loss']:.3e} (converged {w['converged']}, inversion "
-        f"{w['inversion_seconds']:.2f} s); common loss {r['common_loss']:.3e} reached in "
-        f"{r['plain_seconds_to_common_loss']:.2f} s plain vs "
-        f"{r['warm_seconds_to_common_loss']:.2f} s warm: {r['speedup_excl_training']:.2f}x "
-        f"excluding training, {r['speedup_incl_training']:.2f}x including it")
-    assert r["plain_seconds_to_common_loss"] is not None
-    assert r["warm_seconds_to_common_loss"] is not None
+    say(f"[fit] plain {p['iterations']} iterations {p['seconds']:.2f} s to {p['final_loss']:.3e} "
+        f"(converged {p['converged']}); warm {w['iterations']} iterations {w['seconds']:.2f} s "
+        f"to {w['final_loss']:.3e} (converged {w['converged']}, inversion "
+        f"{w['inversion_seconds']:.2f} s), plain fit loss reached after "
+        f"{r['warm_seconds_to_plain_fit_loss']} s: {r['speedup_excl_training']}x excluding "
+        f"training, {r['speedup_incl_training']}x including it")
+    assert r["warm_seconds_to_plain_fit_loss"] is not None
+    assert w["final_loss"] <= p["final_loss"]
     assert r["speedup_excl_training"] > 1.0
