@@ -92,6 +92,29 @@ const char* dnb_version(void);
 dnb_status dnb_accelerations(dnb_ctx* ctx, int64_t n, const double* pos, const double* mass,
                              const dnb_pot* pot, int with_ext, double* acc, void* stream);
 
+/* Largest n that dnb_accelerations_noalloc accepts. */
+#define DNB_NOALLOC_MAX_N 65536
+
+/* For callers that cannot allocate device memory: code under HIP stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  The accelerations of
+ * dnb_accelerations (same arguments, with the pair-term precision given here
+ * instead of by a context), computed without a context and without allocating:
+ * the kernels' scratch (staged sources, slice partials, block records) is one
+ * 16 MiB array of device memory that the library's code object holds on every
+ * GPU it runs on, until the process ends.  n must lie in [1, DNB_NOALLOC_MAX_N]
+ * (DNB_ERR_ARG otherwise, with a message).  No hipMalloc, hipFree or other
+ * allocating call is made (the array's device address is looked up once per
+ * device, on the first call there).  The source slices are capped so that the
+ * partials fit the array (9 slices at n = 65536 against 32 for the context
+ * path), so FP32C results equal dnb_accelerations' to FP32 rounding rather than
+ * bit for bit; FP64 results agree to FP64 rounding.  Every call on one GPU uses
+ * the same array: calls that overlap on a device (other streams or threads)
+ * race, and the caller must serialise them.  pos [3][n], mass [n], acc [3][n]
+ * device pointers (acc must not alias pos); pot is a HOST pointer. */
+dnb_status dnb_accelerations_noalloc(int64_t n, const double* pos, const double* mass,
+                                     const dnb_pot* pot, int with_ext, dnb_prec prec,
+                                     double* acc, void* stream);
+
 /* Accelerations of the targets i_begin .. i_begin + i_count - 1 only, each summed
  * over all n sources (the rectangular block one device computes when the targets
  * are split over several devices, Sec. 2 and Fig. 1).  pos [3][n] and mass [n]

@@ -48,6 +48,7 @@ def load_library(path=LIB_PATH):
         "dnb_version": ([], ctypes.c_char_p),
         "dnb_accelerations": ([P, I64, P, P, POT, I, P, P], I),
         "dnb_accelerations_rows": ([P, I64, P, P, POT, I, I64, I64, P, P], I),
+        "dnb_accelerations_noalloc": ([I64, P, P, POT, I, I, P, P], I),
         "dnb_accelerations_vjp": ([P, I64, P, P, POT, I, P, I64, I64, P, P, P], I),
         "dnb_step": ([P, I64, P, P, P, POT, D, P], I),
         "dnb_tape_doubles": ([I64, I64, I64], I64),

@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libdnb.so")
 SOURCES = ["api.hip", "pair.hip", "kdk.hip", "aux.hip", "batch.hip", "orbitfit.hip",
-           "surrogate.hip"]
+           "surrogate.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

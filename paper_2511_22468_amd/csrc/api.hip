@@ -295,6 +295,10 @@ dnb_status run_forward(dnb_ctx* c, int64_t n, double* pos, double* vel, const do
 }  // namespace
 
 void dnb::set_error(const char* msg) { g_err = msg; }
+dnb_status dnb::check_pot_args(const dnb_pot* p, const char* fn) { return check_pot(p, fn); }
+dnb_status dnb::check_device_ptr(const void* p, const char* name, const char* fn) {
+    return check_dev(p, name, fn);
+}
 
 extern "C" {
 
@@ -321,6 +325,7 @@ dnb_status dnb_create(dnb_ctx** out, int64_t max_n, dnb_prec prec) {
     // default for experiments.
     c->target_blocks = env_int("DNB_TARGET_BLOCKS", TARGET_BLOCKS, {1024, 2048, 4096, 8192, 16384});
     c->slice_rows = max_slice_rows(max_n, BS, c->target_blocks);
+    c->smax = S_MAX;
     c->nbmax = (int)cdiv(max_n, BS);
     const int64_t npadmax = (int64_t)c->nbmax * BS;
     struct A { void** p; size_t bytes; } allocs[] = {

@@ -224,6 +224,7 @@ struct dnb_ctx {
     int64_t slice_rows;      // capacity of S * npad
     int nbmax;               // max blocks of the O(N) kernels
     int target_blocks;       // pair-kernel blocks wanted per launch
+    int smax;                // cap on the source slices of the square pair launches
     // forward path
     void* js;                // staged sources: FP32C float4 (x, y, z relative to a centre; m),
                              // FP64 double4 (x, y, z, m); padded to pad_sources(n)
@@ -270,14 +271,18 @@ namespace dnb {
 
 // Message returned by dnb_last_error() on this host thread.
 void set_error(const char* msg);
+// Host-side argument checks shared by the entry points (DNB_OK or DNB_ERR_ARG
+// with the message set).
+dnb_status check_pot_args(const dnb_pot* p, const char* fn);
+dnb_status check_device_ptr(const void* p, const char* name, const char* fn);
 
 // Geometry of the forward and VJP pair kernels for this context (FP64 uses one
 // target per lane).
 inline Slicing fwd_slicing(const dnb_ctx* c, int64_t n) {
-    return pair_slicing(n, n, c->target_blocks, S_MAX);
+    return pair_slicing(n, n, c->target_blocks, c->smax);
 }
 inline Slicing vjp_slicing(const dnb_ctx* c, int64_t n) {
-    return pair_slicing(n, n, c->target_blocks, S_MAX);
+    return pair_slicing(n, n, c->target_blocks, c->smax);
 }
 inline Slicing plain_slicing(const dnb_ctx* c, int64_t n) {
     return slicing_for(n, BS, c->target_blocks);

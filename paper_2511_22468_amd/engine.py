@@ -58,6 +58,25 @@ def _arr(t, shape, name):
     return t
 
 
+NOALLOC_MAX_N = 65536
+
+
+def accelerations_noalloc(pos, mass, pot, with_ext=True, prec="fp32c", out=None):
+    """dnb_accelerations_noalloc: the accelerations without a context or any
+    device allocation in the library (n <= 65536; calls on one device must not
+    overlap).  out (optional) receives them in place."""
+    if prec not in _lib.PRECISIONS:
+        raise ValueError(f"prec must be one of {list(_lib.PRECISIONS)}")
+    n = mass.shape[0]
+    _vec(pos, n, "pos"); _arr(mass, (n,), "mass")
+    acc = torch.empty(3, n, dtype=torch.float64, device=pos.device) if out is None \
+        else _vec(out, n, "out")
+    _lib.check(_lib.lib().dnb_accelerations_noalloc(
+        n, _lib.ptr(pos), _lib.ptr(mass), pot.c(), int(bool(with_ext)), _lib.PRECISIONS[prec],
+        _lib.ptr(acc), _lib.stream_handle()))
+    return acc
+
+
 def _buffer(t, length, name):
     """A flat float64 CUDA buffer of at least `length` elements."""
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
