@@ -195,25 +195,104 @@ __device__ inline void ext_hvp(const Pot& p, double x, double y, double z, doubl
     }
 }
 
-// Deterministic block sum of NV doubles per thread (fixed tree order).
-template <int NV>
-__device__ inline void block_sum(double (&v)[NV], double* sh /* [NV][BS] */) {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) sh[k * BS + t] = v[k];
-    __syncthreads();
-    for (int off = BS / 2; off > 0; off >>= 1) {
-        if (t < off) {
-#pragma unroll
-            for (int k = 0; k < NV; ++k) sh[k * BS + t] += sh[k * BS + t + off];
+// ext_accel and ext_hvp at one point in one pass: the square roots, the NFW
+// enclosed-mass profile and the shared quotients are formed once, with the same
+// expressions as in those functions, so both results are the same bits.
+__device__ inline void ext_accel_hvp(const Pot& p, double x, double y, double z, double wx,
+                                     double wy, double wz, Ext& e, double& hx, double& hy,
+                                     double& hz) {
+    e = Ext{};
+    hx = hy = hz = 0.0;
+    if (p.m_nfw != 0.0) {
+        double r2 = x * x + y * y + z * z;
+        double tx = 0.0, ty = 0.0, tz = 0.0;
+        if (r2 != 0.0) {
+            const double G = p.G, rs = p.rs_nfw;
+            double r = sqrt(r2);
+            double mu = nfw_mu(r / rs);
+            double g = G * mu / (r2 * r);
+            e.nx = -g * x; e.ny = -g * y; e.nz = -g * z;
+            double rp = r + rs;
+            double gp = G * (1.0 / (r2 * rp * rp) - 3.0 * mu / (r2 * r2));
+            double c = gp / r * (x * wx + y * wy + z * wz);
+            tx = -g * wx - c * x; ty = -g * wy - c * y; tz = -g * wz - c * z;
         }
-        __syncthreads();
+        hx += p.m_nfw * tx; hy += p.m_nfw * ty; hz += p.m_nfw * tz;
     }
+    if (p.m_mn != 0.0) {
+        const double G = p.G, a = p.a_mn, b = p.b_mn;
+        double S = sqrt(z * z + b * b);
+        double A = a + S;
+        double D2 = x * x + y * y + A * A;
+        double D = sqrt(D2);
+        double k = G / (D2 * D);
+        e.mx = -k * x; e.my = -k * y;
+        e.mz = (S == 0.0) ? 0.0 : -k * z * A / S;
+        double iD3 = 1.0 / (D2 * D);
+        double iD5 = iD3 / D2;
+        double hxx = -G * (iD3 - 3.0 * x * x * iD5);
+        double hyy = -G * (iD3 - 3.0 * y * y * iD5);
+        double hxy = 3.0 * G * x * y * iD5;
+        double hxz = 0.0, hyz = 0.0, hzz = -G * iD3;
+        if (S != 0.0) {
+            double zA_S = z * A / S;
+            hxz = 3.0 * G * x * zA_S * iD5;
+            hyz = 3.0 * G * y * zA_S * iD5;
+            hzz = -G * ((1.0 + a * b * b / (S * S * S)) * iD3 - 3.0 * zA_S * zA_S * iD5);
+        }
+        double tx = hxx * wx + hxy * wy + hxz * wz;
+        double ty = hxy * wx + hyy * wy + hyz * wz;
+        double tz = hxz * wx + hyz * wy + hzz * wz;
+        hx += p.m_mn * tx; hy += p.m_mn * ty; hz += p.m_mn * tz;
+    }
+    e.ax = p.m_nfw * e.nx + p.m_mn * e.mx;
+    e.ay = p.m_nfw * e.ny + p.m_mn * e.my;
+    e.az = p.m_nfw * e.nz + p.m_mn * e.mz;
+}
+
+// Deterministic sum over a block of BS threads of NV doubles per thread: a
+// butterfly across the lanes of each wave (lane i adds lane i ^ m for m = 32 ..
+// 1; x + y == y + x exactly, so every lane of a wave holds the same bits), then
+// the BS / 64 wave sums in wave order.  Every thread gets the block's sums.
+// sh: at least NV * BS / 64 doubles.
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double* sh) {
+    constexpr int NW = BS / 64;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = sh[k * BS];
+    for (int m = 32; m > 0; m >>= 1) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], m, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[k * NW + w] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double a = sh[k * NW];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) a += sh[k * NW + q];
+        v[k] = a;
+    }
     __syncthreads();
 }
 
+// Largest value over a block of BS threads (every thread gets it).  sh: at
+// least BS / 64 doubles.
+__device__ inline double block_max(double v, double* sh) {
+    constexpr int NW = BS / 64;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double a = sh[0];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) a = fmax(a, sh[q]);
+    __syncthreads();
+    return a;
+}
 // ------------------------------------------------------------------ context --
 }  // namespace dnb
 

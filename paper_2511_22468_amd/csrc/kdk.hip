@@ -75,38 +75,51 @@ __global__ __launch_bounds__(BS) void k_stage(const double* __restrict__ x,
 template <int MODE, bool F32>
 __global__ __launch_bounds__(BS) void k_kdk(FwdArgs a, const void* __restrict__ part, int S,
                                             int64_t npad, int64_t nj, void* __restrict__ js) {
-    __shared__ double sh[4 * BS];
+    __shared__ double sh[10 * BS / 64];
     const int64_t n = a.n;
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
     const bool ok = i < n;
     const int64_t k = ok ? i : 0;
     const bool drift = (MODE == KDK_FIRST || MODE == KDK_MID);
+    const bool reduced = F32 && a.ared;
 
+    // every load that does not wait for the block reductions, issued first
+    const double x = a.x[k], y = a.x[n + k], z = a.x[2 * n + k];
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    if (reduced) { ax = a.ared[k]; ay = a.ared[n + k]; az = a.ared[2 * n + k]; }
+    double ux = 0.0, uy = 0.0, uz = 0.0;     // v (FIRST) or v_half (MID, LAST)
+    if (MODE == KDK_FIRST) { ux = a.v[k]; uy = a.v[n + k]; uz = a.v[2 * n + k]; }
+    if (MODE == KDK_MID || MODE == KDK_LAST) { ux = a.vh[k]; uy = a.vh[n + k]; uz = a.vh[2 * n + k]; }
+    const double mk = drift ? a.mass[k] : 0.0;
+
+    // staging centre and net internal force (FP32C), one block reduction
     double cx = 0.0, cy = 0.0, cz = 0.0;
-    if (F32 && drift) {
-        if (a.centre_override) {
-            cx = a.centre_override[0]; cy = a.centre_override[1]; cz = a.centre_override[2];
+    double tot[4] = {0.0, 0.0, 0.0, 1.0};
+    if (F32) {
+        const bool centre = drift && !a.centre_override;
+        if (centre && reduced) {
+            centre_and_total(a.cpart_in, a.nb_in, n, a.arec, a.nr, sh, cx, cy, cz, tot);
         } else {
-            centre_from(a.cpart_in, a.nb_in, n, sh, cx, cy, cz, true);
+            if (centre) centre_from(a.cpart_in, a.nb_in, n, sh, cx, cy, cz, true);
+            if (reduced) rec_total(a.arec, a.nr, sh, tot);
+        }
+        if (drift && a.centre_override) {
+            cx = a.centre_override[0]; cy = a.centre_override[1]; cz = a.centre_override[2];
         }
     }
 
-    double ax, ay, az;
-    if (F32 && a.ared) {
-        // reduced internal acceleration minus the net internal force per unit mass
-        double tot[4];
-        rec_total(a.arec, a.nr, sh, tot);
+    if (reduced) {
+        // the reduced internal acceleration minus the net internal force per unit mass
         const double inv_m = 1.0 / tot[3];
-        ax = a.ared[k] - tot[0] * inv_m;
-        ay = a.ared[n + k] - tot[1] * inv_m;
-        az = a.ared[2 * n + k] - tot[2] * inv_m;
+        ax -= tot[0] * inv_m;
+        ay -= tot[1] * inv_m;
+        az -= tot[2] * inv_m;
     } else {
         pair_sum<F32>(part, S, npad, k, a.pot.G, ax, ay, az);
     }
     if (a.aint_out && ok) {
         a.aint_out[i] = ax; a.aint_out[n + i] = ay; a.aint_out[2 * n + i] = az;
     }
-    const double x = a.x[k], y = a.x[n + k], z = a.x[2 * n + k];
     if (a.with_ext) {
         Ext e = ext_accel(a.pot, x, y, z);
         ax += e.ax; ay += e.ay; az += e.az;
@@ -117,17 +130,17 @@ __global__ __launch_bounds__(BS) void k_kdk(FwdArgs a, const void* __restrict__ 
         if (MODE == KDK_ACC) {
             if (a.acc_out) { a.acc_out[i] = ax; a.acc_out[n + i] = ay; a.acc_out[2 * n + i] = az; }
         } else if (MODE == KDK_LAST) {
-            a.v[i] = fma(hdt, ax, a.vh[i]);
-            a.v[n + i] = fma(hdt, ay, a.vh[n + i]);
-            a.v[2 * n + i] = fma(hdt, az, a.vh[2 * n + i]);
+            a.v[i] = fma(hdt, ax, ux);
+            a.v[n + i] = fma(hdt, ay, uy);
+            a.v[2 * n + i] = fma(hdt, az, uz);
         } else {
             double vx, vy, vz;
             if (MODE == KDK_FIRST) {
-                vx = a.v[i]; vy = a.v[n + i]; vz = a.v[2 * n + i];
+                vx = ux; vy = uy; vz = uz;
             } else {
-                vx = fma(hdt, ax, a.vh[i]);
-                vy = fma(hdt, ay, a.vh[n + i]);
-                vz = fma(hdt, az, a.vh[2 * n + i]);
+                vx = fma(hdt, ax, ux);
+                vy = fma(hdt, ay, uy);
+                vz = fma(hdt, az, uz);
             }
             if (a.tape_state) {
                 double* t = a.tape_state;
@@ -141,7 +154,7 @@ __global__ __launch_bounds__(BS) void k_kdk(FwdArgs a, const void* __restrict__ 
         }
     }
     if (drift) {
-        if (i < nj) put_source<F32>(js, i, ok, xn, yn, zn, a.mass[k], cx, cy, cz);
+        if (i < nj) put_source<F32>(js, i, ok, xn, yn, zn, mk, cx, cy, cz);
         if (F32) {
             write_block_sums(xn, yn, zn, xn - x, yn - y, zn - z, ok, sh, a.cpart_out);
             if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -296,39 +309,56 @@ template <bool F32>
 __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restrict__ part, int S,
                                                  int64_t npad, int64_t nj,
                                                  void* __restrict__ jsv) {
-    __shared__ double sh[4 * BS];
+    __shared__ double sh[10 * BS / 64];
     const int64_t n = a.n;
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
     const bool ok = i < n;
     const int64_t k = ok ? i : 0;
     const bool drift = a.x_prev != nullptr;
 
-    double cx = 0.0, cy = 0.0, cz = 0.0;
-    if (F32 && drift) centre_from(a.cpart_in, a.nb_in, n, sh, cx, cy, cz, true);
-
-    double g[3], gm = 0.0;
+    // every load that does not wait for the block reductions, issued first
+    const double x = a.x_n[k], y = a.x_n[n + k], z = a.x_n[2 * n + k];
+    const double wx = a.lv[k], wy = a.lv[n + k], wz = a.lv[2 * n + k];
+    const double lx0 = a.lx[k], ly0 = a.lx[n + k], lz0 = a.lx[2 * n + k];
+    const double ai[3] = {a.aint[k], a.aint[n + k], a.aint[2 * n + k]};
+    double g[3] = {0.0, 0.0, 0.0}, gm = 0.0;
     if (F32) {
-        // reduced J^T w (cotangent scale undone) minus its mean over the particles
-        double tot[4];
-        rec_total(a.grec, a.nr, sh, tot);
-        const double inv_n = 1.0 / (double)n;
-        g[0] = a.gred[k] - tot[0] * inv_n;
-        g[1] = a.gred[n + k] - tot[1] * inv_n;
-        g[2] = a.gred[2 * n + k] - tot[2] * inv_n;
+        g[0] = a.gred[k]; g[1] = a.gred[n + k]; g[2] = a.gred[2 * n + k];
         if (a.with_mass) gm = a.gred[3 * n + k];
+    }
+    double px = 0.0, py = 0.0, pz = 0.0, mk = 0.0;
+    if (drift) {
+        px = a.x_prev[k]; py = a.x_prev[n + k]; pz = a.x_prev[2 * n + k];
+        mk = a.mass[k];
+    }
+    const double acc0[5] = {a.accum[k], a.accum[n + k], a.accum[2 * n + k], a.accum[3 * n + k],
+                            a.with_mass ? a.accum[4 * n + k] : 0.0};
+
+    // staging centre, cotangent scale and sum of J^T w (FP32C)
+    double cx = 0.0, cy = 0.0, cz = 0.0, Sn = 1.0;
+    if (F32) {
+        double tot[4];
+        if (drift) {
+            centre_and_total(a.cpart_in, a.nb_in, n, a.grec, a.nr, sh, cx, cy, cz, tot);
+            Sn = scale_from(a.cpart_in, a.nb_in, sh);
+        } else {
+            rec_total(a.grec, a.nr, sh, tot);
+        }
+        // the reduced J^T w (cotangent scale undone) minus its mean over the particles
+        const double inv_n = 1.0 / (double)n;
+        g[0] -= tot[0] * inv_n;
+        g[1] -= tot[1] * inv_n;
+        g[2] -= tot[2] * inv_n;
     } else {
         vjp_sum<F32>(part, S, npad, k, a.pot.G, a.with_mass != 0, g, gm);
     }
-    const double ai[3] = {a.aint[k], a.aint[n + k], a.aint[2 * n + k]};
-    const double x = a.x_n[k], y = a.x_n[n + k], z = a.x_n[2 * n + k];
-    const double wx = a.lv[k], wy = a.lv[n + k], wz = a.lv[2 * n + k];
-    Ext e = ext_accel(a.pot, x, y, z);
+    Ext e;
     double hx, hy, hz;
-    ext_hvp(a.pot, x, y, z, wx, wy, wz, hx, hy, hz);
+    ext_accel_hvp(a.pot, x, y, z, wx, wy, wz, e, hx, hy, hz);
 
-    const double lx = fma(a.coef, g[0] + hx, a.lx[k]);
-    const double ly = fma(a.coef, g[1] + hy, a.lx[n + k]);
-    const double lz = fma(a.coef, g[2] + hz, a.lx[2 * n + k]);
+    const double lx = fma(a.coef, g[0] + hx, lx0);
+    const double ly = fma(a.coef, g[1] + hy, ly0);
+    const double lz = fma(a.coef, g[2] + hz, lz0);
     const double kc = a.coef / a.dt;
     const double aw_int = ai[0] * wx + ai[1] * wy + ai[2] * wz;
     const double aw_ext = e.ax * wx + e.ay * wy + e.az * wz;
@@ -337,10 +367,8 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
     const double d_mn = a.coef * (e.mx * wx + e.my * wy + e.mz * wz);
     const double d_ms = a.coef * aw_int;
 
-    double px = 0.0, py = 0.0, pz = 0.0;
     double nwx = wx, nwy = wy, nwz = wz;
     if (drift) {
-        px = a.x_prev[k]; py = a.x_prev[n + k]; pz = a.x_prev[2 * n + k];
         const double inv = 1.0 / a.dt;
         const double vx = (x - px) * inv, vy = (y - py) * inv, vz = (z - pz) * inv;
         d_dt += vx * lx + vy * ly + vz * lz;
@@ -348,17 +376,16 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
     }
     if (ok) {
         a.lx[i] = lx; a.lx[n + i] = ly; a.lx[2 * n + i] = lz;
-        a.accum[i] += d_nfw;
-        a.accum[n + i] += d_mn;
-        a.accum[2 * n + i] += d_dt;
-        a.accum[3 * n + i] += d_ms;
-        if (a.with_mass) a.accum[4 * n + i] -= a.coef * gm;
+        a.accum[i] = acc0[0] + d_nfw;
+        a.accum[n + i] = acc0[1] + d_mn;
+        a.accum[2 * n + i] = acc0[2] + d_dt;
+        a.accum[3 * n + i] = acc0[3] + d_ms;
+        if (a.with_mass) a.accum[4 * n + i] = acc0[4] - a.coef * gm;
         if (drift) { a.lv[i] = nwx; a.lv[n + i] = nwy; a.lv[2 * n + i] = nwz; }
     }
     if (drift) {
-        const double Sn = F32 ? scale_from(a.cpart_in, a.nb_in, sh) : 1.0;
         if (i < nj)
-            put_source_w<F32>(jsv, i, ok, px, py, pz, a.mass[k], cx, cy, cz, nwx * Sn, nwy * Sn,
+            put_source_w<F32>(jsv, i, ok, px, py, pz, mk, cx, cy, cz, nwx * Sn, nwy * Sn,
                               nwz * Sn);
         if (F32) {
             write_block_sums(px, py, pz, px - x, py - y, pz - z, ok, sh, a.cpart_out);

@@ -26,22 +26,20 @@ constexpr double FAR64 = 1.0e150;
 // the mean recorded displacement (the centre of the positions one step on).
 __device__ inline void centre_from(const double* __restrict__ cpart, int nb, int64_t n, double* sh,
                                    double& cx, double& cy, double& cz, bool extrapolate) {
-    double v[3] = {0.0, 0.0, 0.0};
-    double d[3] = {0.0, 0.0, 0.0};
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nb; b += BS) {
         v[0] += cpart[REC * b + 0];
         v[1] += cpart[REC * b + 1];
         v[2] += cpart[REC * b + 2];
         if (extrapolate) {
-            d[0] += cpart[REC * b + 4];
-            d[1] += cpart[REC * b + 5];
-            d[2] += cpart[REC * b + 6];
+            v[3] += cpart[REC * b + 4];
+            v[4] += cpart[REC * b + 5];
+            v[5] += cpart[REC * b + 6];
         }
     }
-    block_sum<3>(v, sh);
-    if (extrapolate) block_sum<3>(d, sh);
+    block_sum<6>(v, sh);
     const double inv = 1.0 / (double)n;
-    cx = (v[0] + d[0]) * inv; cy = (v[1] + d[1]) * inv; cz = (v[2] + d[2]) * inv;
+    cx = (v[0] + v[3]) * inv; cy = (v[1] + v[4]) * inv; cz = (v[2] + v[5]) * inv;
 }
 
 // Record of this block: sums of (x, y, z) and of the displacement (dx, dy, dz)
@@ -49,14 +47,13 @@ __device__ inline void centre_from(const double* __restrict__ cpart, int nb, int
 __device__ inline void write_block_sums(double x, double y, double z, double dx, double dy,
                                         double dz, bool valid, double* sh,
                                         double* __restrict__ cpart_out) {
-    double v[3] = {valid ? x : 0.0, valid ? y : 0.0, valid ? z : 0.0};
-    double d[3] = {valid ? dx : 0.0, valid ? dy : 0.0, valid ? dz : 0.0};
-    block_sum<3>(v, sh);
-    block_sum<3>(d, sh);
+    double v[6] = {valid ? x : 0.0, valid ? y : 0.0, valid ? z : 0.0,
+                   valid ? dx : 0.0, valid ? dy : 0.0, valid ? dz : 0.0};
+    block_sum<6>(v, sh);
     if (threadIdx.x == 0) {
         double* c = cpart_out + REC * blockIdx.x;
         c[0] = v[0]; c[1] = v[1]; c[2] = v[2]; c[3] = 0.0;
-        c[4] = d[0]; c[5] = d[1]; c[6] = d[2]; c[7] = 0.0;
+        c[4] = v[3]; c[5] = v[4]; c[6] = v[5]; c[7] = 0.0;
     }
 }
 
@@ -72,28 +69,15 @@ __device__ inline double absmax3(double a, double b, double c) {
 }
 
 __device__ inline void write_block_max(double v, double* sh, double* __restrict__ cpart_out) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = BS / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) cpart_out[REC * blockIdx.x + 3] = sh[0];
-    __syncthreads();
+    const double m = block_max(v, sh);
+    if (threadIdx.x == 0) cpart_out[REC * blockIdx.x + 3] = m;
 }
 
 // Power-of-two scale from the block maxima in slot 3 of cpart (1 if all zero).
 __device__ inline double scale_from(const double* __restrict__ cpart, int nb, double* sh) {
     double m = 0.0;
     for (int b = threadIdx.x; b < nb; b += BS) m = fmax(m, cpart[REC * b + 3]);
-    sh[threadIdx.x] = m;
-    __syncthreads();
-    for (int off = BS / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
-        __syncthreads();
-    }
-    m = sh[0];
-    __syncthreads();
+    m = block_max(m, sh);
     if (!(m > 0.0) || !isfinite(m)) return 1.0;
     int e;
     (void)frexp(m, &e);
@@ -248,25 +232,16 @@ __device__ inline void slice_reduce(const float2* __restrict__ part, int S, int6
     __syncthreads();
 }
 
-// Tree sum over the RT lanes of group 0 of NV values (result in every thread).
+// Butterfly sum over the RT = 64 lanes of each wave of NV values (every lane of
+// a wave gets its wave's sum; group 0, the first wave, holds the block's).
 template <int NV>
-__device__ inline void rt_sum(double (&v)[NV], double* sh) {
-    const int t = threadIdx.x;
-    if (t < RT) {
+__device__ inline void rt_sum(double (&v)[NV]) {
+    static_assert(RT == 64, "one wave per group");
 #pragma unroll
-        for (int k = 0; k < NV; ++k) sh[k * RT + t] = v[k];
+    for (int m = 32; m > 0; m >>= 1) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], m, 64);
     }
-    __syncthreads();
-    for (int off = RT / 2; off > 0; off >>= 1) {
-        if (t < off) {
-#pragma unroll
-            for (int k = 0; k < NV; ++k) sh[k * RT + t] += sh[k * RT + t + off];
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = sh[k * RT];
-    __syncthreads();
 }
 
 // Forward reduction for targets [blockIdx.x RT, +RT) of one system: ared [3][n]
@@ -291,7 +266,7 @@ __device__ inline void fwd_reduce_block(const float2* __restrict__ part, int S, 
         a[0] = a[1] = a[2] = 0.0;
     }
     double v[4] = {m * a[0], m * a[1], m * a[2], m};
-    rt_sum<4>(v, sh);
+    rt_sum<4>(v);
     if (threadIdx.x == 0)
         for (int c = 0; c < 4; ++c) rec[4 * blockIdx.x + c] = v[c];
 }
@@ -322,11 +297,35 @@ __device__ inline void vjp_reduce_block(const float2* __restrict__ part, int S, 
         g[0] = g[1] = g[2] = 0.0;
     }
     double v[3] = {g[0], g[1], g[2]};
-    rt_sum<3>(v, sh);
+    rt_sum<3>(v);
     if (threadIdx.x == 0) {
         for (int c = 0; c < 3; ++c) rec[4 * blockIdx.x + c] = v[c];
         rec[4 * blockIdx.x + 3] = 0.0;
     }
+}
+
+// The staging centre (as centre_from with extrapolation) and the sums of the nr
+// net-force records (as rec_total) in one block reduction.
+__device__ inline void centre_and_total(const double* __restrict__ cpart, int nb, int64_t n,
+                                        const double* __restrict__ rec, int nr, double* sh,
+                                        double& cx, double& cy, double& cz, double (&tot)[4]) {
+    double v[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) v[k] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += BS) {
+        v[0] += cpart[REC * b + 0];
+        v[1] += cpart[REC * b + 1];
+        v[2] += cpart[REC * b + 2];
+        v[3] += cpart[REC * b + 4];
+        v[4] += cpart[REC * b + 5];
+        v[5] += cpart[REC * b + 6];
+    }
+    for (int b = threadIdx.x; b < nr; b += BS)
+        for (int c = 0; c < 4; ++c) v[6 + c] += rec[4 * b + c];
+    block_sum<10>(v, sh);
+    const double inv = 1.0 / (double)n;
+    cx = (v[0] + v[3]) * inv; cy = (v[1] + v[4]) * inv; cz = (v[2] + v[5]) * inv;
+    for (int c = 0; c < 4; ++c) tot[c] = v[6 + c];
 }
 
 // Sum of the nr reduction records (fixed order; every thread gets it).
