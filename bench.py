@@ -159,7 +159,7 @@ def sweep(prec, sizes=(1024, 4096, 8192, 16384, 65536), reps=20):
             ctx.simulate_vjp(m, pot, myr(0.5), T, 1, tape, xx, w)
             torch.cuda.synchronize()
             p = ctx.profile_read()
-        shard = None
+        shard = unequal = None
         if n >= 65536:
             # one device's block of the system split over 8: n / 8 targets x n sources
             ni = n // 8
@@ -183,6 +183,24 @@ def sweep(prec, sizes=(1024, 4096, 8192, 16384, 65536), reps=20):
             shard = {"targets": ni, "sources": n, "fwd_us": s_ms * 1e3,
                      "fwd_pairs_per_s": ni * n / (s_ms * 1e-3), "vjp_us": sv_ms * 1e3,
                      "vjp_pairs_per_s": ni * n / (sv_ms * 1e-3)}
+            # the general (unequal-mass) path of both kernels: masses drawn
+            # uniformly in [0.5, 1.5] x M / n (seeded), the mass inside the pair term
+            mu = np.random.Generator(np.random.PCG64(9)).uniform(0.5, 1.5, n)
+            mu = torch.tensor(mu * (1e5 / mu.sum()), device=dev)
+            for _ in range(2):
+                ctx.profile(True)
+                ctx.profile_read()
+                for _ in range(reps):
+                    ctx.accelerations(x, mu, pot)
+                    ctx.accelerations_vjp(x, mu, pot, w, with_mass=False)
+                torch.cuda.synchronize()
+                q = ctx.profile_read()
+            uf, uv = q["fwd_ms"] / q["fwd_launches"], q["vjp_ms"] / q["vjp_launches"]
+            unequal = {"fwd_us": uf * 1e3, "vjp_us": uv * 1e3,
+                       "fwd_pairs_per_s": n * n / (uf * 1e-3),
+                       "vjp_pairs_per_s": n * n / (uv * 1e-3),
+                       "fwd_frac_of_157.3TF": FLOPS_FWD * n * n / (uf * 1e-3) / 157.3e12,
+                       "vjp_frac_of_157.3TF": FLOPS_VJP * n * n / (uv * 1e-3) / 157.3e12}
         ctx.close()
         f_ms = p["fwd_ms"] / p["fwd_launches"]
         v_ms = p["vjp_ms"] / p["vjp_launches"]
@@ -193,6 +211,8 @@ def sweep(prec, sizes=(1024, 4096, 8192, 16384, 65536), reps=20):
                "vjp_frac_of_157.3TF": FLOPS_VJP * n * n / (v_ms * 1e-3) / 157.3e12}
         if shard:
             row["shard_rows"] = shard
+        if unequal:
+            row["unequal_masses"] = unequal
         rows.append(row)
     return {"sweep": rows, "prec": prec}
 
@@ -557,6 +577,8 @@ def main():
     ap.add_argument("--ckpt-every", type=int, default=1)
     ap.add_argument("--prec", default="fp32c", choices=["fp32c", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-checkpointed", action="store_true",
+                    help="skip the one-step timing with checkpoints every 100 steps")
     ap.add_argument("--no-time-to-fit", action="store_true",
                     help="skip the time-to-fit comparison that the default line carries")
     ap.add_argument("--profile-run", action="store_true",
@@ -753,6 +775,24 @@ def main():
         },
         "cpu_baseline": None,
     }
+    if K == 1 and not args.profile_run and not args.no_checkpointed:
+        # the same step with checkpoints every 100 steps: the reverse sweep
+        # recomputes each segment from its checkpoint (one more forward pair sum
+        # per step) instead of reading a full tape
+        model_k = StreamModel(ctx, xi, zeta, target, T, pot=pot, h=0.2, ckpt_every=100)
+        model_k.loss_and_grad(theta)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Lk, gk = model_k.loss_and_grad(theta)
+        torch.cuda.synchronize()
+        sk = time.perf_counter() - t0
+        out["checkpointed"] = {
+            "ckpt_every": 100, "steps": 1, "warmup": 1, "ms_per_step": sk * 1e3,
+            "value": pairs / sk, "unit": "pair interactions/s (forward and adjoint, as value)",
+            "pair_evaluations_per_s": (pairs + T * float(n) * n) / sk,
+            "tape_bytes": 8 * ctx.tape_len(n, T, 100), "full_tape_bytes": 8 * ctx.tape_len(n, T, 1),
+            "same_gradient_as_full_tape": bool(torch.equal(gk, g) and torch.equal(Lk, L)),
+        }
     ctx.close()
     if args.profile_run:
         # calibration for the traffic counters: a plain copy of 256 MiB
