@@ -49,7 +49,18 @@ __device__ __forceinline__ double rsqrt_f64(double s) {
 // component, one 8-byte load for the consumer).
 // muni: [flag, m] -- flag != 0 when every particle has mass m (set per call by
 // k_mass_info); the branch on it is uniform over the grid.
-template <bool EPS0>
+//
+// Short slices (a system of up to some 16k particles, cut into many slices so
+// that the launch still fills the chip) are latency-bound: a block runs a few
+// hundred pairs per lane, and each scalar-load batch waits on the scalar
+// cache.  With LDS the block first copies its slice into LDS (one coalesced
+// load per lane), and every batch is then an LDS broadcast.  A long slice keeps
+// the scalar loads: an LDS broadcast of 16 bytes to 64 lanes takes the LDS
+// several cycles, which at full occupancy competes with the arithmetic, while
+// scalar loads cost the vector units nothing.  Both give the same bits.
+constexpr int FWD_LDS_SLICE = 256;   // longest slice that takes the LDS kernel
+
+template <bool EPS0, bool LDS>
 __global__ __launch_bounds__(BS) void k_pair_fwd_f32c(const float4* __restrict__ js, int n,
                                                       int i0, int iend, int nj, int jslice,
                                                       float eps2, float* __restrict__ part,
@@ -60,7 +71,20 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f32c(const float4* __restrict__
     const int j1 = min(nj, j0 + jslice);
     const float4 me = js[min(i, n - 1)];
     float h[3] = {0.f, 0.f, 0.f}, l[3] = {0.f, 0.f, 0.f};
-    if (muni[0] != 0.f) {
+    if (LDS) {
+        __shared__ float4 lds[FWD_LDS_SLICE];
+        const int jl = min(j1, j0 + FWD_LDS_SLICE);   // the launcher keeps j1 - j0 within it
+        for (int t = threadIdx.x; t < jl - j0; t += BS) lds[t] = js[j0 + t];
+        __syncthreads();
+        if (muni[0] != 0.f) {
+            fwd_f32c_slice_lds<EPS0, true>(lds, i, j0, jl, eps2, me, h, l);
+            const float m = muni[1];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { h[c] *= m; l[c] *= m; }
+        } else {
+            fwd_f32c_slice_lds<EPS0, false>(lds, i, j0, jl, eps2, me, h, l);
+        }
+    } else if (muni[0] != 0.f) {
         fwd_f32c_slice<EPS0, true>(js, i, j0, j1, eps2, me, h, l);
         const float m = muni[1];
 #pragma unroll
@@ -122,8 +146,11 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f64(const double4* __restrict__
 }
 
 // --------------------------------------------------------------- VJP FP32C --
-// The slice sum is vjp_f32c_slice (pair_common.h).
-template <bool EPS0, bool MASS>
+// The slice sum is vjp_f32c_slice (pair_common.h); with LDS the block first
+// copies its slice (two float4 per source) into LDS, as in the forward kernel.
+constexpr int VJP_LDS_SLICE = 64;    // longest slice that takes the LDS kernel
+
+template <bool EPS0, bool MASS, bool LDS>
 __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__ jsv, int n,
                                                       int i0, int iend, int nj, int jslice,
                                                       float eps2, float* __restrict__ part,
@@ -137,7 +164,20 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__
     const float4 mw = jsv[2 * ii + 1];
     float h[4] = {0.f, 0.f, 0.f, 0.f};
     float l[4] = {0.f, 0.f, 0.f, 0.f};
-    if (muni[0] != 0.f) {
+    if (LDS) {
+        __shared__ float4 lds[2 * VJP_LDS_SLICE];
+        const int jl = min(j1, j0 + VJP_LDS_SLICE);   // the launcher keeps j1 - j0 within it
+        for (int t = threadIdx.x; t < 2 * (jl - j0); t += BS) lds[t] = jsv[2 * j0 + t];
+        __syncthreads();
+        if (muni[0] != 0.f) {
+            vjp_f32c_slice_lds<EPS0, MASS, true>(lds, i, j0, jl, eps2, me, mw, h, l);
+            const float m = muni[1];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { h[c] *= m; l[c] *= m; }
+        } else {
+            vjp_f32c_slice_lds<EPS0, MASS, false>(lds, i, j0, jl, eps2, me, mw, h, l);
+        }
+    } else if (muni[0] != 0.f) {
         vjp_f32c_slice<EPS0, MASS, true>(jsv, i, j0, j1, eps2, me, mw, h, l);
         const float m = muni[1];
 #pragma unroll
@@ -226,12 +266,23 @@ static hipError_t launch_pair_fwd_sliced(dnb_ctx* c, int64_t n, int64_t i0, int6
     if (c->prec == DNB_FP32C) {
         const float eps2 = (float)(eps * eps);
         const float4* js = (const float4*)c->js;
-        if (eps == 0.0)
-            hipLaunchKernelGGL(k_pair_fwd_f32c<true>, grid, dim3(BS), 0, st, js, (int)n, a, e, nj,
-                               sl.jslice, eps2, (float*)c->part, sl.npad, c->muni);
-        else
-            hipLaunchKernelGGL(k_pair_fwd_f32c<false>, grid, dim3(BS), 0, st, js, (int)n, a, e,
-                               nj, sl.jslice, eps2, (float*)c->part, sl.npad, c->muni);
+        float* part = (float*)c->part;
+        const bool lds = sl.jslice <= FWD_LDS_SLICE;
+        if (eps == 0.0) {
+            if (lds)
+                hipLaunchKernelGGL((k_pair_fwd_f32c<true, true>), grid, dim3(BS), 0, st, js,
+                                   (int)n, a, e, nj, sl.jslice, eps2, part, sl.npad, c->muni);
+            else
+                hipLaunchKernelGGL((k_pair_fwd_f32c<true, false>), grid, dim3(BS), 0, st, js,
+                                   (int)n, a, e, nj, sl.jslice, eps2, part, sl.npad, c->muni);
+        } else {
+            if (lds)
+                hipLaunchKernelGGL((k_pair_fwd_f32c<false, true>), grid, dim3(BS), 0, st, js,
+                                   (int)n, a, e, nj, sl.jslice, eps2, part, sl.npad, c->muni);
+            else
+                hipLaunchKernelGGL((k_pair_fwd_f32c<false, false>), grid, dim3(BS), 0, st, js,
+                                   (int)n, a, e, nj, sl.jslice, eps2, part, sl.npad, c->muni);
+        }
     } else {
         const double eps2 = eps * eps;
         const double4* js = (const double4*)c->js;
@@ -258,8 +309,12 @@ template <bool EPS0, bool MASS>
 static void vjp_dispatch(dnb_ctx* c, const Slicing& sl, int64_t n, int i0, int iend, int nj,
                          double eps2, hipStream_t st) {
     dim3 grid(sl.nblk, sl.S);
-    if (c->prec == DNB_FP32C)
-        hipLaunchKernelGGL((k_pair_vjp_f32c<EPS0, MASS>), grid, dim3(BS), 0, st,
+    if (c->prec == DNB_FP32C && sl.jslice <= VJP_LDS_SLICE)
+        hipLaunchKernelGGL((k_pair_vjp_f32c<EPS0, MASS, true>), grid, dim3(BS), 0, st,
+                           (const float4*)c->jsv, (int)n, i0, iend, nj, sl.jslice, (float)eps2,
+                           (float*)c->partv, sl.npad, c->muni);
+    else if (c->prec == DNB_FP32C)
+        hipLaunchKernelGGL((k_pair_vjp_f32c<EPS0, MASS, false>), grid, dim3(BS), 0, st,
                            (const float4*)c->jsv, (int)n, i0, iend, nj, sl.jslice, (float)eps2,
                            (float*)c->partv, sl.npad, c->muni);
     else

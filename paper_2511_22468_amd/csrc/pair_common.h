@@ -22,6 +22,21 @@ __device__ __forceinline__ int next_batch(int jt, int k, int PB, int kend, int j
     return (k + PB < kend) ? jt + k + PB : min(jt + SUBTILE, j1 - PB);
 }
 
+// One pair of the forward slice sum: source q (position, mass) at index j onto
+// target i at me, accumulated into (ax, ay, az).
+template <bool EPS0, bool UNI>
+__device__ __forceinline__ void fwd_f32c_pair(float4 q, int j, int i, float eps2, float4 me,
+                                              float& ax, float& ay, float& az) {
+    const float dx = q.x - me.x, dy = q.y - me.y, dz = q.z - me.z;
+    const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+    const float r = __builtin_amdgcn_rsqf(s);
+    float w = UNI ? (r * r) * r : (q.w * r) * (r * r);
+    if (EPS0) w = (j == i) ? 0.f : w;
+    ax = fmaf(w, dx, ax);
+    ay = fmaf(w, dy, ay);
+    az = fmaf(w, dz, az);
+}
+
 // Sum over the slice [j0, j1) of the staged sources js for target i (position
 // me) into the (hi, lo) pairs: plain FP32 within sub-tiles of 128 sources, TwoSum
 // across them.  Sources are read with wave-uniform addresses (scalar loads), one
@@ -45,19 +60,37 @@ __device__ __forceinline__ void fwd_f32c_slice(const float4* __restrict__ js, in
 #pragma unroll
             for (int u = 0; u < PB; ++u) qb[u] = js[nx + u];
 #pragma unroll
-            for (int u = 0; u < PB; ++u) {
-                const float4 q = qa[u];
-                const float dx = q.x - me.x, dy = q.y - me.y, dz = q.z - me.z;
-                const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
-                const float r = __builtin_amdgcn_rsqf(s);
-                float w = UNI ? (r * r) * r : (q.w * r) * (r * r);
-                if (EPS0) w = (jt + k + u == i) ? 0.f : w;
-                ax = fmaf(w, dx, ax);
-                ay = fmaf(w, dy, ay);
-                az = fmaf(w, dz, az);
-            }
+            for (int u = 0; u < PB; ++u)
+                fwd_f32c_pair<EPS0, UNI>(qa[u], jt + k + u, i, eps2, me, ax, ay, az);
 #pragma unroll
             for (int u = 0; u < PB; ++u) qa[u] = qb[u];
+        }
+        two_sum_acc(h[0], l[0], ax);
+        two_sum_acc(h[1], l[1], ay);
+        two_sum_acc(h[2], l[2], az);
+    }
+}
+
+// The same sum with the slice's sources held in LDS (lds[j - j0] is source j):
+// the same pairs in the same order, so the result is bit for bit that of
+// fwd_f32c_slice.  The reads are LDS broadcasts issued at the top of each batch
+// of 4; other waves cover their latency, so no batch is held in registers ahead
+// of use.
+template <bool EPS0, bool UNI>
+__device__ __forceinline__ void fwd_f32c_slice_lds(const float4* lds, int i, int j0, int j1,
+                                                   float eps2, float4 me, float (&h)[3],
+                                                   float (&l)[3]) {
+    constexpr int PB = 4;
+    for (int jt = j0; jt < j1; jt += SUBTILE) {
+        float ax = 0.f, ay = 0.f, az = 0.f;
+        const int kend = min(SUBTILE, j1 - jt);
+        for (int k = 0; k < kend; k += PB) {
+            float4 q[PB];
+#pragma unroll
+            for (int u = 0; u < PB; ++u) q[u] = lds[jt - j0 + k + u];
+#pragma unroll
+            for (int u = 0; u < PB; ++u)
+                fwd_f32c_pair<EPS0, UNI>(q[u], jt + k + u, i, eps2, me, ax, ay, az);
         }
         two_sum_acc(h[0], l[0], ax);
         two_sum_acc(h[1], l[1], ay);
@@ -78,6 +111,30 @@ __device__ __forceinline__ void fwd_f32c_slice(const float4* __restrict__ js, in
 // u = m (w_j - w_k): the mass leaves the pair term and is applied once per
 // target, 22 VALU operations and one v_rsq_f32 per pair.
 template <bool EPS0, bool MASS, bool UNI>
+__device__ __forceinline__ void vjp_f32c_pair(float4 q, float4 qw, int j, int i, float eps2,
+                                              float4 me, float4 mw, float (&A)[3],
+                                              float (&B)[3], float& gm) {
+    const float dx = q.x - me.x, dy = q.y - me.y, dz = q.z - me.z;
+    const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
+    float r = __builtin_amdgcn_rsqf(s);
+    if (EPS0) r = (j == i) ? 0.f : r;
+    const float r2 = r * r;
+    const float r3 = r2 * r;
+    const float r5 = r3 * r2;
+    const float ux = UNI ? qw.x - mw.x : fmaf(me.w, qw.x, -(q.w * mw.x));
+    const float uy = UNI ? qw.y - mw.y : fmaf(me.w, qw.y, -(q.w * mw.y));
+    const float uz = UNI ? qw.z - mw.z : fmaf(me.w, qw.z, -(q.w * mw.z));
+    const float t = r5 * fmaf(dx, ux, fmaf(dy, uy, dz * uz));
+    A[0] = fmaf(r3, ux, A[0]);
+    A[1] = fmaf(r3, uy, A[1]);
+    A[2] = fmaf(r3, uz, A[2]);
+    B[0] = fmaf(t, dx, B[0]);
+    B[1] = fmaf(t, dy, B[1]);
+    B[2] = fmaf(t, dz, B[2]);
+    if (MASS) gm = fmaf(fmaf(dx, qw.x, fmaf(dy, qw.y, dz * qw.z)), r3, gm);
+}
+
+template <bool EPS0, bool MASS, bool UNI>
 __device__ __forceinline__ void vjp_f32c_slice(const float4* __restrict__ jsv, int i, int j0,
                                                int j1, float eps2, float4 me, float4 mw,
                                                float (&h)[4], float (&l)[4]) {
@@ -94,30 +151,39 @@ __device__ __forceinline__ void vjp_f32c_slice(const float4* __restrict__ jsv, i
 #pragma unroll
             for (int u = 0; u < PB; ++u) { pb[u] = jsv[2 * (nx + u)]; wb[u] = jsv[2 * (nx + u) + 1]; }
 #pragma unroll
-            for (int u = 0; u < PB; ++u) {
-                const float4 q = pa[u];
-                const float4 qw = wa[u];
-                const float dx = q.x - me.x, dy = q.y - me.y, dz = q.z - me.z;
-                const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
-                float r = __builtin_amdgcn_rsqf(s);
-                if (EPS0) r = (jt + k + u == i) ? 0.f : r;
-                const float r2 = r * r;
-                const float r3 = r2 * r;
-                const float r5 = r3 * r2;
-                const float ux = UNI ? qw.x - mw.x : fmaf(me.w, qw.x, -(q.w * mw.x));
-                const float uy = UNI ? qw.y - mw.y : fmaf(me.w, qw.y, -(q.w * mw.y));
-                const float uz = UNI ? qw.z - mw.z : fmaf(me.w, qw.z, -(q.w * mw.z));
-                const float t = r5 * fmaf(dx, ux, fmaf(dy, uy, dz * uz));
-                A[0] = fmaf(r3, ux, A[0]);
-                A[1] = fmaf(r3, uy, A[1]);
-                A[2] = fmaf(r3, uz, A[2]);
-                B[0] = fmaf(t, dx, B[0]);
-                B[1] = fmaf(t, dy, B[1]);
-                B[2] = fmaf(t, dz, B[2]);
-                if (MASS) gm = fmaf(fmaf(dx, qw.x, fmaf(dy, qw.y, dz * qw.z)), r3, gm);
-            }
+            for (int u = 0; u < PB; ++u)
+                vjp_f32c_pair<EPS0, MASS, UNI>(pa[u], wa[u], jt + k + u, i, eps2, me, mw, A, B, gm);
 #pragma unroll
             for (int u = 0; u < PB; ++u) { pa[u] = pb[u]; wa[u] = wb[u]; }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) two_sum_acc(h[c], l[c], fmaf(-3.f, B[c], A[c]));
+        if (MASS) two_sum_acc(h[3], l[3], gm);
+    }
+}
+
+// The same sum with the slice's interleaved sources held in LDS (lds[2 (j - j0)]
+// and lds[2 (j - j0) + 1] are those of source j): the same pairs in the same
+// order, bit for bit the result of vjp_f32c_slice, with the reads issued at the
+// top of each batch rather than one batch ahead.
+template <bool EPS0, bool MASS, bool UNI>
+__device__ __forceinline__ void vjp_f32c_slice_lds(const float4* lds, int i, int j0, int j1,
+                                                   float eps2, float4 me, float4 mw,
+                                                   float (&h)[4], float (&l)[4]) {
+    constexpr int PB = 4;
+    for (int jt = j0; jt < j1; jt += SUBTILE) {
+        float A[3] = {0.f, 0.f, 0.f}, B[3] = {0.f, 0.f, 0.f}, gm = 0.f;
+        const int kend = min(SUBTILE, j1 - jt);
+        for (int k = 0; k < kend; k += PB) {
+            float4 q[PB], qw[PB];
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                q[u] = lds[2 * (jt - j0 + k + u)];
+                qw[u] = lds[2 * (jt - j0 + k + u) + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < PB; ++u)
+                vjp_f32c_pair<EPS0, MASS, UNI>(q[u], qw[u], jt + k + u, i, eps2, me, mw, A, B, gm);
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) two_sum_acc(h[c], l[c], fmaf(-3.f, B[c], A[c]));
