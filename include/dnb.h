@@ -169,6 +169,42 @@ dnb_status dnb_simulate(dnb_ctx* ctx, int64_t n, double* pos, double* vel, const
                         const dnb_pot* pot, double dt, int64_t n_steps, int64_t ckpt_every,
                         double* tape, void* stream);
 
+/* Debug scan of a state for values no integration can start from (NaN or
+ * infinite): *first_bad (host) receives the smallest particle index i whose
+ * position pos [3][n], velocity vel [3][n] or mass mass [n] holds one, or -1
+ * when every value is finite.  vel and mass may be NULL (not scanned).  Waits
+ * for the stream: a debugging aid, not for the hot loop. */
+dnb_status dnb_check_state(dnb_ctx* ctx, int64_t n, const double* pos, const double* vel,
+                           const double* mass, int64_t* first_bad, void* stream);
+
+/* With on != 0, dnb_simulate, dnb_simulate_resume and dnb_simulate_batch first
+ * scan their initial state as dnb_check_state does (every member of a batch)
+ * and return DNB_ERR_ARG, naming the first non-finite particle, before any step
+ * runs; each such call then waits for its stream.  Off (0) by default. */
+dnb_status dnb_set_checks(dnb_ctx* ctx, int on);
+
+/* Restart of a long forward run from one of its checkpoints (the fixed-step
+ * integration of Sec. 2.2.1 is a deterministic map of the state, so a run may
+ * be continued from any stored state).  tape is a tape that dnb_simulate (or
+ * this call) wrote for (n, tape_steps, tape_ckpt_every) and is only read; ckpt
+ * is one of its checkpoints, 0 <= ckpt < ceil(tape_steps / tape_ckpt_every),
+ * the state at step ckpt * tape_ckpt_every.  pos [3][n] and vel [3][n] receive
+ * that state and are then integrated n_steps >= 0 further with mass, pot and
+ * dt: with the source run's mass, pot and dt the result is bit for bit the
+ * state the uninterrupted run reached after as many steps (in FP32C the run
+ * stages the checkpoint's positions, and the positions one step later, with
+ * the two centres the tape stored for them rather than with fresh ones).
+ * tape_out (nullable) receives the continuation's own tape, as dnb_simulate
+ * writes it for (n, n_steps, ckpt_every), which dnb_simulate_vjp then
+ * differentiates.  pos, vel and tape_out must not overlap the source tape or
+ * each other; DNB_ERR_ARG for a checkpoint outside the tape, DNB_ERR_STATE when
+ * a buffer is smaller than its stated size. */
+dnb_status dnb_simulate_resume(dnb_ctx* ctx, int64_t n, const double* tape, int64_t tape_steps,
+                               int64_t tape_ckpt_every, int64_t ckpt, double* pos, double* vel,
+                               const double* mass, const dnb_pot* pot, double dt,
+                               int64_t n_steps, int64_t ckpt_every, double* tape_out,
+                               void* stream);
+
 /* Reverse-mode gradient of a scalar loss through dnb_simulate (Sec. 2: the final
  * state is differentiable with respect to initial conditions, integration time,
  * particle masses and external-potential parameters).  This is the exact

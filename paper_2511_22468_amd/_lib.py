@@ -54,6 +54,9 @@ def load_library(path=LIB_PATH):
         "dnb_tape_doubles": ([I64, I64, I64], I64),
         "dnb_vjp_workspace_doubles": ([I64, I64], I64),
         "dnb_simulate": ([P, I64, P, P, P, POT, D, I64, I64, P, P], I),
+        "dnb_check_state": ([P, I64, P, P, P, ctypes.POINTER(I64), P], I),
+        "dnb_set_checks": ([P, I], I),
+        "dnb_simulate_resume": ([P, I64, P, I64, I64, I64, P, P, P, POT, D, I64, I64, P, P], I),
         "dnb_simulate_vjp": ([P, I64, P, POT, D, I64, I64, P, P, P, P, P, P, P, P, P, P], I),
         "dnb_mmd": ([P, I64, P, I64, P, D, P, P, P], I),
         "dnb_energy": ([P, I64, P, P, P, POT, P, P], I),

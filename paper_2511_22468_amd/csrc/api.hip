@@ -36,7 +36,6 @@ dnb_status fail(dnb_status s, const char* fmt, ...) {
             return fail(DNB_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
     } while (0)
 
-constexpr int64_t MAX_N = int64_t(1) << 26;
 
 bool is_fin(double v) { return std::isfinite(v); }
 
@@ -63,15 +62,7 @@ dnb_status check_ctx(dnb_ctx* c, int64_t n, const char* fn) {
 
 dnb_status check_pot(const dnb_pot* p, const char* fn) {
     if (!p) return fail(DNB_ERR_ARG, "%s: pot is NULL", fn);
-    const double v[7] = {p->G, p->eps, p->m_nfw, p->rs_nfw, p->m_mn, p->a_mn, p->b_mn};
-    for (double x : v)
-        if (!is_fin(x)) return fail(DNB_ERR_ARG, "%s: non-finite potential parameter", fn);
-    if (p->eps < 0) return fail(DNB_ERR_ARG, "%s: eps must be >= 0", fn);
-    if (p->m_nfw != 0 && !(p->rs_nfw > 0)) return fail(DNB_ERR_ARG, "%s: rs_nfw must be > 0", fn);
-    if (p->m_mn != 0 && (p->a_mn < 0 || p->b_mn < 0))
-        return fail(DNB_ERR_ARG, "%s: a_mn and b_mn must be >= 0", fn);
-    if (p->m_mn != 0 && p->a_mn == 0 && p->b_mn == 0)
-        return fail(DNB_ERR_ARG, "%s: a_mn = b_mn = 0 makes the disk a point mass; use b_mn > 0", fn);
+    if (const char* why = pot_error(*p)) return fail(DNB_ERR_ARG, "%s: %s", fn, why);
     return DNB_OK;
 }
 
@@ -108,41 +99,17 @@ dnb_status check_extent(const void* p, size_t bytes, const char* name, const cha
     return DNB_OK;
 }
 
-// Tape descriptors (dnb_ctx::tapes).  A dnb_simulate or dnb_step that moves the
-// positions pos in place makes every tape whose final positions are pos stale;
-// a tape written over another one's memory replaces it.
+// Tape descriptors (dnb_ctx::tapes, see TapeRing).
 void forget_tapes(dnb_ctx* c, const double* pos, const double* tape, int64_t tape_len) {
-    for (int k = 0; k < c->tape_count; ++k) {
-        dnb_ctx::TapeDesc& d = c->tapes[k];
-        if (!d.tape) continue;
-        const int64_t dl = d.batch ? dnb_batch_tape_doubles(d.batch, d.n, d.n_steps)
-                                   : dnb_tape_doubles(d.n, d.n_steps, d.ckpt_every);
-        const bool overlap = tape && tape < d.tape + dl && d.tape < tape + tape_len;
-        if (d.pos == pos || overlap) d.tape = nullptr;
-    }
+    c->tapes.forget(pos, tape, tape_len);
 }
 
-void remember_tape(dnb_ctx* c, const dnb_ctx::TapeDesc& d) {
-    c->tapes[c->tape_head] = d;
-    c->tape_head = (c->tape_head + 1) % dnb_ctx::TAPE_RING;
-    if (c->tape_count < dnb_ctx::TAPE_RING) ++c->tape_count;
-}
+void remember_tape(dnb_ctx* c, const TapeDesc& d) { c->tapes.remember(d); }
 
-dnb_ctx::TapeDesc single_desc(const double* tape, const double* pos, const double* mass,
-                              int64_t n, int64_t T, int64_t K, double dt, const dnb_pot& p) {
-    return dnb_ctx::TapeDesc{tape, pos, mass, n, T, K, dt,
-                             {p.G, p.eps, p.m_nfw, p.rs_nfw, p.m_mn, p.a_mn, p.b_mn}, 0, 0};
-}
-
-// FNV-1a over the bytes of a batch's host parameter table [batch][8].
-uint64_t table_hash(const double* params, int64_t batch) {
-    const unsigned char* b = (const unsigned char*)params;
-    uint64_t h = 1469598103934665603ull;
-    for (size_t i = 0; i < sizeof(double) * 8 * (size_t)batch; ++i) {
-        h ^= b[i];
-        h *= 1099511628211ull;
-    }
-    return h;
+TapeDesc single_desc(const double* tape, const double* pos, const double* mass, int64_t n,
+                     int64_t T, int64_t K, double dt, const dnb_pot& p) {
+    return TapeDesc{tape, pos, mass, n, T, K, dt,
+                    {p.G, p.eps, p.m_nfw, p.rs_nfw, p.m_mn, p.a_mn, p.b_mn}, 0, 0};
 }
 
 // The descriptor of a batched tape, checked against the arguments of
@@ -150,9 +117,8 @@ uint64_t table_hash(const double* params, int64_t batch) {
 dnb_status match_batch_tape(dnb_ctx* c, const double* tape, const double* pos_T,
                             const double* mass, int64_t batch, int64_t n, int64_t T,
                             const double* params, const char* fn) {
-    for (int k = 0; k < c->tape_count; ++k) {
-        const dnb_ctx::TapeDesc& d = c->tapes[k];
-        if (!d.tape || d.tape != tape) continue;
+    if (const TapeDesc* dp = c->tapes.find(tape)) {
+        const TapeDesc& d = *dp;
         if (d.batch != batch || d.n != n || d.n_steps != T)
             return fail(DNB_ERR_STATE,
                         "%s: the tape was written for batch = %lld, n = %lld, n_steps = %lld "
@@ -176,9 +142,8 @@ dnb_status match_tape(dnb_ctx* c, const double* tape, const double* pos_T, const
                       int64_t n, int64_t T, int64_t K, double dt, const dnb_pot& p,
                       const char* fn) {
     const double pv[7] = {p.G, p.eps, p.m_nfw, p.rs_nfw, p.m_mn, p.a_mn, p.b_mn};
-    for (int k = 0; k < c->tape_count; ++k) {
-        const dnb_ctx::TapeDesc& d = c->tapes[k];
-        if (!d.tape || d.tape != tape) continue;
+    if (const TapeDesc* dp = c->tapes.find(tape)) {
+        const TapeDesc& d = *dp;
         if (d.batch != 0)
             return fail(DNB_ERR_STATE, "%s: the tape was written by dnb_simulate_batch", fn);
         if (d.n != n || d.n_steps != T || d.ckpt_every != K)
@@ -258,16 +223,20 @@ struct Tape {
 };
 
 // Forward integration from (x, v) for n_steps; tape optional.  Positions and
-// velocities are updated in place.
+// velocities are updated in place.  centres (nullable): the two FP32C staging
+// centres a checkpoint stored (those of its positions and of the positions one
+// step later), which a run resumed from that checkpoint takes instead of the
+// ones a fresh start computes, so that it continues bit for bit.
 dnb_status run_forward(dnb_ctx* c, int64_t n, double* pos, double* vel, const double* mass,
                        const Pot& p, double dt, int64_t T, int64_t K, const Tape* tape,
-                       hipStream_t st) {
+                       hipStream_t st, const double* centres = nullptr) {
     if (T == 0) return DNB_OK;
     const int nb = (int)cdiv(n, BS);
     double* cp[2] = {c->cpart, c->cpart + REC * c->nbmax};
     HIP_TRY(launch_mass_info(c, mass, n, st));
-    if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(pos, n, cp[0], st, nullptr, vel, dt));
-    HIP_TRY(launch_stage(c, pos, mass, n, cp[0], nb, nullptr, tape ? tape->centre(0) : nullptr, st));
+    if (c->prec == DNB_FP32C && !centres)
+        HIP_TRY(launch_block_sums(pos, n, cp[0], st, nullptr, vel, dt));
+    HIP_TRY(launch_stage(c, pos, mass, n, cp[0], nb, centres, tape ? tape->centre(0) : nullptr, st));
     int q = 0;
     const bool f32 = c->prec == DNB_FP32C;
     for (int64_t s = 0; s <= T; ++s) {
@@ -285,6 +254,7 @@ dnb_status run_forward(dnb_ctx* c, int64_t n, double* pos, double* vel, const do
         if (tape && s == T) a.aint_out = tape->aint_final();
         if (tape && s + 1 < T && (s + 1) % K == 0) a.tape_centre_next = tape->centre((s + 1) / K);
         if (tape && s < T && s % K == 0) a.tape_centre_cur = tape->centre_next(s / K);
+        if (s == 0 && centres) a.centre_override = centres + 4;
         KdkMode mode = (s == 0) ? KDK_FIRST : (s == T ? KDK_LAST : KDK_MID);
         HIP_TRY(launch_kdk(c, mode, a, st));
         q = 1 - q;
@@ -345,6 +315,7 @@ dnb_status dnb_create(dnb_ctx** out, int64_t max_n, dnb_prec prec) {
         {(void**)&c->gred, sizeof(double) * 4 * npadmax},
         {(void**)&c->arec, sizeof(double) * 4 * (cdiv(npadmax, RT) + DNB_BATCH_MAX)},
         {(void**)&c->grec, sizeof(double) * 4 * (cdiv(npadmax, RT) + DNB_BATCH_MAX)},
+        {(void**)&c->scan, sizeof(int64_t) * (c->nbmax + 1)},
     };
     for (auto& a : allocs) {
         if (hipMalloc(a.p, a.bytes) != hipSuccess) {
@@ -367,7 +338,8 @@ void dnb_destroy(dnb_ctx* c) {
         delete pf;
     }
     void* ps[] = {c->js, c->part, c->cpart, c->vh, c->jsv, c->partv, c->cpartv, c->wscale, c->muni,
-                  c->bparams, c->bwscale, c->red, c->ared, c->gred, c->arec, c->grec};
+                  c->bparams, c->bwscale, c->red, c->ared, c->gred, c->arec, c->grec,
+                  c->scan};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     delete c;
@@ -454,14 +426,40 @@ dnb_status dnb_accelerations_vjp(dnb_ctx* c, int64_t n, const double* pos, const
 }
 
 int64_t dnb_tape_doubles(int64_t n, int64_t n_steps, int64_t ckpt_every) {
-    if (n < 1 || n_steps < 0 || ckpt_every < 1) return -1;
-    if (n_steps == 0) return 0;
-    return cdiv(n_steps, ckpt_every) * (9 * n + 8) + 3 * n;
+    return tape_doubles(n, n_steps, ckpt_every);
 }
 
 int64_t dnb_vjp_workspace_doubles(int64_t n, int64_t ckpt_every) {
-    if (n < 1 || ckpt_every < 1) return -1;
-    return 3 * n * (ckpt_every + 1) + 16 * n + 3 * n * ckpt_every;
+    return vjp_workspace_doubles(n, ckpt_every);
+}
+
+// The state scan: *first = index of the first particle (b n + i for member b)
+// with a non-finite position, velocity or mass, -1 when there is none.  Waits
+// for the stream.
+static dnb_status scan_state(dnb_ctx* c, const double* x, const double* v, const double* m,
+                             int64_t n, int64_t nsys, hipStream_t st, int64_t* first) {
+    int64_t r = 0;
+    HIP_TRY(launch_scan_state(c, x, v, m, n, nsys, st));
+    HIP_TRY(hipMemcpyAsync(&r, c->scan + c->nbmax, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *first = (r == INT64_MAX) ? -1 : r;
+    return DNB_OK;
+}
+
+// With checks on (dnb_set_checks): refuse an initial state that holds a
+// non-finite value, naming the first such particle.
+static dnb_status checked_state(dnb_ctx* c, const double* x, const double* v, const double* m,
+                                int64_t n, int64_t nsys, hipStream_t st, const char* fn) {
+    if (!c->checks) return DNB_OK;
+    int64_t first = -1;
+    CHECK(scan_state(c, x, v, m, n, nsys, st, &first));
+    if (first < 0) return DNB_OK;
+    if (nsys > 1)
+        return fail(DNB_ERR_ARG, "%s: initial state of member %lld, particle %lld holds a "
+                    "non-finite position, velocity or mass", fn, (long long)(first / n),
+                    (long long)(first % n));
+    return fail(DNB_ERR_ARG, "%s: initial state of particle %lld holds a non-finite position, "
+                "velocity or mass", fn, (long long)first);
 }
 
 static dnb_status check_sim_args(dnb_ctx* c, int64_t n, const void* pos, const void* vel,
@@ -493,12 +491,72 @@ dnb_status dnb_simulate(dnb_ctx* c, int64_t n, double* pos, double* vel, const d
     CHECK(check_dev(tape, "tape", fn, true));
     const int64_t tl = dnb_tape_doubles(n, n_steps, ckpt_every);
     if (tape && n_steps > 0) CHECK(check_extent(tape, sizeof(double) * tl, "tape", fn));
+    CHECK(checked_state(c, pos, vel, mass, n, 1, (hipStream_t)stream, fn));
     forget_tapes(c, pos, tape, tape ? tl : 0);
     Tape tp{tape, n, cdiv(n_steps, ckpt_every)};
     CHECK(run_forward(c, n, pos, vel, mass, to_pot(*pot), dt, n_steps, ckpt_every,
                       tape ? &tp : nullptr, (hipStream_t)stream));
     if (tape && n_steps > 0)
         remember_tape(c, single_desc(tape, pos, mass, n, n_steps, ckpt_every, dt, *pot));
+    return DNB_OK;
+}
+
+dnb_status dnb_set_checks(dnb_ctx* c, int on) {
+    if (!c) return fail(DNB_ERR_ARG, "dnb_set_checks: ctx is NULL");
+    c->checks = on ? 1 : 0;
+    return DNB_OK;
+}
+
+dnb_status dnb_check_state(dnb_ctx* c, int64_t n, const double* pos, const double* vel,
+                           const double* mass, int64_t* first_bad, void* stream) {
+    const char* fn = "dnb_check_state";
+    CHECK(check_ctx(c, n, fn));
+    if (!first_bad) return fail(DNB_ERR_ARG, "%s: first_bad is NULL", fn);
+    CHECK(check_dev(pos, "pos", fn));
+    CHECK(check_dev(vel, "vel", fn, true));
+    CHECK(check_dev(mass, "mass", fn, true));
+    return scan_state(c, pos, vel, mass, n, 1, (hipStream_t)stream, first_bad);
+}
+
+dnb_status dnb_simulate_resume(dnb_ctx* c, int64_t n, const double* tape, int64_t tape_steps,
+                               int64_t tape_ckpt_every, int64_t ckpt, double* pos, double* vel,
+                               const double* mass, const dnb_pot* pot, double dt,
+                               int64_t n_steps, int64_t ckpt_every, double* tape_out,
+                               void* stream) {
+    const char* fn = "dnb_simulate_resume";
+    CHECK(check_sim_args(c, n, pos, vel, mass, pot, dt, n_steps, ckpt_every, fn));
+    if (tape_steps < 1 || tape_ckpt_every < 1)
+        return fail(DNB_ERR_ARG, "%s: tape_steps and tape_ckpt_every must be >= 1", fn);
+    const int64_t n_ckpt = cdiv(tape_steps, tape_ckpt_every);
+    if (ckpt < 0 || ckpt >= n_ckpt)
+        return fail(DNB_ERR_ARG, "%s: ckpt = %lld outside [0, %lld), the tape's checkpoints", fn,
+                    (long long)ckpt, (long long)n_ckpt);
+    CHECK(check_dev(tape, "tape", fn));
+    CHECK(check_dev(tape_out, "tape_out", fn, true));
+    const int64_t tl = dnb_tape_doubles(n, tape_steps, tape_ckpt_every);
+    CHECK(check_extent(tape, sizeof(double) * tl, "tape", fn));
+    const int64_t tlo = dnb_tape_doubles(n, n_steps, ckpt_every);
+    if (tape_out && n_steps > 0) CHECK(check_extent(tape_out, sizeof(double) * tlo, "tape_out", fn));
+    auto overlaps = [](const double* a, int64_t na, const double* b, int64_t nb_) {
+        return a && b && a < b + nb_ && b < a + na;
+    };
+    if (overlaps(pos, 3 * n, tape, tl) || overlaps(vel, 3 * n, tape, tl) ||
+        overlaps(tape_out, tape_out && n_steps > 0 ? tlo : 0, tape, tl) || pos == vel)
+        return fail(DNB_ERR_ARG, "%s: pos, vel and tape_out must not overlap the source tape "
+                    "or each other", fn);
+    hipStream_t st = (hipStream_t)stream;
+    const Tape src{const_cast<double*>(tape), n, n_ckpt};
+    const double* x0 = src.state(ckpt);
+    const size_t vec = sizeof(double) * 3 * n;
+    forget_tapes(c, pos, tape_out, tape_out ? tlo : 0);
+    HIP_TRY(hipMemcpyAsync(pos, x0, vec, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(vel, x0 + 3 * n, vec, hipMemcpyDeviceToDevice, st));
+    CHECK(checked_state(c, pos, vel, mass, n, 1, st, fn));
+    Tape tp{tape_out, n, cdiv(n_steps, ckpt_every)};
+    CHECK(run_forward(c, n, pos, vel, mass, to_pot(*pot), dt, n_steps, ckpt_every,
+                      tape_out ? &tp : nullptr, st, src.centre(ckpt)));
+    if (tape_out && n_steps > 0)
+        remember_tape(c, single_desc(tape_out, pos, mass, n, n_steps, ckpt_every, dt, *pot));
     return DNB_OK;
 }
 
@@ -726,9 +784,7 @@ static dnb_status put_batch_params(dnb_ctx* c, int64_t batch, const double* para
 }
 
 int64_t dnb_batch_tape_doubles(int64_t batch, int64_t n, int64_t n_steps) {
-    if (batch < 1 || n < 1 || n_steps < 0) return -1;
-    if (n_steps == 0) return 0;
-    return (6 * n_steps + 3 * (n_steps + 1)) * batch * n;
+    return batch_tape_doubles(batch, n, n_steps);
 }
 
 dnb_status dnb_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* pos, double* vel,
@@ -749,11 +805,12 @@ dnb_status dnb_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* pos,
     CHECK(put_batch_params(c, batch, params, true, st, fn));
     const int64_t tl = dnb_batch_tape_doubles(batch, n, n_steps);
     if (tape && n_steps > 0) CHECK(check_extent(tape, sizeof(double) * tl, "tape", fn));
+    CHECK(checked_state(c, pos, vel, mass, n, batch, st, fn));
     forget_tapes(c, pos, tape, tape ? tl : 0);
     HIP_TRY(launch_simulate_batch(c, batch, n, pos, vel, mass, c->bparams, n_steps, tape, st));
     if (tape && n_steps > 0)
-        remember_tape(c, dnb_ctx::TapeDesc{tape, pos, mass, n, n_steps, 1, 0.0, {}, batch,
-                                           table_hash(params, batch)});
+        remember_tape(c, TapeDesc{tape, pos, mass, n, n_steps, 1, 0.0, {}, batch,
+                                  table_hash(params, batch)});
     return DNB_OK;
 }
 

@@ -1,7 +1,10 @@
 // Kernels around the integrator: the MMD loss and its gradient (Sec. 2.2.1 and
 // Fig. 2, step 4), energies, the test-particle orbit of the progenitor's centre of
 // mass and its adjoint (Fig. 2, step 2), and the Plummer-sphere placement with its
-// adjoint (Fig. 2, step 3).  All FP64.
+// adjoint (Fig. 2, step 3), and the debug scan of a state for non-finite values.
+// All FP64.
+#include <algorithm>
+
 #include "dnb_internal.h"
 
 namespace dnb {
@@ -597,6 +600,67 @@ hipError_t launch_place_vjp(dnb_ctx* c, int64_t n, const double* zeta, double m_
                        c->red);
     hipLaunchKernelGGL(k_place_vjp_final, dim3(1), dim3(BS), 0, st, c->red, nb, n, dvs_dm, gw,
                        gm_tot);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ state scan --
+// Smallest index p = b n + i (member b, particle i) of nsys systems laid out as
+// x, v [nsys][3][n] and m [nsys][n] at which a coordinate, a velocity component
+// or the mass is NaN or infinite; INT64_MAX when there is none.  v and m may be
+// NULL.  Blocks stride over the particles and write their minimum to out[b];
+// k_scan_final takes the minimum of the nb block minima into out[slot].
+__device__ inline int64_t wave_min_i64(int64_t a) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        const int64_t o = __shfl_xor(a, m, 64);
+        a = o < a ? o : a;
+    }
+    return a;
+}
+
+__device__ inline int64_t block_min_i64(int64_t a) {
+    __shared__ int64_t sh[BS / 64];
+    a = wave_min_i64(a);
+    if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = a;
+    __syncthreads();
+    a = sh[0];
+    for (int w = 1; w < BS / 64; ++w) a = sh[w] < a ? sh[w] : a;
+    return a;
+}
+
+__global__ __launch_bounds__(BS) void k_scan_state(const double* __restrict__ x,
+                                                   const double* __restrict__ v,
+                                                   const double* __restrict__ m, int64_t n,
+                                                   int64_t total, int64_t* __restrict__ out) {
+    int64_t bad = INT64_MAX;
+    for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < total;
+         p += (int64_t)gridDim.x * BS) {
+        const int64_t b = p / n, i = p - b * n;
+        bool ok = true;
+        for (int c = 0; c < 3; ++c) {
+            ok = ok && isfinite(x[(3 * b + c) * n + i]);
+            if (v) ok = ok && isfinite(v[(3 * b + c) * n + i]);
+        }
+        if (m) ok = ok && isfinite(m[p]);
+        if (!ok && p < bad) bad = p;
+    }
+    bad = block_min_i64(bad);
+    if (threadIdx.x == 0) out[blockIdx.x] = bad;
+}
+
+__global__ __launch_bounds__(BS) void k_scan_final(int64_t* __restrict__ out, int nb, int slot) {
+    int64_t bad = INT64_MAX;
+    for (int b = threadIdx.x; b < nb; b += BS) bad = out[b] < bad ? out[b] : bad;
+    bad = block_min_i64(bad);
+    if (threadIdx.x == 0) out[slot] = bad;
+}
+
+hipError_t launch_scan_state(dnb_ctx* c, const double* x, const double* v, const double* m,
+                             int64_t n, int64_t nsys, hipStream_t st) {
+    const int64_t total = n * nsys;
+    const int nb = (int)std::min<int64_t>(cdiv(total, BS), c->nbmax);
+    hipLaunchKernelGGL(k_scan_state, dim3(nb), dim3(BS), 0, st, x, v, m, n, total, c->scan);
+    hipLaunchKernelGGL(k_scan_final, dim3(1), dim3(BS), 0, st, c->scan, nb, c->nbmax);
     return hipGetLastError();
 }
 

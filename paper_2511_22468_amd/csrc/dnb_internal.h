@@ -6,82 +6,15 @@
 #include <stdint.h>
 
 #include "../../include/dnb.h"
+#include "host_logic.h"
 
 namespace dnb {
 
-// ---------------------------------------------------------------- geometry --
-constexpr int BS = 256;              // threads per block of every particle kernel
-constexpr int TILE = 256;            // sources staged in LDS per tile
-constexpr int SUBTILE = 128;         // sources summed in plain FP32 before a TwoSum
-constexpr int TARGET_BLOCKS = 8192;  // pair-kernel blocks wanted per launch (32 per CU)
-constexpr int S_MAX = 64;            // maximum number of source slices
-constexpr int SLICE_GRAIN = 32;      // pair-kernel source slices are multiples of this
-constexpr int REC = 8;               // doubles per block record of the O(N) kernels
-constexpr int RT = 64;               // targets per block of the FP32C slice reductions (a wave)
-constexpr int RG = BS / RT;          // slice groups per block of those reductions
+// Launch geometry, buffer sizes, the host-galaxy parameter check and the tape
+// descriptors are in host_logic.h (no HIP in it).
 
 // Number of reduction blocks (and net-force records) of a system of n particles.
 __host__ __device__ inline int red_blocks(int64_t n) { return (int)((n + RT - 1) / RT); }
-
-inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
-// Length of the staged source arrays: n rounded up to whole sub-tiles; the
-// entries past n are far-away zero-mass particles.
-inline int64_t pad_sources(int64_t n) { return cdiv(n, SUBTILE) * SUBTILE; }
-
-// Source slicing of the O(N^2) kernels: the grid is (target blocks) x S, each
-// block owns tpb targets (one per lane) and sums one contiguous slice of
-// sources.  Small N gets more slices so that the launch still fills the 256
-// compute units with about `target` blocks.  slicing_for serves the MMD and
-// energy kernels (slices of whole LDS tiles); pair_slicing below the pair
-// kernels.
-struct Slicing {
-    int S;          // number of slices
-    int jslice;     // sources per slice (a multiple of TILE, SLICE_GRAIN for the pair kernels)
-    int nblk;       // target blocks
-    int64_t npad;   // row stride of the partial buffers (n rounded up to tpb)
-};
-
-inline Slicing slicing_for(int64_t n, int tpb, int target) {
-    Slicing s;
-    s.nblk = (int)cdiv(n, tpb);
-    s.npad = (int64_t)s.nblk * tpb;
-    int64_t want = target / s.nblk;
-    int64_t max_by_tiles = cdiv(n, TILE);   // at least one tile per slice
-    if (want > max_by_tiles) want = max_by_tiles;
-    if (want > S_MAX) want = S_MAX;
-    if (want < 1) want = 1;
-    s.jslice = (int)(cdiv(cdiv(n, want), TILE) * TILE);
-    s.S = (int)cdiv(n, s.jslice);
-    return s;
-}
-
-// Source slicing of the pair kernels: ni targets (blocks of BS) against n
-// sources in slices of a multiple of SLICE_GRAIN sources (a slice shorter than a
-// sub-tile is summed as one short sub-tile), S <= smax.  A small system gets
-// short slices so that its launch still spreads over many compute units.
-inline Slicing pair_slicing(int64_t ni, int64_t n, int target, int smax) {
-    Slicing s;
-    s.nblk = (int)cdiv(ni, BS);
-    s.npad = (int64_t)s.nblk * BS;
-    int64_t want = target / s.nblk;
-    const int64_t max_by_grain = cdiv(n, SLICE_GRAIN);
-    if (want > max_by_grain) want = max_by_grain;
-    if (want > smax) want = smax;
-    if (want < 1) want = 1;
-    s.jslice = (int)(cdiv(cdiv(n, want), SLICE_GRAIN) * SLICE_GRAIN);
-    s.S = (int)cdiv(n, s.jslice);
-    return s;
-}
-
-// Upper bound of S * npad over all n <= max_n for blocks of at most tpb targets:
-// S <= want = clamp(target / nblk, 1, S_MAX), so S * npad <= want * nblk * tpb
-// <= max(target * tpb, npad(max_n)).
-inline int64_t max_slice_rows(int64_t max_n, int tpb, int target) {
-    const int64_t np = cdiv(max_n, tpb) * tpb;
-    const int64_t small = (int64_t)target * tpb;
-    return np > small ? np : small;
-}
 
 // ------------------------------------------------------------- potential ---
 struct Pot {
@@ -326,24 +259,13 @@ struct dnb_ctx {
     double* gred;            // [4][npadmax] FP32C J^T w (3 rows) and mass term reduced likewise
     double* arec;            // [cdiv(npadmax, RT) + DNB_BATCH_MAX][4] net-force records
     double* grec;            // the same for J^T w
+    int64_t* scan;           // [nbmax + 1] block minima and result of the state scan
+    int checks;              // nonzero: the integrators scan their initial state first
     void* prof;              // host-side event pool of dnb_profile (null when off)
-    // Descriptors of the tapes written by the most recent dnb_simulate calls (a
-    // ring, newest at tape_head - 1): dnb_simulate_vjp accepts only a tape, with
-    // its final positions and the arguments it was written with, listed here.
-    struct TapeDesc {
-        const double* tape;
-        const double* pos;   // the in-place position array: the final positions
-        const double* mass;
-        int64_t n, n_steps, ckpt_every;
-        double dt;
-        double pot[7];       // G, eps, m_nfw, rs_nfw, m_mn, a_mn, b_mn
-        int64_t batch;       // 0: dnb_simulate; else the members of dnb_simulate_batch
-        uint64_t table;      // hash of the batch's host parameter table (0 for a single system)
-    };
-    static constexpr int TAPE_RING = 16;
-    TapeDesc tapes[TAPE_RING];
-    int tape_count;          // valid entries (<= TAPE_RING)
-    int tape_head;           // next slot to write
+    // Descriptors of the tapes written by the most recent dnb_simulate calls:
+    // dnb_simulate_vjp accepts only a tape, with its final positions and the
+    // arguments it was written with, listed here.
+    dnb::TapeRing tapes;
 };
 
 namespace dnb {
@@ -538,6 +460,10 @@ size_t lm_workspace_bytes(int64_t batch);
 hipError_t launch_track_lm(const dnb_track_model& md, const double* trk, int K, int batch,
                            double* p, int64_t n_iter, double lam0, double* chi2, void* work,
                            hipStream_t st);
+// Debug scan: the index of the first non-finite particle of nsys systems (or
+// INT64_MAX) into c->scan[nbmax]; see aux.hip.
+hipError_t launch_scan_state(dnb_ctx* c, const double* x, const double* v, const double* m,
+                             int64_t n, int64_t nsys, hipStream_t st);
 hipError_t launch_mmd_batch(dnb_ctx* c, int64_t batch, int64_t n, const double* pos, int64_t m,
                             const double* tgt, int per_member, double h, double* loss,
                             double* gpos, hipStream_t st);

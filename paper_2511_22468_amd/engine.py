@@ -185,6 +185,45 @@ class Context:
                                            _lib.stream_handle()))
         return tape
 
+    def check_state(self, pos, vel=None, mass=None):
+        """Index of the first particle with a NaN or infinite position, velocity
+        or mass, or -1 (waits for the stream)."""
+        n = pos.shape[1]
+        _vec(pos, n, "pos")
+        if vel is not None:
+            _vec(vel, n, "vel")
+        if mass is not None:
+            _arr(mass, (n,), "mass")
+        out = ctypes.c_int64(-2)
+        _lib.check(_lib.lib().dnb_check_state(
+            self._h, n, _lib.ptr(pos), _lib.ptr(vel) if vel is not None else None,
+            _lib.ptr(mass) if mass is not None else None, ctypes.byref(out),
+            _lib.stream_handle()))
+        return int(out.value)
+
+    def set_checks(self, on=True):
+        """With checks on, the integrators refuse a non-finite initial state."""
+        _lib.check(_lib.lib().dnb_set_checks(self._h, 1 if on else 0))
+
+    def simulate_resume(self, tape, tape_steps, tape_ckpt_every, ckpt, pos, vel, mass, pot, dt,
+                        n_steps, ckpt_every=0, tape_out=None):
+        """pos, vel <- checkpoint ckpt of tape (written for tape_steps, tape_ckpt_every),
+        then n_steps further steps, continuing the source run bit for bit.  With
+        ckpt_every > 0 the continuation's tape is written (and returned)."""
+        n = mass.shape[0]
+        _vec(pos, n, "pos"); _vec(vel, n, "vel"); _arr(mass, (n,), "mass")
+        _buffer(tape, self.tape_len(n, tape_steps, tape_ckpt_every), "tape")
+        K = int(ckpt_every)
+        if K > 0 and tape_out is None:
+            tape_out = self._new(max(1, self.tape_len(n, n_steps, K)))
+        if K > 0:
+            _buffer(tape_out, self.tape_len(n, n_steps, K), "tape_out")
+        _lib.check(_lib.lib().dnb_simulate_resume(
+            self._h, n, _lib.ptr(tape), int(tape_steps), int(tape_ckpt_every), int(ckpt),
+            _lib.ptr(pos), _lib.ptr(vel), _lib.ptr(mass), pot.c(), float(dt), int(n_steps),
+            max(K, 1), _lib.ptr(tape_out) if K > 0 else None, _lib.stream_handle()))
+        return tape_out
+
     def simulate_vjp(self, mass, pot, dt, n_steps, ckpt_every, tape, pos_T, gpos_T, gvel_T=None,
                      with_mass=False, workspace=None):
         """Returns (gpos_0, gvel_0, gmass or None, gparams[4]) with gparams =

@@ -102,6 +102,14 @@ def test_arguments_rejected_before_any_device_work(lib):
     assert lib.dnb_track_lm(None, ctypes.byref(model), 4, None, 1, None, 10, 1e-3, None,
                             None) == _lib.DNB_ERR_ARG
     assert b"ctx is NULL" in lib.dnb_last_error()
+    assert lib.dnb_simulate_resume(None, 10, None, 20, 5, 1, None, None, None, ctypes.byref(pot),
+                                   0.1, 5, 1, None, None) == _lib.DNB_ERR_ARG
+    first = ctypes.c_int64(7)
+    assert lib.dnb_check_state(None, 10, None, None, None, ctypes.byref(first),
+                               None) == _lib.DNB_ERR_ARG
+    assert first.value == 7
+    assert lib.dnb_set_checks(None, 1) == _lib.DNB_ERR_ARG
+    assert b"ctx is NULL" in lib.dnb_last_error()
     lib.dnb_destroy(None)
 
 

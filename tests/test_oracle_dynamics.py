@@ -102,6 +102,21 @@ def test_time_reversibility():
     assert np.abs(-v2 - v).max() < 1e-6
 
 
+def test_restart_from_a_stored_state_is_bitwise():
+    # the fixed-step map is a function of the state alone: stopping after k steps
+    # and continuing from the stored (x, v) reproduces the uninterrupted run
+    x, v, m = _cluster()
+    pot = Potential()
+    dt = C.myr(0.5)
+    stored = {}
+    xT, vT = integrate.simulate(x, v, m, pot, dt, 30,
+                                callback=lambda k, xk, vk: stored.update({k: (xk.copy(), vk.copy())}))
+    for k in (1, 10, 29):
+        xk, vk = stored[k]
+        x2, v2 = integrate.simulate(xk, vk, m, pot, dt, 30 - k)
+        assert np.array_equal(x2, xT) and np.array_equal(v2, vT)
+
+
 # -------------------------------------------------------------------- adjoint
 
 def _cs(fun, h=1e-30):
