@@ -103,6 +103,7 @@ __global__ __launch_bounds__(BS) void k_batch_stage(const double* __restrict__ p
 }
 
 // Pair sums of every member.  grid (nblk, S, batch).
+template <bool NT>
 __global__ __launch_bounds__(BS) void k_batch_pair_fwd(const float4* __restrict__ js, BatchGeom g,
                                                        const double* __restrict__ params,
                                                        const float* __restrict__ muni,
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(BS) void k_batch_pair_fwd(const float4* __restrict_
     }
     if (i < g.n) {
         float2* p = (float2*)part + ((int64_t)b * g.S + blockIdx.y) * 3 * g.npad + i;
-        for (int c = 0; c < 3; ++c) p[c * g.npad] = make_float2(h[c], l[c]);
+        for (int c = 0; c < 3; ++c) put_partial<NT>(p + c * g.npad, h[c], l[c]);
     }
 }
 
@@ -424,6 +425,12 @@ BatchGeom batch_geom(const dnb_ctx* c, int64_t batch, int64_t n) {
     return g;
 }
 
+// Whether a launch's slice partials (rows of float2 per member, slice and
+// target) are many enough for non-temporal stores (put_partial).
+static bool nt_partials(const BatchGeom& g, int64_t batch, int rows) {
+    return batch * g.S * g.npad * rows * 8 >= NT_PARTIAL_BYTES;
+}
+
 // Capacity of the context for a batch (checked before anything is enqueued).
 bool batch_fits(const dnb_ctx* c, int64_t batch, int64_t n) {
     const BatchGeom g = batch_geom(c, batch, n);
@@ -450,8 +457,10 @@ hipError_t launch_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* p
     const dim3 red((unsigned)red_blocks(n), (unsigned)batch);
     int q = 0;
     for (int64_t s = 0; s <= n_steps; ++s) {
-        hipLaunchKernelGGL(k_batch_pair_fwd, dim3(g.nblk, g.S, (unsigned)batch), dim3(BS), 0, st,
-                           js, g, params_dev, c->muni, part);
+        hipLaunchKernelGGL(nt_partials(g, batch, 3) ? k_batch_pair_fwd<true>
+                                                    : k_batch_pair_fwd<false>,
+                           dim3(g.nblk, g.S, (unsigned)batch), dim3(BS), 0, st, js, g,
+                           params_dev, c->muni, part);
         hipLaunchKernelGGL(k_batch_fwd_reduce, red, dim3(BS), 0, st, (const float*)part, g,
                            params_dev, mass, c->ared, c->arec);
         double* ts = (tape && s < n_steps) ? tp.state(s) : nullptr;
@@ -532,6 +541,7 @@ __global__ __launch_bounds__(BS) void k_batch_block_sums_w(const double* __restr
 }
 
 // Pair VJP of every member.  grid (nblk, S, batch).
+template <bool NT>
 __global__ __launch_bounds__(BS) void k_batch_pair_vjp(const float4* __restrict__ jsv,
                                                        BatchGeom g,
                                                        const double* __restrict__ params,
@@ -558,7 +568,7 @@ __global__ __launch_bounds__(BS) void k_batch_pair_vjp(const float4* __restrict_
     }
     if (i < g.n) {
         float2* p = (float2*)part + (b * g.S + blockIdx.y) * 4 * g.npad + i;
-        for (int c = 0; c < 3; ++c) p[c * g.npad] = make_float2(h[c], l[c]);
+        for (int c = 0; c < 3; ++c) put_partial<NT>(p + c * g.npad, h[c], l[c]);
     }
 }
 
@@ -682,7 +692,9 @@ hipError_t launch_simulate_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const
                        cpv[1], c->bwscale, T > 0 ? tp.state(T - 1) : nullptr, (int64_t)6 * n);
     int q = 1, wq = 0;
     for (int64_t m = T; m >= 0; --m) {
-        hipLaunchKernelGGL(k_batch_pair_vjp, dim3(g.nblk, g.S, (unsigned)batch), dim3(BS), 0, st,
+        hipLaunchKernelGGL(nt_partials(g, batch, 3) ? k_batch_pair_vjp<true>
+                                                    : k_batch_pair_vjp<false>,
+                           dim3(g.nblk, g.S, (unsigned)batch), dim3(BS), 0, st,
                            (const float4*)jsv, g, params_dev, c->muni, part);
         hipLaunchKernelGGL(k_batch_vjp_reduce, dim3((unsigned)red_blocks(n), (unsigned)batch),
                            dim3(BS), 0, st, (const float*)part, g, params_dev, c->bwscale, wq,

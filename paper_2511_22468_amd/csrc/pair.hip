@@ -60,7 +60,7 @@ __device__ __forceinline__ double rsqrt_f64(double s) {
 // scalar loads cost the vector units nothing.  Both give the same bits.
 constexpr int FWD_LDS_SLICE = 256;   // longest slice that takes the LDS kernel
 
-template <bool EPS0, bool LDS>
+template <bool EPS0, bool LDS, bool NT>
 __global__ __launch_bounds__(BS) void k_pair_fwd_f32c(const float4* __restrict__ js, int n,
                                                       int i0, int iend, int nj, int jslice,
                                                       float eps2, float* __restrict__ part,
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f32c(const float4* __restrict__
     if (i < iend) {
         float2* p = (float2*)part + (int64_t)blockIdx.y * 3 * npad + (i - i0);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) p[c * npad] = make_float2(h[c], l[c]);
+        for (int c = 0; c < 3; ++c) put_partial<NT>(p + c * npad, h[c], l[c]);
     }
 }
 
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f64(const double4* __restrict__
 // copies its slice (two float4 per source) into LDS, as in the forward kernel.
 constexpr int VJP_LDS_SLICE = 64;    // longest slice that takes the LDS kernel
 
-template <bool EPS0, bool MASS, bool LDS>
+template <bool EPS0, bool MASS, bool LDS, bool NT>
 __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__ jsv, int n,
                                                       int i0, int iend, int nj, int jslice,
                                                       float eps2, float* __restrict__ part,
@@ -188,8 +188,8 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__
     if (i < iend) {
         float2* p = (float2*)part + (int64_t)blockIdx.y * 4 * npad + (i - i0);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) p[c * npad] = make_float2(h[c], l[c]);
-        if (MASS) p[3 * npad] = make_float2(h[3], l[3]);
+        for (int c = 0; c < 3; ++c) put_partial<NT>(p + c * npad, h[c], l[c]);
+        if (MASS) put_partial<NT>(p + 3 * npad, h[3], l[3]);
     }
 }
 
@@ -268,20 +268,21 @@ static hipError_t launch_pair_fwd_sliced(dnb_ctx* c, int64_t n, int64_t i0, int6
         const float4* js = (const float4*)c->js;
         float* part = (float*)c->part;
         const bool lds = sl.jslice <= FWD_LDS_SLICE;
-        if (eps == 0.0) {
-            if (lds)
-                hipLaunchKernelGGL((k_pair_fwd_f32c<true, true>), grid, dim3(BS), 0, st, js,
-                                   (int)n, a, e, nj, sl.jslice, eps2, part, sl.npad, c->muni);
-            else
-                hipLaunchKernelGGL((k_pair_fwd_f32c<true, false>), grid, dim3(BS), 0, st, js,
-                                   (int)n, a, e, nj, sl.jslice, eps2, part, sl.npad, c->muni);
-        } else {
-            if (lds)
-                hipLaunchKernelGGL((k_pair_fwd_f32c<false, true>), grid, dim3(BS), 0, st, js,
-                                   (int)n, a, e, nj, sl.jslice, eps2, part, sl.npad, c->muni);
-            else
-                hipLaunchKernelGGL((k_pair_fwd_f32c<false, false>), grid, dim3(BS), 0, st, js,
-                                   (int)n, a, e, nj, sl.jslice, eps2, part, sl.npad, c->muni);
+        const bool nt = (int64_t)sl.S * sl.npad * 3 * 8 >= NT_PARTIAL_BYTES;
+        auto go = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, grid, dim3(BS), 0, st, js, (int)n, a, e, nj, sl.jslice,
+                               eps2, part, sl.npad, c->muni);
+        };
+        const int which = (eps == 0.0 ? 4 : 0) + (lds ? 2 : 0) + (nt ? 1 : 0);
+        switch (which) {
+            case 0: go(k_pair_fwd_f32c<false, false, false>); break;
+            case 1: go(k_pair_fwd_f32c<false, false, true>); break;
+            case 2: go(k_pair_fwd_f32c<false, true, false>); break;
+            case 3: go(k_pair_fwd_f32c<false, true, true>); break;
+            case 4: go(k_pair_fwd_f32c<true, false, false>); break;
+            case 5: go(k_pair_fwd_f32c<true, false, true>); break;
+            case 6: go(k_pair_fwd_f32c<true, true, false>); break;
+            default: go(k_pair_fwd_f32c<true, true, true>); break;
         }
     } else {
         const double eps2 = eps * eps;
@@ -309,18 +310,22 @@ template <bool EPS0, bool MASS>
 static void vjp_dispatch(dnb_ctx* c, const Slicing& sl, int64_t n, int i0, int iend, int nj,
                          double eps2, hipStream_t st) {
     dim3 grid(sl.nblk, sl.S);
-    if (c->prec == DNB_FP32C && sl.jslice <= VJP_LDS_SLICE)
-        hipLaunchKernelGGL((k_pair_vjp_f32c<EPS0, MASS, true>), grid, dim3(BS), 0, st,
-                           (const float4*)c->jsv, (int)n, i0, iend, nj, sl.jslice, (float)eps2,
-                           (float*)c->partv, sl.npad, c->muni);
-    else if (c->prec == DNB_FP32C)
-        hipLaunchKernelGGL((k_pair_vjp_f32c<EPS0, MASS, false>), grid, dim3(BS), 0, st,
-                           (const float4*)c->jsv, (int)n, i0, iend, nj, sl.jslice, (float)eps2,
-                           (float*)c->partv, sl.npad, c->muni);
-    else
+    const bool nt = (int64_t)sl.S * sl.npad * (MASS ? 4 : 3) * 8 >= NT_PARTIAL_BYTES;
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, grid, dim3(BS), 0, st, (const float4*)c->jsv, (int)n, i0,
+                           iend, nj, sl.jslice, (float)eps2, (float*)c->partv, sl.npad, c->muni);
+    };
+    const bool lds = sl.jslice <= VJP_LDS_SLICE;
+    if (c->prec == DNB_FP32C) {
+        if (lds && nt) go(k_pair_vjp_f32c<EPS0, MASS, true, true>);
+        else if (lds) go(k_pair_vjp_f32c<EPS0, MASS, true, false>);
+        else if (nt) go(k_pair_vjp_f32c<EPS0, MASS, false, true>);
+        else go(k_pair_vjp_f32c<EPS0, MASS, false, false>);
+    } else {
         hipLaunchKernelGGL((k_pair_vjp_f64<EPS0, MASS>), grid, dim3(BS), 0, st,
                            (const double4*)c->jsv, (int)n, i0, iend, nj, sl.jslice, eps2,
                            (double*)c->partv, sl.npad);
+    }
 }
 
 static hipError_t launch_pair_vjp_sliced(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni,

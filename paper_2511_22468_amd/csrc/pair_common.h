@@ -15,6 +15,26 @@ __device__ __forceinline__ void two_sum_acc(float& hi, float& lo, float x) {
     lo += e;
 }
 
+// Stores one slice partial (hi, lo).  With NT the store is non-temporal: the
+// partial streams out to memory instead of staying dirty in L2 until the kernel
+// ends, when the whole launch's partials would be written back at once (that
+// drain cost 3-5 us per launch at n = 8192).  A small launch keeps plain stores:
+// its partials are few, and the reduction that follows reads them from L2.
+// (A compile-time choice: with a run-time flag the compiler merges the two
+// stores into one plain store.)
+template <bool NT>
+__device__ __forceinline__ void put_partial(float2* p, float h, float l) {
+    if (NT) {
+        __builtin_nontemporal_store(h, &p->x);
+        __builtin_nontemporal_store(l, &p->y);
+    } else {
+        *p = make_float2(h, l);
+    }
+}
+
+// Launch-wide bytes of slice partials from which the stores are non-temporal.
+constexpr int64_t NT_PARTIAL_BYTES = int64_t(2) << 20;
+
 // Start index of the batch loaded ahead of batch k of a sub-tile that starts at
 // jt and holds kend sources (SUBTILE, or fewer at the end of a short slice); on
 // the last batch of the slice it re-reads the slice's last batch (in bounds).
