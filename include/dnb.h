@@ -217,10 +217,14 @@ dnb_status dnb_simulate_resume(dnb_ctx* ctx, int64_t n, const double* tape, int6
  * (the position array that call moved in place); gpos_T, gvel_T [3][n], the
  * loss cotangents of the final state (gvel_T may be NULL for zero).  workspace
  * holds dnb_vjp_workspace_doubles(n, ckpt_every).  Outputs: gpos_0, gvel_0
- * [3][n]; gmass [n] (nullable): dL/dm_k; gparams [4] (device): dL/dm_nfw,
- * dL/dm_mn, dL/ddt, and sum_k m_k dL/dm_k (the derivative with respect to a
+ * [3][n]; gmass [n] (nullable): dL/dm_k; gparams [7] (device): dL/dm_nfw,
+ * dL/dm_mn, dL/ddt, sum_k m_k dL/dm_k (the derivative with respect to a
  * common log-scale of all particle masses, which is what a progenitor-mass
- * parameter needs).  Outputs must not alias inputs.
+ * parameter needs), then the derivatives with respect to the host's shape
+ * parameters dL/drs_nfw, dL/da_mn and dL/db_mn (Sec. 2.2.2 fits the halo's scale
+ * radius and the disk's scale lengths with the masses; where b_mn = 0 and
+ * z = 0 the disk's derivatives in z are taken as 0, as its z-acceleration is).
+ * Outputs must not alias inputs.
  *
  * Call sequence: the context records each tape that dnb_simulate writes (its
  * address, the position and mass arrays, n, n_steps, ckpt_every, dt and pot;

@@ -92,17 +92,34 @@ def accel_vjp(pos, mass, pot, w, with_ext=True, self_gravity=True):
     return gx, gm, g_nfw, g_mn
 
 
+def ext_shape_vjp(pos, pot, w):
+    """Cotangents of the host's shape parameters for an incoming cotangent w of
+    the accelerations: (sum w . da/drs_nfw, sum w . da/da_mn, sum w . da/db_mn)."""
+    g_rs = g_a = g_b = 0.0
+    if pot.m_nfw != 0:
+        g_rs = np.sum(forces.nfw_accel_drs(pos, pot.G, pot.m_nfw, pot.rs_nfw) * w)
+    if pot.m_mn != 0:
+        da, db = forces.mn_accel_dab(pos, pot.G, pot.m_mn, pot.a_mn, pot.b_mn)
+        g_a, g_b = np.sum(da * w), np.sum(db * w)
+    return g_rs, g_a, g_b
+
+
 def simulate_vjp(traj, mass, pot, dt, gx_T, gv_T, with_ext=True, self_gravity=True):
     """Reverse sweep through a trajectory recorded by integrate.simulate(keep=True).
 
     Returns a dict with the cotangents of x_0, v_0, the particle masses, the
-    two host masses and the step size dt.
+    two host masses, the host's three shape parameters and the step size dt.
     """
     xs, vhs, acs = traj["x"], traj["vh"], traj["a"]
     lx = np.array(gx_T, copy=True)
     lv = np.array(gv_T, copy=True)
     lm = np.zeros(np.shape(mass), dtype=np.result_type(lx, float))
     l_nfw = l_mn = l_dt = 0.0
+    l_shape = np.zeros(3, dtype=lx.dtype)
+
+    def shape(x, w):
+        return np.array(ext_shape_vjp(x, pot, w)) if with_ext else 0.0
+
     for n in range(len(vhs) - 1, -1, -1):
         # v_{n+1} = v_half + dt/2 a(x_{n+1})
         gx, gm, gn, gd = accel_vjp(xs[n + 1], mass, pot, lv, with_ext, self_gravity)
@@ -110,6 +127,7 @@ def simulate_vjp(traj, mass, pot, dt, gx_T, gv_T, with_ext=True, self_gravity=Tr
         lm = lm + 0.5 * dt * gm
         l_nfw = l_nfw + 0.5 * dt * gn
         l_mn = l_mn + 0.5 * dt * gd
+        l_shape = l_shape + 0.5 * dt * shape(xs[n + 1], lv)
         l_dt = l_dt + 0.5 * np.sum(acs[n + 1] * lv)
         # x_{n+1} = x_n + dt v_half
         l_dt = l_dt + np.sum(vhs[n] * lx)
@@ -120,5 +138,7 @@ def simulate_vjp(traj, mass, pot, dt, gx_T, gv_T, with_ext=True, self_gravity=Tr
         lm = lm + 0.5 * dt * gm
         l_nfw = l_nfw + 0.5 * dt * gn
         l_mn = l_mn + 0.5 * dt * gd
+        l_shape = l_shape + 0.5 * dt * shape(xs[n], lv)
         l_dt = l_dt + 0.5 * np.sum(acs[n] * lv)
-    return dict(x0=lx, v0=lv, mass=lm, m_nfw=l_nfw, m_mn=l_mn, dt=l_dt)
+    return dict(x0=lx, v0=lv, mass=lm, m_nfw=l_nfw, m_mn=l_mn, dt=l_dt,
+                rs_nfw=l_shape[0], a_mn=l_shape[1], b_mn=l_shape[2])

@@ -143,6 +143,22 @@ def nfw_hvp(pos, w, G, M, rs):
     return -g[:, None] * w - (gp / r * xw)[:, None] * pos
 
 
+def nfw_accel_drs(pos, G, M, rs):
+    """Derivative of the NFW acceleration with respect to the scale radius.
+
+    With x = r/rs, mu'(x) = x/(1+x)^2 and dx/drs = -x/rs,
+        da/drs = -G M mu'(x) (-x/rs) r_vec / r^3 = G M x^2 / ((1+x)^2 rs) r_vec / r^3;
+    zero at r = 0.
+    """
+    pos = np.asarray(pos)
+    r2 = pos[:, 0] ** 2 + pos[:, 1] ** 2 + pos[:, 2] ** 2
+    zero = _real(r2) == 0
+    r = np.sqrt(np.where(zero, 1.0, r2))
+    x = r / rs
+    f = np.where(zero, 0.0, G * M * x * x / ((1.0 + x) ** 2 * rs) / (r * r * r))
+    return f[:, None] * pos
+
+
 # ------------------------------------------------------- Miyamoto-Nagai ----
 
 def mn_potential(pos, G, M, a, b):
@@ -165,6 +181,39 @@ def mn_accel(pos, G, M, a, b):
     Ssafe = np.where(_real(S) == 0, 1.0, S)
     az = np.where(_real(S) == 0, 0.0, -k * z * (a + S) / Ssafe)
     return np.stack([-k * x, -k * y, az], axis=1)
+
+
+def mn_accel_dab(pos, G, M, a, b):
+    """Derivatives of the MN acceleration with respect to the scale lengths a and b.
+
+    With S = sqrt(z^2+b^2), A = a+S, D^2 = R^2 + A^2, so that dD^2/da = 2A and
+    dS/db = dA/db = b/S:
+        da_x/da = 3 G M x A / D^5 (likewise y),
+        da_z/da = -G M (z/S) (1/D^3 - 3 A^2/D^5),
+        da_x/db = (b/S) da_x/da,
+        da_z/db = -G M z [d(A/S)/db / D^3 - 3 (A/S) A (b/S) / D^5]
+                = G M z b [a/(S^3 D^3) + 3 A^2/(S^2 D^5)]      (d(A/S)/db = -a b/S^3).
+    Where S = 0 the z-derivatives and b/S are taken as zero, as mn_accel takes a_z.
+    Returns (da/da, da/db), each (N, 3).
+    """
+    pos = np.asarray(pos)
+    x, y, z = pos[:, 0], pos[:, 1], pos[:, 2]
+    S = np.sqrt(z * z + b * b)
+    A = a + S
+    D2 = x * x + y * y + A * A
+    D = np.sqrt(D2)
+    D3 = D2 * D
+    D5 = D3 * D2
+    GM = G * M
+    flat = _real(S) == 0
+    Ss = np.where(flat, 1.0, S)
+    dxa = 3.0 * GM * A / D5
+    dza = np.where(flat, 0.0, -GM * (z / Ss) * (1.0 / D3 - 3.0 * A * A / D5))
+    bS = np.where(flat, 0.0, b / Ss)
+    dzb = np.where(flat, 0.0, GM * z * b * (a / (Ss ** 3 * D3) + 3.0 * A * A / (Ss * Ss * D5)))
+    da = np.stack([dxa * x, dxa * y, dza], axis=1)
+    db = np.stack([bS * dxa * x, bS * dxa * y, dzb], axis=1)
+    return da, db
 
 
 def mn_hvp(pos, w, G, M, a, b):

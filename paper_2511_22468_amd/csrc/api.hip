@@ -579,6 +579,7 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
         return fail(DNB_ERR_ARG, "%s: outputs must not alias inputs", fn);
     CHECK(check_extent(workspace, sizeof(double) * dnb_vjp_workspace_doubles(n, ckpt_every),
                        "workspace", fn));
+    CHECK(check_extent(gparams, sizeof(double) * 7, "gparams", fn));
     if (n_steps > 0) {
         CHECK(check_extent(tape, sizeof(double) * dnb_tape_doubles(n, n_steps, ckpt_every), "tape",
                            fn));
@@ -593,12 +594,12 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
     double* lv = gvel_0;
     double* seg = workspace;                         // [(K+1)][3][n]
     double* vrec = workspace + 3 * n * (K + 1);      // [3][n]
-    double* accum = vrec + 3 * n;                    // [5][n]
+    double* accum = vrec + 3 * n;                    // [8][n]
     double* seg_a = workspace + 3 * n * (K + 1) + 16 * n;   // [K][3][n]
     HIP_TRY(hipMemcpyAsync(lx, gpos_T, vec, hipMemcpyDeviceToDevice, st));
     if (gvel_T) HIP_TRY(hipMemcpyAsync(lv, gvel_T, vec, hipMemcpyDeviceToDevice, st));
     else HIP_TRY(hipMemsetAsync(lv, 0, vec, st));
-    HIP_TRY(hipMemsetAsync(accum, 0, sizeof(double) * 5 * n, st));
+    HIP_TRY(hipMemsetAsync(accum, 0, sizeof(double) * 8 * n, st));
     HIP_TRY(launch_mass_info(c, mass, n, st));
     const int with_mass = gmass != nullptr;
     if (T > 0) {
@@ -692,8 +693,8 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
             wq = 1 - wq;
         }
     }
-    HIP_TRY(launch_reduce_accum(accum, n, 4, gparams, c->red, st));
-    if (gmass) HIP_TRY(hipMemcpyAsync(gmass, accum + 4 * n, sizeof(double) * n,
+    HIP_TRY(launch_reduce_accum(accum, n, 7, gparams, c->red, st));
+    if (gmass) HIP_TRY(hipMemcpyAsync(gmass, accum + 7 * n, sizeof(double) * n,
                                       hipMemcpyDeviceToDevice, st));
     return DNB_OK;
 }

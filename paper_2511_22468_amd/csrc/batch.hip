@@ -662,7 +662,7 @@ __global__ __launch_bounds__(BS) void k_batch_rev_kick(
 }
 
 // Per-member sums of the four per-particle cotangent accumulators (the order of
-// k_reduce_rows5).  One block per member.
+// k_reduce_rows).  One block per member.
 __global__ __launch_bounds__(BS) void k_batch_reduce4(const double* __restrict__ accum, int64_t n,
                                                       double* __restrict__ out) {
     __shared__ double sh[5 * BS];

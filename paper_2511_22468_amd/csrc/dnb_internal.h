@@ -131,11 +131,22 @@ __device__ inline void ext_hvp(const Pot& p, double x, double y, double z, doubl
 // ext_accel and ext_hvp at one point in one pass: the square roots, the NFW
 // enclosed-mass profile and the shared quotients are formed once, with the same
 // expressions as in those functions, so both results are the same bits.
+// shape (nullable) receives the derivatives of the acceleration with respect to
+// the three shape parameters, each dotted with w: (da/drs_nfw . w, da/da_mn . w,
+// da/db_mn . w).  With x = r / rs, mu'(x) = x / (1 + x)^2 and dx/drs = -x / rs:
+//   da_NFW/drs = G m_nfw x^2 / ((1 + x)^2 rs) r_vec / r^3.
+// With S = sqrt(z^2 + b^2), A = a + S, D^2 = R^2 + A^2 (dD^2/da = 2 A,
+// dS/db = b / S):
+//   da_x/da = 3 G M x A / D^5 (likewise y),  da_z/da = -G M (z / S)(1/D^3 - 3 A^2/D^5),
+//   da_x/db = (b / S) da_x/da,  da_z/db = G M z b (a / (S^3 D^3) + 3 A^2 / (S^2 D^5)),
+// the z-derivatives (and b / S) taken as 0 where S = 0, as the acceleration's z
+// component is.
 __device__ inline void ext_accel_hvp(const Pot& p, double x, double y, double z, double wx,
                                      double wy, double wz, Ext& e, double& hx, double& hy,
-                                     double& hz) {
+                                     double& hz, double* shape = nullptr) {
     e = Ext{};
     hx = hy = hz = 0.0;
+    double s_rs = 0.0, s_a = 0.0, s_b = 0.0;
     if (p.m_nfw != 0.0) {
         double r2 = x * x + y * y + z * z;
         double tx = 0.0, ty = 0.0, tz = 0.0;
@@ -149,6 +160,11 @@ __device__ inline void ext_accel_hvp(const Pot& p, double x, double y, double z,
             double gp = G * (1.0 / (r2 * rp * rp) - 3.0 * mu / (r2 * r2));
             double c = gp / r * (x * wx + y * wy + z * wz);
             tx = -g * wx - c * x; ty = -g * wy - c * y; tz = -g * wz - c * z;
+            if (shape) {
+                const double xr = r / rs;
+                const double q = xr / (1.0 + xr);
+                s_rs = p.m_nfw * (G * (q * q / rs) / (r2 * r)) * (x * wx + y * wy + z * wz);
+            }
         }
         hx += p.m_nfw * tx; hy += p.m_nfw * ty; hz += p.m_nfw * tz;
     }
@@ -177,10 +193,23 @@ __device__ inline void ext_accel_hvp(const Pot& p, double x, double y, double z,
         double ty = hxy * wx + hyy * wy + hyz * wz;
         double tz = hxz * wx + hyz * wy + hzz * wz;
         hx += p.m_mn * tx; hy += p.m_mn * ty; hz += p.m_mn * tz;
+        if (shape) {
+            const double xyw = x * wx + y * wy;
+            const double dxa = 3.0 * G * A * iD5;
+            double bS = 0.0, dza = 0.0, dzb = 0.0;
+            if (S != 0.0) {
+                bS = b / S;
+                dza = -G * (z / S) * (iD3 - 3.0 * A * A * iD5);
+                dzb = G * z * b * (a / (S * S * S) * iD3 + 3.0 * A * A / (S * S) * iD5);
+            }
+            s_a = p.m_mn * (dxa * xyw + dza * wz);
+            s_b = p.m_mn * (dxa * bS * xyw + dzb * wz);
+        }
     }
     e.ax = p.m_nfw * e.nx + p.m_mn * e.mx;
     e.ay = p.m_nfw * e.ny + p.m_mn * e.my;
     e.az = p.m_nfw * e.nz + p.m_mn * e.mz;
+    if (shape) { shape[0] = s_rs; shape[1] = s_a; shape[2] = s_b; }
 }
 
 // Deterministic sum over a block of BS threads of NV doubles per thread: a
@@ -374,7 +403,8 @@ struct RevArgs {
     const double* aint;     // [3][n] internal acceleration at x_n (from the forward pass)
     double* lx;             // [3][n] position cotangent (in/out)
     double* lv;             // [3][n] velocity cotangent (in/out)
-    double* accum;          // [5][n] per-particle running sums: m_nfw, m_mn, dt, mass scale, mass
+    double* accum;          // [8][n] per-particle running sums: m_nfw, m_mn, dt, mass scale,
+                            // rs_nfw, a_mn, b_mn, mass
     int with_mass;
     const double* cpart_in; int nb_in; double* cpart_out;
     const double* wscale_in;   // scale the consumed cotangent was staged with (FP32C)

@@ -331,8 +331,9 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
         px = a.x_prev[k]; py = a.x_prev[n + k]; pz = a.x_prev[2 * n + k];
         mk = a.mass[k];
     }
-    const double acc0[5] = {a.accum[k], a.accum[n + k], a.accum[2 * n + k], a.accum[3 * n + k],
-                            a.with_mass ? a.accum[4 * n + k] : 0.0};
+    const double acc0[8] = {a.accum[k], a.accum[n + k], a.accum[2 * n + k], a.accum[3 * n + k],
+                            a.accum[4 * n + k], a.accum[5 * n + k], a.accum[6 * n + k],
+                            a.with_mass ? a.accum[7 * n + k] : 0.0};
 
     // staging centre, cotangent scale and sum of J^T w (FP32C)
     double cx = 0.0, cy = 0.0, cz = 0.0, Sn = 1.0;
@@ -354,7 +355,8 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
     }
     Ext e;
     double hx, hy, hz;
-    ext_accel_hvp(a.pot, x, y, z, wx, wy, wz, e, hx, hy, hz);
+    double shp[3];
+    ext_accel_hvp(a.pot, x, y, z, wx, wy, wz, e, hx, hy, hz, shp);
 
     const double lx = fma(a.coef, g[0] + hx, lx0);
     const double ly = fma(a.coef, g[1] + hy, ly0);
@@ -380,7 +382,10 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
         a.accum[n + i] = acc0[1] + d_mn;
         a.accum[2 * n + i] = acc0[2] + d_dt;
         a.accum[3 * n + i] = acc0[3] + d_ms;
-        if (a.with_mass) a.accum[4 * n + i] = acc0[4] - a.coef * gm;
+        a.accum[4 * n + i] = acc0[4] + a.coef * shp[0];
+        a.accum[5 * n + i] = acc0[5] + a.coef * shp[1];
+        a.accum[6 * n + i] = acc0[6] + a.coef * shp[2];
+        if (a.with_mass) a.accum[7 * n + i] = acc0[7] - a.coef * gm;
         if (drift) { a.lv[i] = nwx; a.lv[n + i] = nwy; a.lv[2 * n + i] = nwz; }
     }
     if (drift) {
@@ -506,13 +511,14 @@ hipError_t launch_rev_kick(dnb_ctx* c, const RevArgs& a, hipStream_t st) {
 
 // Sum of nterms per-particle arrays [nterms][n] -> out[nterms]; one block,
 // fixed order.
-__global__ __launch_bounds__(BS) void k_reduce_rows5(const double* __restrict__ v, int64_t n,
-                                                     int nterms, double* __restrict__ out) {
-    __shared__ double sh[5 * BS];
-    double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+// Sums over the particles of up to 7 rows [nterms][n] (one block, fixed order).
+__global__ __launch_bounds__(BS) void k_reduce_rows(const double* __restrict__ v, int64_t n,
+                                                    int nterms, double* __restrict__ out) {
+    __shared__ double sh[7 * BS];
+    double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t i = threadIdx.x; i < n; i += BS)
         for (int t = 0; t < nterms; ++t) s[t] += v[t * n + i];
-    block_sum<5>(s, sh);
+    block_sum<7>(s, sh);
     if (threadIdx.x == 0)
         for (int t = 0; t < nterms; ++t) out[t] = s[t];
 }
@@ -520,7 +526,7 @@ __global__ __launch_bounds__(BS) void k_reduce_rows5(const double* __restrict__ 
 hipError_t launch_reduce_accum(const double* accum, int64_t n, int nterms, double* out,
                                double* scratch, hipStream_t st) {
     (void)scratch;
-    hipLaunchKernelGGL(k_reduce_rows5, dim3(1), dim3(BS), 0, st, accum, n, nterms, out);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(BS), 0, st, accum, n, nterms, out);
     return hipGetLastError();
 }
 

@@ -226,8 +226,9 @@ class Context:
 
     def simulate_vjp(self, mass, pot, dt, n_steps, ckpt_every, tape, pos_T, gpos_T, gvel_T=None,
                      with_mass=False, workspace=None):
-        """Returns (gpos_0, gvel_0, gmass or None, gparams[4]) with gparams =
-        (dL/dm_nfw, dL/dm_mn, dL/ddt, sum_k m_k dL/dm_k)."""
+        """Returns (gpos_0, gvel_0, gmass or None, gparams[7]) with gparams =
+        (dL/dm_nfw, dL/dm_mn, dL/ddt, sum_k m_k dL/dm_k, dL/drs_nfw, dL/da_mn,
+        dL/db_mn)."""
         n = mass.shape[0]
         _arr(mass, (n,), "mass"); _vec(pos_T, n, "pos_T"); _vec(gpos_T, n, "gpos_T")
         if gvel_T is not None:
@@ -241,7 +242,7 @@ class Context:
             _buffer(tape, self.tape_len(n, n_steps, K), "tape")
         gpos0, gvel0 = self._new(3, n), self._new(3, n)
         gmass = self._new(n) if with_mass else None
-        gpar = self._new(4)
+        gpar = self._new(7)
         _lib.check(_lib.lib().dnb_simulate_vjp(
             self._h, n, _lib.ptr(mass), pot.c(), float(dt), int(n_steps), K, _lib.ptr(tape),
             _lib.ptr(pos_T), _lib.ptr(gpos_T), _lib.ptr(gvel_T), _lib.ptr(workspace),

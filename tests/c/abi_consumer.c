@@ -34,7 +34,7 @@ int main(void) {
         hipMalloc((void**)&tape, sizeof(double) * tape_n) ||
         hipMalloc((void**)&work, sizeof(double) * work_n) ||
         hipMalloc((void**)&g0, sizeof pos) || hipMalloc((void**)&gv0, sizeof pos) ||
-        hipMalloc((void**)&gpar, sizeof(double) * 4))
+        hipMalloc((void**)&gpar, sizeof(double) * 7))
         FAIL("hipMalloc failed");
     hipMemcpy(dpos, pos, sizeof pos, hipMemcpyHostToDevice);
     hipMemcpy(dvel, vel, sizeof vel, hipMemcpyHostToDevice);

@@ -63,7 +63,7 @@ def test_vjp_refuses_a_tape_it_did_not_write(mods, prec):
                        device="cuda")
     outs = (torch.zeros(3, N, dtype=torch.float64, device="cuda"),
             torch.zeros(3, N, dtype=torch.float64, device="cuda"),
-            torch.zeros(4, dtype=torch.float64, device="cuda"))
+            torch.zeros(7, dtype=torch.float64, device="cuda"))
 
     # no dnb_simulate has written this tape
     assert raw_vjp(lib, ctx, m, pot, dt, T, K, tape, x, g, work, outs) == _lib.DNB_ERR_STATE
@@ -133,7 +133,7 @@ def test_vjp_refuses_a_short_device_buffer(mods):
         outs = [ctypes.c_void_p(t.data_ptr()) for t in
                 (torch.zeros(3, N, dtype=torch.float64, device="cuda"),
                  torch.zeros(3, N, dtype=torch.float64, device="cuda"),
-                 torch.zeros(4, dtype=torch.float64, device="cuda"))]
+                 torch.zeros(7, dtype=torch.float64, device="cuda"))]
         st = lib.dnb_simulate_vjp(ctx._h, N, ctypes.c_void_p(m.data_ptr()), pot.c(), 5e-4, T, K,
                                   ctypes.c_void_p(tape.data_ptr()),
                                   ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(g.data_ptr()),

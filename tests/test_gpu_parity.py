@@ -232,6 +232,9 @@ def test_adjoint_matches_oracle(dnb, prec, K, masses):
     assert abs(gp[1] / ref["m_mn"] - 1) <= tol
     assert abs(gp[2] / ref["dt"] - 1) <= tol
     assert abs(gp[3] / np.sum(m * ref["mass"]) - 1) <= tol
+    # the host's shape parameters: NFW scale radius, MN scale lengths a and b
+    for k, name in ((4, "rs_nfw"), (5, "a_mn"), (6, "b_mn")):
+        assert abs(gp[k] / ref[name] - 1) <= tol, (name, gp[k], ref[name])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])

@@ -132,8 +132,10 @@ def test_adjoint_matches_complex_step_of_the_forward_map():
     dx, dv = rng.normal(size=x.shape) * 1e-3, rng.normal(size=v.shape)
     dm = rng.normal(size=m.shape)
 
-    def run(z, px=0, pv=0, pm=0, pn=0.0, pd=0.0, pdt=0.0):
-        pp = pot.replace(m_nfw=pot.m_nfw + z * pn, m_mn=pot.m_mn + z * pd)
+    def run(z, px=0, pv=0, pm=0, pn=0.0, pd=0.0, pdt=0.0, prs=0.0, pa=0.0, pb=0.0):
+        pp = pot.replace(m_nfw=pot.m_nfw + z * pn, m_mn=pot.m_mn + z * pd,
+                         rs_nfw=pot.rs_nfw + z * prs, a_mn=pot.a_mn + z * pa,
+                         b_mn=pot.b_mn + z * pb)
         xT, vT = integrate.simulate(x + z * px, v + z * pv, m + z * pm, pp, dt + z * pdt, n_steps)
         return np.sum(wx * xT) + np.sum(wv * vT)
 
@@ -145,6 +147,9 @@ def test_adjoint_matches_complex_step_of_the_forward_map():
     np.testing.assert_allclose(g["m_nfw"], _cs(lambda z: run(z, pn=1.0)), rtol=1e-10)
     np.testing.assert_allclose(g["m_mn"], _cs(lambda z: run(z, pd=1.0)), rtol=1e-10)
     np.testing.assert_allclose(g["dt"], _cs(lambda z: run(z, pdt=1.0)), rtol=1e-10)
+    np.testing.assert_allclose(g["rs_nfw"], _cs(lambda z: run(z, prs=1.0)), rtol=1e-10)
+    np.testing.assert_allclose(g["a_mn"], _cs(lambda z: run(z, pa=1.0)), rtol=1e-10)
+    np.testing.assert_allclose(g["b_mn"], _cs(lambda z: run(z, pb=1.0)), rtol=1e-10)
 
 
 def test_pair_vjp_dot_product_identity():

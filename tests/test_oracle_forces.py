@@ -199,6 +199,37 @@ def test_external_hessian_vector_products(which):
     np.testing.assert_allclose(hv, cs_jvp(f, p, w), rtol=1e-11, atol=1e-12 * np.abs(hv).max())
 
 
+def test_nfw_scale_radius_derivative_against_complex_step():
+    # positions from the centre (the small-x series of mu) out to 20 scale radii
+    rng = np.random.default_rng(13)
+    dirs = rng.normal(size=(9, 3))
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+    radii = np.array([1e-6, 1e-3, 0.5, 4.0, 12.0, 16.0, 40.0, 120.0, 320.0])
+    p = dirs * radii[:, None]
+    got = forces.nfw_accel_drs(p, G, 1e12, 16.0)
+    ref = np.imag(forces.nfw_accel(p, G, 1e12, 16.0 + 1e-30j)) / 1e-30
+    np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-14 * np.abs(ref).max())
+    assert np.all(forces.nfw_accel_drs(np.zeros((1, 3)), G, 1e12, 16.0) == 0.0)
+
+
+@pytest.mark.parametrize("b", [0.28, 0.0])
+def test_mn_scale_length_derivatives_against_complex_step(b):
+    # points above, below and in the disk plane (b = 0: the razor-thin disk, whose
+    # b-derivative vanishes off the plane and is taken as zero on it)
+    rng = np.random.default_rng(14)
+    p = rng.normal(scale=6.0, size=(10, 3))
+    p[:3, 2] = 0.0
+    da, db = forces.mn_accel_dab(p, G, 6.5e10, 3.0, b)
+    ra = np.imag(forces.mn_accel(p, G, 6.5e10, 3.0 + 1e-30j, b)) / 1e-30
+    rb = np.imag(forces.mn_accel(p, G, 6.5e10, 3.0, b + 1e-30j)) / 1e-30
+    np.testing.assert_allclose(da, ra, rtol=1e-10, atol=1e-14 * np.abs(ra).max())
+    if b > 0:
+        np.testing.assert_allclose(db, rb, rtol=1e-10, atol=1e-14 * np.abs(rb).max())
+    else:
+        np.testing.assert_allclose(db[3:], rb[3:], atol=1e-14 * np.abs(ra).max())
+        assert np.all(db[:3] == 0.0)
+
+
 def test_external_potential_defaults_and_circular_speed():
     pot = Potential()
     p = np.array([[12.0, 0.0, 0.0]])
