@@ -1,12 +1,18 @@
 // Learned-surrogate kernels: BF16 matrix-core MLP (forward, backward, MSE,
 // Adam) and the orbit-frame density image of a stream.
 //
-// The MLP products use v_mfma_f32_16x16x16_bf16 (BF16 inputs, FP32
-// accumulation).  A 256-thread block computes a 64 x 64 output tile; each of its
-// four waves owns a 32 x 32 quadrant as 2 x 2 MFMA tiles; K advances in steps of
-// 16 through LDS.  Operand strides are arguments, so transposed operands (W^T in
-// the data gradient, X^T in the weight gradient) need no copies.  Tile loads are
-// bounds-checked and zero-filled, so any M, N, K work (the first layer has K = 4).
+// The MLP products use gfx950's v_mfma_f32_16x16x32_bf16 (BF16 inputs, FP32
+// accumulation, 32 products per output per instruction).  A 256-thread block
+// computes a 64 x 64 output tile; each of its four waves owns a 32 x 32 quadrant
+// as 2 x 2 MFMA tiles; K advances in steps of 32 through LDS, where both operand
+// tiles are stored K-contiguous (A as [m][k], B transposed as [n][k], rows padded
+// to 80 bytes), so each lane reads its eight K-values of an operand with one
+// 16-byte LDS load.  Operand strides are arguments, so transposed operands (W^T
+// in the data gradient, X^T in the weight gradient) need no copies: the tile
+// loader reads eight consecutive elements with one 16-byte global load along
+// whichever dimension is contiguous, and falls back to bounds-checked,
+// zero-filled element loads at ragged edges and unaligned addresses, so any
+// M, N, K work (the first layer has K = 4).
 // Epilogues fuse the bias, the GELU, and the GELU derivative of the backward
 // pass.  The networks here are small (batch <= 65536, widths <= 2048); these
 // kernels are latency-bound, not MFMA-bound.
@@ -18,8 +24,24 @@
 
 namespace dnb {
 
-typedef short mfma_s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mfma_bf8 __attribute__((ext_vector_type(8)));
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int GK = 32;        // K per step of the GEMM
+constexpr int GLD = GK + 8;   // LDS row length (elements): 80-byte rows, 16-byte aligned
+
+// Eight consecutive elements p[0], p[step], ..., p[7 step] of a BF16 operand,
+// of which the first `valid` exist (the rest read as zero): one 16-byte load
+// when the elements are contiguous, whole and 16-byte aligned.
+__device__ __forceinline__ u16x8 load8(const uint16_t* __restrict__ p, int64_t step, int valid) {
+    if (step == 1 && valid >= 8 && ((uintptr_t)p & 15) == 0)
+        return *(const u16x8*)p;
+    u16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (j < valid) ? p[j * step] : (uint16_t)0;
+    return v;
+}
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
     uint32_t b = __float_as_uint(f);
@@ -64,8 +86,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K,
                                                    float* __restrict__ outf,
                                                    uint16_t* __restrict__ outb, int64_t ldo,
                                                    int kchunk) {
-    __shared__ uint16_t As[64][16];
-    __shared__ uint16_t Bs[16][64];
+    __shared__ __attribute__((aligned(16))) uint16_t As[64][GLD];   // A tile, [m][k]
+    __shared__ __attribute__((aligned(16))) uint16_t Bt[64][GLD];   // B tile, [n][k]
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
@@ -76,31 +98,57 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K,
         for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f4{0.f, 0.f, 0.f, 0.f};
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(K, kbeg + kchunk);
-    for (int k0 = kbeg; k0 < kend; k0 += 16) {
+    // which operand dimension the loader walks eight elements along
+    const bool a_k = sak == 1 || sam != 1;   // A: along k (else along m)
+    const bool b_k = sbk == 1 || sbn != 1;   // B: along k (else along n)
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+        // 64 x 32 elements of each operand, eight per thread
+        if (a_k) {
+            const int r = t >> 2, c = (t & 3) * 8;
+            const int gm = m0 + r, gk = k0 + c;
+            const int valid = gm < M ? max(0, min(8, kend - gk)) : 0;
+            const u16x8 v = load8(A + (valid ? gm * sam + gk * sak : 0), sak, valid);
+            *(u16x8*)&As[r][c] = v;
+        } else {
+            const int kk = t >> 3, c = (t & 7) * 8;
+            const int gk = k0 + kk, gm = m0 + c;
+            const int valid = gk < kend ? max(0, min(8, M - gm)) : 0;
+            const u16x8 v = load8(A + (valid ? gm * sam + gk * sak : 0), sam, valid);
 #pragma unroll
-        for (int e = t; e < 1024; e += 256) {
-            const int r = e >> 4, kk = e & 15;
-            const int gm = m0 + r, gk = k0 + kk;
-            As[r][kk] = (gm < M && gk < kend) ? A[gm * sam + gk * sak] : (uint16_t)0;
-            const int kb = e >> 6, c = e & 63;
-            const int gk2 = k0 + kb, gn = n0 + c;
-            Bs[kb][c] = (gk2 < kend && gn < N) ? B[gk2 * sbk + gn * sbn] : (uint16_t)0;
+            for (int j = 0; j < 8; ++j) As[c + j][kk] = v[j];
+        }
+        if (b_k) {
+            const int n = t >> 2, c = (t & 3) * 8;
+            const int gn = n0 + n, gk = k0 + c;
+            const int valid = gn < N ? max(0, min(8, kend - gk)) : 0;
+            const u16x8 v = load8(B + (valid ? gk * sbk + gn * sbn : 0), sbk, valid);
+            *(u16x8*)&Bt[n][c] = v;
+        } else {
+            const int kk = t >> 3, c = (t & 7) * 8;
+            const int gk = k0 + kk, gn = n0 + c;
+            const int valid = gk < kend ? max(0, min(8, N - gn)) : 0;
+            const u16x8 v = load8(B + (valid ? gk * sbk + gn * sbn : 0), sbn, valid);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) Bt[c + j][kk] = v[j];
         }
         __syncthreads();
-        const int kq = 4 * (lane >> 4);
+        // lane l supplies K-values 8 (l / 16) .. 8 (l / 16) + 7 of row / column l % 16
+        // for both operands, so the instruction pairs equal k whatever its internal
+        // order of the 32 products
+        const int kq = 8 * (lane >> 4);
+        mfma_bf8 a[2], b[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            const int row = wr + i * 16 + (lane & 15);
-            const mfma_s4 a = {(short)As[row][kq], (short)As[row][kq + 1], (short)As[row][kq + 2],
-                               (short)As[row][kq + 3]};
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int col = wc + j * 16 + (lane & 15);
-                const mfma_s4 b = {(short)Bs[kq][col], (short)Bs[kq + 1][col],
-                                   (short)Bs[kq + 2][col], (short)Bs[kq + 3][col]};
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i][j], 0, 0, 0);
-            }
+            const u16x8 va = *(const u16x8*)&As[wr + i * 16 + (lane & 15)][kq];
+            const u16x8 vb = *(const u16x8*)&Bt[wc + i * 16 + (lane & 15)][kq];
+            a[i] = __builtin_bit_cast(mfma_bf8, va);
+            b[i] = __builtin_bit_cast(mfma_bf8, vb);
         }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         __syncthreads();
     }
 #pragma unroll
@@ -163,7 +211,7 @@ static void gemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sa
         ldo == N) {
         int splits = K / 128;
         if (splits > KSPLIT_MAX) splits = KSPLIT_MAX;
-        const int kchunk = (int)(cdiv(cdiv(K, splits), 16) * 16);
+        const int kchunk = (int)(cdiv(cdiv(K, splits), GK) * GK);
         splits = (int)cdiv(K, kchunk);
         hipLaunchKernelGGL(k_gemm_bf16<EPI_PARTIAL>, dim3(grid.x, grid.y, (unsigned)splits),
                            dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, bias, zin, kpart,
