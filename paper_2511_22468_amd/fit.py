@@ -200,3 +200,15 @@ def run(quick=False, seed=50, n_train=None, n_draws=None, train_steps=None, max_
     ctx.close()
     gen_ctx.close()
     return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--quick", action="store_true", help="the small configuration")
+    ap.add_argument("--seed", type=int, default=50)
+    a = ap.parse_args()
+    print(json.dumps(run(quick=a.quick, seed=a.seed)), flush=True)
+
+
+if __name__ == "__main__":
+    main()
