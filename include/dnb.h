@@ -156,7 +156,9 @@ dnb_status dnb_step(dnb_ctx* ctx, int64_t n, double* pos, double* vel, const dou
 int64_t dnb_tape_doubles(int64_t n, int64_t n_steps, int64_t ckpt_every);
 
 /* Number of doubles of the segment workspace that dnb_simulate_vjp needs:
- * 3n (ckpt_every + 1) + 16n + 3n ckpt_every. */
+ * 16n for ckpt_every = 1; otherwise 16n + 2 (6n ckpt_every + 3n), room for two
+ * recomputed checkpoint segments (the next one is recomputed while the sweep
+ * reads the current one); -1 for invalid or oversized arguments. */
 int64_t dnb_vjp_workspace_doubles(int64_t n, int64_t ckpt_every);
 
 /* n_steps kick-drift-kick steps of size dt (Sec. 2.2.1: fixed steps), in place

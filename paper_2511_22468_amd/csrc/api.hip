@@ -337,6 +337,9 @@ void dnb_destroy(dnb_ctx* c) {
             for (hipEvent_t e : *v) (void)hipEventDestroy(e);
         delete pf;
     }
+    for (hipEvent_t e : c->revents)
+        if (e) (void)hipEventDestroy(e);
+    if (c->rstream) (void)hipStreamDestroy(c->rstream);
     void* ps[] = {c->js, c->part, c->cpart, c->vh, c->jsv, c->partv, c->cpartv, c->wscale, c->muni,
                   c->bparams, c->bwscale, c->red, c->ared, c->gred, c->arec, c->grec,
                   c->scan};
@@ -592,10 +595,18 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
     const size_t vec = sizeof(double) * 3 * n;
     double* lx = gpos_0;
     double* lv = gvel_0;
-    double* seg = workspace;                         // [(K+1)][3][n]
-    double* vrec = workspace + 3 * n * (K + 1);      // [3][n]
-    double* accum = vrec + 3 * n;                    // [8][n]
-    double* seg_a = workspace + 3 * n * (K + 1) + 16 * n;   // [K][3][n]
+    double* vrec = workspace;                        // [3][n]
+    double* accum = workspace + 3 * n;               // [8][n]
+    // two buffers of a recomputed segment (K > 1): positions [(K+1)][3][n],
+    // then accelerations [K][3][n]; segment cs uses buffer cs & 1
+    double* seg[2] = {nullptr, nullptr};
+    double* seg_a[2] = {nullptr, nullptr};
+    if (K > 1) {
+        for (int b = 0; b < 2; ++b) {
+            seg[b] = workspace + vjp_segment_offset(n, K, b);
+            seg_a[b] = seg[b] + vjp_segment_accel_offset(n, K);
+        }
+    }
     HIP_TRY(hipMemcpyAsync(lx, gpos_T, vec, hipMemcpyDeviceToDevice, st));
     if (gvel_T) HIP_TRY(hipMemcpyAsync(lv, gvel_T, vec, hipMemcpyDeviceToDevice, st));
     else HIP_TRY(hipMemsetAsync(lv, 0, vec, st));
@@ -607,72 +618,101 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
         auto get_pos = [&](int64_t m) -> const double* {
             if (m == T) return pos_T;
             if (m % K == 0) return tp.state(m / K);
-            return seg + (m % K) * 3 * n;
+            return seg[(m / K) & 1] + (m % K) * 3 * n;
         };
         auto get_aint = [&](int64_t m) -> const double* {
             if (m == T) return tp.aint_final();
             if (m % K == 0) return tp.aint(m / K);
-            return seg_a + (m % K) * 3 * n;
+            return seg_a[(m / K) & 1] + (m % K) * 3 * n;
         };
+        // Segment cs spans steps n0 = cs K .. n1 = min(n0 + K, T); the sweep
+        // needs its interior positions recomputed when it has more than one step.
+        auto needs = [&](int64_t cs) { return (cs * K + K < T ? K : T - cs * K) >= 2; };
+        // The recomputation runs on a stream of its own: while the caller's
+        // stream sweeps segment cs, segment cs - 1 is recomputed into the other
+        // buffer.  The two share no scratch (the recomputation uses the forward
+        // staging, partials and reductions, the sweep the VJP ones), so this
+        // changes no result, only what overlaps: each one's latency-bound O(N)
+        // kernels and launch gaps run beside the other one's pair kernels.
+        hipStream_t rs = st;
+        hipEvent_t* ev = c->revents;
+        if (K > 1) {
+            if (!c->rstream) {
+                HIP_TRY(hipStreamCreateWithFlags(&c->rstream, hipStreamNonBlocking));
+                for (hipEvent_t& e : c->revents)
+                    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            }
+            rs = c->rstream;
+            HIP_TRY(hipEventRecord(ev[4], st));
+            HIP_TRY(hipStreamWaitEvent(rs, ev[4], 0));
+        }
         double* cpf[2] = {c->cpart, c->cpart + REC * c->nbmax};
         // Positions x_{n0+1} .. x_{n1-1} of segment cs and their internal
         // accelerations, from its checkpoint, bitwise as in the forward run (the
         // first two stagings take the centres the run stored with the checkpoint;
         // from then on the centres follow from the recomputed positions as they
-        // did in the run).
+        // did in the run), then the event that the buffer is ready.
         auto recompute = [&](int64_t cs) -> dnb_status {
+            if (!needs(cs)) return DNB_OK;
             const int64_t n0 = cs * K, n1 = (n0 + K < T) ? n0 + K : T;
-            if (n1 - n0 < 2) return DNB_OK;
+            double* sx = seg[cs & 1];
+            double* sa = seg_a[cs & 1];
             double* x0 = tp.state(cs);
-            HIP_TRY(launch_stage(c, x0, mass, n, nullptr, 0, tp.centre(cs), nullptr, st));
+            HIP_TRY(launch_stage(c, x0, mass, n, nullptr, 0, tp.centre(cs), nullptr, rs));
             int q = 0;
             for (int64_t s = n0; s <= n1 - 1; ++s) {
-                double* xc = (s == n0) ? x0 : seg + (s - n0) * 3 * n;
-                HIP_TRY(profiled(c, 0, st, [&] { return launch_pair_fwd(c, n, p.eps, st); }));
+                double* xc = (s == n0) ? x0 : sx + (s - n0) * 3 * n;
+                HIP_TRY(profiled(c, 0, rs, [&] { return launch_pair_fwd(c, n, p.eps, rs); }));
                 FwdArgs a{};
                 if (c->prec == DNB_FP32C) {
-                    HIP_TRY(launch_fwd_reduce(c, n, mass, p.G, st));
+                    HIP_TRY(launch_fwd_reduce(c, n, mass, p.G, rs));
                     a.ared = c->ared; a.arec = c->arec; a.nr = red_blocks(n);
                 }
                 a.n = n; a.mass = mass; a.pot = p; a.dt = dt; a.with_ext = 1;
                 a.x = xc;
-                a.aint_out = (s == n0) ? nullptr : seg_a + (s - n0) * 3 * n;
+                a.aint_out = (s == n0) ? nullptr : sa + (s - n0) * 3 * n;
                 if (s == n1 - 1) {   // last position of the segment: acceleration only
-                    HIP_TRY(launch_kdk(c, KDK_ACC, a, st));
+                    HIP_TRY(launch_kdk(c, KDK_ACC, a, rs));
                     break;
                 }
-                a.x_out = seg + (s - n0 + 1) * 3 * n;
+                a.x_out = sx + (s - n0 + 1) * 3 * n;
                 a.v = (s == n0) ? x0 + 3 * n : nullptr;
                 a.vh = vrec;
                 a.cpart_in = cpf[q]; a.cpart_out = cpf[1 - q]; a.nb_in = nb;
                 if (s == n0) a.centre_override = tp.centre_next(cs);
-                HIP_TRY(launch_kdk(c, s == n0 ? KDK_FIRST : KDK_MID, a, st));
+                HIP_TRY(launch_kdk(c, s == n0 ? KDK_FIRST : KDK_MID, a, rs));
                 q = 1 - q;
+            }
+            HIP_TRY(hipEventRecord(ev[cs & 1], rs));
+            return DNB_OK;
+        };
+        int64_t waited = -1;   // the segment whose buffer the sweep has waited for
+        auto wait_for = [&](int64_t cs) -> dnb_status {
+            if (K > 1 && needs(cs) && waited != cs) {
+                HIP_TRY(hipStreamWaitEvent(st, ev[cs & 1], 0));
+                waited = cs;
             }
             return DNB_OK;
         };
+        const int64_t c_last = (T - 1) / K;
+        if (K > 1) {   // the two newest segments, one per buffer
+            CHECK(recompute(c_last));
+            if (c_last >= 1) CHECK(recompute(c_last - 1));
+        }
         double* cpv[2] = {c->cpartv, c->cpartv + REC * c->nbmax};
-        int q = 0;
-        int64_t cur = -1;
         // x_{T-1} first: its displacement from x_T centres the first staging of
         // the sweep
-        if ((T - 1) % K != 0) {
-            CHECK(recompute((T - 1) / K));
-            cur = (T - 1) / K;
-        }
+        CHECK(wait_for(c_last));
         if (c->prec == DNB_FP32C) HIP_TRY(launch_block_sums(pos_T, n, cpv[0], st, lv));
         HIP_TRY(launch_rev_stage(c, n, pos_T, mass, lv, cpv[0], nb, cpv[1], c->wscale, st,
                                  get_pos(T - 1)));
-        q = 1;
+        int q = 1;
         int wq = 0;   // c->wscale[wq]: scale of the currently staged cotangent
         for (int64_t m = T; m >= 0; --m) {
-            if (m > 0) {
-                const int64_t cs = (m - 1) / K;
-                if ((m - 1) % K != 0 && cur != cs) {
-                    CHECK(recompute(cs));
-                    cur = cs;
-                }
-            }
+            // step m reads x_m, x_{m-1} and the acceleration at x_m: the buffer of
+            // segment (m - 1) / K for m >= 1
+            const int64_t cs = m > 0 ? (m - 1) / K : -1;
+            if (m > 0) CHECK(wait_for(cs));
             const double* xm = get_pos(m);
             HIP_TRY(profiled(c, 1, st, [&] { return launch_pair_vjp(c, n, with_mass, p.eps, st); }));
             RevArgs r{};
@@ -691,6 +731,13 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
             HIP_TRY(launch_rev_kick(c, r, st));
             q = 1 - q;
             wq = 1 - wq;
+            // step cs K + 1 is the last to read segment cs: its buffer goes to
+            // segment cs - 2
+            if (K > 1 && m > 0 && m == cs * K + 1 && cs >= 2) {
+                HIP_TRY(hipEventRecord(ev[2 + (cs & 1)], st));
+                HIP_TRY(hipStreamWaitEvent(rs, ev[2 + (cs & 1)], 0));
+                CHECK(recompute(cs - 2));
+            }
         }
     }
     HIP_TRY(launch_reduce_accum(accum, n, 7, gparams, c->red, st));

@@ -291,6 +291,12 @@ struct dnb_ctx {
     int64_t* scan;           // [nbmax + 1] block minima and result of the state scan
     int checks;              // nonzero: the integrators scan their initial state first
     void* prof;              // host-side event pool of dnb_profile (null when off)
+    // The reverse sweep recomputes checkpoint segments on a second stream of
+    // its own (created on first use, default priority) while the caller's stream
+    // sweeps the previous one; events: [0..1] segment buffer b recomputed,
+    // [2..3] segment buffer b released by the sweep, [4] start of the sweep.
+    hipStream_t rstream;
+    hipEvent_t revents[5];
     // Descriptors of the tapes written by the most recent dnb_simulate calls:
     // dnb_simulate_vjp accepts only a tape, with its final positions and the
     // arguments it was written with, listed here.

@@ -110,14 +110,24 @@ inline int64_t tape_doubles(int64_t n, int64_t T, int64_t K) {
     return per + 3 * n;
 }
 
-// Doubles of the workspace of dnb_simulate_vjp: the recomputed segment's
-// positions (3n (K + 1)) and accelerations (3n K), and 16n of per-sweep rows.
+// Doubles of the workspace of dnb_simulate_vjp: 16n of per-sweep rows and, with
+// checkpoints K > 1 steps apart, two buffers of a recomputed segment (one
+// recomputed while the sweep reads the other), each the segment's positions
+// (3n (K + 1)) and accelerations (3n K).
 inline int64_t vjp_workspace_doubles(int64_t n, int64_t K) {
     if (n < 1 || n > MAX_N || K < 1) return -1;
-    const int64_t seg = mul_capped(6 * n, K);
-    if (seg < 0 || seg > MAX_DOUBLES - 19 * n) return -1;
-    return seg + 19 * n;
+    if (K == 1) return 16 * n;
+    const int64_t seg = mul_capped(12 * n, K);
+    if (seg < 0 || seg > MAX_DOUBLES - 22 * n) return -1;
+    return seg + 22 * n;
 }
+
+// Offset (doubles) of segment buffer b (0 or 1) in that workspace, and its
+// accelerations' offset within the buffer.
+inline int64_t vjp_segment_offset(int64_t n, int64_t K, int b) {
+    return 16 * n + (int64_t)b * (6 * n * K + 3 * n);
+}
+inline int64_t vjp_segment_accel_offset(int64_t n, int64_t K) { return 3 * n * (K + 1); }
 
 // Doubles of the tape of dnb_simulate_batch: every step's state (6 n per member)
 // and the internal accelerations at the n_steps + 1 positions (3 n per member).

@@ -79,7 +79,14 @@ static void sizes() {
                 const int64_t nc = cdiv(T, K);
                 const int64_t layout = nc * 6 * n + nc * 8 + nc * 3 * n + 3 * n;
                 EXPECT(tape_doubles(n, T, K) == layout);
-                EXPECT(vjp_workspace_doubles(n, K) == 3 * n * (K + 1) + 16 * n + 3 * n * K);
+                const int64_t ws = vjp_workspace_doubles(n, K);
+                EXPECT(ws == (K == 1 ? 16 * n : 16 * n + 2 * (3 * n * (K + 1) + 3 * n * K)));
+                if (K > 1) {   // the second segment buffer ends where the workspace does
+                    EXPECT(vjp_segment_offset(n, K, 1) + vjp_segment_accel_offset(n, K) +
+                               3 * n * K == ws);
+                    EXPECT(vjp_segment_offset(n, K, 0) + vjp_segment_accel_offset(n, K) +
+                               3 * n * K == vjp_segment_offset(n, K, 1));
+                }
             }
             for (int64_t b : {int64_t(1), int64_t(64), int64_t(DNB_BATCH_MAX)})
                 EXPECT(batch_tape_doubles(b, n, T) == (6 * T + 3 * (T + 1)) * b * n);

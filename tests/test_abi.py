@@ -66,7 +66,8 @@ def test_version_and_size_queries(lib):
     assert lib.dnb_tape_doubles(10, 7, 3) == 3 * (90 + 8) + 30
     assert lib.dnb_tape_doubles(10, 0, 3) == 0
     assert lib.dnb_tape_doubles(10, 7, 0) == -1
-    assert lib.dnb_vjp_workspace_doubles(10, 4) == 3 * 10 * 5 + 160 + 3 * 10 * 4
+    assert lib.dnb_vjp_workspace_doubles(10, 4) == 160 + 2 * (3 * 10 * 5 + 3 * 10 * 4)
+    assert lib.dnb_vjp_workspace_doubles(10, 1) == 160
     assert lib.dnb_vjp_workspace_doubles(0, 4) == -1
 
 
