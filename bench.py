@@ -462,6 +462,48 @@ def configs():
     return out
 
 
+def small_gradient(n=1000, T=1000, reps=5):
+    """One small system's pipeline gradient at the paper's inference size (n = 1000
+    particles, 1000 steps of t_end / 1000, eps = a_P = 0.01 kpc, MMD against a mock
+    stream from its own IC seed), through the single-system path, with the tape every
+    step and with checkpoints every 10 steps.  Best and median of `reps` timed
+    evaluations after one warm-up; one JSON object."""
+    import torch
+
+    from paper_2511_22468_amd import engine, gyr
+    from paper_2511_22468_amd.pipeline import StreamModel, make_target
+    from synth import plummer_unit
+
+    dev = torch.device("cuda", 0)
+    t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device=dev)
+    pot = engine.Potential(eps=0.01)
+    ctx = engine.Context(n, "fp32c")
+    theta = torch.tensor([gyr(1.75), 10 ** 4.5, 1e12, 6.5e10], dtype=torch.float64, device=dev)
+    xt, zt = plummer_unit(n, 11)
+    target = make_target(ctx, t3(xt), t3(zt), theta, T, pot=pot)
+    xi, zeta = plummer_unit(n, 12)
+    out = {"n": n, "steps": T, "eps_kpc": 0.01}
+    grads = []
+    for K in (1, 10):
+        model = StreamModel(ctx, t3(xi), t3(zeta), target, T, pot=pot, h=0.2, ckpt_every=K)
+        th = theta * 1.05
+        L, g = model.loss_and_grad(th)
+        torch.cuda.synchronize()
+        grads.append(g.cpu().numpy())
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            model.loss_and_grad(th)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        times.sort()
+        out[f"ckpt_every_{K}"] = {"best_us_per_step": times[0] / T * 1e6,
+                                  "median_us_per_step": times[len(times) // 2] / T * 1e6}
+    out["same_gradient"] = bool(np.array_equal(grads[0], grads[1]))
+    ctx.close()
+    return out
+
+
 def cpu_sweep(sizes=(1024, 8192, 16384, 65536), budget_pairs=2.0e8):
     """The oracle's pair sum at each workload size on one host thread and on all of
     them (at most 16), on sampled target rows bounded by budget_pairs pairs."""
@@ -612,6 +654,10 @@ def main():
     ap.add_argument("--configs", action="store_true",
                     help="end-to-end time of the N = 1024, 16384 and 8192 (gradient) workloads, "
                          "one JSON line each")
+    ap.add_argument("--small", action="store_true",
+                    help="one small system's pipeline gradient at the paper's inference size "
+                         "(n = 1000, 1000 steps), tape every step and every 10 steps, one JSON "
+                         "line")
     ap.add_argument("--cpu-sweep", action="store_true",
                     help="the FP64 oracle's pair sum at every workload size on one and on all "
                          "host threads, one JSON line (no GPU)")
@@ -620,11 +666,14 @@ def main():
         print(json.dumps(cpu_sweep()), flush=True)
         return
     if (args.sweep or args.ensemble or args.orbit_fit or args.configs or args.grid
-            or args.bootstrap or args.infer or args.time_to_fit) and args.gpus != 1:
+            or args.bootstrap or args.infer or args.time_to_fit or args.small) and args.gpus != 1:
         print("bench.py measures one GPU only (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.sweep:
         print(json.dumps(sweep(args.prec)), flush=True)
+        return
+    if args.small:
+        print(json.dumps({"small_system_gradient": small_gradient()}), flush=True)
         return
     if args.ensemble:
         print(json.dumps(ensemble()), flush=True)
