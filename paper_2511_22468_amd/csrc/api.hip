@@ -236,15 +236,21 @@ dnb_status run_forward(dnb_ctx* c, int64_t n, double* pos, double* vel, const do
     HIP_TRY(launch_mass_info(c, mass, n, st));
     if (c->prec == DNB_FP32C && !centres)
         HIP_TRY(launch_block_sums(pos, n, cp[0], st, nullptr, vel, dt));
-    HIP_TRY(launch_stage(c, pos, mass, n, cp[0], nb, centres, tape ? tape->centre(0) : nullptr, st));
+    HIP_TRY(launch_stage(c, pos, mass, n, cp[0], nb, centres, tape ? tape->centre(0) : nullptr,
+                         st));
     int q = 0;
     const bool f32 = c->prec == DNB_FP32C;
     for (int64_t s = 0; s <= T; ++s) {
-        HIP_TRY(profiled(c, 0, st, [&] { return launch_pair_fwd(c, n, p.eps, st); }));
+        // FP32C: the pair launch's extra row evaluates the external field at pos
+        const ExtRow row = f32 ? ExtRow{pos, nullptr, p} : ExtRow{};
+        bool row_done = false;
+        HIP_TRY(profiled(c, 0, st,
+                         [&] { return launch_pair_fwd(c, n, p.eps, st, row, &row_done); }));
         if (f32) HIP_TRY(launch_fwd_reduce(c, n, mass, p.G, st));
         FwdArgs a{};
         a.n = n; a.mass = mass; a.pot = p; a.dt = dt;
         if (f32) { a.ared = c->ared; a.arec = c->arec; a.nr = red_blocks(n); }
+        if (row_done) a.aext = c->aext_f;
         a.x = pos; a.x_out = pos; a.v = vel; a.vh = c->vh; a.with_ext = 1;
         a.cpart_in = cp[q]; a.cpart_out = cp[1 - q]; a.nb_in = nb;
         if (tape && s < T && s % K == 0) {
@@ -294,6 +300,9 @@ dnb_status dnb_create(dnb_ctx** out, int64_t max_n, dnb_prec prec) {
     // Blocks per pair-kernel launch; DNB_TARGET_BLOCKS overrides the tuned
     // default for experiments.
     c->target_blocks = env_int("DNB_TARGET_BLOCKS", TARGET_BLOCKS, {1024, 2048, 4096, 8192, 16384});
+    // DNB_EXT_ROW=0: the kicks evaluate the external field themselves (the same
+    // bits; for comparisons)
+    c->ext_row = env_int("DNB_EXT_ROW", 1, {0, 1});
     c->slice_rows = max_slice_rows(max_n, BS, c->target_blocks);
     c->smax = S_MAX;
     c->nbmax = (int)cdiv(max_n, BS);
@@ -316,6 +325,8 @@ dnb_status dnb_create(dnb_ctx** out, int64_t max_n, dnb_prec prec) {
         {(void**)&c->arec, sizeof(double) * 4 * (cdiv(npadmax, RT) + DNB_BATCH_MAX)},
         {(void**)&c->grec, sizeof(double) * 4 * (cdiv(npadmax, RT) + DNB_BATCH_MAX)},
         {(void**)&c->scan, sizeof(int64_t) * (c->nbmax + 1)},
+        {(void**)&c->aext_f, sizeof(double) * 3 * npadmax},
+        {(void**)&c->aext_v, sizeof(double) * 9 * npadmax},
     };
     for (auto& a : allocs) {
         if (hipMalloc(a.p, a.bytes) != hipSuccess) {
@@ -342,7 +353,7 @@ void dnb_destroy(dnb_ctx* c) {
     if (c->rstream) (void)hipStreamDestroy(c->rstream);
     void* ps[] = {c->js, c->part, c->cpart, c->vh, c->jsv, c->partv, c->cpartv, c->wscale, c->muni,
                   c->bparams, c->bwscale, c->red, c->ared, c->gred, c->arec, c->grec,
-                  c->scan};
+                  c->scan, c->aext_f, c->aext_v};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     delete c;
@@ -539,7 +550,8 @@ dnb_status dnb_simulate_resume(dnb_ctx* c, int64_t n, const double* tape, int64_
     const int64_t tl = dnb_tape_doubles(n, tape_steps, tape_ckpt_every);
     CHECK(check_extent(tape, sizeof(double) * tl, "tape", fn));
     const int64_t tlo = dnb_tape_doubles(n, n_steps, ckpt_every);
-    if (tape_out && n_steps > 0) CHECK(check_extent(tape_out, sizeof(double) * tlo, "tape_out", fn));
+    if (tape_out && n_steps > 0)
+        CHECK(check_extent(tape_out, sizeof(double) * tlo, "tape_out", fn));
     auto overlaps = [](const double* a, int64_t na, const double* b, int64_t nb_) {
         return a && b && a < b + nb_ && b < a + na;
     };
@@ -662,12 +674,17 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
             int q = 0;
             for (int64_t s = n0; s <= n1 - 1; ++s) {
                 double* xc = (s == n0) ? x0 : sx + (s - n0) * 3 * n;
-                HIP_TRY(profiled(c, 0, rs, [&] { return launch_pair_fwd(c, n, p.eps, rs); }));
+                const ExtRow row = c->prec == DNB_FP32C ? ExtRow{xc, nullptr, p} : ExtRow{};
+                bool row_done = false;
+                HIP_TRY(profiled(c, 0, rs, [&] {
+                    return launch_pair_fwd(c, n, p.eps, rs, row, &row_done);
+                }));
                 FwdArgs a{};
                 if (c->prec == DNB_FP32C) {
                     HIP_TRY(launch_fwd_reduce(c, n, mass, p.G, rs));
                     a.ared = c->ared; a.arec = c->arec; a.nr = red_blocks(n);
                 }
+                if (row_done) a.aext = c->aext_f;
                 a.n = n; a.mass = mass; a.pot = p; a.dt = dt; a.with_ext = 1;
                 a.x = xc;
                 a.aint_out = (s == n0) ? nullptr : sa + (s - n0) * 3 * n;
@@ -714,12 +731,19 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
             const int64_t cs = m > 0 ? (m - 1) / K : -1;
             if (m > 0) CHECK(wait_for(cs));
             const double* xm = get_pos(m);
-            HIP_TRY(profiled(c, 1, st, [&] { return launch_pair_vjp(c, n, with_mass, p.eps, st); }));
+            // FP32C: the pair launch's extra row evaluates the reverse kick's
+            // external-field terms at x_m for the cotangent lv
+            const ExtRow row = c->prec == DNB_FP32C ? ExtRow{xm, lv, p} : ExtRow{};
+            bool row_done = false;
+            HIP_TRY(profiled(c, 1, st, [&] {
+                return launch_pair_vjp(c, n, with_mass, p.eps, st, row, &row_done);
+            }));
             RevArgs r{};
             if (c->prec == DNB_FP32C) {
                 HIP_TRY(launch_vjp_reduce(c, n, p.G, with_mass, c->wscale + wq, st));
                 r.gred = c->gred; r.grec = c->grec; r.nr = red_blocks(n);
             }
+            if (row_done) r.aext = c->aext_v;
             r.n = n; r.mass = mass; r.pot = p; r.dt = dt;
             r.coef = (m == T || m == 0) ? 0.5 * dt : dt;
             r.x_n = xm;

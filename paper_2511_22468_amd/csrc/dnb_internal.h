@@ -286,10 +286,15 @@ struct dnb_ctx {
     double* red;             // [nbmax][8] reduction scratch
     double* ared;            // [3][npadmax] FP32C internal accelerations reduced from the slices
     double* gred;            // [4][npadmax] FP32C J^T w (3 rows) and mass term reduced likewise
+    double* aext_f;          // [3][npadmax] external acceleration at the staged positions, from the
+                             // forward pair kernel's extra block row (FP32C), for the kick
+    double* aext_v;          // [9][npadmax] the reverse kick's external-field terms, from the VJP
+                             // pair kernel's extra block row (FP32C; see ExtRow)
     double* arec;            // [cdiv(npadmax, RT) + DNB_BATCH_MAX][4] net-force records
     double* grec;            // the same for J^T w
     int64_t* scan;           // [nbmax + 1] block minima and result of the state scan
     int checks;              // nonzero: the integrators scan their initial state first
+    int ext_row;             // nonzero: small FP32C pair launches carry the external-field row
     void* prof;              // host-side event pool of dnb_profile (null when off)
     // The reverse sweep recomputes checkpoint segments on a second stream of
     // its own (created on first use, default priority) while the caller's stream
@@ -335,6 +340,21 @@ inline Slicing rows_slicing(const dnb_ctx* c, int64_t ni, int64_t n) {
 // Kernel launchers (defined in the .hip files).  All return hipError_t of the launch.
 enum KdkMode { KDK_FIRST = 0, KDK_MID = 1, KDK_LAST = 2, KDK_ACC = 3 };
 
+// An extra row of blocks in a pair launch (blockIdx.y == 0, the source slices
+// following in rows 1 .. S) that evaluates the external field at the FP64
+// positions x[3][n] for the kick that follows, beside the pair sums (at small n
+// the pair launch leaves most compute units idle):
+//   forward (w null): the acceleration, rows 0-2;
+//   reverse (w = the velocity cotangent): H w (rows 0-2), a_ext . w (3),
+//   (da/dm_nfw) . w (4), (da/dm_mn) . w (5) and (da/dp) . w for the three shape
+//   parameters (6-8), with the expressions of ext_accel_hvp and k_rev_kick, so
+//   the kick gets the same bits as evaluating them itself.
+struct ExtRow {
+    const double* x;   // null: no extra row
+    const double* w;
+    Pot pot;
+};
+
 struct FwdArgs {
     int64_t n;
     const double* mass;
@@ -366,6 +386,7 @@ struct FwdArgs {
     const double* ared;
     const double* arec;
     int nr;
+    const double* aext;   // [3][n] external acceleration at x from an ExtRow (null: evaluate)
 };
 
 // Block records of x into cpart (layout REC of kdk_common.h): sums of x in
@@ -381,7 +402,11 @@ hipError_t launch_block_sums(const double* x, int64_t n, double* cpart, hipStrea
 hipError_t launch_stage(dnb_ctx* c, const double* x, const double* mass, int64_t n,
                         const double* cpart, int nb, const double* centre_override,
                         double* centre_out, hipStream_t st);
-hipError_t launch_pair_fwd(dnb_ctx* c, int64_t n, double eps, hipStream_t st);
+// ext: the external-field row to add if the launch takes one (small FP32C
+// systems); *ext_done (nullable) says whether it did, i.e. whether the kick may
+// read ctx->aext_f (aext_v) instead of evaluating the field itself.
+hipError_t launch_pair_fwd(dnb_ctx* c, int64_t n, double eps, hipStream_t st,
+                           const ExtRow& ext = ExtRow{}, bool* ext_done = nullptr);
 hipError_t launch_pair_fwd_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, double eps,
                                 hipStream_t st);
 hipError_t launch_acc_rows(dnb_ctx* c, const double* x, int64_t n, int64_t i0, int64_t ni,
@@ -420,6 +445,7 @@ struct RevArgs {
     const double* gred;
     const double* grec;
     int nr;
+    const double* aext;   // [9][n] the external-field terms of an ExtRow (null: evaluate)
 };
 
 // xprev (nullable): the positions the sweep stages next, whose displacement from
@@ -427,7 +453,8 @@ struct RevArgs {
 hipError_t launch_rev_stage(dnb_ctx* c, int64_t n, const double* x, const double* mass,
                             const double* w, const double* cpart, int nb, double* cpart_out,
                             double* wscale_out, hipStream_t st, const double* xprev = nullptr);
-hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, int with_mass, double eps, hipStream_t st);
+hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, int with_mass, double eps, hipStream_t st,
+                           const ExtRow& ext = ExtRow{}, bool* ext_done = nullptr);
 hipError_t launch_pair_vjp_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, int with_mass,
                                 double eps, hipStream_t st);
 hipError_t launch_acc_vjp_rows(dnb_ctx* c, const double* x, const double* w, int64_t n,

@@ -91,6 +91,9 @@ __global__ __launch_bounds__(BS) void k_kdk(FwdArgs a, const void* __restrict__ 
     if (MODE == KDK_FIRST) { ux = a.v[k]; uy = a.v[n + k]; uz = a.v[2 * n + k]; }
     if (MODE == KDK_MID || MODE == KDK_LAST) { ux = a.vh[k]; uy = a.vh[n + k]; uz = a.vh[2 * n + k]; }
     const double mk = drift ? a.mass[k] : 0.0;
+    const bool pre = a.with_ext && a.aext;   // external field from the pair launch's extra row
+    double ex = 0.0, ey = 0.0, ez = 0.0;
+    if (pre) { ex = a.aext[k]; ey = a.aext[n + k]; ez = a.aext[2 * n + k]; }
 
     // staging centre and net internal force (FP32C), one block reduction
     double cx = 0.0, cy = 0.0, cz = 0.0;
@@ -120,7 +123,9 @@ __global__ __launch_bounds__(BS) void k_kdk(FwdArgs a, const void* __restrict__ 
     if (a.aint_out && ok) {
         a.aint_out[i] = ax; a.aint_out[n + i] = ay; a.aint_out[2 * n + i] = az;
     }
-    if (a.with_ext) {
+    if (pre) {
+        ax += ex; ay += ey; az += ez;
+    } else if (a.with_ext) {
         Ext e = ext_accel(a.pot, x, y, z);
         ax += e.ax; ay += e.ay; az += e.az;
     }
@@ -334,6 +339,12 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
     const double acc0[8] = {a.accum[k], a.accum[n + k], a.accum[2 * n + k], a.accum[3 * n + k],
                             a.accum[4 * n + k], a.accum[5 * n + k], a.accum[6 * n + k],
                             a.with_mass ? a.accum[7 * n + k] : 0.0};
+    // the external-field terms from the pair launch's extra row, if it ran
+    double xt[9];
+    if (a.aext) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) xt[c] = a.aext[(int64_t)c * n + k];
+    }
 
     // staging centre, cotangent scale and sum of J^T w (FP32C)
     double cx = 0.0, cy = 0.0, cz = 0.0, Sn = 1.0;
@@ -353,20 +364,27 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
     } else {
         vjp_sum<F32>(part, S, npad, k, a.pot.G, a.with_mass != 0, g, gm);
     }
-    Ext e;
-    double hx, hy, hz;
-    double shp[3];
-    ext_accel_hvp(a.pot, x, y, z, wx, wy, wz, e, hx, hy, hz, shp);
+    double hx, hy, hz, aw_ext, nw, mw, shp[3];
+    if (a.aext) {
+        hx = xt[0]; hy = xt[1]; hz = xt[2];
+        aw_ext = xt[3]; nw = xt[4]; mw = xt[5];
+        shp[0] = xt[6]; shp[1] = xt[7]; shp[2] = xt[8];
+    } else {
+        Ext e;
+        ext_accel_hvp(a.pot, x, y, z, wx, wy, wz, e, hx, hy, hz, shp);
+        aw_ext = e.ax * wx + e.ay * wy + e.az * wz;
+        nw = e.nx * wx + e.ny * wy + e.nz * wz;
+        mw = e.mx * wx + e.my * wy + e.mz * wz;
+    }
 
     const double lx = fma(a.coef, g[0] + hx, lx0);
     const double ly = fma(a.coef, g[1] + hy, ly0);
     const double lz = fma(a.coef, g[2] + hz, lz0);
     const double kc = a.coef / a.dt;
     const double aw_int = ai[0] * wx + ai[1] * wy + ai[2] * wz;
-    const double aw_ext = e.ax * wx + e.ay * wy + e.az * wz;
     double d_dt = kc * (aw_int + aw_ext);
-    const double d_nfw = a.coef * (e.nx * wx + e.ny * wy + e.nz * wz);
-    const double d_mn = a.coef * (e.mx * wx + e.my * wy + e.mz * wz);
+    const double d_nfw = a.coef * nw;
+    const double d_mn = a.coef * mw;
     const double d_ms = a.coef * aw_int;
 
     double nwx = wx, nwy = wy, nwz = wz;

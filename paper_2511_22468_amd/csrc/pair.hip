@@ -42,6 +42,44 @@ __device__ __forceinline__ double rsqrt_f64(double s) {
 }
 
 
+// ------------------------------------------------------- external-field row --
+// The row is added only if the launch's blocks still fit in one round of
+// resident blocks (256 CUs x 8 blocks of 256 threads): a launch that fills the
+// chip (n = 8192: 32 x 64 blocks) would push pair blocks into a second round and
+// lose more than the kick saves.
+constexpr int RESIDENT_BLOCKS = 256 * 8;
+inline bool ext_row_fits(const Slicing& sl) {
+    return (int64_t)sl.nblk * (sl.S + 1) <= RESIDENT_BLOCKS;
+}
+
+// The blocks of an ExtRow (see dnb_internal.h), the launch's first row of blocks
+// (blockIdx.y = 0; the slices follow), so that their FP64 work starts with the
+// launch instead of waiting for a free slot behind the pair blocks: particles
+// [blockIdx.x BS, +BS).
+__device__ inline void ext_row_fwd(const ExtRow& er, int n, double* __restrict__ out) {
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    const double* x = er.x;
+    const Ext e = ext_accel(er.pot, x[i], x[n + i], x[2 * n + i]);
+    out[i] = e.ax; out[n + i] = e.ay; out[2 * n + i] = e.az;
+}
+
+__device__ inline void ext_row_vjp(const ExtRow& er, int n, double* __restrict__ out) {
+    const int i = blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    const double* x = er.x;
+    const double* w = er.w;
+    const double wx = w[i], wy = w[n + i], wz = w[2 * n + i];
+    Ext e;
+    double hx, hy, hz, shp[3];
+    ext_accel_hvp(er.pot, x[i], x[n + i], x[2 * n + i], wx, wy, wz, e, hx, hy, hz, shp);
+    const double r[9] = {hx, hy, hz, e.ax * wx + e.ay * wy + e.az * wz,
+                         e.nx * wx + e.ny * wy + e.nz * wz, e.mx * wx + e.my * wy + e.mz * wz,
+                         shp[0], shp[1], shp[2]};
+#pragma unroll
+    for (int c = 0; c < 9; ++c) out[(int64_t)c * n + i] = r[c];
+}
+
 // ------------------------------------------------------------ forward FP32C --
 // js: staged sources (x, y, z, m), padded to nj = roundup(n, 128).
 // part: [S][3][npad] float2 = (hi, lo) of the x, y and z components of
@@ -60,14 +98,20 @@ __device__ __forceinline__ double rsqrt_f64(double s) {
 // scalar loads cost the vector units nothing.  Both give the same bits.
 constexpr int FWD_LDS_SLICE = 256;   // longest slice that takes the LDS kernel
 
-template <bool EPS0, bool LDS, bool NT>
+template <bool EPS0, bool LDS, bool NT, bool ROW>
 __global__ __launch_bounds__(BS) void k_pair_fwd_f32c(const float4* __restrict__ js, int n,
                                                       int i0, int iend, int nj, int jslice,
                                                       float eps2, float* __restrict__ part,
                                                       int64_t npad,
-                                                      const float* __restrict__ muni) {
+                                                      const float* __restrict__ muni,
+                                                      ExtRow er, double* __restrict__ aext) {
+    if (ROW && blockIdx.y == 0) {   // the external-field row, first so it starts at once
+        ext_row_fwd(er, n, aext);
+        return;
+    }
     const int i = i0 + blockIdx.x * BS + threadIdx.x;
-    const int j0 = blockIdx.y * jslice;
+    const int sy = blockIdx.y - (ROW ? 1 : 0);   // source slice
+    const int j0 = sy * jslice;
     const int j1 = min(nj, j0 + jslice);
     const float4 me = js[min(i, n - 1)];
     float h[3] = {0.f, 0.f, 0.f}, l[3] = {0.f, 0.f, 0.f};
@@ -93,7 +137,7 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f32c(const float4* __restrict__
         fwd_f32c_slice<EPS0, false>(js, i, j0, j1, eps2, me, h, l);
     }
     if (i < iend) {
-        float2* p = (float2*)part + (int64_t)blockIdx.y * 3 * npad + (i - i0);
+        float2* p = (float2*)part + (int64_t)sy * 3 * npad + (i - i0);
 #pragma unroll
         for (int c = 0; c < 3; ++c) put_partial<NT>(p + c * npad, h[c], l[c]);
     }
@@ -150,14 +194,20 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f64(const double4* __restrict__
 // copies its slice (two float4 per source) into LDS, as in the forward kernel.
 constexpr int VJP_LDS_SLICE = 64;    // longest slice that takes the LDS kernel
 
-template <bool EPS0, bool MASS, bool LDS, bool NT>
+template <bool EPS0, bool MASS, bool LDS, bool NT, bool ROW>
 __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__ jsv, int n,
                                                       int i0, int iend, int nj, int jslice,
                                                       float eps2, float* __restrict__ part,
                                                       int64_t npad,
-                                                      const float* __restrict__ muni) {
+                                                      const float* __restrict__ muni,
+                                                      ExtRow er, double* __restrict__ aext) {
+    if (ROW && blockIdx.y == 0) {   // the external-field row, first so it starts at once
+        ext_row_vjp(er, n, aext);
+        return;
+    }
     const int i = i0 + blockIdx.x * BS + threadIdx.x;
-    const int j0 = blockIdx.y * jslice;
+    const int sy = blockIdx.y - (ROW ? 1 : 0);   // source slice
+    const int j0 = sy * jslice;
     const int j1 = min(nj, j0 + jslice);
     const int ii = min(i, n - 1);
     const float4 me = jsv[2 * ii];
@@ -186,7 +236,7 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__
         vjp_f32c_slice<EPS0, MASS, false>(jsv, i, j0, j1, eps2, me, mw, h, l);
     }
     if (i < iend) {
-        float2* p = (float2*)part + (int64_t)blockIdx.y * 4 * npad + (i - i0);
+        float2* p = (float2*)part + (int64_t)sy * 4 * npad + (i - i0);
 #pragma unroll
         for (int c = 0; c < 3; ++c) put_partial<NT>(p + c * npad, h[c], l[c]);
         if (MASS) put_partial<NT>(p + 3 * npad, h[3], l[3]);
@@ -259,7 +309,9 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__
 // Targets [i0, i0 + ni) against all n staged sources with the slicing sl; slice
 // partials of target i at row i - i0 (the whole system: i0 = 0, ni = n).
 static hipError_t launch_pair_fwd_sliced(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni,
-                                         const Slicing& sl, double eps, hipStream_t st) {
+                                         const Slicing& sl, double eps, hipStream_t st,
+                                         const ExtRow& er = ExtRow{}, bool* ext_done = nullptr) {
+    if (ext_done) *ext_done = false;
     const int nj = (int)pad_sources(n);
     const int a = (int)i0, e = (int)(i0 + ni);
     dim3 grid(sl.nblk, sl.S);
@@ -269,20 +321,30 @@ static hipError_t launch_pair_fwd_sliced(dnb_ctx* c, int64_t n, int64_t i0, int6
         float* part = (float*)c->part;
         const bool lds = sl.jslice <= FWD_LDS_SLICE;
         const bool nt = (int64_t)sl.S * sl.npad * 3 * 8 >= NT_PARTIAL_BYTES;
+        // the external-field row (whole-system launches, so the row blocks cover n;
+        // the LDS instances, those of small systems, only; and only while the launch
+        // stays within one round of resident blocks)
+        const bool row = c->ext_row && er.x && i0 == 0 && ni == n && lds && ext_row_fits(sl);
+        if (row) grid.y += 1;
+        if (ext_done) *ext_done = row;
         auto go = [&](auto kernel) {
             hipLaunchKernelGGL(kernel, grid, dim3(BS), 0, st, js, (int)n, a, e, nj, sl.jslice,
-                               eps2, part, sl.npad, c->muni);
+                               eps2, part, sl.npad, c->muni, row ? er : ExtRow{}, c->aext_f);
         };
-        const int which = (eps == 0.0 ? 4 : 0) + (lds ? 2 : 0) + (nt ? 1 : 0);
+        const int which = (eps == 0.0 ? 8 : 0) + (lds ? 4 : 0) + (nt ? 2 : 0) + (row ? 1 : 0);
         switch (which) {
-            case 0: go(k_pair_fwd_f32c<false, false, false>); break;
-            case 1: go(k_pair_fwd_f32c<false, false, true>); break;
-            case 2: go(k_pair_fwd_f32c<false, true, false>); break;
-            case 3: go(k_pair_fwd_f32c<false, true, true>); break;
-            case 4: go(k_pair_fwd_f32c<true, false, false>); break;
-            case 5: go(k_pair_fwd_f32c<true, false, true>); break;
-            case 6: go(k_pair_fwd_f32c<true, true, false>); break;
-            default: go(k_pair_fwd_f32c<true, true, true>); break;
+            case 0: go(k_pair_fwd_f32c<false, false, false, false>); break;
+            case 2: go(k_pair_fwd_f32c<false, false, true, false>); break;
+            case 4: go(k_pair_fwd_f32c<false, true, false, false>); break;
+            case 5: go(k_pair_fwd_f32c<false, true, false, true>); break;
+            case 6: go(k_pair_fwd_f32c<false, true, true, false>); break;
+            case 7: go(k_pair_fwd_f32c<false, true, true, true>); break;
+            case 8: go(k_pair_fwd_f32c<true, false, false, false>); break;
+            case 10: go(k_pair_fwd_f32c<true, false, true, false>); break;
+            case 12: go(k_pair_fwd_f32c<true, true, false, false>); break;
+            case 13: go(k_pair_fwd_f32c<true, true, false, true>); break;
+            case 14: go(k_pair_fwd_f32c<true, true, true, false>); break;
+            default: go(k_pair_fwd_f32c<true, true, true, true>); break;   // 15
         }
     } else {
         const double eps2 = eps * eps;
@@ -297,8 +359,9 @@ static hipError_t launch_pair_fwd_sliced(dnb_ctx* c, int64_t n, int64_t i0, int6
     return hipGetLastError();
 }
 
-hipError_t launch_pair_fwd(dnb_ctx* c, int64_t n, double eps, hipStream_t st) {
-    return launch_pair_fwd_sliced(c, n, 0, n, fwd_slicing(c, n), eps, st);
+hipError_t launch_pair_fwd(dnb_ctx* c, int64_t n, double eps, hipStream_t st,
+                           const ExtRow& ext, bool* ext_done) {
+    return launch_pair_fwd_sliced(c, n, 0, n, fwd_slicing(c, n), eps, st, ext, ext_done);
 }
 
 hipError_t launch_pair_fwd_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, double eps,
@@ -308,19 +371,29 @@ hipError_t launch_pair_fwd_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, d
 
 template <bool EPS0, bool MASS>
 static void vjp_dispatch(dnb_ctx* c, const Slicing& sl, int64_t n, int i0, int iend, int nj,
-                         double eps2, hipStream_t st) {
+                         double eps2, hipStream_t st, const ExtRow& er, bool* ext_done) {
     dim3 grid(sl.nblk, sl.S);
     const bool nt = (int64_t)sl.S * sl.npad * (MASS ? 4 : 3) * 8 >= NT_PARTIAL_BYTES;
+    const bool lds = sl.jslice <= VJP_LDS_SLICE;
+    // the external-field row (whole-system launches, so the row blocks cover n;
+    // the LDS instances, those of small systems, only; and only while the launch
+    // stays within one round of resident blocks)
+    const bool row = c->prec == DNB_FP32C && c->ext_row && er.x && i0 == 0 && iend == n &&
+                     lds && ext_row_fits(sl);
+    if (row) grid.y += 1;
+    if (ext_done) *ext_done = row;
     auto go = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, grid, dim3(BS), 0, st, (const float4*)c->jsv, (int)n, i0,
-                           iend, nj, sl.jslice, (float)eps2, (float*)c->partv, sl.npad, c->muni);
+                           iend, nj, sl.jslice, (float)eps2, (float*)c->partv, sl.npad, c->muni,
+                           row ? er : ExtRow{}, c->aext_v);
     };
-    const bool lds = sl.jslice <= VJP_LDS_SLICE;
     if (c->prec == DNB_FP32C) {
-        if (lds && nt) go(k_pair_vjp_f32c<EPS0, MASS, true, true>);
-        else if (lds) go(k_pair_vjp_f32c<EPS0, MASS, true, false>);
-        else if (nt) go(k_pair_vjp_f32c<EPS0, MASS, false, true>);
-        else go(k_pair_vjp_f32c<EPS0, MASS, false, false>);
+        if (lds && nt && row) go(k_pair_vjp_f32c<EPS0, MASS, true, true, true>);
+        else if (lds && nt) go(k_pair_vjp_f32c<EPS0, MASS, true, true, false>);
+        else if (lds && row) go(k_pair_vjp_f32c<EPS0, MASS, true, false, true>);
+        else if (lds) go(k_pair_vjp_f32c<EPS0, MASS, true, false, false>);
+        else if (nt) go(k_pair_vjp_f32c<EPS0, MASS, false, true, false>);
+        else go(k_pair_vjp_f32c<EPS0, MASS, false, false, false>);
     } else {
         hipLaunchKernelGGL((k_pair_vjp_f64<EPS0, MASS>), grid, dim3(BS), 0, st,
                            (const double4*)c->jsv, (int)n, i0, iend, nj, sl.jslice, eps2,
@@ -330,22 +403,26 @@ static void vjp_dispatch(dnb_ctx* c, const Slicing& sl, int64_t n, int i0, int i
 
 static hipError_t launch_pair_vjp_sliced(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni,
                                          const Slicing& sl, int with_mass, double eps,
-                                         hipStream_t st) {
+                                         hipStream_t st, const ExtRow& er = ExtRow{},
+                                         bool* ext_done = nullptr) {
+    if (ext_done) *ext_done = false;
     const int nj = (int)pad_sources(n);
     const int a = (int)i0, e = (int)(i0 + ni);
     const double eps2 = eps * eps;
     if (eps == 0.0) {
-        if (with_mass) vjp_dispatch<true, true>(c, sl, n, a, e, nj, eps2, st);
-        else vjp_dispatch<true, false>(c, sl, n, a, e, nj, eps2, st);
+        if (with_mass) vjp_dispatch<true, true>(c, sl, n, a, e, nj, eps2, st, er, ext_done);
+        else vjp_dispatch<true, false>(c, sl, n, a, e, nj, eps2, st, er, ext_done);
     } else {
-        if (with_mass) vjp_dispatch<false, true>(c, sl, n, a, e, nj, eps2, st);
-        else vjp_dispatch<false, false>(c, sl, n, a, e, nj, eps2, st);
+        if (with_mass) vjp_dispatch<false, true>(c, sl, n, a, e, nj, eps2, st, er, ext_done);
+        else vjp_dispatch<false, false>(c, sl, n, a, e, nj, eps2, st, er, ext_done);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, int with_mass, double eps, hipStream_t st) {
-    return launch_pair_vjp_sliced(c, n, 0, n, vjp_slicing(c, n), with_mass, eps, st);
+hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, int with_mass, double eps, hipStream_t st,
+                           const ExtRow& ext, bool* ext_done) {
+    return launch_pair_vjp_sliced(c, n, 0, n, vjp_slicing(c, n), with_mass, eps, st, ext,
+                                  ext_done);
 }
 
 hipError_t launch_pair_vjp_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, int with_mass,

@@ -262,6 +262,49 @@ def test_checkpoint_recompute_is_bitwise(dnb, prec):
     assert not bad, bad
 
 
+@pytest.mark.parametrize("n", [300, 1000, 4096, 8192])
+def test_external_field_row_equals_the_kick_evaluating_it(dnb, n):
+    # small FP32C pair launches carry an extra row of blocks that evaluates the
+    # external field (and, in the sweep, its Hessian-vector product and parameter
+    # derivatives) for the kick; DNB_EXT_ROW=0 has the kicks evaluate it
+    # themselves.  The same expressions: the same bits.  n = 8192 fills the chip,
+    # so there the launch takes no row and the kick must evaluate the field.
+    import os
+    pk, engine, ctx = dnb
+    say(f"[ext row] n={n}")
+    old = os.environ.get("DNB_EXT_ROW")
+    os.environ["DNB_EXT_ROW"] = "0"
+    try:
+        plain = engine.Context(8192, "fp32c")
+    finally:
+        if old is None:
+            del os.environ["DNB_EXT_ROW"]
+        else:
+            os.environ["DNB_EXT_ROW"] = old
+    rowed = engine.Context(8192, "fp32c")
+    try:
+        x, v, m = plummer_state(n, 43)
+        pot = gpu_pot(engine, OPot())
+        w = to_dev(np.random.default_rng(44).normal(size=x.shape))
+        outs = []
+        for c in (rowed, plain):
+            for K in (1, 4):
+                px, pv, pm = to_dev(x), to_dev(v), to_dev(m)
+                tape = c.simulate(px, pv, pm, pot, pk.myr(0.5), 8, ckpt_every=K)
+                g = c.simulate_vjp(pm, pot, pk.myr(0.5), 8, K, tape, px, w, with_mass=True)
+                outs.append((px, pv, tape) + tuple(g))
+        names = ("pos_T", "vel_T", "tape", "gpos_0", "gvel_0", "gmass", "gparams")
+        for k in range(2):   # K = 1 and 4
+            bad = [nm for nm, a, b in zip(names, outs[k], outs[2 + k]) if not torch.equal(a, b)]
+            assert not bad, (k, bad)
+        if n <= 1000:   # and the run is the oracle's (a stale field would move it away)
+            ref = np.asarray(oint.simulate(x, v, m, OPot(), pk.myr(0.5), 8)[0])
+            assert rel_rows(to_host(outs[0][0]), ref).max() <= 1e-7
+    finally:
+        plain.close()
+        rowed.close()
+
+
 def test_mmd_matches_oracle(dnb):
     pk, engine, ctx = dnb
     rng = np.random.default_rng(11)
