@@ -50,9 +50,9 @@ FLOPS_COUNTED = {"k_pair_fwd_f32c": 18.2, "k_pair_vjp_f32c": 34.2}
 # profiles/pair_kernels_n65536_traffic.md (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the
 # factors measured on a 256 MiB copy), valid only for the kernel source they were
 # measured on (sha256 prefix of pair.hip followed by pair_common.h) and for N = 65536.
-TRAFFIC_SRC_SHA = "fabd03ec61b0c966"
+TRAFFIC_SRC_SHA = "356bb9f8efeeb0db"
 TRAFFIC_N = 65536
-TRAFFIC_KIB = {"k_pair_fwd_f32c": (7701.0, 49152.0), "k_pair_vjp_f32c": (15388.1, 49152.0)}
+TRAFFIC_KIB = {"k_pair_fwd_f32c": (7701.5, 49152.0), "k_pair_vjp_f32c": (15380.6, 49152.0)}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
