@@ -585,6 +585,8 @@ def time_to_fit_summary(seed=50):
     from paper_2511_22468_amd import fit
     r = fit.run(seed=seed)
     p, w = r["plain"], r["warm"]
+    tp, tw = r["plain_fit_seconds"], r["warm_seconds_to_plain_fit_loss"]
+    cost = r["surrogate"]["data_seconds"] + r["surrogate"]["train_seconds"]
     return {
         "workload": (f"held-out target drawn from the priors (seed {seed + 1}); fit N = "
                      f"{r['n_fit']}, {r['n_steps']} steps, eps {r['eps_kpc']} kpc; surrogate "
@@ -599,6 +601,9 @@ def time_to_fit_summary(seed=50):
         "plain_reaches_warm_final_loss": r["plain_reaches_warm_final_loss"],
         "speedup_excl_training": r["speedup_excl_training"],
         "speedup_incl_training": r["speedup_incl_training"],
+        # fits of this kind after which one trained surrogate has repaid its
+        # training set and training (null when the warm arm saves nothing)
+        "fits_to_repay_training": (cost / (tp - tw)) if tw is not None and tp > tw else None,
         "data_seconds": r["surrogate"]["data_seconds"],
         "train_seconds": r["surrogate"]["train_seconds"],
         "inversion_seconds": w["inversion_seconds"],
