@@ -103,111 +103,220 @@ def time_to(hist, level):
     return None
 
 
-def run(quick=False, seed=50, n_train=None, n_draws=None, train_steps=None, max_iter=None):
-    """Both arms for one held-out target.  n_train, n_draws and train_steps set
-    the surrogate's training set (particles per run, runs, KDK steps per run over
-    the same t_end).  By default it is the workload's: 512 runs of 4096 particles
-    with 4000 steps, and the fit runs 8192 particles with 4000 steps.  The density
-    images are normalised to sum 1, so runs of another size map to the same
-    image.  quick: fit 2048 particles with 1000 steps, 64 training runs of 1024
-    particles with 1000 steps."""
-    dev = torch.device("cuda", 0)
-    from synth import draw_theta, mlp_init, flatten, plummer_unit
-
+def _config(quick, n_train=None, n_draws=None, train_steps=None, max_iter=None):
+    """Sizes of the experiment.  By default the workload's: the fit runs 8192
+    particles with 4000 steps, the surrogate's training set is 512 runs of 4096
+    particles with 4000 steps.  quick: fit 2048 particles with 1000 steps, 64
+    training runs of 1024 particles with 1000 steps."""
     n_fit, T = (2048, 1000) if quick else (8192, 4000)
-    n_train = int(n_train or (1024 if quick else 4096))
-    n_draws = int(n_draws or (64 if quick else 512))
-    T_train = int(train_steps or (1000 if quick else 4000))
-    cap = int(max_iter or (30 if quick else 60))
     lr0 = 0.5
-    lr_min = lr0 / 64
-    pot = engine.Potential(eps=EPS_FIT)
-    t3 = lambda a: torch.tensor(np.ascontiguousarray(a.T), device=dev)
-    ctx = engine.Context(n_fit, "fp32c")
-    gen_ctx = engine.Context(n_train * n_draws, "fp32c")   # the training runs as one ensemble
-    f9 = orbit_frame(W_X, W_V)
+    return {"quick": quick, "n_fit": n_fit, "T": T,
+            "n_train": int(n_train or (1024 if quick else 4096)),
+            "n_draws": int(n_draws or (64 if quick else 512)),
+            "T_train": int(train_steps or (1000 if quick else 4000)),
+            "cap": int(max_iter or (30 if quick else 60)),
+            "epochs": 60 if quick else 300, "lr0": lr0, "lr_min": lr0 / 64}
 
-    # held-out target: parameters from the priors (own seed), own IC seed
-    th_star = draw_theta(1, seed + 1)[0]
-    xt, zt = plummer_unit(n_fit, seed + 2)
-    u_star = normalise(th_star)[0]
-    target = make_target(ctx, t3(xt), t3(zt), torch.tensor(theta_internal(u_star), device=dev), T,
-                         pot=pot)
-    target_img = density_grid(target, f9).reshape(-1)
-    xi, zeta = plummer_unit(n_fit, seed + 3)
-    model = StreamModel(ctx, t3(xi), t3(zeta), target, T, pot=pot, h=0.2, ckpt_every=1)
-    model.loss_and_grad(torch.tensor(theta_internal(np.zeros(4)), device=dev))   # warm-up
-    torch.cuda.synchronize()
 
-    # plain arm
+def _t3(a, dev):
+    return torch.tensor(np.ascontiguousarray(a.T), device=dev)
+
+
+def train_surrogate(gen_ctx, cfg, seed, T_train, pot, f9):
+    """The surrogate's training set from the engine's own runs (cfg n_draws
+    parameter rows drawn from the priors with this seed, cfg n_train particles,
+    T_train KDK steps over the same t_end as the fit), then its training.  The
+    density images are normalised to sum 1, so runs of another size or step
+    count map to the same kind of image."""
+    from synth import draw_theta, mlp_init, flatten, plummer_unit
+    dev = torch.device("cuda", 0)
     t0 = time.perf_counter()
-    u_plain, L_plain, hist_plain, conv_plain = descend(model, np.zeros(4), lr0, cap, lr_min,
-                                                       clock0=t0)
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-
-    # surrogate: data from the engine's own runs, then training
-    t0 = time.perf_counter()
-    thetas = draw_theta(n_draws, seed)
-    xs, zs = plummer_unit(n_train, seed + 4)
-    X, Y = generate_dataset(gen_ctx, thetas, t3(xs), t3(zs), T_train, pot, f9)
+    thetas = draw_theta(cfg["n_draws"], seed)
+    xs, zs = plummer_unit(cfg["n_train"], seed + 4)
+    X, Y = generate_dataset(gen_ctx, thetas, _t3(xs, dev), _t3(zs, dev), T_train, pot, f9)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     t0 = time.perf_counter()
     net = MLP(flatten(mlp_init(seed + 5)), dev)
     Ym = Y.mean(dim=0, keepdim=True)
-    losses = net.train(X, (Y - Ym).contiguous() * 100.0, epochs=60 if quick else 300,
-                       batch=64, lr=2e-3, lr_final=2e-4, seed=seed + 6)
+    losses = net.train(X, (Y - Ym).contiguous() * 100.0, epochs=cfg["epochs"], batch=64,
+                       lr=2e-3, lr_final=2e-4, seed=seed + 6)
     torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
+    return {"net": net, "Ym": Ym, "n_train_steps": int(T_train), "data_seconds": t_data,
+            "train_seconds": time.perf_counter() - t0, "losses": losses}
 
-    # warm arm: surrogate inversion, then the same descent
+
+def _target(ctx, cfg, seed, pot, f9):
+    """A held-out target drawn from the priors (parameters from seed + 1, its own
+    initial-condition seed + 2), its density image, and the fit's model (initial
+    conditions from seed + 3), warmed up once."""
+    from synth import draw_theta, plummer_unit
+    dev = torch.device("cuda", 0)
+    th_star = draw_theta(1, seed + 1)[0]
+    xt, zt = plummer_unit(cfg["n_fit"], seed + 2)
+    u_star = normalise(th_star)[0]
+    target = make_target(ctx, _t3(xt, dev), _t3(zt, dev),
+                         torch.tensor(theta_internal(u_star), device=dev), cfg["T"], pot=pot)
+    target_img = density_grid(target, f9).reshape(-1)
+    xi, zeta = plummer_unit(cfg["n_fit"], seed + 3)
+    model = StreamModel(ctx, _t3(xi, dev), _t3(zeta, dev), target, cfg["T"], pot=pot, h=0.2,
+                        ckpt_every=1)
+    model.loss_and_grad(torch.tensor(theta_internal(np.zeros(4)), device=dev))   # warm-up
+    torch.cuda.synchronize()
+    return {"theta_star": th_star, "u_star": u_star, "image": target_img, "model": model}
+
+
+def _plain_arm(tg, cfg):
     t0 = time.perf_counter()
-    u_warm, err_w = net.invert(((target_img - Ym.reshape(-1)) * 100.0).contiguous(),
-                               n_starts=64, iters=300, lr=0.05, seed=seed + 7)
-    t_inv = time.perf_counter() - t0
-    u_fit, L_warm, hist_warm, conv_warm = descend(model, u_warm, lr0, cap, lr_min, clock0=t0)
+    u, L, hist, conv = descend(tg["model"], np.zeros(4), cfg["lr0"], cfg["cap"], cfg["lr_min"],
+                               clock0=t0)
     torch.cuda.synchronize()
-    t_warm = time.perf_counter() - t0
+    return {"seconds": time.perf_counter() - t0, "iterations": len(hist) - 1, "final_loss": L,
+            "converged": bool(conv), "u": u.tolist(), "hist": hist}
 
-    tp = t_plain                       # the plain fit, until its descent stops
-    tw = time_to(hist_warm, L_plain)   # the warm arm, until it matches the plain fit
+
+def _warm_arm(tg, sur, cfg, seed):
+    """The surrogate's inversion on the target's image (starts from seed + 7), then
+    the plain arm's descent from there."""
+    net, Ym = sur["net"], sur["Ym"]
+    t0 = time.perf_counter()
+    u_warm, err = net.invert(((tg["image"] - Ym.reshape(-1)) * 100.0).contiguous(),
+                             n_starts=64, iters=300, lr=0.05, seed=seed + 7)
+    t_inv = time.perf_counter() - t0
+    u, L, hist, conv = descend(tg["model"], u_warm, cfg["lr0"], cfg["cap"], cfg["lr_min"],
+                               clock0=t0)
+    torch.cuda.synchronize()
+    return {"seconds": time.perf_counter() - t0, "inversion_seconds": t_inv,
+            "inversion_image_mse": err, "iterations": len(hist) - 1, "final_loss": L,
+            "converged": bool(conv), "u_surrogate": u_warm.tolist(), "u": u.tolist(),
+            "hist": hist}
+
+
+def run(quick=False, seed=50, n_train=None, n_draws=None, train_steps=None, max_iter=None):
+    """Both arms for one held-out target.  n_train, n_draws and train_steps set
+    the surrogate's training set (particles per run, runs, KDK steps per run over
+    the same t_end); the defaults are those of _config."""
+    cfg = _config(quick, n_train, n_draws, train_steps, max_iter)
+    pot = engine.Potential(eps=EPS_FIT)
+    ctx = engine.Context(cfg["n_fit"], "fp32c")
+    gen_ctx = engine.Context(cfg["n_train"] * cfg["n_draws"], "fp32c")   # the training runs as one ensemble
+    f9 = orbit_frame(W_X, W_V)
+    tg = _target(ctx, cfg, seed, pot, f9)
+    p = _plain_arm(tg, cfg)
+    sur = train_surrogate(gen_ctx, cfg, seed, cfg["T_train"], pot, f9)
+    w = _warm_arm(tg, sur, cfg, seed)
+    tp = p["seconds"]                             # the plain fit, until its descent stops
+    tw = time_to(w["hist"], p["final_loss"])      # the warm arm, until it matches the plain fit
     out = {
         "metric": "time-to-fit: surrogate warm start vs plain N-body gradient descent",
-        "n_fit": n_fit, "n_steps": T, "n_train_runs": n_draws, "n_train_particles": n_train,
-        "n_train_steps": T_train, "eps_kpc": EPS_FIT,
-        "stop_rule": f"step length below {lr_min:g} (start {lr0:g}, halved on every rise) or "
-                     f"{cap} iterations",
-        "theta_star": th_star.tolist(),
-        "plain": {"seconds": t_plain, "iterations": len(hist_plain) - 1, "final_loss": L_plain,
-                  "converged": bool(conv_plain), "u": u_plain.tolist(),
-                  "loss_curve": [h[1] for h in hist_plain]},
-        "warm": {"seconds": t_warm, "inversion_seconds": t_inv,
-                 "iterations": len(hist_warm) - 1, "final_loss": L_warm,
-                 "converged": bool(conv_warm), "u_surrogate": u_warm.tolist(),
-                 "u": u_fit.tolist(), "loss_curve": [h[1] for h in hist_warm]},
-        "surrogate": {"data_seconds": t_data, "train_seconds": t_train,
-                      "train_loss_first_last": [losses[0], losses[-1]],
-                      "inversion_image_mse": err_w},
-        "u_star": u_star.tolist(),
-        "plain_fit_loss": L_plain,
+        "n_fit": cfg["n_fit"], "n_steps": cfg["T"], "n_train_runs": cfg["n_draws"],
+        "n_train_particles": cfg["n_train"], "n_train_steps": cfg["T_train"], "eps_kpc": EPS_FIT,
+        "stop_rule": f"step length below {cfg['lr_min']:g} (start {cfg['lr0']:g}, halved on "
+                     f"every rise) or {cfg['cap']} iterations",
+        "theta_star": tg["theta_star"].tolist(),
+        "plain": {"seconds": tp, "iterations": p["iterations"], "final_loss": p["final_loss"],
+                  "converged": p["converged"], "u": p["u"],
+                  "loss_curve": [h[1] for h in p["hist"]]},
+        "warm": {"seconds": w["seconds"], "inversion_seconds": w["inversion_seconds"],
+                 "iterations": w["iterations"], "final_loss": w["final_loss"],
+                 "converged": w["converged"], "u_surrogate": w["u_surrogate"], "u": w["u"],
+                 "loss_curve": [h[1] for h in w["hist"]]},
+        "surrogate": {"data_seconds": sur["data_seconds"], "train_seconds": sur["train_seconds"],
+                      "train_loss_first_last": [sur["losses"][0], sur["losses"][-1]],
+                      "inversion_image_mse": w["inversion_image_mse"]},
+        "u_star": tg["u_star"].tolist(),
+        "plain_fit_loss": p["final_loss"],
         "plain_fit_seconds": tp,
         "warm_seconds_to_plain_fit_loss": tw,
-        "plain_reaches_warm_final_loss": time_to(hist_plain, L_warm) is not None,
+        "plain_reaches_warm_final_loss": time_to(p["hist"], w["final_loss"]) is not None,
         "speedup_excl_training": (tp / tw) if tw else None,
-        "speedup_incl_training": (tp / (tw + t_data + t_train)) if tw else None,
+        "speedup_incl_training": (tp / (tw + sur["data_seconds"] + sur["train_seconds"]))
+                                 if tw else None,
     }
     ctx.close()
     gen_ctx.close()
     return out
 
 
+def study(seeds=(50, 60, 70, 80, 90), train_steps=None, quick=False, sur_seed=50):
+    """One surrogate per training-set step count, each trained once (from sur_seed)
+    and then used for every held-out target, as a surrogate is meant to be used.
+
+    Per target: the plain fit, and each surrogate's warm arm timed until it first
+    reaches the plain fit's final loss.  Per surrogate: how many targets it brings
+    to that loss, the median speedup over those, and the amortised ratio over all
+    targets including its one-off cost,
+        sum of plain fit times / (data + training + sum of warm costs),
+    where a target the warm arm does not bring to the plain fit's loss costs the
+    whole warm descent plus the plain fit (the plain loop is the fallback).  The
+    first target with sur_seed = seed reproduces run(seed=sur_seed)'s arms.
+    train_steps defaults to the fit's step count and a quarter of it."""
+    cfg = _config(quick)
+    if train_steps is None:
+        train_steps = (cfg["T"], cfg["T"] // 4)
+    pot = engine.Potential(eps=EPS_FIT)
+    ctx = engine.Context(cfg["n_fit"], "fp32c")
+    f9 = orbit_frame(W_X, W_V)
+    gen_ctx = engine.Context(cfg["n_train"] * cfg["n_draws"], "fp32c")
+    surs = [train_surrogate(gen_ctx, cfg, sur_seed, ts, pot, f9) for ts in train_steps]
+    gen_ctx.close()
+    targets = []
+    for s in seeds:
+        tg = _target(ctx, cfg, s, pot, f9)
+        p = _plain_arm(tg, cfg)
+        row = {"seed": int(s), "theta_star": tg["theta_star"].tolist(),
+               "plain": {"seconds": p["seconds"], "iterations": p["iterations"],
+                         "final_loss": p["final_loss"], "converged": p["converged"]},
+               "warm": []}
+        for sur in surs:
+            w = _warm_arm(tg, sur, cfg, s)
+            tw = time_to(w["hist"], p["final_loss"])
+            row["warm"].append({
+                "n_train_steps": sur["n_train_steps"], "seconds_to_plain_fit_loss": tw,
+                "speedup_excl_training": (p["seconds"] / tw) if tw else None,
+                "seconds": w["seconds"], "inversion_seconds": w["inversion_seconds"],
+                "iterations": w["iterations"], "final_loss": w["final_loss"],
+                "converged": w["converged"],
+                "plain_reaches_warm_final_loss": time_to(p["hist"], w["final_loss"]) is not None})
+        targets.append(row)
+    ctx.close()
+    sums = []
+    for k, sur in enumerate(surs):
+        cost = sur["data_seconds"] + sur["train_seconds"]
+        plain_total = sum(t["plain"]["seconds"] for t in targets)
+        warm_total = 0.0
+        reached = []
+        for t in targets:
+            w = t["warm"][k]
+            if w["seconds_to_plain_fit_loss"] is not None:
+                warm_total += w["seconds_to_plain_fit_loss"]
+                reached.append(w["speedup_excl_training"])
+            else:
+                warm_total += w["seconds"] + t["plain"]["seconds"]
+        saving = plain_total - warm_total
+        sums.append({"n_train_steps": sur["n_train_steps"], "data_seconds": sur["data_seconds"],
+                     "train_seconds": sur["train_seconds"],
+                     "targets_reaching_plain_fit_loss": len(reached), "targets": len(targets),
+                     "median_speedup_excl_training": float(np.median(reached)) if reached else None,
+                     "amortised_speedup_incl_training": plain_total / (cost + warm_total),
+                     "fits_to_repay_training": (cost * len(targets) / saving) if saving > 0 else None})
+    return {"n_fit": cfg["n_fit"], "n_steps": cfg["T"], "n_train_runs": cfg["n_draws"],
+            "n_train_particles": cfg["n_train"], "eps_kpc": EPS_FIT,
+            "stop_rule": f"step length below {cfg['lr_min']:g} (start {cfg['lr0']:g}, halved on "
+                         f"every rise) or {cfg['cap']} iterations",
+            "surrogate_seed": sur_seed, "surrogates": sums, "targets": targets}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--quick", action="store_true", help="the small configuration")
     ap.add_argument("--seed", type=int, default=50)
+    ap.add_argument("--study", action="store_true",
+                    help="one surrogate per training-set step count (the fit's and a quarter "
+                         "of it), trained once and used for five held-out targets")
     a = ap.parse_args()
-    print(json.dumps(run(quick=a.quick, seed=a.seed)), flush=True)
+    out = study(quick=a.quick) if a.study else run(quick=a.quick, seed=a.seed)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

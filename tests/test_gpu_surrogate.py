@@ -184,3 +184,40 @@ def test_warm_start_gains_over_plain_descent():
     assert r["warm_seconds_to_plain_fit_loss"] is not None
     assert w["final_loss"] <= p["final_loss"]
     assert r["speedup_excl_training"] > 1.0
+
+
+def test_one_surrogate_serves_several_targets():
+    """The multi-target time-to-fit study at the quick configuration: a surrogate
+    trained once per training set (the fit's 1000 steps and 250 steps over the
+    same t_end) warm-starts two held-out targets.  Every arm is a deterministic
+    function of its seeds, so the first target with the full-step training set
+    repeats the single-target run bit for bit, and the summaries follow from the
+    per-target rows by their stated formulas."""
+    from paper_2511_22468_amd import fit
+    say("[fit] study: quick, targets 50 and 60, training sets of 1000 and 250 steps")
+    r = fit.study(seeds=(50, 60), quick=True)
+    one = fit.run(quick=True, seed=50)
+    t0 = r["targets"][0]
+    assert [s["n_train_steps"] for s in r["surrogates"]] == [1000, 250]
+    assert t0["plain"]["final_loss"] == one["plain_fit_loss"]
+    assert t0["plain"]["iterations"] == one["plain"]["iterations"]
+    assert t0["warm"][0]["final_loss"] == one["warm"]["final_loss"]
+    assert t0["warm"][0]["iterations"] == one["warm"]["iterations"]
+    for k, s in enumerate(r["surrogates"]):
+        plain = sum(t["plain"]["seconds"] for t in r["targets"])
+        warm, reached = 0.0, 0
+        for t in r["targets"]:
+            w = t["warm"][k]
+            if w["seconds_to_plain_fit_loss"] is None:
+                warm += w["seconds"] + t["plain"]["seconds"]
+            else:
+                assert w["seconds_to_plain_fit_loss"] <= w["seconds"]
+                warm += w["seconds_to_plain_fit_loss"]
+                reached += 1
+        cost = s["data_seconds"] + s["train_seconds"]
+        assert s["targets_reaching_plain_fit_loss"] == reached
+        np.testing.assert_allclose(s["amortised_speedup_incl_training"], plain / (cost + warm),
+                                   rtol=1e-12)
+        say(f"[fit] {s['n_train_steps']}-step training set: data {s['data_seconds']:.2f} s, "
+            f"training {s['train_seconds']:.2f} s, {reached}/2 targets reach the plain fit's "
+            f"loss, amortised {s['amortised_speedup_incl_training']:.2f}x including training")
