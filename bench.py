@@ -861,6 +861,34 @@ def main():
             "tape_bytes": 8 * ctx.tape_len(n, T, 100), "full_tape_bytes": 8 * ctx.tape_len(n, T, 1),
             "same_gradient_as_full_tape": bool(torch.equal(gk, g) and torch.equal(Lk, L)),
         }
+        # the same checkpoints with the trajectory rebuilt by stepping it backward
+        # from the final state: one pair launch per reverse step that sums the VJP
+        # and the acceleration together, no recomputed segments
+        model_r = StreamModel(ctx, xi, zeta, target, T, pot=pot, h=0.2, ckpt_every=100,
+                              reversal=True)
+        model_r.loss_and_grad(theta)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read()
+        t0 = time.perf_counter()
+        Lr, gr = model_r.loss_and_grad(theta)
+        torch.cuda.synchronize()
+        sr = time.perf_counter() - t0
+        pr = ctx.profile_read()
+        ctx.profile(False)
+        from paper_2511_22468_amd import _lib
+        fused_ms = pr["vjp_ms"] / max(pr["vjp_launches"], 1)
+        out["checkpointed"]["reversed"] = {
+            "ckpt_every": 100, "ms_per_step": sr * 1e3, "value": pairs / sr,
+            "fused_launch_ms": fused_ms, "fused_launches": pr["vjp_launches"],
+            "fused_pairs_per_s": float(n) * n / (fused_ms * 1e-3),
+            "workspace_bytes": 8 * int(_lib.lib().dnb_vjp_reversed_workspace_doubles(n)),
+            "recompute_workspace_bytes": 8 * int(_lib.lib().dnb_vjp_workspace_doubles(n, 100)),
+            "loss_same_as_full_tape": bool(torch.equal(Lr, L)),
+            "grad": [float(v) for v in gr.cpu().numpy()],
+            "grad_rel_diff_vs_full_tape": [float(v) for v in
+                                           (gr / g - 1).abs().cpu().numpy()],
+        }
     ctx.close()
     if args.profile_run:
         # calibration for the traffic counters: a plain copy of 256 MiB

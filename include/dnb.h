@@ -244,6 +244,40 @@ dnb_status dnb_simulate_vjp(dnb_ctx* ctx, int64_t n, const double* mass, const d
                             double* workspace, double* gpos_0, double* gvel_0, double* gmass,
                             double* gparams, void* stream);
 
+/* Number of doubles of the workspace that dnb_simulate_vjp_reversed needs:
+ * 17n whatever the checkpoint spacing; -1 for invalid or oversized n. */
+int64_t dnb_vjp_reversed_workspace_doubles(int64_t n);
+
+/* The same gradient as dnb_simulate_vjp, with the trajectory between
+ * checkpoints rebuilt by stepping it backward instead of recomputing it forward
+ * (the kick-drift-kick step is time-reversible, Sec. 2.2.1: its step with -dt
+ * undoes it up to rounding).  The sweep starts from the final state and, newest
+ * step first, runs one pair launch at x_m that sums the pair VJP and the
+ * internal acceleration a(x_m) together; the reverse kick takes the adjoint step
+ * and undoes the forward step that led to x_m.  At every checkpoint the stored
+ * state replaces the rebuilt one.  One pair launch per step instead of two,
+ * and a workspace of 17n doubles instead of two recomputed segments.
+ *
+ * Accuracy: the rebuilt positions differ from the run's by the rounding of at
+ * most ckpt_every backward steps, grown by the dynamics over those steps, and
+ * in FP32C mode also by the FP32 rounding of accelerations staged about a
+ * different centre than the run's.  With ckpt_every = 1 no state is rebuilt:
+ * in FP64 mode the result is then that of dnb_simulate_vjp bit for bit.  Where
+ * the dynamics are chaotic over ckpt_every steps the gradient is that of a
+ * neighbouring trajectory; choose ckpt_every accordingly.
+ *
+ * Arguments as dnb_simulate_vjp, plus vel_T [3][n]: the final velocities, the
+ * velocity array the forward call moved in place (DNB_ERR_STATE when it is not
+ * the array recorded with the tape).  workspace holds
+ * dnb_vjp_reversed_workspace_doubles(n).  Outputs must not alias inputs. */
+dnb_status dnb_simulate_vjp_reversed(dnb_ctx* ctx, int64_t n, const double* mass,
+                                     const dnb_pot* pot, double dt, int64_t n_steps,
+                                     int64_t ckpt_every, const double* tape,
+                                     const double* pos_T, const double* vel_T,
+                                     const double* gpos_T, const double* gvel_T,
+                                     double* workspace, double* gpos_0, double* gvel_0,
+                                     double* gmass, double* gparams, void* stream);
+
 /* Squared maximum mean discrepancy between the point clouds pos [3][n] and
  * tgt [3][m] (Sec. 2.2.1 and Fig. 2, step 4), with the Gaussian kernel
  * k(x, y) = exp(-|x - y|^2 / (2 h^2)) and the biased (V-statistic) estimate:

@@ -58,6 +58,9 @@ def load_library(path=LIB_PATH):
         "dnb_set_checks": ([P, I], I),
         "dnb_simulate_resume": ([P, I64, P, I64, I64, I64, P, P, P, POT, D, I64, I64, P, P], I),
         "dnb_simulate_vjp": ([P, I64, P, POT, D, I64, I64, P, P, P, P, P, P, P, P, P, P], I),
+        "dnb_vjp_reversed_workspace_doubles": ([I64], I64),
+        "dnb_simulate_vjp_reversed": ([P, I64, P, POT, D, I64, I64, P, P, P, P, P, P, P, P, P,
+                                       P, P], I),
         "dnb_mmd": ([P, I64, P, I64, P, D, P, P, P], I),
         "dnb_energy": ([P, I64, P, P, P, POT, P, P], I),
         "dnb_orbit": ([P, P, POT, D, I64, P, P, P], I),

@@ -32,30 +32,31 @@ class Simulate(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, pos0, vel0, mass, m_nfw, m_mn, dt, m_scale, engine_ctx, pot, n_steps,
-                ckpt_every):
+                ckpt_every, reversal=False):
         p = pot.replace(m_nfw=_scalar(m_nfw), m_mn=_scalar(m_mn))
         pos, vel = pos0.detach().clone(), vel0.detach().clone()
         tape = engine_ctx.simulate(pos, vel, mass.detach(), p, _scalar(dt), n_steps,
                                    ckpt_every=ckpt_every)
-        ctx.save_for_backward(mass, pos)
+        ctx.save_for_backward(mass, pos, vel)
         ctx.engine_ctx, ctx.pot, ctx.dt = engine_ctx, p, _scalar(dt)
         ctx.n_steps, ctx.K, ctx.tape = n_steps, ckpt_every, tape
+        ctx.reversal = bool(reversal)
         ctx.mass_req = mass.requires_grad
         ctx.m_scale = None if m_scale is None else _scalar(m_scale)
         return pos, vel
 
     @staticmethod
     def backward(ctx, gpos, gvel):
-        mass, posT = ctx.saved_tensors
+        mass, posT, velT = ctx.saved_tensors
         if gpos is None:
             gpos = torch.zeros_like(posT)
         gx0, gv0, gm, gpar = ctx.engine_ctx.simulate_vjp(
             mass.detach(), ctx.pot, ctx.dt, ctx.n_steps, ctx.K, ctx.tape, posT,
             gpos.contiguous(), None if gvel is None else gvel.contiguous(),
-            with_mass=ctx.mass_req)
+            with_mass=ctx.mass_req, vel_T=velT if ctx.reversal else None)
         ctx.tape = None
         gs = None if ctx.m_scale is None else gpar[3] / ctx.m_scale
-        return gx0, gv0, gm, gpar[0], gpar[1], gpar[2], gs, None, None, None, None
+        return gx0, gv0, gm, gpar[0], gpar[1], gpar[2], gs, None, None, None, None, None
 
 
 class MMD(torch.autograd.Function):
@@ -141,9 +142,13 @@ def accelerations(engine_ctx, pos, mass, pot: Potential, with_ext=True):
 
 
 def simulate(engine_ctx, pos0, vel0, mass, m_nfw, m_mn, dt, pot: Potential, n_steps,
-             ckpt_every=1, m_scale=None):
+             ckpt_every=1, m_scale=None, reversal=False):
+    """reversal: the backward pass rebuilds the trajectory between checkpoints by
+    stepping it backward from the final state instead of recomputing it forward
+    (one pair launch per step instead of two; the gradient of a trajectory that
+    differs from the run's by rounding grown over at most ckpt_every steps)."""
     return Simulate.apply(pos0, vel0, mass, m_nfw, m_mn, dt, m_scale, engine_ctx, pot, n_steps,
-                          ckpt_every)
+                          ckpt_every, reversal)
 
 
 def mmd(engine_ctx, pos, target, h):

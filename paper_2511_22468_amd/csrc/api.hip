@@ -106,10 +106,11 @@ void forget_tapes(dnb_ctx* c, const double* pos, const double* tape, int64_t tap
 
 void remember_tape(dnb_ctx* c, const TapeDesc& d) { c->tapes.remember(d); }
 
-TapeDesc single_desc(const double* tape, const double* pos, const double* mass, int64_t n,
-                     int64_t T, int64_t K, double dt, const dnb_pot& p) {
+TapeDesc single_desc(const double* tape, const double* pos, const double* vel,
+                     const double* mass, int64_t n, int64_t T, int64_t K, double dt,
+                     const dnb_pot& p) {
     return TapeDesc{tape, pos, mass, n, T, K, dt,
-                    {p.G, p.eps, p.m_nfw, p.rs_nfw, p.m_mn, p.a_mn, p.b_mn}, 0, 0};
+                    {p.G, p.eps, p.m_nfw, p.rs_nfw, p.m_mn, p.a_mn, p.b_mn}, 0, 0, vel};
 }
 
 // The descriptor of a batched tape, checked against the arguments of
@@ -137,10 +138,12 @@ dnb_status match_batch_tape(dnb_ctx* c, const double* tape, const double* pos_T,
                 fn);
 }
 
-// The descriptor of `tape`, checked against the arguments of a reverse sweep.
+// The descriptor of `tape`, checked against the arguments of a reverse sweep
+// (vel_T: the final velocities a sweep that steps backward starts from; null for
+// the sweep that recomputes segments).
 dnb_status match_tape(dnb_ctx* c, const double* tape, const double* pos_T, const double* mass,
                       int64_t n, int64_t T, int64_t K, double dt, const dnb_pot& p,
-                      const char* fn) {
+                      const char* fn, const double* vel_T = nullptr) {
     const double pv[7] = {p.G, p.eps, p.m_nfw, p.rs_nfw, p.m_mn, p.a_mn, p.b_mn};
     if (const TapeDesc* dp = c->tapes.find(tape)) {
         const TapeDesc& d = *dp;
@@ -154,6 +157,9 @@ dnb_status match_tape(dnb_ctx* c, const double* tape, const double* pos_T, const
                         (long long)T, (long long)K);
         if (d.pos != pos_T)
             return fail(DNB_ERR_STATE, "%s: pos_T is not the position array the tape's forward "
+                        "run moved", fn);
+        if (vel_T && d.vel != vel_T)
+            return fail(DNB_ERR_STATE, "%s: vel_T is not the velocity array the tape's forward "
                         "run moved", fn);
         if (d.mass != mass || d.dt != dt || std::memcmp(d.pot, pv, sizeof pv) != 0)
             return fail(DNB_ERR_STATE, "%s: mass, dt or pot differ from the tape's forward run",
@@ -447,6 +453,10 @@ int64_t dnb_vjp_workspace_doubles(int64_t n, int64_t ckpt_every) {
     return vjp_workspace_doubles(n, ckpt_every);
 }
 
+int64_t dnb_vjp_reversed_workspace_doubles(int64_t n) {
+    return vjp_reversed_workspace_doubles(n);
+}
+
 // The state scan: *first = index of the first particle (b n + i for member b)
 // with a non-finite position, velocity or mass, -1 when there is none.  Waits
 // for the stream.
@@ -511,7 +521,7 @@ dnb_status dnb_simulate(dnb_ctx* c, int64_t n, double* pos, double* vel, const d
     CHECK(run_forward(c, n, pos, vel, mass, to_pot(*pot), dt, n_steps, ckpt_every,
                       tape ? &tp : nullptr, (hipStream_t)stream));
     if (tape && n_steps > 0)
-        remember_tape(c, single_desc(tape, pos, mass, n, n_steps, ckpt_every, dt, *pot));
+        remember_tape(c, single_desc(tape, pos, vel, mass, n, n_steps, ckpt_every, dt, *pot));
     return DNB_OK;
 }
 
@@ -571,7 +581,7 @@ dnb_status dnb_simulate_resume(dnb_ctx* c, int64_t n, const double* tape, int64_
     CHECK(run_forward(c, n, pos, vel, mass, to_pot(*pot), dt, n_steps, ckpt_every,
                       tape_out ? &tp : nullptr, st, src.centre(ckpt)));
     if (tape_out && n_steps > 0)
-        remember_tape(c, single_desc(tape_out, pos, mass, n, n_steps, ckpt_every, dt, *pot));
+        remember_tape(c, single_desc(tape_out, pos, vel, mass, n, n_steps, ckpt_every, dt, *pot));
     return DNB_OK;
 }
 
@@ -770,6 +780,122 @@ dnb_status dnb_simulate_vjp(dnb_ctx* c, int64_t n, const double* mass, const dnb
     return DNB_OK;
 }
 
+// Reverse sweep that rebuilds the trajectory by stepping it backward.  Each
+// step m (newest first) runs one pair launch at x_m that sums both J(x_m)^T w
+// and the internal acceleration a(x_m); the reverse kick then takes the adjoint
+// step and undoes the forward step that led to x_m (the kick-drift-kick map
+// with -dt: v_{m-1/2} = v_m - dt/2 a(x_m), x_{m-1} = x_m - dt v_{m-1/2}, and
+// v_{m-1} = v_{m-1/2} - dt/2 a(x_{m-1}) in the next step).  The sweep starts from
+// the final state and takes the stored state in place of the rebuilt one at
+// every checkpoint, so the rebuilt positions drift from the run's by at most
+// K steps of rounding, grown by the dynamics over those steps.  One pair launch
+// per step instead of two (a recomputed forward sum and the VJP), and no
+// segment buffers.
+dnb_status dnb_simulate_vjp_reversed(dnb_ctx* c, int64_t n, const double* mass,
+                                     const dnb_pot* pot, double dt, int64_t n_steps,
+                                     int64_t ckpt_every, const double* tape,
+                                     const double* pos_T, const double* vel_T,
+                                     const double* gpos_T, const double* gvel_T,
+                                     double* workspace, double* gpos_0, double* gvel_0,
+                                     double* gmass, double* gparams, void* stream) {
+    const char* fn = "dnb_simulate_vjp_reversed";
+    CHECK(check_sim_args(c, n, pos_T, gpos_0, mass, pot, dt, n_steps, ckpt_every, fn));
+    if (dt == 0.0) return fail(DNB_ERR_ARG, "%s: dt must be non-zero", fn);
+    CHECK(check_dev(vel_T, "vel_T", fn));
+    CHECK(check_dev(gpos_T, "gpos_T", fn));
+    CHECK(check_dev(gvel_T, "gvel_T", fn, true));
+    CHECK(check_dev(workspace, "workspace", fn));
+    CHECK(check_dev(gvel_0, "gvel_0", fn));
+    CHECK(check_dev(gmass, "gmass", fn, true));
+    CHECK(check_dev(gparams, "gparams", fn));
+    if (n_steps > 0) CHECK(check_dev(tape, "tape", fn));
+    if (gpos_0 == gpos_T || gvel_0 == gvel_T || gpos_0 == gvel_0 || gpos_0 == vel_T ||
+        gvel_0 == vel_T)
+        return fail(DNB_ERR_ARG, "%s: outputs must not alias inputs", fn);
+    CHECK(check_extent(vel_T, sizeof(double) * 3 * n, "vel_T", fn));
+    CHECK(check_extent(workspace, sizeof(double) * dnb_vjp_reversed_workspace_doubles(n),
+                       "workspace", fn));
+    CHECK(check_extent(gparams, sizeof(double) * 7, "gparams", fn));
+    if (n_steps > 0) {
+        CHECK(check_extent(tape, sizeof(double) * dnb_tape_doubles(n, n_steps, ckpt_every), "tape",
+                           fn));
+        CHECK(match_tape(c, tape, pos_T, mass, n, n_steps, ckpt_every, dt, *pot, fn, vel_T));
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const Pot p = to_pot(*pot);
+    const int64_t T = n_steps, K = ckpt_every;
+    const int nb = (int)cdiv(n, BS);
+    const size_t vec = sizeof(double) * 3 * n;
+    double* lx = gpos_0;
+    double* lv = gvel_0;
+    double* rv = workspace;                          // [3][n] velocity stepped back
+    double* accum = workspace + 3 * n;               // [8][n]
+    double* xb[2] = {workspace + 11 * n, workspace + 14 * n};   // rebuilt positions
+    HIP_TRY(hipMemcpyAsync(lx, gpos_T, vec, hipMemcpyDeviceToDevice, st));
+    if (gvel_T) HIP_TRY(hipMemcpyAsync(lv, gvel_T, vec, hipMemcpyDeviceToDevice, st));
+    else HIP_TRY(hipMemsetAsync(lv, 0, vec, st));
+    HIP_TRY(hipMemsetAsync(accum, 0, sizeof(double) * 8 * n, st));
+    HIP_TRY(launch_mass_info(c, mass, n, st));
+    const int with_mass = gmass != nullptr;
+    const bool f32 = c->prec == DNB_FP32C;
+    if (T > 0) {
+        Tape tp{const_cast<double*>(tape), n, cdiv(T, K)};
+        // positions of step m: the final ones, a checkpoint's, or rebuilt
+        auto pos_of = [&](int64_t m) -> const double* {
+            if (m == T) return pos_T;
+            if (m % K == 0) return tp.state(m / K);
+            return xb[m & 1];
+        };
+        double* cpv[2] = {c->cpartv, c->cpartv + REC * c->nbmax};
+        // x_{T-1} is not known before the first step: its staging centre is
+        // predicted one drift back at the final velocities
+        if (f32) HIP_TRY(launch_block_sums(pos_T, n, cpv[0], st, lv));
+        HIP_TRY(launch_rev_stage(c, n, pos_T, mass, lv, cpv[0], nb, cpv[1], c->wscale, st,
+                                 nullptr, vel_T, dt));
+        int q = 1;
+        int wq = 0;   // c->wscale[wq]: scale of the currently staged cotangent
+        for (int64_t m = T; m >= 0; --m) {
+            HIP_TRY(profiled(c, 1, st, [&] {
+                return launch_pair_vjp_force(c, n, with_mass, p.eps, st);
+            }));
+            RevArgs r{};
+            if (f32) {
+                HIP_TRY(launch_vjp_reduce(c, n, p.G, with_mass, c->wscale + wq, st));
+                HIP_TRY(launch_fwd_reduce(c, n, mass, p.G, st));
+                r.gred = c->gred; r.grec = c->grec; r.nr = red_blocks(n);
+                r.ared = c->ared; r.arec = c->arec;
+            } else {
+                r.fpart = c->part;
+            }
+            r.rev = 1;
+            r.n = n; r.mass = mass; r.pot = p; r.dt = dt;
+            r.coef = (m == T || m == 0) ? 0.5 * dt : dt;
+            r.x_n = pos_of(m);
+            if (m > 0) {
+                // x_{m-1}: a checkpoint's (exact) or rebuilt into the other buffer
+                if ((m - 1) % K == 0) r.x_prev = tp.state((m - 1) / K);
+                else r.x_rec = xb[(m - 1) & 1];
+                // the velocity at x_m: exact at the end and at checkpoints, else the
+                // half-step velocity the previous step left
+                if (m == T) { r.rv_src = vel_T; r.rv_half = 0; }
+                else if (m % K == 0) { r.rv_src = tp.state(m / K) + 3 * n; r.rv_half = 0; }
+                else { r.rv_src = rv; r.rv_half = 1; }
+                r.rv_out = rv;
+            }
+            r.lx = lx; r.lv = lv; r.accum = accum; r.with_mass = with_mass;
+            r.cpart_in = cpv[q]; r.nb_in = nb; r.cpart_out = cpv[1 - q];
+            r.wscale_in = c->wscale + wq; r.wscale_out = c->wscale + (1 - wq);
+            HIP_TRY(launch_rev_kick(c, r, st));
+            q = 1 - q;
+            wq = 1 - wq;
+        }
+    }
+    HIP_TRY(launch_reduce_accum(accum, n, 7, gparams, c->red, st));
+    if (gmass) HIP_TRY(hipMemcpyAsync(gmass, accum + 7 * n, sizeof(double) * n,
+                                      hipMemcpyDeviceToDevice, st));
+    return DNB_OK;
+}
+
 dnb_status dnb_mmd(dnb_ctx* c, int64_t n, const double* pos, int64_t m, const double* tgt,
                    double h, double* loss, double* gpos, void* stream) {
     const char* fn = "dnb_mmd";
@@ -882,7 +1008,7 @@ dnb_status dnb_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* pos,
     HIP_TRY(launch_simulate_batch(c, batch, n, pos, vel, mass, c->bparams, n_steps, tape, st));
     if (tape && n_steps > 0)
         remember_tape(c, TapeDesc{tape, pos, mass, n, n_steps, 1, 0.0, {}, batch,
-                                  table_hash(params, batch)});
+                                  table_hash(params, batch), vel});
     return DNB_OK;
 }
 

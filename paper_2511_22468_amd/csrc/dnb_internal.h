@@ -446,17 +446,38 @@ struct RevArgs {
     const double* grec;
     int nr;
     const double* aext;   // [9][n] the external-field terms of an ExtRow (null: evaluate)
+    // Reverse sweep that steps the trajectory backward (rev != 0).  The kernel
+    // takes the internal acceleration at x_n from the pair launch that summed it
+    // with the VJP (FP32C: ared and its net-force records arec as the forward
+    // reduction writes them; FP64: the slice partials fpart) instead of aint, and
+    // undoes the step that led to x_n:
+    //   v_n     = v_{n+1/2} - dt/2 a(x_n)     (rv_half; else rv_src holds v_n)
+    //   v_{n-1/2} = v_n - dt/2 a(x_n),  x_{n-1} = x_n - dt v_{n-1/2}
+    // writing v_{n-1/2} to rv_out and, when x_rec is set, x_{n-1} to x_rec (which
+    // is then also x_prev); with x_rec null, x_prev holds x_{n-1} (a checkpoint).
+    int rev;
+    const double* rv_src;
+    int rv_half;
+    double* rv_out;
+    double* x_rec;
+    const double* ared;
+    const double* arec;
+    const void* fpart;
 };
 
 // xprev (nullable): the positions the sweep stages next, whose displacement from
-// x the records in cpart_out carry for the next staging centre.
+// x the records in cpart_out carry for the next staging centre; without them,
+// vback (nullable) stands in with the displacement -dtback vback.
 hipError_t launch_rev_stage(dnb_ctx* c, int64_t n, const double* x, const double* mass,
                             const double* w, const double* cpart, int nb, double* cpart_out,
-                            double* wscale_out, hipStream_t st, const double* xprev = nullptr);
+                            double* wscale_out, hipStream_t st, const double* xprev = nullptr,
+                            const double* vback = nullptr, double dtback = 0.0);
 hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, int with_mass, double eps, hipStream_t st,
                            const ExtRow& ext = ExtRow{}, bool* ext_done = nullptr);
 hipError_t launch_pair_vjp_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, int with_mass,
                                 double eps, hipStream_t st);
+hipError_t launch_pair_vjp_force(dnb_ctx* c, int64_t n, int with_mass, double eps,
+                                 hipStream_t st);
 hipError_t launch_acc_vjp_rows(dnb_ctx* c, const double* x, const double* w, int64_t n,
                                int64_t i0, int64_t ni, const Pot& pot, int with_ext,
                                double* gpos, double* gmass, hipStream_t st);

@@ -122,6 +122,14 @@ inline int64_t vjp_workspace_doubles(int64_t n, int64_t K) {
     return seg + 22 * n;
 }
 
+// Doubles of the workspace of dnb_simulate_vjp_reversed: the velocity being
+// stepped back (3n), the per-particle parameter sums (8n) and two buffers of
+// rebuilt positions (6n), whatever the checkpoint spacing.
+inline int64_t vjp_reversed_workspace_doubles(int64_t n) {
+    if (n < 1 || n > MAX_N) return -1;
+    return 17 * n;
+}
+
 // Offset (doubles) of segment buffer b (0 or 1) in that workspace, and its
 // accelerations' offset within the buffer.
 inline int64_t vjp_segment_offset(int64_t n, int64_t K, int b) {
@@ -166,6 +174,7 @@ struct TapeDesc {
     double pot[7];       // G, eps, m_nfw, rs_nfw, m_mn, a_mn, b_mn
     int64_t batch;       // 0: dnb_simulate; else the members of dnb_simulate_batch
     uint64_t table;      // hash of the batch's host parameter table (0 for a single system)
+    const double* vel;   // the in-place velocity array: the final velocities (single system)
 
     int64_t length() const {
         return batch ? batch_tape_doubles(batch, n, n_steps) : tape_doubles(n, n_steps, ckpt_every);

@@ -285,7 +285,9 @@ __global__ __launch_bounds__(BS) void k_rev_stage(const double* __restrict__ x,
                                                   int nb, void* __restrict__ jsv,
                                                   double* __restrict__ cpart_out,
                                                   double* __restrict__ wscale_out,
-                                                  const double* __restrict__ xprev) {
+                                                  const double* __restrict__ xprev,
+                                                  const double* __restrict__ vback,
+                                                  double dtback) {
     __shared__ double sh[3 * BS];
     double cx = 0.0, cy = 0.0, cz = 0.0;
     double S = 1.0;
@@ -303,7 +305,11 @@ __global__ __launch_bounds__(BS) void k_rev_stage(const double* __restrict__ x,
     if (F32) {
         // the displacement to the positions the reverse sweep stages next
         double dx = 0.0, dy = 0.0, dz = 0.0;
-        if (xprev) { dx = xprev[k] - x0; dy = xprev[n + k] - y0; dz = xprev[2 * n + k] - z0; }
+        if (xprev) {
+            dx = xprev[k] - x0; dy = xprev[n + k] - y0; dz = xprev[2 * n + k] - z0;
+        } else if (vback) {   // positions not known yet: one drift back at velocity vback
+            dx = -dtback * vback[k]; dy = -dtback * vback[n + k]; dz = -dtback * vback[2 * n + k];
+        }
         write_block_sums(x0, y0, z0, dx, dy, dz, ok, sh, cpart_out);
         write_block_max(ok ? absmax3(wx, wy, wz) : 0.0, sh, cpart_out);
         if (blockIdx.x == 0 && threadIdx.x == 0) wscale_out[0] = S;
@@ -319,13 +325,19 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
     const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
     const bool ok = i < n;
     const int64_t k = ok ? i : 0;
-    const bool drift = a.x_prev != nullptr;
+    const bool rev = a.rev != 0;
+    const bool drift = a.x_prev != nullptr || (rev && a.x_rec != nullptr);
+    const bool rebuild = rev && a.x_rec != nullptr;   // x_{n-1} from the step undone
 
     // every load that does not wait for the block reductions, issued first
     const double x = a.x_n[k], y = a.x_n[n + k], z = a.x_n[2 * n + k];
     const double wx = a.lv[k], wy = a.lv[n + k], wz = a.lv[2 * n + k];
     const double lx0 = a.lx[k], ly0 = a.lx[n + k], lz0 = a.lx[2 * n + k];
-    const double ai[3] = {a.aint[k], a.aint[n + k], a.aint[2 * n + k]};
+    double ai[3] = {0.0, 0.0, 0.0};
+    if (!rev) { ai[0] = a.aint[k]; ai[1] = a.aint[n + k]; ai[2] = a.aint[2 * n + k]; }
+    if (rev && F32) { ai[0] = a.ared[k]; ai[1] = a.ared[n + k]; ai[2] = a.ared[2 * n + k]; }
+    double vs[3] = {0.0, 0.0, 0.0};
+    if (rev && drift) { vs[0] = a.rv_src[k]; vs[1] = a.rv_src[n + k]; vs[2] = a.rv_src[2 * n + k]; }
     double g[3] = {0.0, 0.0, 0.0}, gm = 0.0;
     if (F32) {
         g[0] = a.gred[k]; g[1] = a.gred[n + k]; g[2] = a.gred[2 * n + k];
@@ -333,7 +345,7 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
     }
     double px = 0.0, py = 0.0, pz = 0.0, mk = 0.0;
     if (drift) {
-        px = a.x_prev[k]; py = a.x_prev[n + k]; pz = a.x_prev[2 * n + k];
+        if (!rebuild) { px = a.x_prev[k]; py = a.x_prev[n + k]; pz = a.x_prev[2 * n + k]; }
         mk = a.mass[k];
     }
     const double acc0[8] = {a.accum[k], a.accum[n + k], a.accum[2 * n + k], a.accum[3 * n + k],
@@ -361,10 +373,22 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
         g[0] -= tot[0] * inv_n;
         g[1] -= tot[1] * inv_n;
         g[2] -= tot[2] * inv_n;
+        if (rev) {
+            // the internal acceleration summed with the VJP, minus the net internal
+            // force per unit mass, as the forward kick takes it
+            double tota[4];
+            rec_total(a.arec, a.nr, sh, tota);
+            const double inv_m = 1.0 / tota[3];
+            ai[0] -= tota[0] * inv_m;
+            ai[1] -= tota[1] * inv_m;
+            ai[2] -= tota[2] * inv_m;
+        }
     } else {
         vjp_sum<F32>(part, S, npad, k, a.pot.G, a.with_mass != 0, g, gm);
+        if (rev) pair_sum<F32>(a.fpart, S, npad, k, a.pot.G, ai[0], ai[1], ai[2]);
     }
     double hx, hy, hz, aw_ext, nw, mw, shp[3];
+    double ex = 0.0, ey = 0.0, ez = 0.0;   // external acceleration (reversal only)
     if (a.aext) {
         hx = xt[0]; hy = xt[1]; hz = xt[2];
         aw_ext = xt[3]; nw = xt[4]; mw = xt[5];
@@ -375,6 +399,17 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
         aw_ext = e.ax * wx + e.ay * wy + e.az * wz;
         nw = e.nx * wx + e.ny * wy + e.nz * wz;
         mw = e.mx * wx + e.my * wy + e.mz * wz;
+        ex = e.ax; ey = e.ay; ez = e.az;
+    }
+    // the step that led to x_n undone, in the forward kick's expressions with -dt
+    double vhx = 0.0, vhy = 0.0, vhz = 0.0;
+    if (rev && drift) {
+        const double fx = ai[0] + ex, fy = ai[1] + ey, fz = ai[2] + ez;
+        const double mhdt = -0.5 * a.dt;
+        double vx = vs[0], vy = vs[1], vz = vs[2];
+        if (a.rv_half) { vx = fma(mhdt, fx, vx); vy = fma(mhdt, fy, vy); vz = fma(mhdt, fz, vz); }
+        vhx = fma(mhdt, fx, vx); vhy = fma(mhdt, fy, vy); vhz = fma(mhdt, fz, vz);
+        if (rebuild) { px = fma(-a.dt, vhx, x); py = fma(-a.dt, vhy, y); pz = fma(-a.dt, vhz, z); }
     }
 
     const double lx = fma(a.coef, g[0] + hx, lx0);
@@ -405,6 +440,10 @@ __global__ __launch_bounds__(BS) void k_rev_kick(RevArgs a, const void* __restri
         a.accum[6 * n + i] = acc0[6] + a.coef * shp[2];
         if (a.with_mass) a.accum[7 * n + i] = acc0[7] - a.coef * gm;
         if (drift) { a.lv[i] = nwx; a.lv[n + i] = nwy; a.lv[2 * n + i] = nwz; }
+        if (rev && drift) {
+            a.rv_out[i] = vhx; a.rv_out[n + i] = vhy; a.rv_out[2 * n + i] = vhz;
+            if (rebuild) { a.x_rec[i] = px; a.x_rec[n + i] = py; a.x_rec[2 * n + i] = pz; }
+        }
     }
     if (drift) {
         if (i < nj)
@@ -456,14 +495,15 @@ hipError_t launch_vjp_reduce(dnb_ctx* c, int64_t n, double G, int with_mass,
 
 hipError_t launch_rev_stage(dnb_ctx* c, int64_t n, const double* x, const double* mass,
                             const double* w, const double* cpart, int nb, double* cpart_out,
-                            double* wscale_out, hipStream_t st, const double* xprev) {
+                            double* wscale_out, hipStream_t st, const double* xprev,
+                            const double* vback, double dtback) {
     const int64_t nj = pad_sources(n);
     if (c->prec == DNB_FP32C)
         hipLaunchKernelGGL(k_rev_stage<true>, dim3(onblocks(n)), dim3(BS), 0, st, x, mass, w, n,
-                           nj, cpart, nb, c->jsv, cpart_out, wscale_out, xprev);
+                           nj, cpart, nb, c->jsv, cpart_out, wscale_out, xprev, vback, dtback);
     else
         hipLaunchKernelGGL(k_rev_stage<false>, dim3(onblocks(n)), dim3(BS), 0, st, x, mass, w, n,
-                           nj, cpart, nb, c->jsv, cpart_out, wscale_out, xprev);
+                           nj, cpart, nb, c->jsv, cpart_out, wscale_out, xprev, vback, dtback);
     return hipGetLastError();
 }
 

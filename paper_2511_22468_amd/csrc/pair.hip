@@ -194,17 +194,25 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f64(const double4* __restrict__
 // copies its slice (two float4 per source) into LDS, as in the forward kernel.
 constexpr int VJP_LDS_SLICE = 64;    // longest slice that takes the LDS kernel
 
-template <bool EPS0, bool MASS, bool LDS, bool NT, bool ROW>
+//
+// With FORCE the launch also sums the internal acceleration at the staged
+// positions (the reverse sweep that steps the trajectory backward): its slice
+// partials go to partf in the layout of the forward pair kernel's, [S][3][npad]
+// float2, so that the forward reduction sums them.
+template <bool EPS0, bool MASS, bool LDS, bool NT, bool ROW, bool FORCE>
 __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__ jsv, int n,
                                                       int i0, int iend, int nj, int jslice,
                                                       float eps2, float* __restrict__ part,
                                                       int64_t npad,
                                                       const float* __restrict__ muni,
-                                                      ExtRow er, double* __restrict__ aext) {
+                                                      ExtRow er, double* __restrict__ aext,
+                                                      float* __restrict__ partf) {
+    static_assert(!(ROW && FORCE), "the external-field row and FORCE are not combined");
     if (ROW && blockIdx.y == 0) {   // the external-field row, first so it starts at once
         ext_row_vjp(er, n, aext);
         return;
     }
+    constexpr int NH = FORCE ? 7 : 4;
     const int i = i0 + blockIdx.x * BS + threadIdx.x;
     const int sy = blockIdx.y - (ROW ? 1 : 0);   // source slice
     const int j0 = sy * jslice;
@@ -212,45 +220,61 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__
     const int ii = min(i, n - 1);
     const float4 me = jsv[2 * ii];
     const float4 mw = jsv[2 * ii + 1];
-    float h[4] = {0.f, 0.f, 0.f, 0.f};
-    float l[4] = {0.f, 0.f, 0.f, 0.f};
+    float h[NH], l[NH];
+#pragma unroll
+    for (int c = 0; c < NH; ++c) { h[c] = 0.f; l[c] = 0.f; }
+    bool uni = false;
     if (LDS) {
         __shared__ float4 lds[2 * VJP_LDS_SLICE];
         const int jl = min(j1, j0 + VJP_LDS_SLICE);   // the launcher keeps j1 - j0 within it
         for (int t = threadIdx.x; t < 2 * (jl - j0); t += BS) lds[t] = jsv[2 * j0 + t];
         __syncthreads();
         if (muni[0] != 0.f) {
-            vjp_f32c_slice_lds<EPS0, MASS, true>(lds, i, j0, jl, eps2, me, mw, h, l);
-            const float m = muni[1];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) { h[c] *= m; l[c] *= m; }
+            vjp_f32c_slice_lds<EPS0, MASS, true, FORCE>(lds, i, j0, jl, eps2, me, mw, h, l);
+            uni = true;
         } else {
-            vjp_f32c_slice_lds<EPS0, MASS, false>(lds, i, j0, jl, eps2, me, mw, h, l);
+            vjp_f32c_slice_lds<EPS0, MASS, false, FORCE>(lds, i, j0, jl, eps2, me, mw, h, l);
         }
     } else if (muni[0] != 0.f) {
-        vjp_f32c_slice<EPS0, MASS, true>(jsv, i, j0, j1, eps2, me, mw, h, l);
+        vjp_f32c_slice<EPS0, MASS, true, FORCE>(jsv, i, j0, j1, eps2, me, mw, h, l);
+        uni = true;
+    } else {
+        vjp_f32c_slice<EPS0, MASS, false, FORCE>(jsv, i, j0, j1, eps2, me, mw, h, l);
+    }
+    if (uni) {   // the common mass left out of the pair terms
         const float m = muni[1];
 #pragma unroll
         for (int c = 0; c < 3; ++c) { h[c] *= m; l[c] *= m; }
-    } else {
-        vjp_f32c_slice<EPS0, MASS, false>(jsv, i, j0, j1, eps2, me, mw, h, l);
+        if (FORCE) {
+#pragma unroll
+            for (int c = 4; c < 7; ++c) { h[c] *= m; l[c] *= m; }
+        }
     }
     if (i < iend) {
         float2* p = (float2*)part + (int64_t)sy * 4 * npad + (i - i0);
 #pragma unroll
         for (int c = 0; c < 3; ++c) put_partial<NT>(p + c * npad, h[c], l[c]);
         if (MASS) put_partial<NT>(p + 3 * npad, h[3], l[3]);
+        if (FORCE) {
+            float2* pf = (float2*)partf + (int64_t)sy * 3 * npad + (i - i0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) put_partial<NT>(pf + c * npad, h[4 + c], l[4 + c]);
+        }
     }
 }
 
 // ---------------------------------------------------------------- VJP FP64 --
 // jsv: interleaved double4 [2 j] = (x, y, z, m), [2 j + 1] = (w, 0), padded.
 // part: [S][4][npad] doubles: JTw(3), gm.
-template <bool EPS0, bool MASS>
+// FORCE: the internal acceleration at the staged positions as well, into partf
+// [S][3][npad] doubles (the forward pair kernel's layout), with the forward
+// kernel's expressions in its source order, so that at the same positions the
+// partials are those of the forward kernel bit for bit.
+template <bool EPS0, bool MASS, bool FORCE>
 __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__ jsv, int n,
                                                      int i0, int iend, int nj, int jslice,
                                                      double eps2, double* __restrict__ part,
-                                                     int64_t npad) {
+                                                     int64_t npad, double* __restrict__ partf) {
     constexpr int PB = 2;
     const int i = i0 + blockIdx.x * BS + threadIdx.x;
     const int j0 = blockIdx.y * jslice;
@@ -259,6 +283,7 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__
     const double4 me = jsv[2 * ii];
     const double4 mw = jsv[2 * ii + 1];
     double acc[4] = {0, 0, 0, 0};
+    double f[3] = {0, 0, 0};
     double4 pa[PB], wa[PB];
 #pragma unroll
     for (int u = 0; u < PB; ++u) { pa[u] = jsv[2 * (j0 + u)]; wa[u] = jsv[2 * (j0 + u) + 1]; }
@@ -292,6 +317,12 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__
                     const double dw = fma(dx, qw.x, fma(dy, qw.y, dz * qw.z));
                     acc[3] = fma(dw, r3, acc[3]);
                 }
+                if (FORCE) {
+                    const double wf = (q.w * r) * r2;
+                    f[0] = fma(wf, dx, f[0]);
+                    f[1] = fma(wf, dy, f[1]);
+                    f[2] = fma(wf, dz, f[2]);
+                }
             }
 #pragma unroll
             for (int u = 0; u < PB; ++u) { pa[u] = pb[u]; wa[u] = wb[u]; }
@@ -302,6 +333,11 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__
 #pragma unroll
         for (int c = 0; c < 3; ++c) p[c * npad] = acc[c];
         if (MASS) p[3 * npad] = acc[3];
+        if (FORCE) {
+            double* pf = partf + (int64_t)blockIdx.y * 3 * npad + (i - i0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pf[c * npad] = f[c];
+        }
     }
 }
 
@@ -371,50 +407,64 @@ hipError_t launch_pair_fwd_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, d
 
 template <bool EPS0, bool MASS>
 static void vjp_dispatch(dnb_ctx* c, const Slicing& sl, int64_t n, int i0, int iend, int nj,
-                         double eps2, hipStream_t st, const ExtRow& er, bool* ext_done) {
+                         double eps2, hipStream_t st, const ExtRow& er, bool* ext_done,
+                         bool force) {
     dim3 grid(sl.nblk, sl.S);
-    const bool nt = (int64_t)sl.S * sl.npad * (MASS ? 4 : 3) * 8 >= NT_PARTIAL_BYTES;
+    const int comps = (MASS ? 4 : 3) + (force ? 3 : 0);
+    const bool nt = (int64_t)sl.S * sl.npad * comps * 8 >= NT_PARTIAL_BYTES;
     const bool lds = sl.jslice <= VJP_LDS_SLICE;
     // the external-field row (whole-system launches, so the row blocks cover n;
     // the LDS instances, those of small systems, only; and only while the launch
-    // stays within one round of resident blocks)
-    const bool row = c->prec == DNB_FP32C && c->ext_row && er.x && i0 == 0 && iend == n &&
-                     lds && ext_row_fits(sl);
+    // stays within one round of resident blocks); not with the acceleration sum,
+    // whose caller needs the external acceleration itself, which the row does not
+    // return
+    const bool row = !force && c->prec == DNB_FP32C && c->ext_row && er.x && i0 == 0 &&
+                     iend == n && lds && ext_row_fits(sl);
     if (row) grid.y += 1;
     if (ext_done) *ext_done = row;
     auto go = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, grid, dim3(BS), 0, st, (const float4*)c->jsv, (int)n, i0,
                            iend, nj, sl.jslice, (float)eps2, (float*)c->partv, sl.npad, c->muni,
-                           row ? er : ExtRow{}, c->aext_v);
+                           row ? er : ExtRow{}, c->aext_v, (float*)c->part);
     };
     if (c->prec == DNB_FP32C) {
-        if (lds && nt && row) go(k_pair_vjp_f32c<EPS0, MASS, true, true, true>);
-        else if (lds && nt) go(k_pair_vjp_f32c<EPS0, MASS, true, true, false>);
-        else if (lds && row) go(k_pair_vjp_f32c<EPS0, MASS, true, false, true>);
-        else if (lds) go(k_pair_vjp_f32c<EPS0, MASS, true, false, false>);
-        else if (nt) go(k_pair_vjp_f32c<EPS0, MASS, false, true, false>);
-        else go(k_pair_vjp_f32c<EPS0, MASS, false, false, false>);
-    } else {
-        hipLaunchKernelGGL((k_pair_vjp_f64<EPS0, MASS>), grid, dim3(BS), 0, st,
+        if (force) {
+            if (lds && nt) go(k_pair_vjp_f32c<EPS0, MASS, true, true, false, true>);
+            else if (lds) go(k_pair_vjp_f32c<EPS0, MASS, true, false, false, true>);
+            else if (nt) go(k_pair_vjp_f32c<EPS0, MASS, false, true, false, true>);
+            else go(k_pair_vjp_f32c<EPS0, MASS, false, false, false, true>);
+        }
+        else if (lds && nt && row) go(k_pair_vjp_f32c<EPS0, MASS, true, true, true, false>);
+        else if (lds && nt) go(k_pair_vjp_f32c<EPS0, MASS, true, true, false, false>);
+        else if (lds && row) go(k_pair_vjp_f32c<EPS0, MASS, true, false, true, false>);
+        else if (lds) go(k_pair_vjp_f32c<EPS0, MASS, true, false, false, false>);
+        else if (nt) go(k_pair_vjp_f32c<EPS0, MASS, false, true, false, false>);
+        else go(k_pair_vjp_f32c<EPS0, MASS, false, false, false, false>);
+    } else if (force) {
+        hipLaunchKernelGGL((k_pair_vjp_f64<EPS0, MASS, true>), grid, dim3(BS), 0, st,
                            (const double4*)c->jsv, (int)n, i0, iend, nj, sl.jslice, eps2,
-                           (double*)c->partv, sl.npad);
+                           (double*)c->partv, sl.npad, (double*)c->part);
+    } else {
+        hipLaunchKernelGGL((k_pair_vjp_f64<EPS0, MASS, false>), grid, dim3(BS), 0, st,
+                           (const double4*)c->jsv, (int)n, i0, iend, nj, sl.jslice, eps2,
+                           (double*)c->partv, sl.npad, (double*)nullptr);
     }
 }
 
 static hipError_t launch_pair_vjp_sliced(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni,
                                          const Slicing& sl, int with_mass, double eps,
                                          hipStream_t st, const ExtRow& er = ExtRow{},
-                                         bool* ext_done = nullptr) {
+                                         bool* ext_done = nullptr, bool force = false) {
     if (ext_done) *ext_done = false;
     const int nj = (int)pad_sources(n);
     const int a = (int)i0, e = (int)(i0 + ni);
     const double eps2 = eps * eps;
     if (eps == 0.0) {
-        if (with_mass) vjp_dispatch<true, true>(c, sl, n, a, e, nj, eps2, st, er, ext_done);
-        else vjp_dispatch<true, false>(c, sl, n, a, e, nj, eps2, st, er, ext_done);
+        if (with_mass) vjp_dispatch<true, true>(c, sl, n, a, e, nj, eps2, st, er, ext_done, force);
+        else vjp_dispatch<true, false>(c, sl, n, a, e, nj, eps2, st, er, ext_done, force);
     } else {
-        if (with_mass) vjp_dispatch<false, true>(c, sl, n, a, e, nj, eps2, st, er, ext_done);
-        else vjp_dispatch<false, false>(c, sl, n, a, e, nj, eps2, st, er, ext_done);
+        if (with_mass) vjp_dispatch<false, true>(c, sl, n, a, e, nj, eps2, st, er, ext_done, force);
+        else vjp_dispatch<false, false>(c, sl, n, a, e, nj, eps2, st, er, ext_done, force);
     }
     return hipGetLastError();
 }
@@ -423,6 +473,17 @@ hipError_t launch_pair_vjp(dnb_ctx* c, int64_t n, int with_mass, double eps, hip
                            const ExtRow& ext, bool* ext_done) {
     return launch_pair_vjp_sliced(c, n, 0, n, vjp_slicing(c, n), with_mass, eps, st, ext,
                                   ext_done);
+}
+
+// The pair VJP of the whole system together with the internal acceleration at
+// the same staged positions: the VJP partials as launch_pair_vjp writes them, the
+// acceleration partials in the forward pair kernel's buffer and layout (the
+// forward and VJP slicings are the same), for launch_fwd_reduce (FP32C) or the
+// kernel that sums them (FP64).
+hipError_t launch_pair_vjp_force(dnb_ctx* c, int64_t n, int with_mass, double eps,
+                                 hipStream_t st) {
+    return launch_pair_vjp_sliced(c, n, 0, n, vjp_slicing(c, n), with_mass, eps, st, ExtRow{},
+                                  nullptr, true);
 }
 
 hipError_t launch_pair_vjp_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, int with_mass,

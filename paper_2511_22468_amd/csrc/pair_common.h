@@ -121,8 +121,8 @@ __device__ __forceinline__ void fwd_f32c_slice_lds(const float4* lds, int i, int
 // For target k and cotangent w, with d = x_j - x_k, s = |d|^2 + eps^2:
 //   (J^T w)_k / G = sum_j [s^-3/2 u - 3 s^-5/2 (d.u) d],  u = m_k w_j - m_j w_k
 //   gm_k / G      = sum_j (d.w_j) s^-3/2          (mass cotangent, negated later)
-// The internal acceleration the dt and mass-scale terms need is not summed here:
-// the forward pass stores it with the tape.
+// Without FORCE the internal acceleration the dt and mass-scale terms need is not
+// summed here: the forward pass stores it with the tape.
 // jsv: interleaved [2 j] = (x, y, z, m), [2 j + 1] = (wx, wy, wz, 0), padded.
 // part: [S][4][npad] float2 = (hi, lo) of the three J^T w components and of gm.
 // The two terms of J^T w are accumulated apart (A = sum s^-3/2 u,
@@ -130,10 +130,16 @@ __device__ __forceinline__ void fwd_f32c_slice_lds(const float4* lds, int i, int
 // the factor -3 out of the pair loop.  With UNI (all masses equal to m)
 // u = m (w_j - w_k): the mass leaves the pair term and is applied once per
 // target, 22 VALU operations and one v_rsq_f32 per pair.
-template <bool EPS0, bool MASS, bool UNI>
+//
+// With FORCE the pair term of the internal acceleration at the same positions,
+// m_j d s^-3/2 (m_j left out with UNI), is summed into F as well: three more FMA
+// operations on the s^-3/2 the VJP already has.  The reverse sweep that rebuilds
+// the trajectory by stepping backward needs a(x_k) exactly where it evaluates
+// J(x_k)^T w.
+template <bool EPS0, bool MASS, bool UNI, bool FORCE = false>
 __device__ __forceinline__ void vjp_f32c_pair(float4 q, float4 qw, int j, int i, float eps2,
                                               float4 me, float4 mw, float (&A)[3],
-                                              float (&B)[3], float& gm) {
+                                              float (&B)[3], float& gm, float (&F)[3]) {
     const float dx = q.x - me.x, dy = q.y - me.y, dz = q.z - me.z;
     const float s = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
     float r = __builtin_amdgcn_rsqf(s);
@@ -152,18 +158,28 @@ __device__ __forceinline__ void vjp_f32c_pair(float4 q, float4 qw, int j, int i,
     B[1] = fmaf(t, dy, B[1]);
     B[2] = fmaf(t, dz, B[2]);
     if (MASS) gm = fmaf(fmaf(dx, qw.x, fmaf(dy, qw.y, dz * qw.z)), r3, gm);
+    if (FORCE) {
+        const float wf = UNI ? r3 : q.w * r3;
+        F[0] = fmaf(wf, dx, F[0]);
+        F[1] = fmaf(wf, dy, F[1]);
+        F[2] = fmaf(wf, dz, F[2]);
+    }
 }
 
-template <bool EPS0, bool MASS, bool UNI>
+// h, l: (hi, lo) of J^T w (0..2), gm (3) and, with FORCE, the acceleration
+// (4..6).
+template <bool EPS0, bool MASS, bool UNI, bool FORCE = false, int NH>
 __device__ __forceinline__ void vjp_f32c_slice(const float4* __restrict__ jsv, int i, int j0,
                                                int j1, float eps2, float4 me, float4 mw,
-                                               float (&h)[4], float (&l)[4]) {
+                                               float (&h)[NH], float (&l)[NH]) {
+    static_assert(NH >= (FORCE ? 7 : 4), "slice sums need 4 (hi, lo) pairs, 7 with FORCE");
     constexpr int PB = 4;
     float4 pa[PB], wa[PB];
 #pragma unroll
     for (int u = 0; u < PB; ++u) { pa[u] = jsv[2 * (j0 + u)]; wa[u] = jsv[2 * (j0 + u) + 1]; }
     for (int jt = j0; jt < j1; jt += SUBTILE) {
         float A[3] = {0.f, 0.f, 0.f}, B[3] = {0.f, 0.f, 0.f}, gm = 0.f;
+        float F[3] = {0.f, 0.f, 0.f};
         const int kend = min(SUBTILE, j1 - jt);
         for (int k = 0; k < kend; k += PB) {
             const int nx = next_batch(jt, k, PB, kend, j1);
@@ -172,13 +188,18 @@ __device__ __forceinline__ void vjp_f32c_slice(const float4* __restrict__ jsv, i
             for (int u = 0; u < PB; ++u) { pb[u] = jsv[2 * (nx + u)]; wb[u] = jsv[2 * (nx + u) + 1]; }
 #pragma unroll
             for (int u = 0; u < PB; ++u)
-                vjp_f32c_pair<EPS0, MASS, UNI>(pa[u], wa[u], jt + k + u, i, eps2, me, mw, A, B, gm);
+                vjp_f32c_pair<EPS0, MASS, UNI, FORCE>(pa[u], wa[u], jt + k + u, i, eps2, me, mw,
+                                                      A, B, gm, F);
 #pragma unroll
             for (int u = 0; u < PB; ++u) { pa[u] = pb[u]; wa[u] = wb[u]; }
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) two_sum_acc(h[c], l[c], fmaf(-3.f, B[c], A[c]));
         if (MASS) two_sum_acc(h[3], l[3], gm);
+        if (FORCE) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) two_sum_acc(h[4 + c], l[4 + c], F[c]);
+        }
     }
 }
 
@@ -186,13 +207,15 @@ __device__ __forceinline__ void vjp_f32c_slice(const float4* __restrict__ jsv, i
 // and lds[2 (j - j0) + 1] are those of source j): the same pairs in the same
 // order, bit for bit the result of vjp_f32c_slice, with the reads issued at the
 // top of each batch rather than one batch ahead.
-template <bool EPS0, bool MASS, bool UNI>
+template <bool EPS0, bool MASS, bool UNI, bool FORCE = false, int NH>
 __device__ __forceinline__ void vjp_f32c_slice_lds(const float4* lds, int i, int j0, int j1,
                                                    float eps2, float4 me, float4 mw,
-                                                   float (&h)[4], float (&l)[4]) {
+                                                   float (&h)[NH], float (&l)[NH]) {
+    static_assert(NH >= (FORCE ? 7 : 4), "slice sums need 4 (hi, lo) pairs, 7 with FORCE");
     constexpr int PB = 4;
     for (int jt = j0; jt < j1; jt += SUBTILE) {
         float A[3] = {0.f, 0.f, 0.f}, B[3] = {0.f, 0.f, 0.f}, gm = 0.f;
+        float F[3] = {0.f, 0.f, 0.f};
         const int kend = min(SUBTILE, j1 - jt);
         for (int k = 0; k < kend; k += PB) {
             float4 q[PB], qw[PB];
@@ -203,11 +226,16 @@ __device__ __forceinline__ void vjp_f32c_slice_lds(const float4* lds, int i, int
             }
 #pragma unroll
             for (int u = 0; u < PB; ++u)
-                vjp_f32c_pair<EPS0, MASS, UNI>(q[u], qw[u], jt + k + u, i, eps2, me, mw, A, B, gm);
+                vjp_f32c_pair<EPS0, MASS, UNI, FORCE>(q[u], qw[u], jt + k + u, i, eps2, me, mw, A,
+                                                      B, gm, F);
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) two_sum_acc(h[c], l[c], fmaf(-3.f, B[c], A[c]));
         if (MASS) two_sum_acc(h[3], l[3], gm);
+        if (FORCE) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) two_sum_acc(h[4 + c], l[4 + c], F[c]);
+        }
     }
 }
 

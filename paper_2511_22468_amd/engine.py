@@ -225,16 +225,24 @@ class Context:
         return tape_out
 
     def simulate_vjp(self, mass, pot, dt, n_steps, ckpt_every, tape, pos_T, gpos_T, gvel_T=None,
-                     with_mass=False, workspace=None):
+                     with_mass=False, workspace=None, vel_T=None):
         """Returns (gpos_0, gvel_0, gmass or None, gparams[7]) with gparams =
         (dL/dm_nfw, dL/dm_mn, dL/ddt, sum_k m_k dL/dm_k, dL/drs_nfw, dL/da_mn,
-        dL/db_mn)."""
+        dL/db_mn).  With vel_T (the final velocities of the forward run) the
+        sweep rebuilds the trajectory between checkpoints by stepping it backward
+        (dnb_simulate_vjp_reversed); without, it recomputes it forward
+        (dnb_simulate_vjp)."""
         n = mass.shape[0]
         _arr(mass, (n,), "mass"); _vec(pos_T, n, "pos_T"); _vec(gpos_T, n, "gpos_T")
         if gvel_T is not None:
             _vec(gvel_T, n, "gvel_T")
+        if vel_T is not None:
+            _vec(vel_T, n, "vel_T")
         K = int(ckpt_every)
-        ws_len = int(_lib.lib().dnb_vjp_workspace_doubles(n, K))
+        if vel_T is None:
+            ws_len = int(_lib.lib().dnb_vjp_workspace_doubles(n, K))
+        else:
+            ws_len = int(_lib.lib().dnb_vjp_reversed_workspace_doubles(n))
         if workspace is None:
             workspace = self._new(ws_len)
         _buffer(workspace, ws_len, "workspace")
@@ -243,11 +251,14 @@ class Context:
         gpos0, gvel0 = self._new(3, n), self._new(3, n)
         gmass = self._new(n) if with_mass else None
         gpar = self._new(7)
-        _lib.check(_lib.lib().dnb_simulate_vjp(
-            self._h, n, _lib.ptr(mass), pot.c(), float(dt), int(n_steps), K, _lib.ptr(tape),
-            _lib.ptr(pos_T), _lib.ptr(gpos_T), _lib.ptr(gvel_T), _lib.ptr(workspace),
-            _lib.ptr(gpos0), _lib.ptr(gvel0), _lib.ptr(gmass), _lib.ptr(gpar),
-            _lib.stream_handle()))
+        head = (self._h, n, _lib.ptr(mass), pot.c(), float(dt), int(n_steps), K, _lib.ptr(tape),
+                _lib.ptr(pos_T))
+        tail = (_lib.ptr(gpos_T), _lib.ptr(gvel_T), _lib.ptr(workspace), _lib.ptr(gpos0),
+                _lib.ptr(gvel0), _lib.ptr(gmass), _lib.ptr(gpar), _lib.stream_handle())
+        if vel_T is None:
+            _lib.check(_lib.lib().dnb_simulate_vjp(*head, *tail))
+        else:
+            _lib.check(_lib.lib().dnb_simulate_vjp_reversed(*head, _lib.ptr(vel_T), *tail))
         return gpos0, gvel0, gmass, gpar
 
     # --------------------------------------------------------------- loss --

@@ -21,10 +21,11 @@ W_NOW = (12.0, 0.0, 0.0, 0.0, -180.0, 60.0)
 
 class StreamModel:
     def __init__(self, engine_ctx, xi, zeta, target, n_steps, pot=None, h=0.2, a_p=0.01,
-                 ckpt_every=1, w_now=W_NOW):
+                 ckpt_every=1, w_now=W_NOW, reversal=False):
         self.ctx = engine_ctx
         self.xi, self.zeta, self.target = xi, zeta, target
         self.n_steps, self.h, self.a_p, self.K = int(n_steps), float(h), float(a_p), int(ckpt_every)
+        self.reversal = bool(reversal)
         self.pot = pot if pot is not None else Potential()
         self.w_now = torch.tensor(w_now, dtype=torch.float64, device=xi.device)
 
@@ -35,7 +36,7 @@ class StreamModel:
         pos, vel, mass = AG.place_plummer(self.ctx, w0, m_prog, self.xi, self.zeta, self.a_p,
                                           self.pot.G)
         pos_T, _ = AG.simulate(self.ctx, pos, vel, mass, m_nfw, m_mn, dt, self.pot, self.n_steps,
-                               self.K, m_scale=m_prog)
+                               self.K, m_scale=m_prog, reversal=self.reversal)
         return pos_T
 
     def loss(self, theta):

@@ -97,6 +97,8 @@ static void sizes() {
     EXPECT(tape_doubles(0, 5, 1) == -1 && tape_doubles(10, -1, 1) == -1 &&
            tape_doubles(10, 5, 0) == -1 && tape_doubles(MAX_N + 1, 5, 1) == -1);
     EXPECT(vjp_workspace_doubles(0, 1) == -1 && vjp_workspace_doubles(10, 0) == -1);
+    EXPECT(vjp_reversed_workspace_doubles(10) == 170 && vjp_reversed_workspace_doubles(0) == -1);
+    EXPECT(vjp_reversed_workspace_doubles(MAX_N + 1) == -1);
     EXPECT(batch_tape_doubles(0, 10, 5) == -1 && batch_tape_doubles(DNB_BATCH_MAX + 1, 10, 5) == -1);
     // sizes whose products leave int64 are refused rather than wrapped
     const int64_t big = int64_t(1) << 62;
@@ -153,7 +155,7 @@ static void ring() {
     EXPECT(r.find(base) == nullptr);
     const double* pos = base + 60000;
     auto desc = [&](int64_t off, const double* p, int64_t n, int64_t T, int64_t K) {
-        return TapeDesc{base + off, p, nullptr, n, T, K, 0.1, {}, 0, 0};
+        return TapeDesc{base + off, p, nullptr, n, T, K, 0.1, {}, 0, 0, nullptr};
     };
     // 20 tapes into a ring of 16: the oldest 4 drop out
     for (int k = 0; k < 20; ++k) r.remember(desc(1000 * k, base + 50000 + k, 10, 5, 1));
@@ -174,7 +176,7 @@ static void ring() {
     EXPECT(r.find(base + 12000) != nullptr);
     // a batched descriptor measures its length with the batched formula
     TapeRing rb;
-    rb.remember(TapeDesc{base, pos, nullptr, 10, 3, 1, 0.0, {}, 4, 77});
+    rb.remember(TapeDesc{base, pos, nullptr, 10, 3, 1, 0.0, {}, 4, 77, nullptr});
     const int64_t lb = batch_tape_doubles(4, 10, 3);
     EXPECT(lb == (6 * 3 + 3 * 4) * 4 * 10);
     rb.forget(nullptr, base + lb - 1, 1);
