@@ -45,15 +45,20 @@ FLOPS_VJP = 41                    # per pair of the vector-Jacobian product
 # what the hardware's FP32 instruction counters count per pair for that path
 # (profiles/pair_kernels_n65536_flops.md, same kernel sources as the traffic key).
 FLOPS_FWD_EXEC, FLOPS_VJP_EXEC = 18, 35
-FLOPS_COUNTED = {"k_pair_fwd_f32c": 18.2, "k_pair_vjp_f32c": 34.2}
+FLOPS_COUNTED = {"k_pair_fwd_f32c": 18.2, "k_pair_vjp_f32c": 34.2,
+                 "k_pair_vjp_f32c+force": 40.4}
+# The pair launch of the sweep that steps the trajectory backward sums the VJP
+# and the acceleration together: the VJP's count plus three FMA per pair.
+FLOPS_VJP_FORCE, FLOPS_VJP_FORCE_EXEC = FLOPS_VJP + 6, FLOPS_VJP_EXEC + 6
 
 # HBM bytes per launch from the two rocprofv3 counter passes recorded in
 # profiles/pair_kernels_n65536_traffic.md (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the
 # factors measured on a 256 MiB copy), valid only for the kernel source they were
 # measured on (sha256 prefix of pair.hip followed by pair_common.h) and for N = 65536.
-TRAFFIC_SRC_SHA = "356bb9f8efeeb0db"
+TRAFFIC_SRC_SHA = "04d93f804b783b74"
 TRAFFIC_N = 65536
-TRAFFIC_KIB = {"k_pair_fwd_f32c": (7701.5, 49152.0), "k_pair_vjp_f32c": (15380.6, 49152.0)}
+TRAFFIC_KIB = {"k_pair_fwd_f32c": (7701.5, 49152.0), "k_pair_vjp_f32c": (15443.7, 49152.0),
+               "k_pair_vjp_f32c+force": (15383.0, 98304.0)}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
@@ -643,8 +648,9 @@ def main():
                     help="skip the time-to-fit comparison that the default line carries")
     ap.add_argument("--profile-run", action="store_true",
                     help="short run for hardware counters: one step of 20 KDK steps at the "
-                         "same N, plus a 256 MiB device copy that calibrates FETCH_SIZE and "
-                         "WRITE_SIZE")
+                         "same N, one reverse sweep of them that steps the trajectory backward "
+                         "(checkpoints every 10), plus a 256 MiB device copy that calibrates "
+                         "FETCH_SIZE and WRITE_SIZE")
     ap.add_argument("--sweep", action="store_true",
                     help="kernel rates of the forward and VJP pair kernels at every workload "
                          "size (N = 1024 ... 65536), one JSON line")
@@ -878,10 +884,23 @@ def main():
         ctx.profile(False)
         from paper_2511_22468_amd import _lib
         fused_ms = pr["vjp_ms"] / max(pr["vjp_launches"], 1)
+        fused_tf = FLOPS_VJP_FORCE * float(n) * n / (fused_ms * 1e-3) / 1e12
+        counted_f = FLOPS_COUNTED["k_pair_vjp_f32c+force"] if counted else None
         out["checkpointed"]["reversed"] = {
             "ckpt_every": 100, "ms_per_step": sr * 1e3, "value": pairs / sr,
             "fused_launch_ms": fused_ms, "fused_launches": pr["vjp_launches"],
             "fused_pairs_per_s": float(n) * n / (fused_ms * 1e-3),
+            "fused_roofline": {
+                "bound": "alu", "kernel": "k_pair_vjp_f32c (with the acceleration)",
+                "achieved": fused_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": fused_tf / PEAK_FP32_TFLOPS, "flops_per_pair": FLOPS_VJP_FORCE,
+                "flops_per_pair_executed": FLOPS_VJP_FORCE_EXEC,
+                "flops_per_pair_counted": counted_f,
+                "frac_counted": (counted_f * float(n) * n / (fused_ms * 1e-3) / 1e12
+                                 / PEAK_FP32_TFLOPS) if counted else None,
+                "traffic": (measured_traffic("k_pair_vjp_f32c+force", n)
+                            if args.prec == "fp32c" else None),
+            },
             "workspace_bytes": 8 * int(_lib.lib().dnb_vjp_reversed_workspace_doubles(n)),
             "recompute_workspace_bytes": 8 * int(_lib.lib().dnb_vjp_workspace_doubles(n, 100)),
             "loss_same_as_full_tape": bool(torch.equal(Lr, L)),
@@ -889,6 +908,12 @@ def main():
             "grad_rel_diff_vs_full_tape": [float(v) for v in
                                            (gr / g - 1).abs().cpu().numpy()],
         }
+    if args.profile_run:
+        # one reverse sweep that steps the trajectory backward (checkpoints every
+        # 10 of the 20 steps), so that the counter passes see its fused pair launch
+        StreamModel(ctx, xi, zeta, target, T, pot=pot, h=0.2, ckpt_every=10,
+                    reversal=True).loss_and_grad(theta)
+        torch.cuda.synchronize()
     ctx.close()
     if args.profile_run:
         # calibration for the traffic counters: a plain copy of 256 MiB
