@@ -456,7 +456,7 @@ def configs():
     xi, zeta = plummer_unit(n, 3)
     model = StreamModel(ctx, t3(xi), t3(zeta), target, T, ckpt_every=K)
     theta = theta_true * torch.tensor([1.1, 1.2, 0.9, 1.1], dtype=torch.float64, device=dev)
-    secs, _ = timed(lambda: model.loss_and_grad(theta))
+    secs, (L, g) = timed(lambda: model.loss_and_grad(theta))
     # forward: T + 1 pair sums; recompute: K pair sums per segment (K - 1 steps
     # and the acceleration of the segment's last position), T in all; reverse:
     # T + 1 pair VJPs
@@ -464,6 +464,16 @@ def configs():
     out.append({"workload": f"N={n} stream pipeline, {T} steps of t_acc/2000, MMD vs 4096, "
                             f"loss and gradient, checkpoints every {K} (FP32C)",
                 "seconds": secs, "pair_interactions_per_s": pairs / secs})
+    # the same with the trajectory between checkpoints rebuilt by stepping backward
+    model_r = StreamModel(ctx, t3(xi), t3(zeta), target, T, ckpt_every=K, reversal=True)
+    secs_r, (Lr, gr) = timed(lambda: model_r.loss_and_grad(theta))
+    out.append({"workload": f"N={n} stream pipeline, {T} steps of t_acc/2000, MMD vs 4096, "
+                            f"loss and gradient, checkpoints every {K}, trajectory stepped "
+                            f"backward (FP32C)",
+                "seconds": secs_r, "pair_interactions_per_s": 2 * (T + 1) * n * n / secs_r,
+                "grad": [float(v) for v in gr.cpu().numpy()],
+                "grad_recomputed": [float(v) for v in g.cpu().numpy()],
+                "loss_same": bool(torch.equal(L, Lr))})
     ctx.close()
     return out
 
