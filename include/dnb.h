@@ -268,7 +268,9 @@ int64_t dnb_vjp_reversed_workspace_doubles(int64_t n);
  *
  * Arguments as dnb_simulate_vjp, plus vel_T [3][n]: the final velocities, the
  * velocity array the forward call moved in place (DNB_ERR_STATE when it is not
- * the array recorded with the tape).  workspace holds
+ * the array recorded with the tape, or when a later dnb_simulate, dnb_step or
+ * dnb_place_plummer on this context wrote that array; dnb_simulate_vjp, which
+ * does not read it, still accepts the tape then).  workspace holds
  * dnb_vjp_reversed_workspace_doubles(n).  Outputs must not alias inputs. */
 dnb_status dnb_simulate_vjp_reversed(dnb_ctx* ctx, int64_t n, const double* mass,
                                      const dnb_pot* pot, double dt, int64_t n_steps,

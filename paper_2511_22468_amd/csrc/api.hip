@@ -100,8 +100,9 @@ dnb_status check_extent(const void* p, size_t bytes, const char* name, const cha
 }
 
 // Tape descriptors (dnb_ctx::tapes, see TapeRing).
-void forget_tapes(dnb_ctx* c, const double* pos, const double* tape, int64_t tape_len) {
-    c->tapes.forget(pos, tape, tape_len);
+void forget_tapes(dnb_ctx* c, const double* pos, const double* tape, int64_t tape_len,
+                  const double* vel) {
+    c->tapes.forget(pos, tape, tape_len, vel);
 }
 
 void remember_tape(dnb_ctx* c, const TapeDesc& d) { c->tapes.remember(d); }
@@ -503,7 +504,7 @@ static dnb_status check_sim_args(dnb_ctx* c, int64_t n, const void* pos, const v
 dnb_status dnb_step(dnb_ctx* c, int64_t n, double* pos, double* vel, const double* mass,
                     const dnb_pot* pot, double dt, void* stream) {
     CHECK(check_sim_args(c, n, pos, vel, mass, pot, dt, 1, 1, "dnb_step"));
-    forget_tapes(c, pos, nullptr, 0);
+    forget_tapes(c, pos, nullptr, 0, vel);
     return run_forward(c, n, pos, vel, mass, to_pot(*pot), dt, 1, 1, nullptr, (hipStream_t)stream);
 }
 
@@ -516,7 +517,7 @@ dnb_status dnb_simulate(dnb_ctx* c, int64_t n, double* pos, double* vel, const d
     const int64_t tl = dnb_tape_doubles(n, n_steps, ckpt_every);
     if (tape && n_steps > 0) CHECK(check_extent(tape, sizeof(double) * tl, "tape", fn));
     CHECK(checked_state(c, pos, vel, mass, n, 1, (hipStream_t)stream, fn));
-    forget_tapes(c, pos, tape, tape ? tl : 0);
+    forget_tapes(c, pos, tape, tape ? tl : 0, vel);
     Tape tp{tape, n, cdiv(n_steps, ckpt_every)};
     CHECK(run_forward(c, n, pos, vel, mass, to_pot(*pot), dt, n_steps, ckpt_every,
                       tape ? &tp : nullptr, (hipStream_t)stream));
@@ -573,7 +574,7 @@ dnb_status dnb_simulate_resume(dnb_ctx* c, int64_t n, const double* tape, int64_
     const Tape src{const_cast<double*>(tape), n, n_ckpt};
     const double* x0 = src.state(ckpt);
     const size_t vec = sizeof(double) * 3 * n;
-    forget_tapes(c, pos, tape_out, tape_out ? tlo : 0);
+    forget_tapes(c, pos, tape_out, tape_out ? tlo : 0, vel);
     HIP_TRY(hipMemcpyAsync(pos, x0, vec, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(vel, x0 + 3 * n, vec, hipMemcpyDeviceToDevice, st));
     CHECK(checked_state(c, pos, vel, mass, n, 1, st, fn));
@@ -1004,7 +1005,7 @@ dnb_status dnb_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* pos,
     const int64_t tl = dnb_batch_tape_doubles(batch, n, n_steps);
     if (tape && n_steps > 0) CHECK(check_extent(tape, sizeof(double) * tl, "tape", fn));
     CHECK(checked_state(c, pos, vel, mass, n, batch, st, fn));
-    forget_tapes(c, pos, tape, tape ? tl : 0);
+    forget_tapes(c, pos, tape, tape ? tl : 0, vel);
     HIP_TRY(launch_simulate_batch(c, batch, n, pos, vel, mass, c->bparams, n_steps, tape, st));
     if (tape && n_steps > 0)
         remember_tape(c, TapeDesc{tape, pos, mass, n, n_steps, 1, 0.0, {}, batch,
@@ -1135,7 +1136,7 @@ dnb_status dnb_place_plummer_batch(dnb_ctx* c, int64_t batch, int64_t n, const d
     CHECK(check_dev(pos, "pos", fn));
     CHECK(check_dev(vel, "vel", fn));
     CHECK(check_dev(mass, "mass", fn));
-    forget_tapes(c, pos, nullptr, 0);
+    forget_tapes(c, pos, nullptr, 0, vel);
     HIP_TRY(launch_place_batch(batch, n, w, xi, zeta, m_tot, a_p, G, pos, vel, mass,
                                (hipStream_t)stream));
     return DNB_OK;
@@ -1192,7 +1193,7 @@ dnb_status dnb_place_plummer(dnb_ctx* c, int64_t n, const double* w, const doubl
     CHECK(check_dev(pos, "pos", fn));
     CHECK(check_dev(vel, "vel", fn));
     CHECK(check_dev(mass, "mass", fn));
-    forget_tapes(c, pos, nullptr, 0);
+    forget_tapes(c, pos, nullptr, 0, vel);
     HIP_TRY(launch_place(n, w, xi, zeta, m_tot, a_p, G, pos, vel, mass, (hipStream_t)stream));
     return DNB_OK;
 }

@@ -196,8 +196,12 @@ struct TapeRing {
 
     // A run that moves the positions pos in place makes every tape whose final
     // positions are pos stale; a tape written over [tape, tape + len) replaces
-    // every tape it overlaps.
-    void forget(const double* pos, const double* tape, int64_t len) {
+    // every tape it overlaps.  A run that moves the velocities vel in place only
+    // drops them from the tapes whose final velocities they were: the sweep that
+    // steps backward from them refuses such a tape, the one that recomputes
+    // forward does not read them.
+    void forget(const double* pos, const double* tape, int64_t len,
+                const double* vel = nullptr) {
         for (int k = 0; k < count; ++k) {
             TapeDesc& t = d[k];
             if (!t.tape) continue;
@@ -205,6 +209,7 @@ struct TapeRing {
             const bool overlap = tape && len > 0 && tl > 0 && tape < t.tape + tl &&
                                  t.tape < tape + len;
             if (t.pos == pos || overlap) t.tape = nullptr;
+            else if (vel && t.vel == vel) t.vel = nullptr;
         }
     }
 

@@ -174,6 +174,14 @@ static void ring() {
     EXPECT(r.find(base + 11000) != nullptr);
     r.forget(pos, base + 12000 - 10, 10);   // just before tape 12: no overlap
     EXPECT(r.find(base + 12000) != nullptr);
+    // a run that moves a tape's final velocities drops them from its record only
+    {
+        TapeRing rv;
+        const double* vel = base + 40000;
+        rv.remember(TapeDesc{base, pos, nullptr, 10, 5, 1, 0.1, {}, 0, 0, vel});
+        rv.forget(base + 30000, nullptr, 0, vel);
+        EXPECT(rv.find(base) != nullptr && rv.find(base)->vel == nullptr);
+    }
     // a batched descriptor measures its length with the batched formula
     TapeRing rb;
     rb.remember(TapeDesc{base, pos, nullptr, 10, 3, 1, 0.0, {}, 4, 77, nullptr});

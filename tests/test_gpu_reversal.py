@@ -228,3 +228,11 @@ def test_reversed_sweep_refuses_another_velocity_array(dnb):
     assert call(pv) == _lib.DNB_OK
     ref = c.simulate_vjp(pm, pot, dt, T, K, tape, px, g, vel_T=pv)
     assert torch.equal(outs[0], ref[0]) and torch.equal(outs[1], ref[1])
+    # a run that moves the final velocities (here another system's step with
+    # them) makes the backward-stepping sweep refuse the tape; the recomputing
+    # sweep, which does not read them, still takes it
+    qx = px.clone()
+    c.step(qx, pv, pm, pot, dt)
+    assert call(pv) == _lib.DNB_ERR_STATE
+    assert b"vel_T" in lib.dnb_last_error()
+    c.simulate_vjp(pm, pot, dt, T, K, tape, px, g)
