@@ -861,8 +861,7 @@ dnb_status dnb_simulate_vjp_reversed(dnb_ctx* c, int64_t n, const double* mass,
             }));
             RevArgs r{};
             if (f32) {
-                HIP_TRY(launch_vjp_reduce(c, n, p.G, with_mass, c->wscale + wq, st));
-                HIP_TRY(launch_fwd_reduce(c, n, mass, p.G, st));
+                HIP_TRY(launch_vjp_force_reduce(c, n, mass, p.G, with_mass, c->wscale + wq, st));
                 r.gred = c->gred; r.grec = c->grec; r.nr = red_blocks(n);
                 r.ared = c->ared; r.arec = c->arec;
             } else {

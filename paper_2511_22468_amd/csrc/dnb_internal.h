@@ -478,6 +478,8 @@ hipError_t launch_pair_vjp_rows(dnb_ctx* c, int64_t n, int64_t i0, int64_t ni, i
                                 double eps, hipStream_t st);
 hipError_t launch_pair_vjp_force(dnb_ctx* c, int64_t n, int with_mass, double eps,
                                  hipStream_t st);
+hipError_t launch_vjp_force_reduce(dnb_ctx* c, int64_t n, const double* mass, double G,
+                                   int with_mass, const double* wscale, hipStream_t st);
 hipError_t launch_acc_vjp_rows(dnb_ctx* c, const double* x, const double* w, int64_t n,
                                int64_t i0, int64_t ni, const Pot& pot, int with_ext,
                                double* gpos, double* gmass, hipStream_t st);

@@ -476,6 +476,35 @@ __global__ __launch_bounds__(BS) void k_vjp_reduce(const float2* __restrict__ pa
     vjp_reduce_block(part, S, npad, n, G, with_mass != 0, 1.0 / wscale[0], gred, rec, sh);
 }
 
+// Both reductions of the reverse sweep that steps the trajectory backward, in
+// one launch: the VJP partials into gred as k_vjp_reduce, then the acceleration
+// partials the same pair launch summed into ared as k_fwd_reduce (the same device
+// code, so the same bits as the two launches).
+__global__ __launch_bounds__(BS) void k_vjp_force_reduce(const float2* __restrict__ partv,
+                                                         const float2* __restrict__ partf,
+                                                         int S, int64_t npad, int64_t n,
+                                                         double G, int with_mass,
+                                                         const double* __restrict__ wscale,
+                                                         const double* __restrict__ mass,
+                                                         double* __restrict__ gred,
+                                                         double* __restrict__ grec,
+                                                         double* __restrict__ ared,
+                                                         double* __restrict__ arec) {
+    __shared__ double sh[4 * RG * RT];
+    vjp_reduce_block(partv, S, npad, n, G, with_mass != 0, 1.0 / wscale[0], gred, grec, sh);
+    __syncthreads();
+    fwd_reduce_block(partf, S, npad, n, G, mass, ared, arec, sh);
+}
+
+hipError_t launch_vjp_force_reduce(dnb_ctx* c, int64_t n, const double* mass, double G,
+                                   int with_mass, const double* wscale, hipStream_t st) {
+    const Slicing sl = vjp_slicing(c, n);
+    hipLaunchKernelGGL(k_vjp_force_reduce, dim3((unsigned)red_blocks(n)), dim3(BS), 0, st,
+                       (const float2*)c->partv, (const float2*)c->part, sl.S, sl.npad, n, G,
+                       with_mass, wscale, mass, c->gred, c->grec, c->ared, c->arec);
+    return hipGetLastError();
+}
+
 hipError_t launch_fwd_reduce(dnb_ctx* c, int64_t n, const double* mass, double G,
                              hipStream_t st) {
     const Slicing sl = fwd_slicing(c, n);
