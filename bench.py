@@ -482,7 +482,8 @@ def small_gradient(n=1000, T=1000, reps=5):
     """One small system's pipeline gradient at the paper's inference size (n = 1000
     particles, 1000 steps of t_end / 1000, eps = a_P = 0.01 kpc, MMD against a mock
     stream from its own IC seed), through the single-system path, with the tape every
-    step and with checkpoints every 10 steps.  Best and median of `reps` timed
+    step, with checkpoints every 10 steps, and with the same checkpoints and the
+    trajectory stepped backward between them.  Best and median of `reps` timed
     evaluations after one warm-up; one JSON object."""
     import torch
 
@@ -500,8 +501,9 @@ def small_gradient(n=1000, T=1000, reps=5):
     xi, zeta = plummer_unit(n, 12)
     out = {"n": n, "steps": T, "eps_kpc": 0.01}
     grads = []
-    for K in (1, 10):
-        model = StreamModel(ctx, t3(xi), t3(zeta), target, T, pot=pot, h=0.2, ckpt_every=K)
+    for K, rev in ((1, False), (10, False), (10, True)):
+        model = StreamModel(ctx, t3(xi), t3(zeta), target, T, pot=pot, h=0.2, ckpt_every=K,
+                            reversal=rev)
         th = theta * 1.05
         L, g = model.loss_and_grad(th)
         torch.cuda.synchronize()
@@ -513,9 +515,11 @@ def small_gradient(n=1000, T=1000, reps=5):
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
         times.sort()
-        out[f"ckpt_every_{K}"] = {"best_us_per_step": times[0] / T * 1e6,
-                                  "median_us_per_step": times[len(times) // 2] / T * 1e6}
+        out[f"ckpt_every_{K}" + ("_stepped_backward" if rev else "")] = {
+            "best_us_per_step": times[0] / T * 1e6,
+            "median_us_per_step": times[len(times) // 2] / T * 1e6}
     out["same_gradient"] = bool(np.array_equal(grads[0], grads[1]))
+    out["stepped_backward_grad_rel_diff"] = [float(v) for v in np.abs(grads[2] / grads[0] - 1)]
     ctx.close()
     return out
 
