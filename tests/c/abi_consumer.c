@@ -90,6 +90,25 @@ int main(void) {
             FAIL("gradient %d: %.17g %.17g", i, g[i], gv[i]);
     }
 
+    /* the sweep that steps the trajectory backward between checkpoints every 5
+     * steps, from the final velocities the forward run left in dvel: the same
+     * closed form */
+    const int64_t K2 = 5;
+    double* work2;
+    if (hipMalloc((void**)&work2, sizeof(double) * dnb_vjp_reversed_workspace_doubles(n)))
+        FAIL("hipMalloc failed");
+    if (dnb_simulate(ctx, n, dpos, dvel, dmass, &pot, 0.01, T, K2, tape, NULL) != DNB_OK)
+        FAIL("simulate: %s", dnb_last_error());
+    if (dnb_simulate_vjp_reversed(ctx, n, dmass, &pot, 0.01, T, K2, tape, dpos, dvel, dw, NULL,
+                                  work2, g0, gv0, NULL, gpar, NULL) != DNB_OK)
+        FAIL("simulate_vjp_reversed: %s", dnb_last_error());
+    hipMemcpy(g, g0, sizeof g, hipMemcpyDeviceToHost);
+    hipMemcpy(gv, gv0, sizeof gv, hipMemcpyDeviceToHost);
+    for (int i = 0; i < 2; ++i) {
+        if (fabs(g[i] - 1.0) > 1e-12 || fabs(gv[i] - T * 0.01) > 1e-12)
+            FAIL("reversed-sweep gradient %d: %.17g %.17g", i, g[i], gv[i]);
+    }
+
     /* a refused call: negative step count */
     if (dnb_simulate(ctx, n, dpos, dvel, dmass, &pot, 0.01, -1, 1, NULL, NULL) != DNB_ERR_ARG)
         FAIL("negative n_steps was accepted");
