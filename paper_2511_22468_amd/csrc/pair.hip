@@ -104,13 +104,17 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f32c(const float4* __restrict__
                                                       float eps2, float* __restrict__ part,
                                                       int64_t npad,
                                                       const float* __restrict__ muni,
-                                                      ExtRow er, double* __restrict__ aext) {
+                                                      ExtRow er, double* __restrict__ aext,
+                                                      int smaj) {
     if (ROW && blockIdx.y == 0) {   // the external-field row, first so it starts at once
         ext_row_fwd(er, n, aext);
         return;
     }
-    const int i = i0 + blockIdx.x * BS + threadIdx.x;
-    const int sy = blockIdx.y - (ROW ? 1 : 0);   // source slice
+    // smaj: the grid is (slices, target blocks), so that consecutive blocks, which
+    // the dispatcher spreads over the compute units, share their sources
+    const int tb = smaj ? blockIdx.y : blockIdx.x;
+    const int i = i0 + tb * BS + threadIdx.x;
+    const int sy = smaj ? blockIdx.x : blockIdx.y - (ROW ? 1 : 0);   // source slice
     const int j0 = sy * jslice;
     const int j1 = min(nj, j0 + jslice);
     const float4 me = js[min(i, n - 1)];
@@ -206,15 +210,16 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f32c(const float4* __restrict__
                                                       int64_t npad,
                                                       const float* __restrict__ muni,
                                                       ExtRow er, double* __restrict__ aext,
-                                                      float* __restrict__ partf) {
+                                                      float* __restrict__ partf, int smaj) {
     static_assert(!(ROW && FORCE), "the external-field row and FORCE are not combined");
     if (ROW && blockIdx.y == 0) {   // the external-field row, first so it starts at once
         ext_row_vjp(er, n, aext);
         return;
     }
     constexpr int NH = FORCE ? 7 : 4;
-    const int i = i0 + blockIdx.x * BS + threadIdx.x;
-    const int sy = blockIdx.y - (ROW ? 1 : 0);   // source slice
+    const int tb = smaj ? blockIdx.y : blockIdx.x;   // grid (slices, target blocks) with smaj
+    const int i = i0 + tb * BS + threadIdx.x;
+    const int sy = smaj ? blockIdx.x : blockIdx.y - (ROW ? 1 : 0);   // source slice
     const int j0 = sy * jslice;
     const int j1 = min(nj, j0 + jslice);
     const int ii = min(i, n - 1);
@@ -363,9 +368,13 @@ static hipError_t launch_pair_fwd_sliced(dnb_ctx* c, int64_t n, int64_t i0, int6
         const bool row = c->ext_row && er.x && i0 == 0 && ni == n && lds && ext_row_fits(sl);
         if (row) grid.y += 1;
         if (ext_done) *ext_done = row;
+        // (slices, target blocks) order, see dnb_ctx::slice_major
+        const int smaj = (c->slice_major && !row && sl.nblk <= 65535) ? 1 : 0;
+        const dim3 grid32 = smaj ? dim3(sl.S, sl.nblk) : grid;
         auto go = [&](auto kernel) {
-            hipLaunchKernelGGL(kernel, grid, dim3(BS), 0, st, js, (int)n, a, e, nj, sl.jslice,
-                               eps2, part, sl.npad, c->muni, row ? er : ExtRow{}, c->aext_f);
+            hipLaunchKernelGGL(kernel, grid32, dim3(BS), 0, st, js, (int)n, a, e, nj, sl.jslice,
+                               eps2, part, sl.npad, c->muni, row ? er : ExtRow{}, c->aext_f,
+                               smaj);
         };
         const int which = (eps == 0.0 ? 8 : 0) + (lds ? 4 : 0) + (nt ? 2 : 0) + (row ? 1 : 0);
         switch (which) {
@@ -422,10 +431,15 @@ static void vjp_dispatch(dnb_ctx* c, const Slicing& sl, int64_t n, int i0, int i
                      iend == n && lds && ext_row_fits(sl);
     if (row) grid.y += 1;
     if (ext_done) *ext_done = row;
+    // (slices, target blocks) order: the FP32C kernels only (the FP64 kernels read
+    // the grid as (target blocks, slices))
+    const int smaj =
+        (c->prec == DNB_FP32C && c->slice_major && !row && sl.nblk <= 65535) ? 1 : 0;
+    const dim3 grid32 = smaj ? dim3(sl.S, sl.nblk) : grid;
     auto go = [&](auto kernel) {
-        hipLaunchKernelGGL(kernel, grid, dim3(BS), 0, st, (const float4*)c->jsv, (int)n, i0,
+        hipLaunchKernelGGL(kernel, grid32, dim3(BS), 0, st, (const float4*)c->jsv, (int)n, i0,
                            iend, nj, sl.jslice, (float)eps2, (float*)c->partv, sl.npad, c->muni,
-                           row ? er : ExtRow{}, c->aext_v, (float*)c->part);
+                           row ? er : ExtRow{}, c->aext_v, (float*)c->part, smaj);
     };
     if (c->prec == DNB_FP32C) {
         if (force) {
