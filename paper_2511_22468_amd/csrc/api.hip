@@ -310,7 +310,7 @@ dnb_status dnb_create(dnb_ctx** out, int64_t max_n, dnb_prec prec) {
     // DNB_EXT_ROW=0: the kicks evaluate the external field themselves (the same
     // bits; for comparisons)
     c->ext_row = env_int("DNB_EXT_ROW", 1, {0, 1});
-    // FP32C pair grids in (slices, target blocks) order: the dispatcher spreads
+    // Pair grids in (slices, target blocks) order: the dispatcher spreads
     // consecutive blocks over the compute units, so each unit then runs blocks of
     // one slice, whose sources its scalar cache keeps (DNB_SLICE_MAJOR=0: the
     // (target blocks, slices) order, the same bits; for comparisons)

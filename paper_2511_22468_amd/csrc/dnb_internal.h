@@ -295,7 +295,7 @@ struct dnb_ctx {
     int64_t* scan;           // [nbmax + 1] block minima and result of the state scan
     int checks;              // nonzero: the integrators scan their initial state first
     int ext_row;             // nonzero: small FP32C pair launches carry the external-field row
-    int slice_major;         // nonzero: FP32C pair grids ordered (slices, target blocks)
+    int slice_major;         // nonzero: pair grids ordered (slices, target blocks)
     void* prof;              // host-side event pool of dnb_profile (null when off)
     // The reverse sweep recomputes checkpoint segments on a second stream of
     // its own (created on first use, default priority) while the caller's stream

@@ -154,10 +154,12 @@ template <bool EPS0>
 __global__ __launch_bounds__(BS) void k_pair_fwd_f64(const double4* __restrict__ js, int n,
                                                      int i0, int iend, int nj, int jslice,
                                                      double eps2, double* __restrict__ part,
-                                                     int64_t npad) {
+                                                     int64_t npad, int smaj) {
     constexpr int PB = 4;
-    const int i = i0 + blockIdx.x * BS + threadIdx.x;
-    const int j0 = blockIdx.y * jslice;
+    const int tb = smaj ? blockIdx.y : blockIdx.x;   // grid (slices, target blocks) with smaj
+    const int sy = smaj ? blockIdx.x : blockIdx.y;
+    const int i = i0 + tb * BS + threadIdx.x;
+    const int j0 = sy * jslice;
     const int j1 = min(nj, j0 + jslice);
     const double4 me = js[min(i, n - 1)];
     double ax = 0.0, ay = 0.0, az = 0.0;
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(BS) void k_pair_fwd_f64(const double4* __restrict__
         }
     }
     if (i < iend) {
-        double* p = part + (int64_t)blockIdx.y * 3 * npad + (i - i0);
+        double* p = part + (int64_t)sy * 3 * npad + (i - i0);
         p[0] = ax; p[npad] = ay; p[2 * npad] = az;
     }
 }
@@ -279,10 +281,13 @@ template <bool EPS0, bool MASS, bool FORCE>
 __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__ jsv, int n,
                                                      int i0, int iend, int nj, int jslice,
                                                      double eps2, double* __restrict__ part,
-                                                     int64_t npad, double* __restrict__ partf) {
+                                                     int64_t npad, double* __restrict__ partf,
+                                                     int smaj) {
     constexpr int PB = 2;
-    const int i = i0 + blockIdx.x * BS + threadIdx.x;
-    const int j0 = blockIdx.y * jslice;
+    const int tb = smaj ? blockIdx.y : blockIdx.x;   // grid (slices, target blocks) with smaj
+    const int sy = smaj ? blockIdx.x : blockIdx.y;
+    const int i = i0 + tb * BS + threadIdx.x;
+    const int j0 = sy * jslice;
     const int j1 = min(nj, j0 + jslice);
     const int ii = min(i, n - 1);
     const double4 me = jsv[2 * ii];
@@ -334,12 +339,12 @@ __global__ __launch_bounds__(BS) void k_pair_vjp_f64(const double4* __restrict__
         }
     }
     if (i < iend) {
-        double* p = part + (int64_t)blockIdx.y * 4 * npad + (i - i0);
+        double* p = part + (int64_t)sy * 4 * npad + (i - i0);
 #pragma unroll
         for (int c = 0; c < 3; ++c) p[c * npad] = acc[c];
         if (MASS) p[3 * npad] = acc[3];
         if (FORCE) {
-            double* pf = partf + (int64_t)blockIdx.y * 3 * npad + (i - i0);
+            double* pf = partf + (int64_t)sy * 3 * npad + (i - i0);
 #pragma unroll
             for (int c = 0; c < 3; ++c) pf[c * npad] = f[c];
         }
@@ -394,12 +399,14 @@ static hipError_t launch_pair_fwd_sliced(dnb_ctx* c, int64_t n, int64_t i0, int6
     } else {
         const double eps2 = eps * eps;
         const double4* js = (const double4*)c->js;
+        const int smaj = (c->slice_major && sl.nblk <= 65535) ? 1 : 0;
+        const dim3 grid64 = smaj ? dim3(sl.S, sl.nblk) : grid;
         if (eps == 0.0)
-            hipLaunchKernelGGL(k_pair_fwd_f64<true>, grid, dim3(BS), 0, st, js, (int)n, a, e, nj,
-                               sl.jslice, eps2, (double*)c->part, sl.npad);
+            hipLaunchKernelGGL(k_pair_fwd_f64<true>, grid64, dim3(BS), 0, st, js, (int)n, a, e,
+                               nj, sl.jslice, eps2, (double*)c->part, sl.npad, smaj);
         else
-            hipLaunchKernelGGL(k_pair_fwd_f64<false>, grid, dim3(BS), 0, st, js, (int)n, a, e,
-                               nj, sl.jslice, eps2, (double*)c->part, sl.npad);
+            hipLaunchKernelGGL(k_pair_fwd_f64<false>, grid64, dim3(BS), 0, st, js, (int)n, a, e,
+                               nj, sl.jslice, eps2, (double*)c->part, sl.npad, smaj);
     }
     return hipGetLastError();
 }
@@ -431,10 +438,9 @@ static void vjp_dispatch(dnb_ctx* c, const Slicing& sl, int64_t n, int i0, int i
                      iend == n && lds && ext_row_fits(sl);
     if (row) grid.y += 1;
     if (ext_done) *ext_done = row;
-    // (slices, target blocks) order: the FP32C kernels only (the FP64 kernels read
-    // the grid as (target blocks, slices))
-    const int smaj =
-        (c->prec == DNB_FP32C && c->slice_major && !row && sl.nblk <= 65535) ? 1 : 0;
+    // (slices, target blocks) order, see dnb_ctx::slice_major (not with the row,
+    // which is the grid's first row of blocks)
+    const int smaj = (c->slice_major && !row && sl.nblk <= 65535) ? 1 : 0;
     const dim3 grid32 = smaj ? dim3(sl.S, sl.nblk) : grid;
     auto go = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, grid32, dim3(BS), 0, st, (const float4*)c->jsv, (int)n, i0,
@@ -455,13 +461,13 @@ static void vjp_dispatch(dnb_ctx* c, const Slicing& sl, int64_t n, int i0, int i
         else if (nt) go(k_pair_vjp_f32c<EPS0, MASS, false, true, false, false>);
         else go(k_pair_vjp_f32c<EPS0, MASS, false, false, false, false>);
     } else if (force) {
-        hipLaunchKernelGGL((k_pair_vjp_f64<EPS0, MASS, true>), grid, dim3(BS), 0, st,
+        hipLaunchKernelGGL((k_pair_vjp_f64<EPS0, MASS, true>), grid32, dim3(BS), 0, st,
                            (const double4*)c->jsv, (int)n, i0, iend, nj, sl.jslice, eps2,
-                           (double*)c->partv, sl.npad, (double*)c->part);
+                           (double*)c->partv, sl.npad, (double*)c->part, smaj);
     } else {
-        hipLaunchKernelGGL((k_pair_vjp_f64<EPS0, MASS, false>), grid, dim3(BS), 0, st,
+        hipLaunchKernelGGL((k_pair_vjp_f64<EPS0, MASS, false>), grid32, dim3(BS), 0, st,
                            (const double4*)c->jsv, (int)n, i0, iend, nj, sl.jslice, eps2,
-                           (double*)c->partv, sl.npad, (double*)nullptr);
+                           (double*)c->partv, sl.npad, (double*)nullptr, smaj);
     }
 }
 
