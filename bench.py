@@ -55,10 +55,10 @@ FLOPS_VJP_FORCE, FLOPS_VJP_FORCE_EXEC = FLOPS_VJP + 6, FLOPS_VJP_EXEC + 6
 # profiles/pair_kernels_n65536_traffic.md (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the
 # factors measured on a 256 MiB copy), valid only for the kernel source they were
 # measured on (sha256 prefix of pair.hip followed by pair_common.h) and for N = 65536.
-TRAFFIC_SRC_SHA = "7fd2d8ae9c075cbb"
+TRAFFIC_SRC_SHA = "7349c404d30ef7bd"
 TRAFFIC_N = 65536
-TRAFFIC_KIB = {"k_pair_fwd_f32c": (4502.1, 49152.0), "k_pair_vjp_f32c": (9084.8, 49152.0),
-               "k_pair_vjp_f32c+force": (9017.2, 98304.0)}
+TRAFFIC_KIB = {"k_pair_fwd_f32c": (4501.6, 49152.0), "k_pair_vjp_f32c": (8988.6, 49152.0),
+               "k_pair_vjp_f32c+force": (9023.6, 98304.0)}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
