@@ -62,6 +62,56 @@ TRAFFIC_KIB = {"k_pair_fwd_f32c": (4501.6, 49152.0), "k_pair_vjp_f32c": (8988.6,
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
+class ClockSampler:
+    """Samples the GPU's current shader clock from sysfs (the level marked '*'
+    in pp_dpm_sclk of the first card that has one) every `period` seconds in a
+    background thread, so that the timed region's clock is recorded beside its
+    result.  Reads a file only; reports None where the file is not readable."""
+
+    def __init__(self, period=0.2):
+        import glob
+        import threading
+        paths = sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"))
+        self.path = paths[0] if paths else None
+        self.period, self.samples = period, []
+        self._stop = threading.Event()
+        self._thread = threading.Thread(target=self._run, daemon=True)
+
+    def _read(self):
+        try:
+            with open(self.path) as f:
+                for line in f:
+                    if line.rstrip().endswith("*"):
+                        return float(line.split(":")[1].strip().split("Mhz")[0].split("MHz")[0])
+        except (OSError, ValueError, IndexError):
+            return None
+        return None
+
+    def __enter__(self):
+        if self.path:
+            self._thread.start()
+        return self
+
+    def _run(self):
+        while not self._stop.is_set():
+            v = self._read()
+            if v is not None:
+                self.samples.append(v)
+            self._stop.wait(self.period)
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        if self.path:
+            self._thread.join()
+
+    def summary(self):
+        if not self.samples:
+            return None
+        v = sorted(self.samples)
+        return {"source": self.path, "samples": len(v), "min": v[0], "median": v[len(v) // 2],
+                "max": v[-1]}
+
+
 def kernel_source_sha():
     """sha256 prefix of the pair-kernel sources (pair.hip, then pair_common.h)."""
     import hashlib
@@ -778,11 +828,12 @@ def main():
     ctx.profile(True)
     ctx.profile_read()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        L, g = model.loss_and_grad(theta)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    with ClockSampler() as clock:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            L, g = model.loss_and_grad(theta)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     prof = ctx.profile_read()
     ctx.profile(False)
 
@@ -862,6 +913,7 @@ def main():
                              / 1e12 / PEAK_FP32_TFLOPS) if counted else None,
         },
         "cpu_baseline": None,
+        "sclk_mhz": clock.summary(),
     }
     if K == 1 and not args.profile_run and not args.no_checkpointed:
         # the same step with checkpoints every 100 steps: the reverse sweep
