@@ -102,16 +102,48 @@ __global__ __launch_bounds__(BS) void k_batch_stage(const double* __restrict__ p
     }
 }
 
+// Target block x, source slice y and member b of a block of a batched pair
+// launch (grid (nblk, S, batch)).  The dispatcher deals consecutive blocks out to
+// the XCDs and their compute units in turn, so the blocks one compute unit holds
+// at a time lie about 256 apart in the linear block index.  With remap, the
+// linear index L is read so that those blocks share (member, slice) and differ in
+// the target block, and their sources stay in the unit's scalar cache: L = r +
+// 256 q, x = q mod nblk, and the (member, slice) index is r + 256 (q / nblk), over
+// the largest multiple of 256 (member, slice) pairs; the pairs left over take
+// the plain order.  A bijection of the blocks, so the results are the same bits.
+struct BatchBlock {
+    int x, y;
+    int64_t b;
+};
+__device__ inline BatchBlock batch_block(const BatchGeom& g, int remap) {
+    if (!remap) return BatchBlock{(int)blockIdx.x, (int)blockIdx.y, (int64_t)blockIdx.z};
+    constexpr int64_t G = 256;
+    const int64_t L = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+    const int64_t Q = ((int64_t)g.S * gridDim.z) / G;
+    const int64_t head = (int64_t)g.nblk * G * Q;
+    int64_t x, c;
+    if (L < head) {
+        const int64_t q = L / G;
+        x = q % g.nblk;
+        c = L % G + G * (q / g.nblk);
+    } else {
+        x = (L - head) % g.nblk;
+        c = G * Q + (L - head) / g.nblk;
+    }
+    return BatchBlock{(int)x, (int)(c % g.S), c / g.S};
+}
+
 // Pair sums of every member.  grid (nblk, S, batch).
 template <bool NT>
 __global__ __launch_bounds__(BS) void k_batch_pair_fwd(const float4* __restrict__ js, BatchGeom g,
                                                        const double* __restrict__ params,
                                                        const float* __restrict__ muni,
-                                                       float* __restrict__ part) {
-    const int b = blockIdx.z;
+                                                       float* __restrict__ part, int remap) {
+    const BatchBlock bb = batch_block(g, remap);
+    const int b = (int)bb.b;
     const float4* jb = js + (int64_t)b * g.nj;
-    const int i = blockIdx.x * BS + threadIdx.x;
-    const int j0 = blockIdx.y * g.jslice;
+    const int i = bb.x * BS + threadIdx.x;
+    const int j0 = bb.y * g.jslice;
     const int j1 = min(g.nj, j0 + g.jslice);
     const double eps = params[8 * b + 1];
     const float eps2 = (float)(eps * eps);
@@ -125,7 +157,7 @@ __global__ __launch_bounds__(BS) void k_batch_pair_fwd(const float4* __restrict_
         fwd_f32c_slice<false, false>(jb, i, j0, j1, eps2, me, h, l);
     }
     if (i < g.n) {
-        float2* p = (float2*)part + ((int64_t)b * g.S + blockIdx.y) * 3 * g.npad + i;
+        float2* p = (float2*)part + ((int64_t)b * g.S + bb.y) * 3 * g.npad + i;
         for (int c = 0; c < 3; ++c) put_partial<NT>(p + c * g.npad, h[c], l[c]);
     }
 }
@@ -460,7 +492,7 @@ hipError_t launch_simulate_batch(dnb_ctx* c, int64_t batch, int64_t n, double* p
         hipLaunchKernelGGL(nt_partials(g, batch, 3) ? k_batch_pair_fwd<true>
                                                     : k_batch_pair_fwd<false>,
                            dim3(g.nblk, g.S, (unsigned)batch), dim3(BS), 0, st, js, g,
-                           params_dev, c->muni, part);
+                           params_dev, c->muni, part, c->slice_major);
         hipLaunchKernelGGL(k_batch_fwd_reduce, red, dim3(BS), 0, st, (const float*)part, g,
                            params_dev, mass, c->ared, c->arec);
         double* ts = (tape && s < n_steps) ? tp.state(s) : nullptr;
@@ -546,11 +578,12 @@ __global__ __launch_bounds__(BS) void k_batch_pair_vjp(const float4* __restrict_
                                                        BatchGeom g,
                                                        const double* __restrict__ params,
                                                        const float* __restrict__ muni,
-                                                       float* __restrict__ part) {
-    const int64_t b = blockIdx.z;
+                                                       float* __restrict__ part, int remap) {
+    const BatchBlock bb = batch_block(g, remap);
+    const int64_t b = bb.b;
     const float4* jb = jsv + b * g.nj * 2;
-    const int i = blockIdx.x * BS + threadIdx.x;
-    const int j0 = blockIdx.y * g.jslice;
+    const int i = bb.x * BS + threadIdx.x;
+    const int j0 = bb.y * g.jslice;
     const int j1 = min(g.nj, j0 + g.jslice);
     const int ii = min(i, g.n - 1);
     const float4 me = jb[2 * ii];
@@ -567,7 +600,7 @@ __global__ __launch_bounds__(BS) void k_batch_pair_vjp(const float4* __restrict_
         vjp_f32c_slice<false, false, false>(jb, i, j0, j1, eps2, me, mw, h, l);
     }
     if (i < g.n) {
-        float2* p = (float2*)part + (b * g.S + blockIdx.y) * 4 * g.npad + i;
+        float2* p = (float2*)part + (b * g.S + bb.y) * 4 * g.npad + i;
         for (int c = 0; c < 3; ++c) put_partial<NT>(p + c * g.npad, h[c], l[c]);
     }
 }
@@ -695,7 +728,7 @@ hipError_t launch_simulate_batch_vjp(dnb_ctx* c, int64_t batch, int64_t n, const
         hipLaunchKernelGGL(nt_partials(g, batch, 3) ? k_batch_pair_vjp<true>
                                                     : k_batch_pair_vjp<false>,
                            dim3(g.nblk, g.S, (unsigned)batch), dim3(BS), 0, st,
-                           (const float4*)jsv, g, params_dev, c->muni, part);
+                           (const float4*)jsv, g, params_dev, c->muni, part, c->slice_major);
         hipLaunchKernelGGL(k_batch_vjp_reduce, dim3((unsigned)red_blocks(n), (unsigned)batch),
                            dim3(BS), 0, st, (const float*)part, g, params_dev, c->bwscale, wq,
                            c->gred, c->grec);
