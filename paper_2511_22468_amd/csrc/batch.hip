@@ -103,34 +103,19 @@ __global__ __launch_bounds__(BS) void k_batch_stage(const double* __restrict__ p
 }
 
 // Target block x, source slice y and member b of a block of a batched pair
-// launch (grid (nblk, S, batch)).  The dispatcher deals consecutive blocks out to
-// the XCDs and their compute units in turn, so the blocks one compute unit holds
-// at a time lie about 256 apart in the linear block index.  With remap, the
-// linear index L is read so that those blocks share (member, slice) and differ in
-// the target block, and their sources stay in the unit's scalar cache: L = r +
-// 256 q, x = q mod nblk, and the (member, slice) index is r + 256 (q / nblk), over
-// the largest multiple of 256 (member, slice) pairs; the pairs left over take
-// the plain order.  A bijection of the blocks, so the results are the same bits.
+// launch (grid (nblk, S, batch)); with remap, read from the linear block index by
+// batch_block_index (host_logic.h) so that the blocks one compute unit holds at a
+// time share their sources.
 struct BatchBlock {
     int x, y;
     int64_t b;
 };
 __device__ inline BatchBlock batch_block(const BatchGeom& g, int remap) {
     if (!remap) return BatchBlock{(int)blockIdx.x, (int)blockIdx.y, (int64_t)blockIdx.z};
-    constexpr int64_t G = 256;
-    const int64_t L = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
-    const int64_t Q = ((int64_t)g.S * gridDim.z) / G;
-    const int64_t head = (int64_t)g.nblk * G * Q;
-    int64_t x, c;
-    if (L < head) {
-        const int64_t q = L / G;
-        x = q % g.nblk;
-        c = L % G + G * (q / g.nblk);
-    } else {
-        x = (L - head) % g.nblk;
-        c = G * Q + (L - head) / g.nblk;
-    }
-    return BatchBlock{(int)x, (int)(c % g.S), c / g.S};
+    const int64_t L =
+        blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+    const BatchBlockIdx t = batch_block_index(L, g.nblk, g.S, gridDim.z);
+    return BatchBlock{(int)t.x, (int)t.y, t.b};
 }
 
 // Pair sums of every member.  grid (nblk, S, batch).

@@ -26,6 +26,35 @@ constexpr int RT = 64;               // targets per block of the FP32C slice red
 constexpr int RG = BS / RT;          // slice groups per block of those reductions
 constexpr int64_t MAX_N = int64_t(1) << 26;   // largest context (particles)
 
+// Target block x, source slice y and member b of the block with linear index L
+// of a batched pair launch over (nblk target blocks, S slices, B members).  The
+// dispatcher deals consecutive blocks out to the XCDs and their compute units in
+// turn, so the blocks one compute unit holds at a time lie about 256 apart in L.
+// Read as L = r + 256 q, with x = q mod nblk and (member, slice) index
+// r + 256 (q / nblk), those blocks share member and slice and differ in the
+// target block, so their sources stay in the unit's scalar cache; this covers
+// the largest multiple of 256 (member, slice) pairs, and the pairs left over take
+// the plain order.  A bijection of [0, nblk S B) onto the blocks (constexpr, so
+// device code calls it too).
+struct BatchBlockIdx {
+    int64_t x, y, b;
+};
+constexpr BatchBlockIdx batch_block_index(int64_t L, int64_t nblk, int64_t S, int64_t B) {
+    const int64_t G = 256;
+    const int64_t Q = (S * B) / G;
+    const int64_t head = nblk * G * Q;
+    int64_t x = 0, c = 0;
+    if (L < head) {
+        const int64_t q = L / G;
+        x = q % nblk;
+        c = L % G + G * (q / nblk);
+    } else {
+        x = (L - head) % nblk;
+        c = G * Q + (L - head) / nblk;
+    }
+    return BatchBlockIdx{x, c % S, c / S};
+}
+
 // ceil(a / b) for a >= 0, b > 0 (without forming a + b, which could overflow).
 inline int64_t cdiv(int64_t a, int64_t b) { return a / b + (a % b != 0 ? 1 : 0); }
 

@@ -174,6 +174,29 @@ static void ring() {
     EXPECT(r.find(base + 11000) != nullptr);
     r.forget(pos, base + 12000 - 10, 10);   // just before tape 12: no overlap
     EXPECT(r.find(base + 12000) != nullptr);
+    // the batched pair blocks' remapped index: a bijection for every shape, and
+    // the blocks 256 apart share member and slice
+    {
+        const int64_t shapes[][3] = {{16, 8, 512}, {4, 32, 1}, {4, 8, 1000}, {1, 64, 3},
+                                     {16, 8, 64},  {4, 8, 4096}, {2, 8, 33}, {256, 32, 1},
+                                     {3, 17, 19}, {4, 8, 31}, {1, 8, 1}};
+        for (const auto& sh : shapes) {
+            const int64_t nb = sh[0], S = sh[1], B = sh[2], tot = nb * S * B;
+            std::vector<char> seen((size_t)tot, 0);
+            for (int64_t L = 0; L < tot; ++L) {
+                const BatchBlockIdx t = batch_block_index(L, nb, S, B);
+                EXPECT(t.x >= 0 && t.x < nb && t.y >= 0 && t.y < S && t.b >= 0 && t.b < B);
+                const int64_t k = (t.b * S + t.y) * nb + t.x;
+                EXPECT(!seen[(size_t)k]);
+                seen[(size_t)k] = 1;
+            }
+        }
+        for (int64_t k = 1; k < 8; ++k) {
+            const BatchBlockIdx a = batch_block_index(37, 16, 8, 512);
+            const BatchBlockIdx b = batch_block_index(37 + 256 * k, 16, 8, 512);
+            EXPECT(a.y == b.y && a.b == b.b && b.x == a.x + k);
+        }
+    }
     // a run that moves a tape's final velocities drops them from its record only
     {
         TapeRing rv;
