@@ -54,7 +54,8 @@ FLOPS_VJP_FORCE, FLOPS_VJP_FORCE_EXEC = FLOPS_VJP + 6, FLOPS_VJP_EXEC + 6
 # HBM bytes per launch from the two rocprofv3 counter passes recorded in
 # profiles/pair_kernels_n65536_traffic.md (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the
 # factors measured on a 256 MiB copy), valid only for the kernel source they were
-# measured on (sha256 prefix of pair.hip followed by pair_common.h) and for N = 65536.
+# measured on (sha256 prefix of pair.hip, pair_common.h and host_logic.h) and for
+# N = 65536.
 TRAFFIC_SRC_SHA = "7349c404d30ef7bd"
 TRAFFIC_N = 65536
 TRAFFIC_KIB = {"k_pair_fwd_f32c": (4501.6, 49152.0), "k_pair_vjp_f32c": (8988.6, 49152.0),
@@ -113,10 +114,11 @@ class ClockSampler:
 
 
 def kernel_source_sha():
-    """sha256 prefix of the pair-kernel sources (pair.hip, then pair_common.h)."""
+    """sha256 prefix of the pair-kernel sources and their launch geometry (pair.hip,
+    pair_common.h, then host_logic.h)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("pair.hip", "pair_common.h"):
+    for name in ("pair.hip", "pair_common.h", "host_logic.h"):
         with open(os.path.join(ROOT, "paper_2511_22468_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -18,7 +18,7 @@ namespace dnb {
 constexpr int BS = 256;              // threads per block of every particle kernel
 constexpr int TILE = 256;            // sources staged in LDS per tile
 constexpr int SUBTILE = 128;         // sources summed in plain FP32 before a TwoSum
-constexpr int TARGET_BLOCKS = 8192;  // pair-kernel blocks wanted per launch (32 per CU)
+constexpr int TARGET_BLOCKS = 16384; // pair-kernel blocks wanted per launch (64 per CU)
 constexpr int S_MAX = 64;            // maximum number of source slices
 constexpr int SLICE_GRAIN = 32;      // pair-kernel source slices are multiples of this
 constexpr int REC = 8;               // doubles per block record of the O(N) kernels
