@@ -56,10 +56,10 @@ FLOPS_VJP_FORCE, FLOPS_VJP_FORCE_EXEC = FLOPS_VJP + 6, FLOPS_VJP_EXEC + 6
 # factors measured on a 256 MiB copy), valid only for the kernel source they were
 # measured on (sha256 prefix of pair.hip, pair_common.h and host_logic.h) and for
 # N = 65536.
-TRAFFIC_SRC_SHA = "7349c404d30ef7bd"
+TRAFFIC_SRC_SHA = "6365a8ba9647dfaf"
 TRAFFIC_N = 65536
-TRAFFIC_KIB = {"k_pair_fwd_f32c": (4501.6, 49152.0), "k_pair_vjp_f32c": (8988.6, 49152.0),
-               "k_pair_vjp_f32c+force": (9023.6, 98304.0)}
+TRAFFIC_KIB = {"k_pair_fwd_f32c": (4565.6, 98304.0), "k_pair_vjp_f32c": (9116.7, 98304.0),
+               "k_pair_vjp_f32c+force": (9135.6, 196608.0)}
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 
 
